@@ -1,0 +1,733 @@
+/*
+ * labf_oracle.c -- plain FP64 CPU oracle of the lambda-ABF alchemical
+ * nonbonded step.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, by the package smoke check
+ * and by the CPU-baseline leg of the benchmark; never by the product path.
+ * It shares no code with the HIP path.
+ *
+ * What it computes, in the paper's order (section and equation names refer
+ * to the lambda-ABF paper):
+ *   - the alchemical schedule lambda -> (lambda_e, lambda_v), Implementation,
+ *     "Alchemical pathway" (Tinker-HP convention b_v, b_e; NAMD staggered
+ *     decoupling convention), and the SI lambda-schedule table;
+ *   - the lambda-dependent potential V(q; lambda) of the Theory section,
+ *     Eq. (lambdadyn-Hamiltonian), with soft-core Lennard-Jones (NAMD
+ *     paragraph of "Alchemical pathway") and cutoff shifted-force Coulomb
+ *     linearly scaled by lambda_e (same paragraph; cutoff electrostatics
+ *     replaces PME here), decoupling (solute-solute terms kept at full
+ *     strength);
+ *   - lambda-switched harmonic restraints k(lambda) = k0 + lambda (k1 - k0)
+ *     (restraint release in "Binding restraints");
+ *   - Langevin dynamics of atoms and of the extended lambda coordinate,
+ *     Eq. (lambdadyn-Langevin-process) with the ABF term of Eq. (lambda-abf),
+ *     reflecting lambda boundaries, integrated by BAOAB (SI "Setup used for
+ *     numerical results"; BAOA for lambda in "Software interface");
+ *   - multiple-walker ABF on lambda: bin-averaged dV/dlambda as A'_t, linear
+ *     ramp up to fullSamples ("ABF parameters"), walkers sharing their
+ *     estimates every K steps ("Orthogonal space sampling");
+ *   - the Riemann-sum readout of A(lambda) from the bin averages ("Adaptive
+ *     Biasing Force using lambda as a collective variable").
+ * Readings of points the paper leaves open are listed in the design notes
+ * of the repository; each is restated where it is used below.
+ */
+#include "labf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_ST_NONFINITE 1u
+#define ORC_ST_REFLECT 2u
+
+static inline double sq(double a) { return a * a; }
+
+/* ---------------------------------------------------------------------------
+ * Alchemical schedule ("Alchemical pathway"): each channel x in {e, v} has a
+ * piecewise-linear ramp m_x(lambda) = clip((lambda - s_x)/(e_x - s_x), 0, 1).
+ * Coupling direction (Tinker-HP): c_x = m_x.  Decoupling direction (NAMD):
+ * c_x = 1 - m_x.  The derivative dc_x/dlambda is +-1/(e_x - s_x) on
+ * [s_x, e_x) and also at lambda = e_x = hi (left derivative at the upper
+ * end); zero elsewhere.
+ * out = {c_e, c_v, dc_e/dlambda, dc_v/dlambda}.
+ * ------------------------------------------------------------------------- */
+static void channel(double lam, double s0, double s1, int coupling, double hi,
+                    double *c, double *dc) {
+  double m, dm;
+  double w = s1 - s0;
+  if (lam <= s0) {
+    m = 0.0;
+  } else if (lam >= s1) {
+    m = 1.0;
+  } else {
+    m = (lam - s0) / w;
+  }
+  if ((lam >= s0 && lam < s1) || (lam == s1 && s1 == hi)) {
+    dm = 1.0 / w;
+  } else {
+    dm = 0.0;
+  }
+  if (coupling) {
+    *c = m;
+    *dc = dm;
+  } else {
+    *c = 1.0 - m;
+    *dc = -dm;
+  }
+}
+
+void orc_schedule(const orc_sys *s, double lam, double out[4]) {
+  double ce, dce, cv, dcv;
+  channel(lam, s->elec_start, s->elec_end, s->direction == 1, s->lam_hi, &ce, &dce);
+  channel(lam, s->vdw_start, s->vdw_end, s->direction == 1, s->lam_hi, &cv, &dcv);
+  out[0] = ce;
+  out[1] = cv;
+  out[2] = dce;
+  out[3] = dcv;
+}
+
+/* ---------------------------------------------------------------------------
+ * Pair terms at separation r, for a pair with mixed parameters (sig, eps),
+ * charge product qq (coulomb constant included) and channel couplings
+ * (cv, ce).
+ *
+ * Soft-core LJ (Beutler form, alpha, p):
+ *   s(r, c)   = 1 / (alpha (1-c)^p + (r/sig)^6)
+ *   phi(r, c) = 4 eps c (s^2 - s)
+ *   U_LJ      = phi(r, c) - phi(r_cut, c)        (shift at the same c)
+ *   dU_LJ/dc  = psi(r) - psi(r_cut),
+ *   psi       = 4 eps [(s^2 - s) + c alpha p (1-c)^(p-1) (2s - 1) s^2]
+ *   F/r       = 24 eps c (2s - 1) s^2 (r/sig)^6 / r^2   (repulsive > 0)
+ * Shifted-force Coulomb, linear in c_e:
+ *   g(r)      = 1/r - 1/r_cut + (r - r_cut)/r_cut^2
+ *   U_C       = ce qq g(r);  dU_C/dce = qq g(r)
+ *   F/r       = ce qq (1/r^2 - 1/r_cut^2) / r
+ * With shift = 0 the LJ potential shift is omitted (used by unit tests).
+ * out = {U_LJ, dU_LJ/dc_v, (F/r)_LJ, U_C, dU_C/dc_e, (F/r)_C}.
+ * ------------------------------------------------------------------------- */
+static double sc_s(double r, double sig, double c, double alpha, int p) {
+  double u = pow(r / sig, 6.0);
+  return 1.0 / (alpha * pow(1.0 - c, (double)p) + u);
+}
+
+void orc_pair_terms(double r, double sig, double eps, double qq, double cv, double ce,
+                    double alpha, int32_t p, double r_cut, int32_t shift, double out[6]) {
+  int k;
+  for (k = 0; k < 6; ++k) out[k] = 0.0;
+  if (eps != 0.0) {
+    double s = sc_s(r, sig, cv, alpha, p);
+    double u = pow(r / sig, 6.0);
+    double dsc = (p >= 1) ? alpha * (double)p * pow(1.0 - cv, (double)(p - 1)) : 0.0;
+    double phi = 4.0 * eps * cv * (s * s - s);
+    double psi = 4.0 * eps * ((s * s - s) + cv * dsc * (2.0 * s - 1.0) * s * s);
+    out[2] = 24.0 * eps * cv * (2.0 * s - 1.0) * s * s * u / (r * r);
+    if (shift) {
+      double sc = sc_s(r_cut, sig, cv, alpha, p);
+      phi -= 4.0 * eps * cv * (sc * sc - sc);
+      psi -= 4.0 * eps * ((sc * sc - sc) + cv * dsc * (2.0 * sc - 1.0) * sc * sc);
+    }
+    out[0] = phi;
+    out[1] = psi;
+  }
+  if (qq != 0.0) {
+    double g = 1.0 / r - 1.0 / r_cut + (r - r_cut) / (r_cut * r_cut);
+    out[4] = qq * g;
+    if (ce != 0.0) {
+      out[3] = ce * qq * g;
+      out[5] = ce * qq * (1.0 / (r * r) - 1.0 / (r_cut * r_cut)) / r;
+    }
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Minimum-image separation d = x_j - x_i (the neighbour-set definition):
+ * d_k -= L_k * rint(d_k * (1/L_k)), 1/L_k evaluated once in FP64, rint is
+ * round-half-even; r^2 = (dx*dx + dy*dy) + dz*dz with no fused operations
+ * (this file is compiled with -ffp-contract=off).
+ * ------------------------------------------------------------------------- */
+static double min_image(const double *xi, const double *xj, const double *L,
+                        const double *invL, double d[3]) {
+  int k;
+  for (k = 0; k < 3; ++k) {
+    double dk = xj[k] - xi[k];
+    dk -= L[k] * rint(dk * invL[k]);
+    d[k] = dk;
+  }
+  return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+/* ---------------------------------------------------------------------------
+ * Neighbour set: all pairs (i < j) of walker w with r^2 < r_list^2 under the
+ * minimum-image separation above.  brute = 1 tests every pair; brute = 0
+ * uses a cell list with n_c = floor(L / r_list) >= 3 cells per edge (falls
+ * back to brute force when any edge has fewer than 3 cells).  Pairs are
+ * written as walker-local indices (i, j), sorted lexicographically.
+ * Returns the number of pairs (which may exceed max_pairs; only the first
+ * max_pairs are stored) or -1 on an invalid request.
+ * ------------------------------------------------------------------------- */
+static int cmp_pair(const void *a, const void *b) {
+  const int64_t *pa = (const int64_t *)a, *pb = (const int64_t *)b;
+  if (pa[0] != pb[0]) return pa[0] < pb[0] ? -1 : 1;
+  if (pa[1] != pb[1]) return pa[1] < pb[1] ? -1 : 1;
+  return 0;
+}
+
+typedef struct {
+  int nc[3];
+  int64_t *head; /* first atom of each cell, -1 terminated lists */
+  int64_t *next;
+} cells_t;
+
+static int cells_build(cells_t *c, const double *x, int64_t n, const double *L, double r) {
+  int k;
+  int64_t i, ncell;
+  for (k = 0; k < 3; ++k) {
+    int m = (int)floor(L[k] / r);
+    while (m > 0 && L[k] / (double)m < r * (1.0 + 1e-12)) --m;
+    c->nc[k] = m;
+    if (m < 3) return 0;
+  }
+  ncell = (int64_t)c->nc[0] * c->nc[1] * c->nc[2];
+  c->head = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+  c->next = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  for (i = 0; i < ncell; ++i) c->head[i] = -1;
+  /* insert in decreasing index order so each cell lists atoms ascending */
+  for (i = n - 1; i >= 0; --i) {
+    int ci[3];
+    int64_t id;
+    for (k = 0; k < 3; ++k) {
+      double f = x[3 * i + k] / L[k];
+      f -= floor(f);
+      ci[k] = (int)floor(f * c->nc[k]);
+      if (ci[k] >= c->nc[k]) ci[k] = c->nc[k] - 1;
+      if (ci[k] < 0) ci[k] = 0;
+    }
+    id = ((int64_t)ci[0] * c->nc[1] + ci[1]) * c->nc[2] + ci[2];
+    c->next[i] = c->head[id];
+    c->head[id] = i;
+  }
+  return 1;
+}
+
+static void cells_free(cells_t *c) {
+  free(c->head);
+  free(c->next);
+}
+
+/* Calls visit(i, j, d, r2) once for every unordered pair (i < j) with
+ * r2 < rmax^2.  Uses the cell list when possible. */
+typedef void (*visit_fn)(void *ctx, int64_t i, int64_t j, const double d[3], double r2);
+
+static void for_each_pair(const double *x, int64_t n, const double *L, double rmax,
+                          int brute, visit_fn visit, void *ctx) {
+  double invL[3];
+  double r2max = rmax * rmax;
+  int k;
+  cells_t c;
+  for (k = 0; k < 3; ++k) invL[k] = 1.0 / L[k];
+  /* tiny walkers: scanning mostly empty cells costs more than all pairs */
+  if (!brute) {
+    double ncell = 1.0;
+    for (k = 0; k < 3; ++k) ncell *= floor(L[k] / rmax);
+    if ((double)n * (double)n < 27.0 * ncell) brute = 1;
+  }
+  if (!brute && cells_build(&c, x, n, L, rmax)) {
+    int a, b, e;
+    for (a = 0; a < c.nc[0]; ++a)
+      for (b = 0; b < c.nc[1]; ++b)
+        for (e = 0; e < c.nc[2]; ++e) {
+          int64_t id = ((int64_t)a * c.nc[1] + b) * c.nc[2] + e;
+          int da, db, de;
+          /* the 27 neighbouring cells, each visited once (n_c >= 3) */
+          for (da = -1; da <= 1; ++da)
+            for (db = -1; db <= 1; ++db)
+              for (de = -1; de <= 1; ++de) {
+                int a2 = (a + da + c.nc[0]) % c.nc[0];
+                int b2 = (b + db + c.nc[1]) % c.nc[1];
+                int e2 = (e + de + c.nc[2]) % c.nc[2];
+                int64_t id2 = ((int64_t)a2 * c.nc[1] + b2) * c.nc[2] + e2;
+                int64_t i, j;
+                for (i = c.head[id]; i >= 0; i = c.next[i])
+                  for (j = c.head[id2]; j >= 0; j = c.next[j]) {
+                    double d[3], r2;
+                    if (j <= i) continue;
+                    r2 = min_image(x + 3 * i, x + 3 * j, L, invL, d);
+                    if (r2 < r2max) visit(ctx, i, j, d, r2);
+                  }
+              }
+        }
+    cells_free(&c);
+  } else {
+    int64_t i, j;
+    for (i = 0; i < n; ++i)
+      for (j = i + 1; j < n; ++j) {
+        double d[3];
+        double r2 = min_image(x + 3 * i, x + 3 * j, L, invL, d);
+        if (r2 < r2max) visit(ctx, i, j, d, r2);
+      }
+  }
+}
+
+typedef struct {
+  int64_t count, max;
+  int64_t *pairs;
+} pair_ctx;
+
+static void collect_pair(void *vctx, int64_t i, int64_t j, const double d[3], double r2) {
+  pair_ctx *p = (pair_ctx *)vctx;
+  (void)d;
+  (void)r2;
+  if (p->count < p->max) {
+    p->pairs[2 * p->count] = i;
+    p->pairs[2 * p->count + 1] = j;
+  }
+  p->count++;
+}
+
+int64_t orc_neighbor_pairs(const orc_sys *s, int32_t w, const double *x, double r_list,
+                           int32_t brute, int64_t max_pairs, int64_t *pairs) {
+  pair_ctx ctx;
+  int64_t n;
+  const double *L;
+  int k;
+  if (w < 0 || w >= s->n_walkers) return -1;
+  L = s->box + 3 * w;
+  for (k = 0; k < 3; ++k)
+    if (!(r_list < 0.5 * L[k])) return -1;
+  n = s->atom_offset[w + 1] - s->atom_offset[w];
+  ctx.count = 0;
+  ctx.max = max_pairs;
+  ctx.pairs = pairs;
+  for_each_pair(x, n, L, r_list, brute, collect_pair, &ctx);
+  if (ctx.count <= max_pairs) qsort(pairs, (size_t)ctx.count, 2 * sizeof(int64_t), cmp_pair);
+  return ctx.count;
+}
+
+/* ---------------------------------------------------------------------------
+ * Potential, forces and dU/dlambda of one walker at (x, lambda).
+ * Pair classes: alchemical iff exactly one atom is solute (decoupling:
+ * solute-solute and environment-environment pairs use c = 1).  Mixing is
+ * Lorentz-Berthelot.  Restraints: U = 1/2 k(lambda) |x - anchor|^2 with
+ * minimum image, dU/dlambda = 1/2 (k1 - k0) |x - anchor|^2.
+ * f: [n_w][3] forces (may be NULL); u_parts: [5]; dudl: scalar.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_sys *s;
+  int64_t base;
+  double ce, cv, dce, dcv;
+  double *f;
+  double u[5];
+  double dudl;
+  /* optional parameter gradient: [n][3] = dU/d(eps, sigma, q) */
+  double *g;
+} eval_ctx;
+
+static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], double r2) {
+  eval_ctx *c = (eval_ctx *)vctx;
+  const orc_sys *s = c->s;
+  int64_t gi = c->base + i, gj = c->base + j;
+  double rc = s->r_cut;
+  double r, sig, eps, qq, cv, ce, t[6], fr;
+  int si, sj, alch;
+  int k;
+  if (!(r2 < rc * rc)) return;
+  r = sqrt(r2);
+  si = s->is_solute[gi] != 0;
+  sj = s->is_solute[gj] != 0;
+  alch = si != sj;
+  sig = 0.5 * (s->sigma[gi] + s->sigma[gj]);
+  eps = sqrt(s->epsilon[gi] * s->epsilon[gj]);
+  qq = s->coulomb_k * s->charge[gi] * s->charge[gj];
+  cv = alch ? c->cv : 1.0;
+  ce = alch ? c->ce : 1.0;
+  orc_pair_terms(r, sig, eps, qq, cv, ce, s->sc_alpha, s->sc_power, rc, 1, t);
+  fr = t[2] + t[5];
+  if (c->f) {
+    /* d = x_j - x_i; a repulsive pair pushes i along -d */
+    for (k = 0; k < 3; ++k) {
+      c->f[3 * i + k] -= fr * d[k];
+      c->f[3 * j + k] += fr * d[k];
+    }
+  }
+  if (alch) {
+    c->u[ORC_U_ALCH_LJ] += t[0];
+    c->u[ORC_U_ALCH_C] += t[3];
+    if (c->dcv != 0.0) c->dudl += c->dcv * t[1];
+    if (c->dce != 0.0) c->dudl += c->dce * t[4];
+  } else if (si) {
+    c->u[ORC_U_SOLUTE] += t[0] + t[3];
+  } else {
+    c->u[ORC_U_ENV] += t[0] + t[3];
+  }
+  if (c->g) {
+    /* dU/d(eps_a, sigma_a, q_a) of both atoms of the pair:
+     *   eps_ij = sqrt(eps_i eps_j): dU/deps_i = U_LJ / (2 eps_i)
+     *   sig_ij = (sig_i + sig_j)/2: dU/dsig_i = 1/2 dU/dsig_ij,
+     *     dphi/dsig = 24 eps c (2s-1) s^2 (r/sig)^6 / sig (shift included)
+     *   U_C = ce k q_i q_j g(r): dU/dq_i = ce k q_j g(r)                     */
+    double dsig = 0.0;
+    if (eps != 0.0) {
+      double a = s->sc_alpha * pow(1.0 - cv, (double)s->sc_power);
+      double u1 = pow(r / sig, 6.0), u2 = pow(rc / sig, 6.0);
+      double s1 = 1.0 / (a + u1), s2 = 1.0 / (a + u2);
+      dsig = 24.0 * eps * cv * ((2.0 * s1 - 1.0) * s1 * s1 * u1 - (2.0 * s2 - 1.0) * s2 * s2 * u2) / sig;
+    }
+    if (s->epsilon[gi] != 0.0) c->g[3 * i + 0] += t[0] / (2.0 * s->epsilon[gi]);
+    if (s->epsilon[gj] != 0.0) c->g[3 * j + 0] += t[0] / (2.0 * s->epsilon[gj]);
+    c->g[3 * i + 1] += 0.5 * dsig;
+    c->g[3 * j + 1] += 0.5 * dsig;
+    if (ce != 0.0) {
+      double gfun = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+      c->g[3 * i + 2] += ce * s->coulomb_k * s->charge[gj] * gfun;
+      c->g[3 * j + 2] += ce * s->coulomb_k * s->charge[gi] * gfun;
+    }
+  }
+}
+
+static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam, int brute,
+                       double *f, double *u_parts, double *dudl, double *g) {
+  eval_ctx c;
+  int64_t n, i;
+  const double *L;
+  double sch[4], invL[3];
+  int k;
+  if (w < 0 || w >= s->n_walkers) return -1;
+  L = s->box + 3 * w;
+  for (k = 0; k < 3; ++k) {
+    if (!(s->r_cut < 0.5 * L[k])) return -1;
+    invL[k] = 1.0 / L[k];
+  }
+  n = s->atom_offset[w + 1] - s->atom_offset[w];
+  memset(&c, 0, sizeof(c));
+  c.s = s;
+  c.base = s->atom_offset[w];
+  orc_schedule(s, lam, sch);
+  c.ce = sch[0];
+  c.cv = sch[1];
+  c.dce = sch[2];
+  c.dcv = sch[3];
+  c.f = f;
+  c.g = g;
+  if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
+  if (g) memset(g, 0, sizeof(double) * 3 * (size_t)n);
+  for_each_pair(x, n, L, s->r_cut, brute, eval_pair, &c);
+  if (s->anchor && s->k0 && s->k1) {
+    for (i = 0; i < n; ++i) {
+      int64_t gi = c.base + i;
+      double k0 = s->k0[gi], k1 = s->k1[gi];
+      double kl, d[3], r2;
+      if (k0 == 0.0 && k1 == 0.0) continue;
+      kl = k0 + lam * (k1 - k0);
+      r2 = min_image(s->anchor + 3 * gi, x + 3 * i, L, invL, d); /* d = x - anchor */
+      c.u[ORC_U_RESTR] += 0.5 * kl * r2;
+      c.dudl += 0.5 * (k1 - k0) * r2;
+      if (f)
+        for (k = 0; k < 3; ++k) f[3 * i + k] -= kl * d[k];
+    }
+  }
+  if (u_parts)
+    for (k = 0; k < 5; ++k) u_parts[k] = c.u[k];
+  if (dudl) *dudl = c.dudl;
+  return 0;
+}
+
+int32_t orc_evaluate(const orc_sys *s, int32_t w, const double *x, double lam, int32_t brute,
+                     double *f, double *u_parts, double *dudl) {
+  return eval_walker(s, w, x, lam, brute, f, u_parts, dudl, NULL);
+}
+
+int32_t orc_param_grad(const orc_sys *s, int32_t w, const double *x, double lam, double *g) {
+  return eval_walker(s, w, x, lam, 0, NULL, NULL, NULL, g);
+}
+
+/* ---------------------------------------------------------------------------
+ * Noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC'11), written from its published description:
+ * ten rounds of two 32x32->64 multiplications by 0xD2511F53 and 0xCD9E8D57
+ * and a word permutation, the key bumped by the Weyl constants 0x9E3779B9 and
+ * 0xBB67AE85 between rounds.  Gaussian pairs come from Box-Muller in FP64
+ * with u1 = (a + 1) 2^-32 in (0, 1] and u2 = b 2^-32 in [0, 1).
+ * Counter = (atom, step, walker, purpose), key = (low, high words of seed).
+ * Lambda noise uses atom = 0xFFFFFFFF; purpose 0 = Langevin O step,
+ * purpose 1 = initial Maxwell-Boltzmann velocities.
+ * ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  int r;
+  for (r = 0; r < 10; ++r) {
+    uint64_t p0, p1;
+    uint32_t n0, n1, n2, n3;
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    n1 = (uint32_t)p1;
+    n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    n3 = (uint32_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+void orc_normals(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker, uint32_t purpose,
+                 double out[4]) {
+  const double two32 = 4294967296.0;
+  const double two_pi = 6.283185307179586;
+  uint32_t ctr[4], key[2], o[4];
+  int k;
+  ctr[0] = atom;
+  ctr[1] = step;
+  ctr[2] = walker;
+  ctr[3] = purpose;
+  key[0] = (uint32_t)seed;
+  key[1] = (uint32_t)(seed >> 32);
+  orc_philox4x32_10(ctr, key, o);
+  for (k = 0; k < 2; ++k) {
+    double u1 = ((double)o[2 * k] + 1.0) / two32;
+    double u2 = (double)o[2 * k + 1] / two32;
+    double rad = sqrt(-2.0 * log(u1));
+    out[2 * k] = rad * cos(two_pi * u2);
+    out[2 * k + 1] = rad * sin(two_pi * u2);
+  }
+}
+
+/* Maxwell-Boltzmann velocities, v = sqrt(kT a / m) xi (noise purpose 1, step 0),
+ * and p_lambda = sqrt(m_lambda kT_lambda) xi (atom index 0xFFFFFFFF). */
+int32_t orc_init_velocities(const orc_sys *s, orc_state *st) {
+  int32_t w;
+  for (w = 0; w < s->n_walkers; ++w) {
+    int64_t a;
+    double z[4];
+    for (a = s->atom_offset[w]; a < s->atom_offset[w + 1]; ++a) {
+      double sd = sqrt(s->kT * s->accel_unit / s->mass[a]);
+      int k;
+      orc_normals(s->seed, (uint32_t)(a - s->atom_offset[w]), 0u, (uint32_t)w, 1u, z);
+      for (k = 0; k < 3; ++k) st->v[3 * a + k] = sd * z[k];
+    }
+    orc_normals(s->seed, 0xFFFFFFFFu, 0u, (uint32_t)w, 1u, z);
+    st->p_lambda[w] = sqrt(s->m_lambda * s->kT_lambda) * z[0];
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * ABF on lambda.  Bin b = min(floor((lambda - lo)/w), nbins - 1),
+ * w = (hi - lo)/nbins.  The bias force on lambda is +A'_t(lambda) (the blue
+ * term of Eq. lambda-abf) with A'_t = ramp(n_b) S_b / n_b, ramp(n) =
+ * min(1, n/fullSamples), 0 for an empty bin.  A walker sees the shared
+ * accumulator as of the last merge plus its own unshared samples; the bias
+ * of a step uses the state before that step's samples are added.
+ * ------------------------------------------------------------------------- */
+int32_t orc_bin_of(const orc_sys *s, double lam) {
+  double w = (s->lam_hi - s->lam_lo) / (double)s->n_bins;
+  int32_t b = (int32_t)floor((lam - s->lam_lo) / w);
+  if (b > s->n_bins - 1) b = s->n_bins - 1;
+  if (b < 0) b = 0;
+  return b;
+}
+
+static double abf_bias(const orc_sys *s, const orc_state *st, int32_t w, int32_t b) {
+  int64_t n = st->bin_count[b] + st->loc_count[(int64_t)w * s->n_bins + b];
+  double sum = st->bin_sum[b] + st->loc_sum[(int64_t)w * s->n_bins + b];
+  double ramp;
+  if (n <= 0) return 0.0;
+  ramp = (double)n / (double)s->full_samples;
+  if (ramp > 1.0) ramp = 1.0;
+  return ramp * (sum / (double)n);
+}
+
+int32_t orc_abf_readout(int32_t n_bins, double lo, double hi, const int64_t *count,
+                        const double *sum, double *grad, double *profile, double *delta_a) {
+  double w = (hi - lo) / (double)n_bins;
+  double acc = 0.0;
+  int32_t b, empty = 0;
+  for (b = 0; b < n_bins; ++b) {
+    double g = 0.0;
+    if (count[b] > 0)
+      g = sum[b] / (double)count[b];
+    else
+      empty = 1;
+    if (grad) grad[b] = g;
+    if (profile) profile[b] = acc; /* A(lo + b w) - A(lo) */
+    acc += g * w;
+  }
+  if (delta_a) *delta_a = acc;
+  return empty ? -7 : 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Reflecting boundaries at [lo, hi] for lambda: lambda -> 2 lo - lambda or
+ * 2 hi - lambda, p_lambda -> -p_lambda.  A second reflection would be needed
+ * only for a jump larger than the interval; then lambda is clamped and the
+ * walker's status records it.
+ * ------------------------------------------------------------------------- */
+static void reflect(const orc_sys *s, double *lam, double *p, uint32_t *status) {
+  if (*lam < s->lam_lo) {
+    *lam = 2.0 * s->lam_lo - *lam;
+    *p = -*p;
+  } else if (*lam > s->lam_hi) {
+    *lam = 2.0 * s->lam_hi - *lam;
+    *p = -*p;
+  }
+  if (*lam < s->lam_lo || *lam > s->lam_hi) {
+    *lam = *lam < s->lam_lo ? s->lam_lo : s->lam_hi;
+    *status |= ORC_ST_REFLECT;
+  }
+}
+
+static void wrap_positions(const double *L, double *x, int64_t n) {
+  int64_t i;
+  int k;
+  for (i = 0; i < n; ++i)
+    for (k = 0; k < 3; ++k) {
+      double v = x[3 * i + k];
+      v -= L[k] * floor(v / L[k]);
+      if (v >= L[k]) v -= L[k];
+      x[3 * i + k] = v;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * One step of the coupled Langevin dynamics (Eq. lambda-abf), BAOAB for the
+ * atoms and for (lambda, p_lambda), stored in "pending" form: a step
+ *   1. evaluates F = -grad V and G = dV/dlambda at the current (x, lambda);
+ *   2. ABF: every walker computes its bias from the frozen accumulator, then
+ *      adds its sample (bin(lambda), G) to its unshared deltas;
+ *   3. if a previous step is open, applies its closing half-kick B
+ *      v += h a F/m, p += h (-G + bias);
+ *   4. applies this step's B, A (x += h v, lambda += h p/m_lambda, reflect),
+ *      O (v = c1 v + sqrt((1-c1^2) kT a/m) xi, same for p with gamma_lambda
+ *      and m_lambda), A (and reflect, then wrap x into the box);
+ *   5. every K steps merges the walkers' deltas in walker order.
+ * h = dt/2, a = accel_unit, c1 = exp(-gamma dt).
+ * ------------------------------------------------------------------------- */
+int32_t orc_run(const orc_sys *s, orc_state *st, int64_t n_steps, int32_t brute) {
+  const double h = 0.5 * s->dt;
+  const double c1 = exp(-s->gamma * s->dt);
+  const double c1l = exp(-s->gamma_lambda * s->dt);
+  int32_t W = s->n_walkers;
+  int64_t it;
+  for (it = 0; it < n_steps; ++it) {
+    int32_t w;
+    uint32_t step = (uint32_t)st->step;
+    int32_t bad = 0;
+    /* 1. forces and dV/dlambda (walkers are independent: one thread each) */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad) if (s->atom_offset[W] >= 1024)
+    for (w = 0; w < W; ++w) {
+      int64_t a0 = s->atom_offset[w];
+      double u[5];
+      if (eval_walker(s, w, st->x + 3 * a0, st->lambda[w], brute, st->f + 3 * a0, u, &st->dudl[w],
+                      NULL) != 0)
+        bad = 1;
+      else if (!isfinite(st->dudl[w]))
+        st->status[w] |= ORC_ST_NONFINITE;
+    }
+    if (bad) return -1;
+    /* 2. ABF bias from the frozen state, then this step's samples */
+    for (w = 0; w < W; ++w) {
+      st->bias[w] = 0.0;
+      if (s->abf_on) {
+        int32_t b = orc_bin_of(s, st->lambda[w]);
+        int64_t li = (int64_t)w * s->n_bins + b;
+        st->bias[w] = abf_bias(s, st, w, b);
+        st->loc_count[li] += 1;
+        st->loc_sum[li] += st->dudl[w];
+        st->loc_sum2[li] += st->dudl[w] * st->dudl[w];
+      }
+    }
+    /* 3-4. integrate (walkers are independent) */
+#pragma omp parallel for schedule(static) if (s->atom_offset[W] >= 1024)
+    for (w = 0; w < W; ++w) {
+      int64_t a0 = s->atom_offset[w], a1 = s->atom_offset[w + 1], a;
+      const double *L = s->box + 3 * w;
+      double fl = -st->dudl[w] + st->bias[w];
+      double z[4];
+      int k;
+      for (a = a0; a < a1; ++a) {
+        double im = s->accel_unit / s->mass[a];
+        double sd = sqrt((1.0 - c1 * c1) * s->kT * s->accel_unit / s->mass[a]);
+        orc_normals(s->seed, (uint32_t)(a - a0), step, (uint32_t)w, 0u, z);
+        for (k = 0; k < 3; ++k) {
+          double v = st->v[3 * a + k], x = st->x[3 * a + k], fa = st->f[3 * a + k];
+          if (st->pending) v += h * fa * im;
+          v += h * fa * im;
+          x += h * v;
+          v = c1 * v + sd * z[k];
+          x += h * v;
+          st->v[3 * a + k] = v;
+          st->x[3 * a + k] = x;
+        }
+      }
+      wrap_positions(L, st->x + 3 * a0, a1 - a0);
+      if (!s->fixed_lambda) {
+        double lam = st->lambda[w], p = st->p_lambda[w];
+        double sdl = sqrt((1.0 - c1l * c1l) * s->kT_lambda * s->m_lambda);
+        if (st->pending) p += h * fl;
+        p += h * fl;
+        lam += h * p / s->m_lambda;
+        reflect(s, &lam, &p, &st->status[w]);
+        orc_normals(s->seed, 0xFFFFFFFFu, step, (uint32_t)w, 0u, z);
+        p = c1l * p + sdl * z[0];
+        lam += h * p / s->m_lambda;
+        reflect(s, &lam, &p, &st->status[w]);
+        st->lambda[w] = lam;
+        st->p_lambda[w] = p;
+      }
+    }
+    st->pending = 1;
+    st->step += 1;
+    /* 5. share the ABF deltas every K steps, in walker order */
+    if (s->abf_on && (st->step % s->share_interval) == 0) {
+      int32_t b;
+      for (w = 0; w < W; ++w)
+        for (b = 0; b < s->n_bins; ++b) {
+          int64_t li = (int64_t)w * s->n_bins + b;
+          st->bin_count[b] += st->loc_count[li];
+          st->bin_sum[b] += st->loc_sum[li];
+          st->bin_sum2[b] += st->loc_sum2[li];
+          st->loc_count[li] = 0;
+          st->loc_sum[li] = 0.0;
+          st->loc_sum2[li] = 0.0;
+        }
+    }
+  }
+  return 0;
+}
+
+/* Full-step velocities of the current pending state (the closing half-kick
+ * applied to copies; the state is not modified).  Needs st->f and st->dudl
+ * evaluated at the current positions: it evaluates them itself. */
+int32_t orc_full_step(const orc_sys *s, const orc_state *st, double *v_full, double *p_full) {
+  const double h = 0.5 * s->dt;
+  int32_t w;
+  for (w = 0; w < s->n_walkers; ++w) {
+    int64_t a0 = s->atom_offset[w], a1 = s->atom_offset[w + 1], a, n = a1 - a0;
+    double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double g = 0.0, bias = 0.0;
+    int k;
+    if (eval_walker(s, w, st->x + 3 * a0, st->lambda[w], 0, f, NULL, &g, NULL) != 0) {
+      free(f);
+      return -1;
+    }
+    if (s->abf_on) bias = abf_bias(s, st, w, orc_bin_of(s, st->lambda[w]));
+    for (a = a0; a < a1; ++a)
+      for (k = 0; k < 3; ++k) {
+        double v = st->v[3 * a + k];
+        if (st->pending) v += h * f[3 * (a - a0) + k] * s->accel_unit / s->mass[a];
+        v_full[3 * a + k] = v;
+      }
+    p_full[w] = st->p_lambda[w] + (st->pending ? h * (-g + bias) : 0.0);
+    free(f);
+  }
+  return 0;
+}

@@ -1,0 +1,389 @@
+"""Seeded synthetic inputs for the lambda-ABF alchemical nonbonded step.
+
+This module only builds inputs: lattices, parameters, walker batches and the
+lambda/ABF settings.  It holds none of the method's arithmetic, so that the
+HIP path and the FP64 oracle can both be fed from it without sharing any
+computation.
+
+Workloads (stand-ins for the paper's systems, whose structures and force
+fields are not available):
+  * ``lj_reduced``      -- 512 LJ particles in reduced units at density 0.8,
+                           one soft-core-decoupled solute (alpha 0.5, p 1).
+  * ``harmonic``        -- 3 non-interacting particles with lambda-switched
+                           harmonic restraints k(lambda) = 1 + 3 lambda.
+  * ``charged_lj``      -- a charged LJ fluid (sigma 3.15 A, eps 0.15 kcal/mol,
+                           charges +-0.4 e) at 0.1 atoms/A^3 with a decoupled
+                           solute; the size of the paper's solvated boxes.
+  * ``batch``           -- several walkers of a system with independent
+                           velocities and initial lambda.
+  * ``uneven``          -- walkers of log-uniform sizes, each a solvent box
+                           around a restrained dense cluster with a ligand.
+Positions are put on the grid the chosen precision represents exactly inside
+a box offset by a power of two (see ``quantize``), so that every consumer
+starts from bit-identical coordinates.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# unit constants (real units: A, fs, amu, kcal/mol, e)
+KB_KCAL = 0.0019872041          # kcal/mol/K
+COULOMB_K = 332.0637            # kcal A / (mol e^2)
+ACCEL_REAL = 4.184e-4           # (kcal/mol/A/amu) -> A/fs^2
+
+BASE_SEED = 20230717
+
+
+@dataclasses.dataclass
+class SystemSpec:
+    """Static description of a batch of walkers and its initial state."""
+    atom_offset: np.ndarray          # int64 [W+1]
+    box: np.ndarray                  # float64 [W,3]
+    pos: np.ndarray                  # float64 [N,3], inside [0, L)
+    mass: np.ndarray                 # float64 [N]
+    charge: np.ndarray               # float64 [N]
+    sigma: np.ndarray                # float64 [N]
+    epsilon: np.ndarray              # float64 [N]
+    is_solute: np.ndarray            # uint8 [N]
+    r_cut: float
+    r_skin: float
+    kT: float
+    gamma: float
+    dt: float
+    coulomb_k: float
+    accel_unit: float
+    seed: int
+    precision: str = "fp32"          # "fp32" | "fp64"
+    vel: Optional[np.ndarray] = None     # float64 [N,3]; None -> Maxwell-Boltzmann
+    anchor: Optional[np.ndarray] = None  # float64 [N,3]
+    k0: Optional[np.ndarray] = None      # float64 [N]
+    k1: Optional[np.ndarray] = None      # float64 [N]
+    rebuild_interval: int = 10
+    name: str = ""
+
+    @property
+    def n_walkers(self) -> int:
+        return int(self.atom_offset.shape[0] - 1)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.atom_offset[-1])
+
+    def walker_slice(self, w: int) -> slice:
+        return slice(int(self.atom_offset[w]), int(self.atom_offset[w + 1]))
+
+
+@dataclasses.dataclass
+class LambdaSpec:
+    """Extended-lambda and ABF settings (one set shared by all walkers)."""
+    lambda0: np.ndarray              # float64 [W]
+    p_lambda0: Optional[np.ndarray]  # float64 [W]; None -> Maxwell-Boltzmann
+    m_lambda: float
+    gamma_lambda: float
+    kT_lambda: float
+    elec_start: float = 0.0
+    elec_end: float = 0.5
+    vdw_start: float = 0.5
+    vdw_end: float = 1.0
+    direction: str = "decouple"      # "decouple" | "couple"
+    sc_alpha: float = 0.5
+    sc_power: int = 1
+    n_bins: int = 100
+    lo: float = 0.0
+    hi: float = 1.0
+    full_samples: int = 100
+    share_interval: int = 1
+    fixed_lambda: bool = False
+    abf_on: bool = True
+
+
+def _pow2_at_least(x: float) -> float:
+    return float(2.0 ** math.ceil(math.log2(x)))
+
+
+def quantize(pos: np.ndarray, box: np.ndarray, precision: str):
+    """Round the box edges and positions (wrapped into [0, L)) to the values
+    that ``(B + x) - B`` preserves in the given precision, B being the
+    smallest power of two >= L.  Returns (pos, box) as float64."""
+    pos = np.array(pos, dtype=np.float64, copy=True)
+    box = np.array(box, dtype=np.float64, copy=True)
+    ft = np.float32 if precision == "fp32" else np.float64
+    for k in range(3):
+        L = float(box[k])
+        B = _pow2_at_least(L)
+        Lq = float(ft(ft(B) + ft(L)) - ft(B))
+        box[k] = Lq
+        x = pos[:, k] - Lq * np.floor(pos[:, k] / Lq)
+        xq = (ft(B) + x.astype(ft)).astype(ft)
+        xq = np.where(xq >= ft(B + Lq), xq - ft(Lq), xq)
+        pos[:, k] = (xq - ft(B)).astype(np.float64)
+    return pos, box
+
+
+def _lattice_sc(n_side: int, L: float) -> np.ndarray:
+    a = L / n_side
+    g = (np.arange(n_side) + 0.5) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def _lattice_fcc(n_cell: int, L: float) -> np.ndarray:
+    a = L / n_cell
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]], dtype=np.float64)
+    g = np.arange(n_cell, dtype=np.float64)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    sites = (cells[:, None, :] + basis[None, :, :] + 0.25).reshape(-1, 3)
+    return sites * a
+
+
+# ----------------------------------------------------------------------------
+# reduced-unit LJ fluid with one decoupled solute
+# ----------------------------------------------------------------------------
+def lj_reduced(n_atoms: int = 512, density: float = 0.8, seed: int = BASE_SEED,
+               precision: str = "fp64", r_cut: float = 2.5, r_skin: float = 0.3,
+               n_walkers: int = 1, lambda0: float = 0.0, n_bins: int = 50,
+               full_samples: int = 100, jitter: float = 0.05, charges: float = 0.0):
+    """512 LJ particles (sigma = eps = m = 1), cubic periodic box at the given
+    density, seeded simple-cubic lattice with +-jitter, T = 1, gamma = 1,
+    dt = 0.005, atom 0 decoupled through soft-core vdW only
+    (c_v = 1 - lambda); m_lambda = 10, gamma_lambda = 1."""
+    rng = np.random.default_rng(seed)
+    L = (n_atoms / density) ** (1.0 / 3.0)
+    n_side = int(math.ceil(n_atoms ** (1.0 / 3.0) - 1e-9))
+    sites = _lattice_sc(n_side, L)
+    if sites.shape[0] > n_atoms:
+        sites = sites[np.sort(rng.permutation(sites.shape[0])[:n_atoms])]
+    pos1 = sites + rng.uniform(-jitter, jitter, size=sites.shape)
+    pos_all, boxes = [], []
+    for w in range(n_walkers):
+        p, b = quantize(pos1, np.array([L, L, L]), precision)
+        pos_all.append(p)
+        boxes.append(b)
+    N = n_atoms * n_walkers
+    q = np.zeros(n_atoms)
+    if charges:
+        q = np.where(rng.permutation(n_atoms) % 2 == 0, charges, -charges)
+    spec = SystemSpec(
+        atom_offset=np.arange(n_walkers + 1, dtype=np.int64) * n_atoms,
+        box=np.array(boxes), pos=np.concatenate(pos_all),
+        mass=np.ones(N), charge=np.tile(q, n_walkers), sigma=np.ones(N), epsilon=np.ones(N),
+        is_solute=np.tile((np.arange(n_atoms) == 0).astype(np.uint8), n_walkers),
+        r_cut=r_cut, r_skin=r_skin, kT=1.0, gamma=1.0, dt=0.005, coulomb_k=1.0,
+        accel_unit=1.0, seed=seed, precision=precision, name="lj_reduced")
+    lam = LambdaSpec(lambda0=np.full(n_walkers, float(lambda0)), p_lambda0=None,
+                     m_lambda=10.0, gamma_lambda=1.0, kT_lambda=1.0,
+                     elec_start=0.0, elec_end=1.0, vdw_start=0.0, vdw_end=1.0,
+                     direction="decouple", sc_alpha=0.5, sc_power=1, n_bins=n_bins,
+                     lo=0.0, hi=1.0, full_samples=full_samples, share_interval=1)
+    return spec, lam
+
+
+# ----------------------------------------------------------------------------
+# lambda-switched harmonic restraints (closed-form free energy)
+# ----------------------------------------------------------------------------
+def harmonic(n_walkers: int = 1, seed: int = BASE_SEED + 100, precision: str = "fp64",
+             k0: float = 1.0, k1: float = 4.0, n_bins: int = 50, full_samples: int = 100,
+             L: float = 64.0):
+    """3 particles (m = 1) with anchors at the box centre, no pair
+    interactions (eps = q = 0), k(lambda) = k0 + lambda (k1 - k0) on every
+    Cartesian component, T = 1, gamma = 1, dt = 0.005, m_lambda = 10,
+    gamma_lambda = 1.  The box is large enough never to be felt."""
+    rng = np.random.default_rng(seed)
+    n = 3
+    c = np.full((n, 3), L / 2)
+    pos = []
+    boxes = []
+    for w in range(n_walkers):
+        p, b = quantize(c + rng.normal(0.0, 0.5, size=(n, 3)), np.array([L, L, L]), precision)
+        pos.append(p)
+        boxes.append(b)
+    anchor, _ = quantize(np.tile(c, (n_walkers, 1)), boxes[0], precision)
+    N = n * n_walkers
+    spec = SystemSpec(
+        atom_offset=np.arange(n_walkers + 1, dtype=np.int64) * n, box=np.array(boxes),
+        pos=np.concatenate(pos), mass=np.ones(N), charge=np.zeros(N), sigma=np.ones(N),
+        epsilon=np.zeros(N), is_solute=np.zeros(N, np.uint8), r_cut=2.5, r_skin=0.3, kT=1.0,
+        gamma=1.0, dt=0.005, coulomb_k=1.0, accel_unit=1.0, seed=seed, precision=precision,
+        anchor=anchor, k0=np.full(N, k0), k1=np.full(N, k1), name="harmonic")
+    lam = LambdaSpec(lambda0=rng.uniform(0, 1, n_walkers), p_lambda0=None, m_lambda=10.0,
+                     gamma_lambda=1.0, kT_lambda=1.0, elec_start=0.0, elec_end=1.0,
+                     vdw_start=0.0, vdw_end=1.0, direction="decouple", n_bins=n_bins,
+                     full_samples=full_samples, share_interval=1)
+    return spec, lam
+
+
+# ----------------------------------------------------------------------------
+# charged LJ fluid in real units with a decoupled solute
+# ----------------------------------------------------------------------------
+SOLVENT_SIGMA = 3.15
+SOLVENT_EPS = 0.15
+SOLVENT_Q = 0.4
+SOLVENT_MASS = 18.015
+SOLUTE_MASS = 12.011
+
+
+def _solute_params(rng, n_solute: int):
+    sig = rng.uniform(2.5, 3.8, n_solute)
+    eps = np.full(n_solute, 0.15)
+    q = rng.uniform(-0.8, 0.8, n_solute)
+    q[-1] = -np.sum(q[:-1])
+    return sig, eps, q
+
+
+def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
+               seed: int = BASE_SEED + 1, precision: str = "fp32", r_cut: float = 12.0,
+               r_skin: float = 1.0, temperature: float = 300.0, dt: float = 2.0,
+               gamma_ps: float = 1.0, jitter: float = 0.05, sigma: float = SOLVENT_SIGMA):
+    """One walker: n_atoms (solvent + solute) of a charged LJ fluid on a
+    seeded FCC lattice (vacancies chosen by a seeded permutation, +-jitter A),
+    solvent charges +-0.4 e alternating over a seeded permutation; the solute
+    is the n_solute occupied sites nearest the box centre with sigma ~
+    U(2.5, 3.8) A, eps 0.15, charges ~ U(-0.8, 0.8) summing to zero.
+    Lambda: electrostatics removed over [0, 0.5], soft-core vdW over
+    [0.5, 1] (decoupling), m_lambda = 150000 kcal/mol fs^2,
+    gamma_lambda = 1000 /ps, 100 bins, fullSamples 100."""
+    rng = np.random.default_rng(seed)
+    L = (n_atoms / density) ** (1.0 / 3.0)
+    n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
+    sites = _lattice_fcc(n_cell, L)
+    keep = np.sort(rng.permutation(sites.shape[0])[:n_atoms])
+    pos = sites[keep] + rng.uniform(-jitter, jitter, size=(n_atoms, 3))
+    pos, box = quantize(pos, np.array([L, L, L]), precision)
+    d = np.linalg.norm(pos - L / 2, axis=1)
+    order = np.lexsort((np.arange(n_atoms), d))
+    solute = np.zeros(n_atoms, np.uint8)
+    solute[order[:n_solute]] = 1
+    perm = rng.permutation(n_atoms - n_solute)
+    q_solv = np.where(perm % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
+    charge = np.zeros(n_atoms)
+    sig = np.full(n_atoms, sigma)
+    eps = np.full(n_atoms, SOLVENT_EPS)
+    mass = np.full(n_atoms, SOLVENT_MASS)
+    charge[solute == 0] = q_solv
+    s_sig, s_eps, s_q = _solute_params(rng, n_solute)
+    idx = np.nonzero(solute)[0]
+    sig[idx], eps[idx], charge[idx], mass[idx] = s_sig, s_eps, s_q, SOLUTE_MASS
+    spec = SystemSpec(
+        atom_offset=np.array([0, n_atoms], np.int64), box=box[None, :], pos=pos, mass=mass,
+        charge=charge, sigma=sig, epsilon=eps, is_solute=solute, r_cut=r_cut, r_skin=r_skin,
+        kT=KB_KCAL * temperature, gamma=gamma_ps * 1e-3, dt=dt, coulomb_k=COULOMB_K,
+        accel_unit=ACCEL_REAL, seed=seed, precision=precision, name="charged_lj")
+    lam = LambdaSpec(lambda0=np.array([0.0]), p_lambda0=None, m_lambda=150000.0,
+                     gamma_lambda=1000.0 * 1e-3, kT_lambda=KB_KCAL * temperature,
+                     elec_start=0.0, elec_end=0.5, vdw_start=0.5, vdw_end=1.0,
+                     direction="decouple", sc_alpha=0.5, sc_power=1, n_bins=100, lo=0.0,
+                     hi=1.0, full_samples=100, share_interval=1)
+    return spec, lam
+
+
+def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
+    """n_walkers copies of a one-walker system (same coordinates and
+    parameters, independent velocity streams through the walker index),
+    initial lambda ~ U(0, 1)."""
+    assert spec.n_walkers == 1
+    rng = np.random.default_rng(seed)
+    n = spec.n_atoms
+    rep = lambda a: None if a is None else np.concatenate([a] * n_walkers)
+    out = dataclasses.replace(
+        spec, atom_offset=np.arange(n_walkers + 1, dtype=np.int64) * n,
+        box=np.repeat(spec.box, n_walkers, axis=0), pos=rep(spec.pos), mass=rep(spec.mass),
+        charge=rep(spec.charge), sigma=rep(spec.sigma), epsilon=rep(spec.epsilon),
+        is_solute=rep(spec.is_solute), vel=rep(spec.vel), anchor=rep(spec.anchor),
+        k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}")
+    lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None)
+    return out, lam2
+
+
+def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
+    """Concatenate one-walker systems (which must share r_cut, units and
+    precision) into one batch of uneven walkers."""
+    W = len(specs)
+    off = np.zeros(W + 1, np.int64)
+    for w, s in enumerate(specs):
+        off[w + 1] = off[w] + s.n_atoms
+    cat = lambda f: np.concatenate([getattr(s, f) for s in specs])
+    has_r = all(s.anchor is not None for s in specs)
+    s0 = specs[0]
+    out = dataclasses.replace(
+        s0, atom_offset=off, box=np.concatenate([s.box for s in specs]), pos=cat("pos"),
+        mass=cat("mass"), charge=cat("charge"), sigma=cat("sigma"), epsilon=cat("epsilon"),
+        is_solute=cat("is_solute"), vel=None,
+        anchor=cat("anchor") if has_r else None, k0=cat("k0") if has_r else None,
+        k1=cat("k1") if has_r else None, seed=seed, name=name)
+    lam2 = dataclasses.replace(lam, lambda0=np.asarray(lambda0, np.float64), p_lambda0=None)
+    return out, lam2
+
+
+def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
+           seed: int = BASE_SEED + 3, precision: str = "fp32", r_cut: float = 12.0,
+           r_skin: float = 1.0):
+    """Walkers with atom counts log-uniform in [n_min, n_max]: each a charged
+    LJ solvent box around a dense cluster (0.12 atoms/A^3, FCC) restrained
+    harmonically (k = 1 kcal/mol/A^2, lambda-independent) to its initial
+    sites, with a 20-80 atom decoupled ligand just outside the cluster."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for w in range(n_walkers):
+        N = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        n_cl = int(round(math.exp(rng.uniform(math.log(2000), math.log(20000)))))
+        n_cl = int(np.clip(n_cl, 2000, N // 2))
+        n_lig = int(rng.integers(20, 81))
+        specs.append(_cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed + w))
+    _, lam = charged_lj(n_atoms=3000, precision=precision)
+    return concat(specs, lam, rng.uniform(0, 1, n_walkers), seed, "uneven")
+
+
+def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
+    vol = n_cl / 0.12 + (N - n_cl) / 0.1
+    L = vol ** (1.0 / 3.0)
+    R = (3.0 * n_cl / (4.0 * math.pi * 0.12)) ** (1.0 / 3.0)
+    c = np.full(3, L / 2)
+    # cluster: FCC at 0.12 inside the sphere (closest sites to the centre)
+    a_cl = (4.0 / 0.12) ** (1.0 / 3.0)
+    ncl_side = int(math.ceil(2 * R / a_cl)) + 2
+    cl_sites = _lattice_fcc(ncl_side, ncl_side * a_cl) - ncl_side * a_cl / 2 + c
+    dcl = np.linalg.norm(cl_sites - c, axis=1)
+    cl = cl_sites[np.argsort(dcl, kind="stable")[:n_cl]]
+    R_eff = np.linalg.norm(cl - c, axis=1).max()
+    # ligand: sites in a shell just outside the cluster, along a seeded direction
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    solv_sites = _lattice_fcc(int(math.ceil(L / (4.0 / 0.1) ** (1.0 / 3.0))),
+                              L)
+    ds = np.linalg.norm(solv_sites - c, axis=1)
+    outside = solv_sites[ds > R_eff + 1.0]
+    lig_c = c + u * (R_eff + 3.0)
+    dl = np.linalg.norm(outside - lig_c, axis=1)
+    order = np.argsort(dl, kind="stable")
+    lig = outside[order[:n_lig]]
+    rest = outside[order[n_lig:]]
+    n_solv = N - n_cl - n_lig
+    if rest.shape[0] < n_solv:
+        raise ValueError("solvent lattice too small")
+    solv = rest[np.sort(rng.permutation(rest.shape[0])[:n_solv])]
+    pos = np.concatenate([cl, lig, solv]) + rng.uniform(-0.05, 0.05, size=(N, 3))
+    pos, box = quantize(pos, np.array([L, L, L]), precision)
+    anchor = pos.copy()
+    k = np.zeros(N)
+    k[:n_cl] = 1.0
+    solute = np.zeros(N, np.uint8)
+    solute[n_cl:n_cl + n_lig] = 1
+    sig = np.full(N, SOLVENT_SIGMA)
+    eps = np.full(N, SOLVENT_EPS)
+    mass = np.full(N, SOLVENT_MASS)
+    charge = np.zeros(N)
+    env = np.nonzero(solute == 0)[0]
+    charge[env] = np.where(rng.permutation(env.size) % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
+    s_sig, s_eps, s_q = _solute_params(rng, n_lig)
+    li = np.arange(n_cl, n_cl + n_lig)
+    sig[li], eps[li], charge[li], mass[li] = s_sig, s_eps, s_q, SOLUTE_MASS
+    return SystemSpec(
+        atom_offset=np.array([0, N], np.int64), box=box[None, :], pos=pos, mass=mass,
+        charge=charge, sigma=sig, epsilon=eps, is_solute=solute, r_cut=r_cut, r_skin=r_skin,
+        kT=KB_KCAL * 300.0, gamma=1e-3, dt=2.0, coulomb_k=COULOMB_K, accel_unit=ACCEL_REAL,
+        seed=seed, precision=precision, anchor=anchor, k0=k, k1=k.copy(), name="cluster")
