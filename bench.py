@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the lambda-ABF alchemical nonbonded step on one MI355X.
+
+Metric: walker-steps/s and pair-interactions/s at 30k atoms, batched vs plain.
+Workload (default): 16 walkers x 30,000-atom charged LJ fluid (0.1 atoms/A^3,
+12 A cutoff, 2 fs, FP32 pairs with FP64 dV/dlambda, lambda and ABF bins),
+one launch pair per step, 10-step blocks replayed as HIP graphs, shared
+100-bin ABF accumulator.  A "step" is one pass of the whole path for every
+walker: neighbour rebuild (every 10 steps), pair forces and dV/dlambda,
+BAOAB of atoms and lambda, ABF accumulation.
+
+Before timing, the seeded lattice is equilibrated on the GPU (untimed:
+500 steps at dt = 1 fs, gamma = 20/ps), then the production parameters are
+restored.  Pairs are counted exactly (FP64 decision) by a separate, untimed
+pass before and after the timed region.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s and pair-interactions/s at 30k atoms, batched vs plain, 1 GPU"
+# minimal FP32 VALU issue slots per in-cutoff environment pair (half list):
+# dx,dy,dz 3; r^2 3; cutoff compare 1; rsqrt 4 (quarter-rate transcendental);
+# 1/r^2 1; 1/r^6 2; LJ coefficients 4; LJ scalar 3; Coulomb scalar 3; sum 1;
+# i and j force FMAs 6.
+SLOTS_PER_PAIR = 31
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, non-packed FP32 VALU lane-operations/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+            return
+    except Exception:
+        pass
+
+
+def _ensure_built():
+    from paper_2307_08006_amd import build
+    if not os.path.exists(build.LIB):
+        build.build(force=True)
+
+
+def equilibrate(spec, lam, steps):
+    """Untimed GPU equilibration of a one-walker system: strong friction and
+    a 1 fs step; returns the spec with the equilibrated coordinates."""
+    from paper_2307_08006_amd import labf
+    eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0)
+    with labf.System(eq, lam) as s:
+        s.step(steps)
+        pos, _ = s.read_atoms()
+        st = s.read_walker_state()
+    if st["status"].any() or not np.isfinite(pos).all():
+        raise RuntimeError(f"equilibration failed: status {st['status']}")
+    return dataclasses.replace(spec, pos=pos)
+
+
+def timed_steps(s, n, mode):
+    _sync()
+    t0 = time.perf_counter()
+    s.step(n, mode)
+    _sync()
+    s.read_walker_state()  # synchronises the library's stream as well
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(spec, lam, n_walkers, n_steps):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle
+    sp, lm = spec, lam
+    if spec.n_walkers > n_walkers:
+        off = spec.atom_offset
+        n = int(off[n_walkers])
+        cut = lambda a: None if a is None else a[:n]
+        sp = dataclasses.replace(spec, atom_offset=off[: n_walkers + 1], box=spec.box[:n_walkers],
+                                 pos=cut(spec.pos), vel=None, mass=cut(spec.mass),
+                                 charge=cut(spec.charge), sigma=cut(spec.sigma),
+                                 epsilon=cut(spec.epsilon), is_solute=cut(spec.is_solute),
+                                 anchor=cut(spec.anchor), k0=cut(spec.k0), k1=cut(spec.k1))
+        lm = dataclasses.replace(lam, lambda0=lam.lambda0[:n_walkers])
+    o = oracle.Oracle(sp, lm)
+    o.init_state()
+    t0 = time.perf_counter()
+    o.run(n_steps)
+    dt = time.perf_counter() - t0
+    cores = min(n_walkers, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    return n_walkers * n_steps / dt, cores, dt
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500, help="timed batched steps (K)")
+    ap.add_argument("--warmup", type=int, default=50, help="untimed warm-up steps (W)")
+    ap.add_argument("--walkers", type=int, default=16)
+    ap.add_argument("--atoms", type=int, default=30000)
+    ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--single-steps", type=int, default=500)
+    ap.add_argument("--equil-steps", type=int, default=500)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; walkers shard across GPUs only "
+                                   "in the design notes (no multi-GPU path is built)",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    _ensure_built()
+    from paper_2307_08006_amd import labf, synth
+
+    spec1, lam1 = synth.charged_lj(n_atoms=args.atoms, precision="fp32")
+    log(f"equilibrating {args.atoms} atoms for {args.equil_steps} steps")
+    spec1 = equilibrate(spec1, lam1, args.equil_steps)
+    specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
+
+    out = {}
+    with labf.System(specb, lamb) as s:
+        pairs0 = s.count_pairs()
+        env0 = s.count_pairs(env_only=True)
+        log(f"batched: {args.walkers} walkers, {pairs0.sum()} pairs/step; warm-up {args.warmup}")
+        s.step(args.warmup)
+        dt_b = timed_steps(s, args.steps, "batched")
+        log(f"batched: {args.steps} steps in {dt_b:.3f} s")
+        pairs1 = s.count_pairs()
+        env1 = s.count_pairs(env_only=True)
+        st_b = s.read_walker_state()
+        pairs_per_step = 0.5 * (pairs0.sum() + pairs1.sum())
+        env_pairs_per_step = 0.5 * (env0.sum() + env1.sum())
+        # plain: one walker per launch sequence, no graph, same walkers
+        dt_p = timed_steps(s, args.plain_steps, "plain")
+        log(f"plain: {args.plain_steps} steps in {dt_p:.3f} s")
+        st_p = s.read_walker_state()
+        # per-kernel times with HIP events around single launches
+        prof = s.profile_steps(args.profile_steps)
+        info = s.info()
+    with labf.System(spec1, lam1) as s1:
+        pairs_1 = float(s1.count_pairs().sum())
+        s1.step(args.warmup)
+        dt_1 = timed_steps(s1, args.single_steps, "batched")
+        log(f"single walker: {args.single_steps} steps in {dt_1:.3f} s")
+        st_1 = s1.read_walker_state()
+
+    W = args.walkers
+    value = W * args.steps / dt_b
+    env_ms = prof["env_ms"]
+    achieved = SLOTS_PER_PAIR * env_pairs_per_step / (env_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt_b / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{W} walkers x {args.atoms}-atom charged LJ fluid (0.1 atoms/A^3, 12 A "
+                        "cutoff, 2 fs, 30-atom decoupled solute), batched: 10-step HIP-graph blocks",
+            "walkers": W, "atoms_per_walker": args.atoms, "cutoff_A": 12.0, "skin_A": 1.0,
+            "rebuild_interval": 10, "abf_bins": 100, "pair_precision": "f32",
+            "lambda_precision": "f64", "equilibration_steps_untimed": args.equil_steps,
+        },
+        "pair_interactions_per_s": pairs_per_step * args.steps / dt_b,
+        "pairs_per_step": pairs_per_step,
+        "plain": {
+            "walker_steps_per_s": W * args.plain_steps / dt_p,
+            "pair_interactions_per_s": pairs_per_step * args.plain_steps / dt_p,
+            "ms_per_step": 1e3 * dt_p / args.plain_steps, "steps": args.plain_steps,
+        },
+        "single_walker": {
+            "walker_steps_per_s": args.single_steps / dt_1,
+            "pair_interactions_per_s": pairs_1 * args.single_steps / dt_1,
+            "ms_per_step": 1e3 * dt_1 / args.single_steps, "steps": args.single_steps,
+        },
+        "kernels_ms": prof,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_env (environment pair kernel + fused BAOAB epilogue)",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": None,
+            "per_unit": f"{SLOTS_PER_PAIR} FP32 VALU lane-ops per in-cutoff environment pair",
+            "units_per_launch": env_pairs_per_step,
+        },
+        "walker_status": {"batched": int(np.bitwise_or.reduce(st_b["status"])),
+                          "plain": int(np.bitwise_or.reduce(st_p["status"])),
+                          "single": int(np.bitwise_or.reduce(st_1["status"]))},
+        "layout": info,
+    }
+    if not args.no_cpu_baseline and rank == 0:
+        log("cpu baseline (oracle)")
+        v, cores, secs = cpu_baseline(specb, lamb, W, args.cpu_steps)
+        out["cpu_baseline"] = {
+            "value": v, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, {W} walkers x {args.cpu_steps} step(s) of the same "
+                      f"{args.atoms}-atom workload ({secs:.1f} s wall)",
+        }
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

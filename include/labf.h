@@ -1,0 +1,226 @@
+/*
+ * labf.h -- C ABI of the MI355X (gfx950) lambda-ABF alchemical nonbonded step.
+ *
+ * The operation is the per-timestep work every walker of a lambda-ABF run
+ * performs (Lagardere et al., "Lambda-ABF: Simplified, Portable, Accurate,
+ * and Cost-effective Alchemical Free Energy Computation"):
+ *   1. a cell/cluster neighbour build at r_list = r_cut + r_skin;
+ *   2. the lambda-scaled nonbonded forces and the alchemical force
+ *      dV/dlambda ("Alchemical pathway": soft-core LJ for lambda_v and
+ *      linear scaling of electrostatics by lambda_e, decoupling; cutoff
+ *      shifted-force Coulomb stands in for PME);
+ *   3. a BAOAB Langevin step of the atoms and of the extended coordinate
+ *      (lambda, p_lambda) of Eq. (lambdadyn-Langevin-process), with the ABF
+ *      term of Eq. (lambda-abf) and reflecting boundaries;
+ *   4. accumulation of dV/dlambda into ABF bins shared by all walkers
+ *      ("Orthogonal space sampling": multiple walkers sharing their
+ *      mean-force estimate every K steps; "ABF parameters": linear ramp up to
+ *      fullSamples), whose bin averages integrate to A(lambda).
+ * The split mirrors the paper's engine/Colvars interface ("Software
+ * interface"): the engine side owns coordinates and forces, the library
+ * side owns lambda's mass, friction, temperature, bounds, bins and sharing.
+ *
+ * Conventions
+ *   - Units: any consistent set.  Real units: A, fs, amu, kcal/mol, e, with
+ *     accel_unit = 4.184e-4 (kcal/mol/A/amu -> A/fs^2) and coulomb_k =
+ *     332.0637; reduced units: accel_unit = 1.
+ *   - Arrays passed to the calls below are HOST arrays unless stated
+ *     otherwise; they are copied during the call and may be freed after it.
+ *     Atom arrays are in the caller's original atom order, walker w owning
+ *     atoms [atom_offset[w], atom_offset[w+1]).  Vectors are AoS [N][3].
+ *   - The library owns its device memory (allocated in labf_create_system,
+ *     released in labf_destroy_system).  Device work is asynchronous on the
+ *     HIP stream passed in (NULL = default stream); calls that return host
+ *     data synchronise that stream.  A handle is not thread-safe.
+ *   - Errors: every call returns a labf_status.  Argument errors are found on
+ *     the host before any device work.  Numerical faults of a walker
+ *     (non-finite lambda force, neighbour skin exceeded, list capacity
+ *     exceeded) are recorded in that walker's status word (LABF_WS_*) and
+ *     surface in labf_read_walker_state.  labf_last_error() describes the
+ *     last failure of a handle (or of labf_create_system when passed NULL).
+ *   - Positions are stored internally at the precision of the system
+ *     (LABF_FP32 or LABF_FP64) offset by a power of two B >= L per box
+ *     edge, so that every difference of two positions is exact.  Inputs are
+ *     rounded to that grid; labf_read_atoms returns the stored values.
+ */
+#ifndef LABF_H
+#define LABF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct labf_system labf_system; /* opaque; owned by the library */
+typedef int32_t labf_status;
+
+#define LABF_OK 0
+#define LABF_E_ARG (-1)          /* invalid argument (detected on the host)    */
+#define LABF_E_STATE (-2)        /* call not valid in the current state        */
+#define LABF_E_HIP (-3)          /* HIP runtime error                          */
+#define LABF_E_NONFINITE (-4)    /* non-finite value in a walker               */
+#define LABF_E_SKIN (-5)         /* an atom moved more than r_skin/2 between rebuilds */
+#define LABF_E_UNSUPPORTED (-6)  /* configuration not supported                */
+#define LABF_E_EMPTY_BIN (-7)    /* free-energy readout with an empty bin      */
+#define LABF_E_CAPACITY (-8)     /* neighbour list capacity exceeded           */
+
+#define LABF_FP32 0              /* FP32 positions and pair terms; FP64 dV/dlambda, bins, lambda */
+#define LABF_FP64 1              /* FP64 throughout                            */
+
+#define LABF_DECOUPLE 0          /* c_x = 1 - ramp_x(lambda) (NAMD convention)  */
+#define LABF_COUPLE 1            /* c_x = ramp_x(lambda) (Tinker-HP convention) */
+
+#define LABF_MODE_BATCHED 0      /* all walkers per launch, 10-step blocks replayed as HIP graphs */
+#define LABF_MODE_PLAIN 1        /* one walker per launch sequence, no graph    */
+
+/* walker status bits */
+#define LABF_WS_NONFINITE 1u
+#define LABF_WS_REFLECT 2u       /* lambda needed more than one reflection     */
+#define LABF_WS_SKIN 4u
+#define LABF_WS_CAPACITY 8u
+
+/* Static description of a batch of walkers ("Software interface": the
+ * engine side).  All pointers are host pointers. */
+typedef struct labf_system_desc {
+  int32_t n_walkers;           /* W >= 1                                          */
+  int32_t precision;           /* LABF_FP32 | LABF_FP64                           */
+  const int64_t *atom_offset;  /* [W+1], atom_offset[0] = 0, non-decreasing, each walker >= 1 atom */
+  const double *box;           /* [W][3] orthorhombic box edges, periodic         */
+  const double *pos;           /* [N][3] initial positions (wrapped into the box) */
+  const double *vel;           /* [N][3] initial velocities, or NULL: Maxwell-Boltzmann at kT */
+  const double *mass;          /* [N] > 0                                         */
+  const double *charge;        /* [N]                                             */
+  const double *sigma;         /* [N] LJ sigma (> 0 where epsilon > 0)            */
+  const double *epsilon;       /* [N] LJ epsilon >= 0; Lorentz-Berthelot mixing   */
+  const uint8_t *is_solute;    /* [N] 1: atom of the alchemically decoupled group */
+  const double *anchor;        /* [N][3] restraint anchors, or NULL (no restraints) */
+  const double *k0;            /* [N] restraint constant at lambda = 0 (NULL iff anchor NULL) */
+  const double *k1;            /* [N] restraint constant at lambda = 1            */
+  double r_cut;                /* pair cutoff; r_cut + r_skin < L/2 on every edge */
+  double r_skin;               /* list buffer                                     */
+  double kT;                   /* atom bath temperature (energy units)            */
+  double gamma;                /* atom friction (1/time)                          */
+  double dt;                   /* time step                                       */
+  double coulomb_k;            /* Coulomb constant                                */
+  double accel_unit;           /* force/mass -> acceleration factor               */
+  uint64_t seed;               /* Philox4x32-10 key                               */
+  int32_t rebuild_interval;    /* steps between neighbour rebuilds (>= 1; 10 typical) */
+  int32_t reserved;            /* must be 0                                       */
+} labf_system_desc;
+
+/* Extended-lambda and ABF parameters ("Software interface" and "ABF
+ * parameters": the library side; one set shared by all walkers). */
+typedef struct labf_lambda_params {
+  const double *lambda0;       /* [W] initial lambda in [lo, hi]                  */
+  const double *p_lambda0;     /* [W] initial momenta, or NULL: Maxwell-Boltzmann */
+  double m_lambda;             /* fictitious mass (energy * time^2)               */
+  double gamma_lambda;         /* lambda friction (1/time)                        */
+  double kT_lambda;            /* lambda bath temperature                         */
+  double elec_start, elec_end; /* electrostatics ramp over [elec_start, elec_end] */
+  double vdw_start, vdw_end;   /* soft-core vdW ramp over [vdw_start, vdw_end]    */
+  int32_t direction;           /* LABF_DECOUPLE | LABF_COUPLE                     */
+  int32_t sc_power;            /* soft-core exponent p >= 1                       */
+  double sc_alpha;             /* soft-core alpha >= 0                            */
+  int32_t n_bins;              /* ABF bins on [lo, hi], 1..4096                   */
+  int32_t share_interval;      /* K >= 1: walkers merge their ABF samples every K steps */
+  double lo, hi;               /* lambda range = reflecting boundaries            */
+  int64_t full_samples;        /* bias ramp length (>= 1)                         */
+  int32_t fixed_lambda;        /* 1: lambda frozen (samples still accumulated)   */
+  int32_t abf_on;              /* 0: no ABF samples and no bias                   */
+} labf_lambda_params;
+
+/* Create a system: validates the descriptor on the host, allocates device
+ * memory, uploads the atoms and builds the first neighbour list on `stream`.
+ * On success *out receives the handle.  On failure *out is NULL and
+ * labf_last_error(NULL) describes the error. */
+labf_status labf_create_system(const labf_system_desc *desc, void *stream, labf_system **out);
+
+/* Set lambda/ABF parameters and reset lambda state: lambda = lambda0,
+ * p_lambda = p_lambda0 (or Maxwell-Boltzmann draws), ABF bins emptied, the
+ * next step starts a fresh BAOAB sequence.  Required before stepping. */
+labf_status labf_set_lambda_params(labf_system *sys, const labf_lambda_params *lp, void *stream);
+
+/* Advance every walker by n_steps >= 0 steps (asynchronous).  mode:
+ * LABF_MODE_BATCHED or LABF_MODE_PLAIN; both give identical results. */
+labf_status labf_step_walkers(labf_system *sys, int64_t n_steps, int32_t mode, void *stream);
+
+/* Shared ABF accumulator (synchronous).  counts/sum/sum_sq: [n_bins]
+ * (sum_sq may be NULL).  include_unshared = 1 adds the samples walkers have
+ * not merged yet (share_interval > 1). */
+labf_status labf_read_abf_bins(labf_system *sys, int32_t n_bins, int32_t include_unshared,
+                               int64_t *counts, double *sum, double *sum_sq, void *stream);
+
+/* Free-energy readout of the Riemann sum of bin averages (host arithmetic
+ * on labf_read_abf_bins(include_unshared = 1)): grad[b] = sum_b / count_b,
+ * profile[b] = A(lo + b w) - A(lo), *delta_a = A(hi) - A(lo).  Any pointer
+ * may be NULL.  Returns LABF_E_EMPTY_BIN (with the outputs still written)
+ * if a bin has no sample. */
+labf_status labf_free_energy(labf_system *sys, double *grad, double *profile, double *delta_a,
+                             void *stream);
+
+/* Walker state (synchronous), each [W] and nullable: lambda, p_lambda (in
+ * the pending form of the BAOAB sequence: the closing half-kick of the last
+ * step is applied at the start of the next one), the last dV/dlambda and
+ * ABF bias, status bits, and *step = steps taken since the last reset. */
+labf_status labf_read_walker_state(labf_system *sys, double *lambda, double *p_lambda,
+                                   double *dudl, double *bias, uint32_t *status, int64_t *step,
+                                   void *stream);
+
+/* Atom state in original order (synchronous): pos, vel [N][3] (nullable).
+ * Velocities are in the pending form described above. */
+labf_status labf_read_atoms(labf_system *sys, double *pos, double *vel, void *stream);
+
+/* Replace positions and/or velocities ([N][3], nullable); rebuilds the
+ * neighbour list and starts a fresh BAOAB sequence. */
+labf_status labf_write_atoms(labf_system *sys, const double *pos, const double *vel, void *stream);
+
+/* Evaluate, at the current positions and lambda, the forces [N][3], the
+ * energy decomposition energy[W][5] = {environment-environment,
+ * solute-solute, alchemical LJ, alchemical Coulomb, restraints} and
+ * dV/dlambda [W] (synchronous; nullable outputs).  Rebuilds the list. */
+labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy, double *dudl,
+                                void *stream);
+
+/* The neighbour set of walker w held by the device list: every pair (i < j,
+ * walker-local indices) with |x_j - x_i|^2 < r_list^2 under the minimum
+ * image, decided in FP64 as (dx*dx + dy*dy) + dz*dz.  Writes up to
+ * max_pairs pairs [n][2] in lexicographic order and the total count. */
+labf_status labf_export_pairs(labf_system *sys, int32_t walker, int64_t max_pairs, int64_t *pairs,
+                              int64_t *n_pairs, void *stream);
+
+/* Number of unordered pairs with r < r_cut in each walker (FP64 decision),
+ * counted by a separate pass over the device list (rebuilt first):
+ * pairs_all[W] every pair, pairs_env[W] pairs of two environment atoms
+ * (nullable).  Used to convert steps/s into pair-interactions/s. */
+labf_status labf_count_pairs(labf_system *sys, int64_t *pairs_all, int64_t *pairs_env,
+                             void *stream);
+
+/* Timing pass (for roofline reporting): rebuilds the list, then runs
+ * n_steps >= 1 batched steps launched one kernel at a time with HIP events
+ * around each launch on `stream`.  ms[0] = rebuild, ms[1] = alchemical
+ * kernel (average per step), ms[2] = environment kernel (average per step).
+ * Advances the dynamics by n_steps like labf_step_walkers. */
+labf_status labf_profile_steps(labf_system *sys, int64_t n_steps, double *ms, void *stream);
+
+/* Philox4x32-10 on the device (test hook): out[n][4] for counters ctr[n][4]
+ * and key[2], all host arrays. */
+labf_status labf_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
+                        void *stream);
+
+/* Sizes of the device layout (for diagnostics): clusters in use, cluster
+ * capacity, list entries in use, list capacity per cluster. */
+typedef struct labf_info {
+  int64_t n_atoms, n_slots, n_clusters, n_list_entries;
+  int32_t n_walkers, list_cap, precision, uniform_lj;
+} labf_info;
+labf_status labf_get_info(labf_system *sys, labf_info *info, void *stream);
+
+void labf_destroy_system(labf_system *sys);
+const char *labf_last_error(const labf_system *sys);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

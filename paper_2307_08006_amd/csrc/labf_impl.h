@@ -1,0 +1,167 @@
+// labf_impl.h -- internal layout shared by the gfx950 kernels and the host
+// runtime of the lambda-ABF alchemical nonbonded step.
+//
+// Layout in HBM (all walkers of a batch side by side):
+//   * atoms in the caller's order: static parameters, slot_of (current slot).
+//   * slots: clusters of CL = 8 atoms; walker w owns clusters
+//     [cl_begin, cl_begin + cap_env + n_acl): first its environment clusters
+//     (GROMACS-like columns on an x-y grid, each column sorted by z and padded
+//     to a multiple of 8), then its alchemical clusters (solute atoms and
+//     atoms whose restraint depends on lambda).  Per-slot arrays are SoA.
+//   * per cluster: bounding box, a list of neighbour-cluster entries
+//     (cluster index | image-shift code << 26) with a fixed capacity per
+//     cluster, and flags.
+//   * positions are stored offset by B = 2^k >= 2L per box edge: all stored
+//     positions share one exponent, so differences, and image shifts by +-L,
+//     are exact in the storage precision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace labf {
+
+constexpr int CL = 8;                 // atoms per cluster
+constexpr int WAVE = 64;              // CDNA wavefront
+constexpr int SHIFT_BITS = 26;        // cluster index bits in a list entry
+constexpr uint32_t CL_MASK = (1u << SHIFT_BITS) - 1u;
+constexpr int SHIFT_ZERO = 13;        // code of the (0,0,0) image
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point force unit
+constexpr uint32_t LAMBDA_ATOM = 0xFFFFFFFFu;  // noise stream of lambda
+
+struct WalkerMeta {
+  int64_t atom_begin;     // first atom (caller order)
+  int64_t cl_begin;       // first cluster
+  int32_t n_atoms;
+  int32_t n_a;            // alchemical atoms
+  int32_t cap_env;        // environment cluster capacity
+  int32_t n_acl;          // alchemical clusters (static)
+  int32_t ncx, ncy;       // column grid
+  int32_t col_begin;      // first entry in per-column arrays (ncx*ncy + 1 columns)
+  int32_t item_begin;     // first alchemical work item
+  int32_t item_cap;
+  int32_t env_item_begin; // first entry in the environment work table
+  double L[3];            // box edges
+  double B[3];            // storage offset (power of two >= 2L)
+  double cw[2];           // column widths
+};
+
+// Extended-lambda / ABF parameters as the kernels need them.
+struct LamParams {
+  double m_lambda, gamma_lambda, kT_lambda;
+  double elec_start, elec_end, vdw_start, vdw_end;
+  double sc_alpha;
+  double lo, hi, bin_w;
+  double c1l, sdl;          // exp(-gamma_l dt), sqrt((1 - c1l^2) kT_l m_l)
+  int64_t full_samples;
+  int32_t direction, sc_power, n_bins, share_interval, fixed_lambda, abf_on;
+};
+
+// Everything the kernels touch.  Pointers are device pointers.
+template <typename T>
+struct Dev {
+  // --- sizes and scalars
+  int32_t n_walkers;
+  int64_t n_atoms, n_slots, n_clusters;
+  int32_t list_cap;
+  int32_t uniform_lj;
+  double r_cut, r_list, dt, kT, gamma, coulomb_k, accel;
+  double c1;                // exp(-gamma dt)
+  uint64_t seed;
+  T rc2, irc, irc2;         // r_cut^2, 1/r_cut, 1/r_cut^2 (storage precision)
+  T c6, c12, ushift;        // uniform LJ: 4 eps sig^6, 4 eps sig^12, U_LJ(r_cut)
+  LamParams lp;
+  // --- static tables
+  const WalkerMeta *meta;       // [W]
+  const int32_t *atom_walker;   // [N]
+  const int32_t *cl_walker;     // [C]
+  const int32_t *env_table;     // [sum cap_env] -> cluster
+  const int32_t *item_walker;   // [sum item_cap]
+  // --- caller-order atom data
+  const double *a_pos0;         // [N][3] upload staging (B-offset, rounded)
+  const double *a_q, *a_sig, *a_eps, *a_mass, *a_k0, *a_k1, *a_anchor;  // anchor [N][3]
+  const uint8_t *a_sol, *a_alch;
+  int32_t *slot_of, *new_slot, *col_of, *key_col, *members;
+  T *xref;                      // [3][N] positions at the last rebuild
+  // --- per column
+  int32_t *col_count, *col_fill, *col_atom0, *col_cl0;
+  // --- per slot (SoA); X and V double-buffered
+  T *X[2][3];
+  T *V[2][3];
+  T *q;                         // sqrt(coulomb_k) * charge
+  T *lja, *ljb;                 // sigma/2, sqrt(eps) (per-atom mixing mode)
+  T *aim;                       // accel_unit / mass
+  T *nsd;                       // sqrt((1 - c1^2) kT accel_unit / mass)
+  T *rk;                        // lambda-independent restraint constant
+  T *anc[3];                    // restraint anchor (B-offset)
+  double *q64, *sig64, *eps64, *k0_64, *k1_64;
+  uint8_t *sol;                 // is_solute per slot
+  int32_t *orig;                // walker-local atom index or -1
+  unsigned long long *fext[3];  // fixed-point force accumulators (2^-40 units)
+  double *fout;                 // [3][S] forces of an evaluation
+  // --- per cluster
+  double *bbox;                 // [C][6] lo xyz, hi xyz
+  int32_t *cl_col;              // column of an environment cluster
+  int32_t *list_count;
+  uint32_t *list;               // [C * list_cap]
+  uint8_t *has_ext;
+  double *cl_energy;            // [C][2] env-env, restraint (evaluation)
+  // --- alchemical work items
+  int4 *items;                  // (cluster, e0, e1, walker)
+  double *item_dudl;            // [items]
+  double *item_energy;          // [items][5]
+  // --- per walker dynamic state
+  int32_t *n_env, *n_items;
+  uint32_t *ticket;             // per walker
+  uint32_t *gticket;            // [1]
+  uint32_t *status;
+  double *lambda, *p_lambda, *dudl, *bias;
+  int64_t *step, *env_step;     // per walker
+  int64_t *start_step;          // [1] step at which the BAOAB sequence (re)started
+  double *energy;               // [W][5] evaluation output (alchemical side)
+  int64_t *bin_count;           // [nbins]
+  double *bin_sum, *bin_sum2;
+  int64_t *loc_count;           // [W][nbins]
+  double *loc_sum, *loc_sum2;
+  // --- export / counting
+  int64_t *pair_out;            // [max][2]
+  unsigned long long *pair_n;   // [W] counters
+  int64_t pair_max;
+};
+
+// Index ranges a launch covers (batched: everything; plain: one walker).
+struct Range {
+  int64_t a0, an;      // atoms
+  int64_t c0, cn;      // clusters
+  int64_t e0, en;      // environment work-table entries
+  int64_t i0, in_;     // alchemical item slots
+  int64_t k0, kn;      // per-column entries
+  int32_t w0, wn;      // walkers
+};
+
+// Host-side launchers (defined in labf_kernels.hip).
+template <typename T>
+struct Launch {
+  static hipError_t rebuild(const Dev<T> &d, const Range &r, int xb, int vb, int check_disp,
+                            hipStream_t s);
+  static hipError_t step(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
+  static hipError_t step_alch(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
+  static hipError_t step_env(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
+  static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
+  static hipError_t export_pairs(const Dev<T> &d, const Range &r, int xb, int mode,
+                                 hipStream_t s);
+  static hipError_t init_velocities(const Dev<T> &d, int vb, hipStream_t s);
+  static hipError_t gather_atoms(const Dev<T> &d, int xb, int vb, double *pos, double *vel,
+                                 hipStream_t s);
+  static hipError_t scatter_atoms(const Dev<T> &d, int xb, int vb, const double *pos,
+                                  const double *vel, hipStream_t s);
+  static hipError_t gather_forces(const Dev<T> &d, double *f, hipStream_t s);
+};
+
+// lam0 / p0: device arrays [W]; p0 may be NULL (Maxwell-Boltzmann draw).
+template <typename T>
+hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, hipStream_t s);
+
+hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t s);
+
+}  // namespace labf

@@ -1,0 +1,1305 @@
+// labf_kernels.hip -- gfx950 kernels of the lambda-ABF alchemical nonbonded step.
+//
+// Per step (one launch pair, captured 10 steps at a time in a HIP graph):
+//   k_alch  : pairs of alchemical clusters (solute atoms and atoms with a
+//             lambda-dependent restraint) with every neighbour, in FP64:
+//             soft-core LJ scaled by c_v(lambda), shifted-force Coulomb scaled
+//             by c_e(lambda) ("Alchemical pathway"), dV/dlambda, forces on the
+//             alchemical atoms and the reaction on environment atoms
+//             (fixed-point 64-bit accumulation: order-independent).  The last
+//             work item of a walker runs the walker tail: restraints, BAOAB of
+//             its alchemical atoms, the ABF sample and bias, and the BAOAB step
+//             of (lambda, p_lambda) with reflection (Eq. lambda-abf); the last
+//             walker merges the walkers' ABF samples in walker order
+//             ("Orthogonal space sampling").
+//   k_env   : environment-environment pairs in the storage precision: plain
+//             LJ + shifted-force Coulomb, full cluster-pair list (no atomics),
+//             8 i-atoms held in scalar registers against 64 j-atoms in the
+//             lanes; the epilogue adds the reactions and restraints and runs
+//             BAOAB for the cluster's atoms.
+// Every rebuild_interval steps the neighbour structure is rebuilt: columns
+// on an x-y grid, z-sorted, cut into clusters of 8, and per-cluster lists of
+// neighbour clusters within r_list = r_cut + r_skin.
+#include "labf_impl.h"
+
+#include <math.h>
+
+namespace labf {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, multipliers 0xD2511F53 and
+// 0xCD9E8D57, key bumped by 0x9E3779B9 / 0xBB67AE85 between rounds.
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+// Four standard normals for counter (atom, step, walker, purpose): Box-Muller
+// in FP64 with u1 = (a + 1) 2^-32 in (0, 1], u2 = b 2^-32.
+__device__ void gauss4(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker,
+                       uint32_t purpose, double z[4]) {
+  uint32_t c0 = atom, c1 = step, c2 = walker, c3 = purpose;
+  philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double two_pi = 6.283185307179586;
+  const double inv = 2.3283064365386963e-10;  // 2^-32
+  const uint32_t o[4] = {c0, c1, c2, c3};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double u1 = ((double)o[2 * k] + 1.0) * inv;
+    const double u2 = (double)o[2 * k + 1] * inv;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(two_pi * u2, &sn, &cs);
+    z[2 * k] = rad * cs;
+    z[2 * k + 1] = rad * sn;
+  }
+}
+
+__global__ void k_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
+  philox10(c0, c1, c2, c3, k0, k1);
+  out[4 * i] = c0;
+  out[4 * i + 1] = c1;
+  out[4 * i + 2] = c2;
+  out[4 * i + 3] = c3;
+}
+
+// Channel coupling c_x(lambda) and dc_x/dlambda of the alchemical schedule:
+// ramp clip((lambda - s)/(e - s), 0, 1); decoupling c = 1 - ramp, coupling
+// c = ramp; slope on [s, e) and at lambda = e = hi.
+__device__ __forceinline__ void channel(double lam, double s0, double s1, int coupling, double hi,
+                                        double &c, double &dc) {
+  const double w = s1 - s0;
+  double m = lam <= s0 ? 0.0 : (lam >= s1 ? 1.0 : (lam - s0) / w);
+  double dm = ((lam >= s0 && lam < s1) || (lam == s1 && s1 == hi)) ? 1.0 / w : 0.0;
+  c = coupling ? m : 1.0 - m;
+  dc = coupling ? dm : -dm;
+}
+
+template <typename T>
+__device__ __forceinline__ T wrap_pos(T x, T B, T L) {
+  if (x >= B + L) x -= L;
+  else if (x < B) x += L;
+  return x;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+  if (d > 0.5 * L) d -= L;
+  else if (d < -0.5 * L) d += L;
+  return d;
+}
+
+__device__ __forceinline__ unsigned long long to_fix(double f) {
+  return (unsigned long long)(long long)llrint(f * FIX_SCALE);
+}
+__device__ __forceinline__ double from_fix(unsigned long long v) {
+  return (double)(long long)v * (1.0 / FIX_SCALE);
+}
+
+// XCD-aware block order: consecutive logical blocks (neighbouring clusters,
+// sharing j-data) land on the same XCD and its L2.  Grid = 8 * ceil(nb / 8).
+__device__ __forceinline__ int xcd_block(int nb) {
+  const int per = (nb + 7) >> 3;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// rebuild: columns -> z-sorted clusters -> cluster-pair lists
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_key(Dev<T> d, Range r, int xb, int check) {
+  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= r.a0 + r.an) return;
+  const int w = d.atom_walker[a];
+  const WalkerMeta &m = d.meta[w];
+  const int s = d.slot_of[a];
+  double x[3];
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T xw = wrap_pos<T>(d.X[xb][k][s], (T)m.B[k], (T)m.L[k]);
+    x[k] = (double)xw;
+    finite = finite && isfinite(x[k]);
+  }
+  if (!finite) atomicOr(&d.status[w], 1u);
+  if (check) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double dd = min_image(x[k] - (double)d.xref[(int64_t)k * d.n_atoms + a], m.L[k]);
+      r2 += dd * dd;
+    }
+    const double half_skin = 0.5 * (d.r_list - d.r_cut);
+    if (r2 > half_skin * half_skin) atomicOr(&d.status[w], 4u);
+  }
+  // clamp in floating point before converting (non-finite or far positions)
+  const double fx = fmin(fmax(floor((x[0] - m.B[0]) / m.cw[0]), 0.0), (double)(m.ncx - 1));
+  const double fy = fmin(fmax(floor((x[1] - m.B[1]) / m.cw[1]), 0.0), (double)(m.ncy - 1));
+  const int cx = finite ? (int)fx : 0;
+  const int cy = finite ? (int)fy : 0;
+  const int kc = cx * m.ncy + cy;
+  const int col = d.a_alch[a] ? m.ncx * m.ncy : kc;
+  d.key_col[a] = kc;
+  d.col_of[a] = col;
+  atomicAdd(&d.col_count[m.col_begin + col], 1);
+}
+
+// Block-wide exclusive scan of one int per thread (256 threads).
+__device__ int block_excl_scan(int v, int *sm, int &total) {
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += t;
+  }
+  if (lane == WAVE - 1) sm[wv] = inc;
+  __syncthreads();
+  int base = 0;
+  for (int k = 0; k < wv; ++k) base += sm[k];
+  total = sm[0] + sm[1] + sm[2] + sm[3];
+  __syncthreads();
+  return base + inc - v;
+}
+
+// One block per walker: cluster starts of the columns (each padded to a
+// multiple of 8 atoms), atom starts of the member lists; the alchemical
+// column starts at cap_env.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan(Dev<T> d, Range r) {
+  __shared__ int sm[8];
+  __shared__ int run_a, run_c;
+  const int w = r.w0 + blockIdx.x;
+  const WalkerMeta &m = d.meta[w];
+  const int ncol = m.ncx * m.ncy;
+  if (threadIdx.x == 0) {
+    run_a = 0;
+    run_c = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < ncol + 1; base += 256) {
+    const int c = base + threadIdx.x;
+    const int cnt = c <= ncol ? d.col_count[m.col_begin + c] : 0;
+    const int ncl = c < ncol ? (cnt + CL - 1) / CL : 0;
+    int ta, tc;
+    const int ea = block_excl_scan(cnt, sm, ta);
+    const int ec = block_excl_scan(ncl, sm + 4, tc);
+    if (c <= ncol) {
+      d.col_atom0[m.col_begin + c] = run_a + ea;
+      d.col_cl0[m.col_begin + c] = c < ncol ? run_c + ec : m.cap_env;
+      d.col_fill[m.col_begin + c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      run_a += ta;
+      run_c += tc;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int ne = run_c;
+    if (ne > m.cap_env) {
+      atomicOr(&d.status[w], 8u);
+      ne = m.cap_env;
+    }
+    d.n_env[w] = ne;
+  }
+}
+
+template <typename T>
+__global__ void k_members(Dev<T> d, Range r) {
+  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= r.a0 + r.an) return;
+  const int w = d.atom_walker[a];
+  const WalkerMeta &m = d.meta[w];
+  const int col = d.col_of[a];
+  const int pos = d.col_atom0[m.col_begin + col] + atomicAdd(&d.col_fill[m.col_begin + col], 1);
+  d.members[m.atom_begin + pos] = (int32_t)(a - m.atom_begin);
+}
+
+// Rank of an atom inside its column by (z, index); alchemical atoms by
+// (x-y column, z, index).  Deterministic whatever the member order.
+template <typename T>
+__global__ void k_rank(Dev<T> d, Range r, int xb) {
+  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= r.a0 + r.an) return;
+  const int w = d.atom_walker[a];
+  const WalkerMeta &m = d.meta[w];
+  const int col = d.col_of[a];
+  const int n = d.col_count[m.col_begin + col];
+  const int64_t mb = m.atom_begin + d.col_atom0[m.col_begin + col];
+  const T *Z = d.X[xb][2];
+  const T z = Z[d.slot_of[a]];
+  const int me = (int)(a - m.atom_begin);
+  const int kc = d.key_col[a];
+  const bool alchcol = col == m.ncx * m.ncy;
+  int rank = 0;
+  for (int t = 0; t < n; ++t) {
+    const int bl = d.members[mb + t];
+    const int64_t b = m.atom_begin + bl;
+    const T zb = Z[d.slot_of[b]];
+    bool less = zb < z || (zb == z && bl < me);
+    if (alchcol) {
+      const int kb = d.key_col[b];
+      less = kb < kc || (kb == kc && less);
+    }
+    rank += less ? 1 : 0;
+  }
+  d.new_slot[a] = (int32_t)((m.cl_begin + d.col_cl0[m.col_begin + col]) * CL + rank);
+}
+
+template <typename T>
+__global__ void k_clear_slots(Dev<T> d, Range r, int xb_new, int vb_new) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (r.c0 + r.cn) * CL) return;
+  const int w = d.cl_walker[s / CL];
+  const WalkerMeta &m = d.meta[w];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d.X[xb_new][k][s] = (T)(m.B[k] + 3.0 * m.L[k]);
+    d.V[vb_new][k][s] = (T)0;
+    d.anc[k][s] = (T)m.B[k];
+  }
+  d.q[s] = (T)0;
+  d.lja[s] = (T)0;
+  d.ljb[s] = (T)0;
+  d.aim[s] = (T)0;
+  d.nsd[s] = (T)0;
+  d.rk[s] = (T)0;
+  d.q64[s] = 0.0;
+  d.sig64[s] = 1.0;
+  d.eps64[s] = 0.0;
+  d.k0_64[s] = 0.0;
+  d.k1_64[s] = 0.0;
+  d.sol[s] = 0;
+  d.orig[s] = -1;
+}
+
+template <typename T>
+__global__ void k_scatter(Dev<T> d, Range r, int xb_old, int vb_old, int xb_new, int vb_new) {
+  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= r.a0 + r.an) return;
+  const int w = d.atom_walker[a];
+  const WalkerMeta &m = d.meta[w];
+  const int s = d.slot_of[a], s2 = d.new_slot[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T x = wrap_pos<T>(d.X[xb_old][k][s], (T)m.B[k], (T)m.L[k]);
+    d.X[xb_new][k][s2] = x;
+    d.xref[(int64_t)k * d.n_atoms + a] = x;
+    d.V[vb_new][k][s2] = d.V[vb_old][k][s];
+  }
+  const double mass = d.a_mass[a];
+  d.q[s2] = (T)(sqrt(d.coulomb_k) * d.a_q[a]);
+  d.lja[s2] = (T)(0.5 * d.a_sig[a]);
+  d.ljb[s2] = (T)sqrt(24.0 * d.a_eps[a]);
+  d.aim[s2] = (T)(d.accel / mass);
+  d.nsd[s2] = (T)sqrt((1.0 - d.c1 * d.c1) * d.kT * d.accel / mass);
+  d.q64[s2] = d.a_q[a];
+  d.sig64[s2] = d.a_sig[a];
+  d.eps64[s2] = d.a_eps[a];
+  if (d.a_k0) {
+    d.k0_64[s2] = d.a_k0[a];
+    d.k1_64[s2] = d.a_k1[a];
+    d.rk[s2] = d.a_alch[a] ? (T)0 : (T)d.a_k0[a];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.anc[k][s2] = (T)d.a_anchor[3 * a + k];
+  }
+  d.sol[s2] = d.a_sol[a];
+  d.orig[s2] = (int32_t)(a - m.atom_begin);
+  d.slot_of[a] = s2;
+}
+
+__device__ __forceinline__ bool cluster_used(const WalkerMeta &m, int ne, int64_t c) {
+  const int64_t loc = c - m.cl_begin;
+  return loc < ne || (loc >= m.cap_env && loc < (int64_t)m.cap_env + m.n_acl);
+}
+
+template <typename T>
+__global__ void k_bbox(Dev<T> d, Range r, int xb) {
+  const int64_t c = r.c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= r.c0 + r.cn) return;
+  d.has_ext[c] = 0;
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  if (!cluster_used(m, d.n_env[w], c)) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int col = -1;
+  for (int t = 0; t < CL; ++t) {
+    const int64_t s = c * CL + t;
+    const int o = d.orig[s];
+    if (o < 0) continue;
+    if (col < 0) col = d.key_col[m.atom_begin + o];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double x = (double)d.X[xb][k][s];
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d.bbox[c * 6 + k] = lo[k];
+    d.bbox[c * 6 + 3 + k] = hi[k];
+  }
+  d.cl_col[c] = col;
+}
+
+__device__ __forceinline__ double gap1(double lo_i, double hi_i, double lo_j, double hi_j) {
+  return fmax(0.0, fmax(lo_j - hi_i, lo_i - hi_j));
+}
+
+// One wave per cluster.  Environment clusters list environment clusters
+// (their own (I, I, 0) entry first); alchemical clusters list every cluster.
+template <typename T>
+__global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
+  const int64_t c = r.c0 + (int64_t)blockIdx.x * 4 + uni(threadIdx.x >> 6);
+  if (c >= r.c0 + r.cn) return;
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  const int ne = d.n_env[w];
+  const int64_t loc = c - m.cl_begin;
+  if (!cluster_used(m, ne, c)) return;
+  const bool isA = loc >= m.cap_env;
+  const int lane = lane_id();
+  double lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = d.bbox[c * 6 + k];
+    hi[k] = d.bbox[c * 6 + 3 + k];
+  }
+  const int cap = d.list_cap;
+  uint32_t *out = d.list + c * (int64_t)cap;
+  const double rl = d.r_list * (1.0 + 1e-7);
+  const double rl2 = rl * rl;
+  int cnt = 0;
+  if (!isA) {
+    if (lane == 0) out[0] = (uint32_t)c | ((uint32_t)SHIFT_ZERO << SHIFT_BITS);
+    cnt = 1;
+  }
+  const bool box_ok = lo[0] <= hi[0] && isfinite(lo[0] + lo[1] + lo[2] + hi[0] + hi[1] + hi[2]);
+  if (box_ok) {
+    // environment columns within r_list (raw column index carries the image)
+    const double tolx = 1e-9 * m.L[0] + 1e-12, toly = 1e-9 * m.L[1] + 1e-12;
+    // raw column indices carry the image (-1, 0, +1 box shifts only); clamp in
+    // floating point so that far or non-finite boxes cannot produce huge ranges
+    auto raw = [](double v, int n) {
+      return (int)fmin(fmax(floor(v), -(double)n), (double)(2 * n - 1));
+    };
+    const int rx0 = raw((lo[0] - rl - m.B[0]) / m.cw[0] - 1e-9, m.ncx);
+    const int rx1 = raw((hi[0] + rl - m.B[0]) / m.cw[0] + 1e-9, m.ncx);
+    const int ry0 = raw((lo[1] - rl - m.B[1]) / m.cw[1] - 1e-9, m.ncy);
+    const int ry1 = raw((hi[1] + rl - m.B[1]) / m.cw[1] + 1e-9, m.ncy);
+    for (int rx = rx0; rx <= rx1; ++rx) {
+      const int cx = ((rx % m.ncx) + m.ncx) % m.ncx;
+      const int sx = (rx - cx) / m.ncx;
+      if (sx < -1 || sx > 1) continue;
+      const double cxl = m.B[0] + rx * m.cw[0] - tolx, cxh = m.B[0] + (rx + 1) * m.cw[0] + tolx;
+      const double gx = gap1(lo[0], hi[0], cxl, cxh);
+      if (gx >= rl) continue;
+      for (int ry = ry0; ry <= ry1; ++ry) {
+        const int cy = ((ry % m.ncy) + m.ncy) % m.ncy;
+        const int sy = (ry - cy) / m.ncy;
+        if (sy < -1 || sy > 1) continue;
+        const double cyl = m.B[1] + ry * m.cw[1] - toly, cyh = m.B[1] + (ry + 1) * m.cw[1] + toly;
+        const double gy = gap1(lo[1], hi[1], cyl, cyh);
+        if (gx * gx + gy * gy >= rl2) continue;
+        const int col = cx * m.ncy + cy;
+        const int ncl = (d.col_count[m.col_begin + col] + CL - 1) / CL;
+        const int64_t J0 = m.cl_begin + d.col_cl0[m.col_begin + col];
+        for (int t0 = 0; t0 < ncl * 3; t0 += WAVE) {
+          const int t = t0 + lane;
+          bool pass = false;
+          int64_t J = 0;
+          int code = 0;
+          if (t < ncl * 3) {
+            J = J0 + t / 3;
+            const int sz = t % 3 - 1;
+            const double ox = sx * m.L[0], oy = sy * m.L[1], oz = sz * m.L[2];
+            const double *bj = d.bbox + J * 6;
+            const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
+            const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
+            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
+            code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
+            pass = ax * ax + ay * ay + az * az < rl2;
+            if (!isA && J == c && code == SHIFT_ZERO) pass = false;
+          }
+          const unsigned long long bal = __ballot(pass);
+          const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+          if (pass) {
+            const int pos = cnt + pre;
+            if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
+            if (isA) d.has_ext[J] = 1;
+          }
+          cnt += __popcll(bal);
+        }
+      }
+    }
+    if (isA) {
+      const int64_t A0 = m.cl_begin + m.cap_env;
+      for (int t0 = 0; t0 < m.n_acl * 27; t0 += WAVE) {
+        const int t = t0 + lane;
+        bool pass = false;
+        int64_t J = 0;
+        int code = 0;
+        if (t < m.n_acl * 27) {
+          J = A0 + t / 27;
+          code = t % 27;
+          const double ox = (code / 9 - 1) * m.L[0], oy = ((code / 3) % 3 - 1) * m.L[1],
+                       oz = (code % 3 - 1) * m.L[2];
+          const double *bj = d.bbox + J * 6;
+          if (bj[0] <= bj[3]) {
+            const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
+            const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
+            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
+            pass = ax * ax + ay * ay + az * az < rl2;
+          }
+        }
+        const unsigned long long bal = __ballot(pass);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (pass && cnt + pre < cap) out[cnt + pre] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
+        cnt += __popcll(bal);
+      }
+    }
+  }
+  if (lane == 0) {
+    d.list_count[c] = cnt < cap ? cnt : cap;
+    if (cnt > cap) atomicOr(&d.status[w], 8u);
+  }
+}
+
+// Alchemical work items: each alchemical cluster's list cut into chunks of
+// 8 entries; a walker without alchemical atoms gets one empty item so that
+// its lambda tail still runs.
+template <typename T>
+__global__ void k_items(Dev<T> d, Range r) {
+  const int w = r.w0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= r.w0 + r.wn) return;
+  const WalkerMeta &m = d.meta[w];
+  int n = 0;
+  for (int t = 0; t < m.n_acl; ++t) {
+    const int64_t c = m.cl_begin + m.cap_env + t;
+    const int cnt = d.list_count[c];
+    for (int e0 = 0; e0 < cnt; e0 += CL) {
+      if (n < m.item_cap) d.items[m.item_begin + n] = make_int4((int)c, e0, min(e0 + CL, cnt), w);
+      ++n;
+    }
+  }
+  if (n == 0) {
+    d.items[m.item_begin] = make_int4(-1, 0, 0, w);
+    n = 1;
+  }
+  if (n > m.item_cap) {
+    atomicOr(&d.status[w], 8u);
+    n = m.item_cap;
+  }
+  d.n_items[w] = n;
+}
+
+// ---------------------------------------------------------------------------
+// environment pair kernel
+// ---------------------------------------------------------------------------
+template <typename T, bool LB, bool ENERGY, bool DIAG>
+__device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], const T (&yi)[CL],
+                                          const T (&zi)[CL], const T (&qi)[CL], const T (&ai)[CL],
+                                          const T (&bi)[CL], int64_t s0, T xj, T yj, T zj, T qj,
+                                          T aj, T bj, int js, int vmask, T (&fx)[CL],
+                                          T (&fy)[CL], T (&fz)[CL], double &eacc) {
+  const T c12x12 = (T)12 * d.c12, c6x6 = (T)6 * d.c6;
+#pragma unroll
+  for (int ii = 0; ii < CL; ++ii) {
+    const T dx = xj - xi[ii], dy = yj - yi[ii], dz = zj - zi[ii];
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    bool in = r2 < d.rc2;
+    if (DIAG) in = in && (js != (int)(s0 + ii));
+    const T rinv = rsq(r2);
+    const T r2inv = rinv * rinv;
+    T flj, t3 = 0, bij = 0, r6 = 0;
+    if (!LB) {
+      r6 = r2inv * r2inv * r2inv;
+      flj = r6 * (c12x12 * r6 - c6x6);
+    } else {
+      const T sg = ai[ii] + aj;
+      const T t = sg * sg * r2inv;
+      t3 = t * t * t;
+      bij = bi[ii] * bj;
+      flj = bij * t3 * ((T)2 * t3 - (T)1);
+    }
+    const T qq = qi[ii] * qj;
+    const T fc = qq * rinv * (r2inv - d.irc2);
+    T fr = flj * r2inv + fc;
+    fr = in ? fr : (T)0;
+    fx[ii] -= fr * dx;
+    fy[ii] -= fr * dy;
+    fz[ii] -= fr * dz;
+    if (ENERGY) {
+      T el;
+      if (!LB) {
+        el = (d.c12 * r6 - d.c6) * r6 - d.ushift;
+      } else {
+        const T sg = ai[ii] + aj;
+        const T tc = sg * sg * d.irc2;
+        const T tc3 = tc * tc * tc;
+        el = bij / (T)6 * ((t3 * t3 - t3) - (tc3 * tc3 - tc3));
+      }
+      const T rr = r2 * rinv;
+      const T ec = qq * (rinv - d.irc + (rr - (T)d.r_cut) * d.irc2);
+      // padded i-slots share the sentinel position with padded j-slots
+      eacc += (in && ((vmask >> ii) & 1)) ? 0.5 * ((double)el + (double)ec) : 0.0;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void integrate_atom(const Dev<T> &d, const WalkerMeta &m, int64_t s,
+                                               int xb, int vb, int w, int64_t step, bool pending,
+                                               const double F[3]) {
+  const T h = (T)(0.5 * d.dt);
+  const T c1 = (T)d.c1;
+  const T im = d.aim[s], sd = d.nsd[s];
+  double z[4];
+  gauss4(d.seed, (uint32_t)d.orig[s], (uint32_t)step, (uint32_t)w, 0u, z);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T fa = (T)F[k];
+    T v = d.V[vb][k][s];
+    T x = d.X[xb][k][s];
+    if (pending) v += h * fa * im;
+    v += h * fa * im;
+    x += h * v;
+    v = c1 * v + sd * (T)z[k];
+    x += h * v;
+    d.V[vb][k][s] = v;
+    // no wrap here: the cluster-pair list fixes the periodic image of every
+    // cluster pair until the next rebuild, which wraps positions back.
+    d.X[xb ^ 1][k][s] = x;
+  }
+}
+
+template <typename T, bool LB, bool ENERGY, bool INTEG>
+__global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) {
+  const int nb = (int)((r.en + 3) >> 2);
+  const int lb = xcd_block(nb);
+  if (lb >= nb) return;
+  const int64_t e = r.e0 + (int64_t)lb * 4 + uni(threadIdx.x >> 6);
+  if (e >= r.e0 + r.en) return;
+  const int64_t c = d.env_table[e];
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  if (c - m.cl_begin >= d.n_env[w]) return;
+  const int lane = lane_id();
+  const int64_t s0 = c * CL;
+  const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
+  T xi[CL], yi[CL], zi[CL], qi[CL], ai[CL], bi[CL];
+  int vmask = 0;
+#pragma unroll
+  for (int ii = 0; ii < CL; ++ii) {
+    if (ENERGY) vmask |= (d.orig[s0 + ii] >= 0 ? 1 : 0) << ii;
+    xi[ii] = X0[s0 + ii];
+    yi[ii] = X1[s0 + ii];
+    zi[ii] = X2[s0 + ii];
+    qi[ii] = d.q[s0 + ii];
+    ai[ii] = LB ? d.lja[s0 + ii] : (T)0;
+    bi[ii] = LB ? d.ljb[s0 + ii] : (T)0;
+  }
+  T fx[CL], fy[CL], fz[CL];
+#pragma unroll
+  for (int ii = 0; ii < CL; ++ii) fx[ii] = fy[ii] = fz[ii] = (T)0;
+  double eacc = 0.0;
+  const T Lx = (T)m.L[0], Ly = (T)m.L[1], Lz = (T)m.L[2];
+  const T far = (T)(8.0 * m.B[0]);
+  const int n = d.list_count[c];
+  const uint32_t *lst = d.list + c * (int64_t)d.list_cap;
+  for (int e0 = 0; e0 < n; e0 += CL) {
+    const int ee = e0 + (lane >> 3);
+    T xj = far, yj = far, zj = far, qj = (T)0, aj = (T)0, bj = (T)0;
+    int js = -1;
+    if (ee < n) {
+      const uint32_t ent = lst[ee];
+      const int64_t J = ent & CL_MASK;
+      const int code = (int)(ent >> SHIFT_BITS);
+      js = (int)(J * CL + (lane & 7));
+      xj = X0[js] + (T)(code / 9 - 1) * Lx;
+      yj = X1[js] + (T)((code / 3) % 3 - 1) * Ly;
+      zj = X2[js] + (T)(code % 3 - 1) * Lz;
+      qj = d.q[js];
+      if (LB) {
+        aj = d.lja[js];
+        bj = d.ljb[js];
+      }
+    }
+    if (e0 == 0)
+      env_pairs<T, LB, ENERGY, true>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
+                                     vmask, fx, fy, fz, eacc);
+    else
+      env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
+                                      vmask, fx, fy, fz, eacc);
+  }
+  T Fx = (T)0, Fy = (T)0, Fz = (T)0;
+#pragma unroll
+  for (int ii = 0; ii < CL; ++ii) {
+    const T sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+    if (lane == ii) {
+      Fx = sx;
+      Fy = sy;
+      Fz = sz;
+    }
+  }
+  double eres = 0.0;
+  if (lane < CL) {
+    const int64_t s = s0 + lane;
+    const bool valid = d.orig[s] >= 0;
+    double F[3] = {(double)Fx, (double)Fy, (double)Fz};
+    if (d.has_ext[c]) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        F[k] += from_fix(d.fext[k][s]);
+        d.fext[k][s] = 0ull;
+      }
+    }
+    const T kr = d.rk[s];
+    if (valid && kr != (T)0) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T dd0 = d.X[xb][k][s] - d.anc[k][s];
+        const double dd = min_image((double)dd0, m.L[k]);
+        F[k] -= (double)kr * dd;
+        r2 += dd * dd;
+      }
+      eres = 0.5 * (double)kr * r2;
+    }
+    if (INTEG) {
+      if (valid) {
+        const int64_t st = d.env_step[w];
+        integrate_atom<T>(d, m, s, xb, vb, w, st, st != *d.start_step, F);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
+    }
+  }
+  if (ENERGY) {
+    const double et = wave_sum(eacc), er = wave_sum(eres);
+    if (lane == 0) {
+      d.cl_energy[c * 2] = et;
+      d.cl_energy[c * 2 + 1] = er;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// alchemical kernel (FP64) and the per-walker lambda/ABF tail
+// ---------------------------------------------------------------------------
+struct PairOut {
+  double fr, ulj, dulj, uc, duc;
+};
+
+// Soft-core LJ (alpha (1-c)^p + (r/sig)^6 in the denominator, shift at r_cut
+// with the same c) and shifted-force Coulomb, both at coupling (cv, ce).
+__device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq, double cv,
+                                            double ce, double alpha, int p, double rc) {
+  PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double r = sqrt(r2);
+  if (eps != 0.0) {
+    const double sig2 = sig * sig;
+    const double u = (r2 / sig2) * (r2 / sig2) * (r2 / sig2);
+    const double uc0 = (rc * rc / sig2);
+    const double uc = uc0 * uc0 * uc0;
+    const double A = alpha * pow(1.0 - cv, (double)p);
+    const double dsc = p >= 1 ? alpha * (double)p * pow(1.0 - cv, (double)(p - 1)) : 0.0;
+    const double s = 1.0 / (A + u), sc = 1.0 / (A + uc);
+    o.ulj = 4.0 * eps * cv * ((s * s - s) - (sc * sc - sc));
+    o.dulj = 4.0 * eps * (((s * s - s) + cv * dsc * (2.0 * s - 1.0) * s * s) -
+                          ((sc * sc - sc) + cv * dsc * (2.0 * sc - 1.0) * sc * sc));
+    o.fr = 24.0 * eps * cv * (2.0 * s - 1.0) * s * s * u / r2;
+  }
+  if (qq != 0.0) {
+    const double g = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+    o.duc = qq * g;
+    if (ce != 0.0) {
+      o.uc = ce * qq * g;
+      o.fr += ce * qq * (1.0 / r2 - 1.0 / (rc * rc)) / r;
+    }
+  }
+  return o;
+}
+
+template <typename T, bool ENERGY, bool INTEG>
+__device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb) {
+  const WalkerMeta &m = d.meta[w];
+  const int lane = lane_id();
+  const double lam = d.lambda[w];
+  const int64_t step = d.step[w];
+  const bool pending = step != *d.start_step;
+  double gr = 0.0, ur = 0.0;
+  const int64_t a0 = (m.cl_begin + m.cap_env) * CL;
+  for (int t = lane; t < m.n_acl * CL; t += WAVE) {
+    const int64_t s = a0 + t;
+    const bool valid = d.orig[s] >= 0;
+    double F[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      F[k] = from_fix(d.fext[k][s]);
+      d.fext[k][s] = 0ull;
+    }
+    const double k0 = d.k0_64[s], k1 = d.k1_64[s];
+    if (valid && (k0 != 0.0 || k1 != 0.0)) {
+      const double kl = k0 + lam * (k1 - k0);
+      double r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double dd = min_image((double)(d.X[xb][k][s] - d.anc[k][s]), m.L[k]);
+        F[k] -= kl * dd;
+        r2 += dd * dd;
+      }
+      gr += 0.5 * (k1 - k0) * r2;
+      ur += 0.5 * kl * r2;
+    }
+    if (INTEG) {
+      if (valid) {
+        integrate_atom<T>(d, m, s, xb, vb, w, step, pending, F);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
+    }
+  }
+  const int ni = d.n_items[w];
+  double g = 0.0;
+  for (int t = lane; t < ni; t += WAVE) g += d.item_dudl[m.item_begin + t];
+  const double G = wave_sum(g) + wave_sum(gr);
+  if (ENERGY) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      double e = 0.0;
+      for (int t = lane; t < ni; t += WAVE) e += d.item_energy[(int64_t)(m.item_begin + t) * 5 + q];
+      e = wave_sum(e);
+      if (q == 4) e += wave_sum(ur);
+      if (lane == 0) d.energy[w * 5 + q] = e;
+    }
+  }
+  if (!INTEG) {
+    if (lane == 0) {
+      d.dudl[w] = G;
+      d.ticket[w] = 0u;
+    }
+    return;
+  }
+  const LamParams &lp = d.lp;
+  // ABF: bias from the frozen accumulator, then this step's sample
+  if (lane == 0) {
+    double bias = 0.0;
+    if (lp.abf_on) {
+      int b = (int)floor((lam - lp.lo) / lp.bin_w);
+      b = b > lp.n_bins - 1 ? lp.n_bins - 1 : (b < 0 ? 0 : b);
+      const int64_t li = (int64_t)w * lp.n_bins + b;
+      const int64_t n = d.bin_count[b] + d.loc_count[li];
+      const double sum = d.bin_sum[b] + d.loc_sum[li];
+      if (n > 0) {
+        double ramp = (double)n / (double)lp.full_samples;
+        ramp = ramp > 1.0 ? 1.0 : ramp;
+        bias = ramp * (sum / (double)n);
+      }
+      d.loc_count[li] += 1;
+      d.loc_sum[li] += G;
+      d.loc_sum2[li] += G * G;
+    }
+    d.dudl[w] = G;
+    d.bias[w] = bias;
+    double l = lam, p = d.p_lambda[w];
+    uint32_t st = 0u;
+    if (!lp.fixed_lambda) {
+      const double h = 0.5 * d.dt;
+      const double fl = -G + bias;
+      if (pending) p += h * fl;
+      p += h * fl;
+      l += h * p / lp.m_lambda;
+      if (l < lp.lo) {
+        l = 2.0 * lp.lo - l;
+        p = -p;
+      } else if (l > lp.hi) {
+        l = 2.0 * lp.hi - l;
+        p = -p;
+      }
+      if (l < lp.lo || l > lp.hi) {
+        l = l < lp.lo ? lp.lo : lp.hi;
+        st |= 2u;
+      }
+      double z[4];
+      gauss4(d.seed, LAMBDA_ATOM, (uint32_t)step, (uint32_t)w, 0u, z);
+      p = lp.c1l * p + lp.sdl * z[0];
+      l += h * p / lp.m_lambda;
+      if (l < lp.lo) {
+        l = 2.0 * lp.lo - l;
+        p = -p;
+      } else if (l > lp.hi) {
+        l = 2.0 * lp.hi - l;
+        p = -p;
+      }
+      if (l < lp.lo || l > lp.hi) {
+        l = l < lp.lo ? lp.lo : lp.hi;
+        st |= 2u;
+      }
+    }
+    if (!isfinite(G) || !isfinite(l) || !isfinite(p)) st |= 1u;
+    if (st) atomicOr(&d.status[w], st);
+    d.lambda[w] = l;
+    d.p_lambda[w] = p;
+    d.env_step[w] = step;
+    d.step[w] = step + 1;
+    d.ticket[w] = 0u;
+    __threadfence();
+  }
+  // last walker of the step merges the samples in walker order every K steps
+  unsigned old = 0;
+  if (lane == 0) old = atomicAdd(d.gticket, 1u);
+  old = __shfl(old, 0, WAVE);
+  if (old != (unsigned)(d.n_walkers - 1)) return;
+  __threadfence();
+  if (lp.abf_on && ((step + 1) % lp.share_interval) == 0) {
+    for (int b = lane; b < lp.n_bins; b += WAVE) {
+      int64_t n = d.bin_count[b];
+      double s1 = d.bin_sum[b], s2 = d.bin_sum2[b];
+      for (int v = 0; v < d.n_walkers; ++v) {
+        const int64_t li = (int64_t)v * lp.n_bins + b;
+        n += d.loc_count[li];
+        s1 += d.loc_sum[li];
+        s2 += d.loc_sum2[li];
+        d.loc_count[li] = 0;
+        d.loc_sum[li] = 0.0;
+        d.loc_sum2[li] = 0.0;
+      }
+      d.bin_count[b] = n;
+      d.bin_sum[b] = s1;
+      d.bin_sum2[b] = s2;
+    }
+  }
+  if (lane == 0) *d.gticket = 0u;
+}
+
+template <typename T, bool ENERGY, bool INTEG>
+__global__ __launch_bounds__(64) void k_alch(Dev<T> d, Range r, int xb, int vb) {
+  const int64_t k = r.i0 + blockIdx.x;
+  if (k >= r.i0 + r.in_) return;
+  const int w = d.item_walker[k];
+  const WalkerMeta &m = d.meta[w];
+  if (k - m.item_begin >= d.n_items[w]) return;
+  const int lane = lane_id();
+  const int4 it = d.items[k];
+  const LamParams &lp = d.lp;
+  double ce, dce, cv, dcv;
+  const double lam = d.lambda[w];
+  channel(lam, lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
+  channel(lam, lp.vdw_start, lp.vdw_end, lp.direction, lp.hi, cv, dcv);
+  double dudl = 0.0;
+  double e5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (it.x >= 0) {
+    const int64_t c = it.x, s0 = c * CL;
+    const int ee = it.y + (lane >> 3);
+    bool vj = ee < it.z;
+    int64_t js = 0;
+    double xj = 0, yj = 0, zj = 0, qj = 0, sgj = 1, epj = 0;
+    int solj = 0;
+    bool isAj = false;
+    if (vj) {
+      const uint32_t ent = d.list[c * (int64_t)d.list_cap + ee];
+      const int64_t J = ent & CL_MASK;
+      const int code = (int)(ent >> SHIFT_BITS);
+      js = J * CL + (lane & 7);
+      vj = d.orig[js] >= 0;
+      xj = (double)d.X[xb][0][js] + (code / 9 - 1) * m.L[0];
+      yj = (double)d.X[xb][1][js] + ((code / 3) % 3 - 1) * m.L[1];
+      zj = (double)d.X[xb][2][js] + (code % 3 - 1) * m.L[2];
+      qj = d.q64[js];
+      sgj = d.sig64[js];
+      epj = d.eps64[js];
+      solj = d.sol[js];
+      isAj = (J - m.cl_begin) >= m.cap_env;
+    }
+    double rjx = 0, rjy = 0, rjz = 0;
+    const double rc = d.r_cut, rc2 = rc * rc;
+    for (int ii = 0; ii < CL; ++ii) {
+      const int64_t si = s0 + ii;
+      if (d.orig[si] < 0) continue;
+      const double dx = xj - (double)d.X[xb][0][si];
+      const double dy = yj - (double)d.X[xb][1][si];
+      const double dz = zj - (double)d.X[xb][2][si];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      if (vj && r2 < rc2 && js != si) {
+        const int soli = d.sol[si];
+        const bool alch = soli != solj;
+        const double sig = 0.5 * (d.sig64[si] + sgj);
+        const double eps = sqrt(d.eps64[si] * epj);
+        const double qq = d.coulomb_k * d.q64[si] * qj;
+        const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0,
+                                    lp.sc_alpha, lp.sc_power, rc);
+        fx = -o.fr * dx;
+        fy = -o.fr * dy;
+        fz = -o.fr * dz;
+        if (!isAj) {
+          rjx -= fx;
+          rjy -= fy;
+          rjz -= fz;
+        }
+        if (alch && soli) {
+          if (dcv != 0.0) dudl += dcv * o.dulj;
+          if (dce != 0.0) dudl += dce * o.duc;
+        }
+        if (ENERGY && (!isAj || si < js)) {
+          if (alch) {
+            e5[2] += o.ulj;
+            e5[3] += o.uc;
+          } else if (soli) {
+            e5[1] += o.ulj + o.uc;
+          } else {
+            e5[0] += o.ulj + o.uc;
+          }
+        }
+      }
+      fx = wave_sum(fx);
+      fy = wave_sum(fy);
+      fz = wave_sum(fz);
+      if (lane == 0) {
+        atomicAdd(&d.fext[0][si], to_fix(fx));
+        atomicAdd(&d.fext[1][si], to_fix(fy));
+        atomicAdd(&d.fext[2][si], to_fix(fz));
+      }
+    }
+    if (vj && !isAj && (rjx != 0.0 || rjy != 0.0 || rjz != 0.0)) {
+      atomicAdd(&d.fext[0][js], to_fix(rjx));
+      atomicAdd(&d.fext[1][js], to_fix(rjy));
+      atomicAdd(&d.fext[2][js], to_fix(rjz));
+    }
+  }
+  dudl = wave_sum(dudl);
+  if (lane == 0) d.item_dudl[k] = dudl;
+  if (ENERGY) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const double e = wave_sum(e5[q]);
+      if (lane == 0) d.item_energy[k * 5 + q] = e;
+    }
+  }
+  __threadfence();
+  unsigned old = 0;
+  if (lane == 0) old = atomicAdd(&d.ticket[w], 1u);
+  old = __shfl(old, 0, WAVE);
+  if (old != (unsigned)(d.n_items[w] - 1)) return;
+  __threadfence();
+  alch_tail<T, ENERGY, INTEG>(d, w, xb, vb);
+}
+
+// ---------------------------------------------------------------------------
+// neighbour-set export and pair counting (FP64 decision, no fused ops)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pairs(Dev<T> d, Range r, int xb, int mode) {
+  const int64_t c = r.c0 + (int64_t)blockIdx.x * 4 + uni(threadIdx.x >> 6);
+  if (c >= r.c0 + r.cn) return;
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  if (!cluster_used(m, d.n_env[w], c)) return;
+  const bool isA = (c - m.cl_begin) >= m.cap_env;
+  const int lane = lane_id();
+  const int n = d.list_count[c];
+  const double lim = mode == 0 ? d.r_list * d.r_list : d.r_cut * d.r_cut;
+  unsigned long long cnt = 0, cnt_env = 0;
+  for (int e0 = 0; e0 < n; e0 += CL) {
+    const int ee = e0 + (lane >> 3);
+    if (ee >= n) continue;
+    const uint32_t ent = d.list[c * (int64_t)d.list_cap + ee];
+    const int64_t J = ent & CL_MASK;
+    const int code = (int)(ent >> SHIFT_BITS);
+    const int64_t js = J * CL + (lane & 7);
+    const int oj = d.orig[js];
+    if (oj < 0) continue;
+    const bool isAj = (J - m.cl_begin) >= m.cap_env;
+    const double xj = __dadd_rn((double)d.X[xb][0][js], (code / 9 - 1) * m.L[0]);
+    const double yj = __dadd_rn((double)d.X[xb][1][js], ((code / 3) % 3 - 1) * m.L[1]);
+    const double zj = __dadd_rn((double)d.X[xb][2][js], (code % 3 - 1) * m.L[2]);
+    for (int ii = 0; ii < CL; ++ii) {
+      const int64_t si = c * CL + ii;
+      const int oi = d.orig[si];
+      if (oi < 0 || si == js) continue;
+      const double dx = __dsub_rn(xj, (double)d.X[xb][0][si]);
+      const double dy = __dsub_rn(yj, (double)d.X[xb][1][si]);
+      const double dz = __dsub_rn(zj, (double)d.X[xb][2][si]);
+      const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      if (!(r2 < lim)) continue;
+      const bool emit = (isA && !isAj) || oi < oj;
+      if (!emit) continue;
+      if (mode == 0) {
+        const unsigned long long pos = atomicAdd(&d.pair_n[w], 1ull);
+        if ((int64_t)pos < d.pair_max) {
+          d.pair_out[2 * pos] = oi < oj ? oi : oj;
+          d.pair_out[2 * pos + 1] = oi < oj ? oj : oi;
+        }
+      } else {
+        ++cnt;
+        if (!isA) ++cnt_env;
+      }
+    }
+  }
+  if (mode != 0) {
+    cnt = wave_sum(cnt);
+    cnt_env = wave_sum(cnt_env);
+    if (lane == 0 && cnt) atomicAdd(&d.pair_n[w], cnt);
+    if (lane == 0 && cnt_env) atomicAdd(&d.pair_n[d.n_walkers + w], cnt_env);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initialisation and caller-order transfers
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_init_vel(Dev<T> d, int vb) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= d.n_atoms) return;
+  const int w = d.atom_walker[a];
+  const WalkerMeta &m = d.meta[w];
+  double z[4];
+  gauss4(d.seed, (uint32_t)(a - m.atom_begin), 0u, (uint32_t)w, 1u, z);
+  const double sd = sqrt(d.kT * d.accel / d.a_mass[a]);
+  const int s = d.slot_of[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.V[vb][k][s] = (T)(sd * z[k]);
+}
+
+template <typename T>
+__global__ void k_init_lambda(Dev<T> d, const double *lam0, const double *p0) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < d.n_walkers) {
+    d.lambda[w] = lam0[w];
+    if (p0) {
+      d.p_lambda[w] = p0[w];
+    } else {
+      double z[4];
+      gauss4(d.seed, LAMBDA_ATOM, 0u, (uint32_t)w, 1u, z);
+      d.p_lambda[w] = sqrt(d.lp.m_lambda * d.lp.kT_lambda) * z[0];
+    }
+    d.dudl[w] = 0.0;
+    d.bias[w] = 0.0;
+    d.step[w] = 0;
+    d.env_step[w] = 0;
+    d.ticket[w] = 0u;
+    d.status[w] = 0u;
+    for (int b = 0; b < d.lp.n_bins; ++b) {
+      d.loc_count[(int64_t)w * d.lp.n_bins + b] = 0;
+      d.loc_sum[(int64_t)w * d.lp.n_bins + b] = 0.0;
+      d.loc_sum2[(int64_t)w * d.lp.n_bins + b] = 0.0;
+    }
+  }
+  if (w == 0) {
+    *d.gticket = 0u;
+    *d.start_step = 0;
+    for (int b = 0; b < d.lp.n_bins; ++b) {
+      d.bin_count[b] = 0;
+      d.bin_sum[b] = 0.0;
+      d.bin_sum2[b] = 0.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_gather_atoms(Dev<T> d, int xb, int vb, double *pos, double *vel) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= d.n_atoms) return;
+  const WalkerMeta &m = d.meta[d.atom_walker[a]];
+  const int s = d.slot_of[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (pos) pos[3 * a + k] = (double)wrap_pos<T>(d.X[xb][k][s], (T)m.B[k], (T)m.L[k]) - m.B[k];
+    if (vel) vel[3 * a + k] = (double)d.V[vb][k][s];
+  }
+}
+
+// pos: B-offset positions already rounded on the host (exact in T).
+template <typename T>
+__global__ void k_scatter_atoms(Dev<T> d, int xb, int vb, const double *pos, const double *vel) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= d.n_atoms) return;
+  const int s = d.slot_of[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (pos) d.X[xb][k][s] = (T)pos[3 * a + k];
+    if (vel) d.V[vb][k][s] = (T)vel[3 * a + k];
+  }
+}
+
+template <typename T>
+__global__ void k_gather_forces(Dev<T> d, double *f) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= d.n_atoms) return;
+  const int s = d.slot_of[a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[3 * a + k] = d.fout[(int64_t)k * d.n_slots + s];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+template <typename T>
+hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, int check,
+                              hipStream_t s) {
+  if (r.an <= 0) return hipSuccess;
+  k_fill_i32<<<nblk(r.kn, 256), 256, 0, s>>>(d.col_count + r.k0, r.kn, 0);
+  k_key<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, check);
+  k_scan<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r);
+  k_members<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r);
+  k_rank<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb);
+  k_clear_slots<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r, xb ^ 1, vb ^ 1);
+  k_scatter<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, vb, xb ^ 1, vb ^ 1);
+  k_bbox<T><<<nblk(r.cn, 256), 256, 0, s>>>(d, r, xb ^ 1);
+  k_list<T><<<nblk(r.cn, 4), 256, 0, s>>>(d, r);
+  k_items<T><<<nblk(r.wn, 64), 64, 0, s>>>(d, r);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, bool energy, bool integ,
+                       hipStream_t s) {
+  const int nb = (int)((r.en + 3) / 4);
+  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+  if (grid == 0) return;
+  if (d.uniform_lj) {
+    if (integ) k_env<T, false, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    else if (energy) k_env<T, false, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    else k_env<T, false, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+  } else {
+    if (integ) k_env<T, true, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    else if (energy) k_env<T, true, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    else k_env<T, true, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+  }
+}
+
+template <typename T>
+hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
+  env_launch<T>(d, r, xb, vb, false, true, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
+  env_launch<T>(d, r, xb, vb, false, true, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, true, false><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
+  env_launch<T>(d, r, xb, vb, true, false, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::export_pairs(const Dev<T> &d, const Range &r, int xb, int mode,
+                                   hipStream_t s) {
+  k_fill_u64<<<nblk(2 * d.n_walkers, 256), 256, 0, s>>>(d.pair_n, 2 * d.n_walkers);
+  if (r.cn > 0) k_pairs<T><<<nblk(r.cn, 4), 256, 0, s>>>(d, r, xb, mode);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::init_velocities(const Dev<T> &d, int vb, hipStream_t s) {
+  k_init_vel<T><<<nblk(d.n_atoms, 256), 256, 0, s>>>(d, vb);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::gather_atoms(const Dev<T> &d, int xb, int vb, double *pos, double *vel,
+                                   hipStream_t s) {
+  k_gather_atoms<T><<<nblk(d.n_atoms, 256), 256, 0, s>>>(d, xb, vb, pos, vel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::scatter_atoms(const Dev<T> &d, int xb, int vb, const double *pos,
+                                    const double *vel, hipStream_t s) {
+  k_scatter_atoms<T><<<nblk(d.n_atoms, 256), 256, 0, s>>>(d, xb, vb, pos, vel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::gather_forces(const Dev<T> &d, double *f, hipStream_t s) {
+  k_gather_forces<T><<<nblk(d.n_atoms, 256), 256, 0, s>>>(d, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, hipStream_t s) {
+  k_init_lambda<T><<<nblk(d.n_walkers, 64), 64, 0, s>>>(d, lam0, p0);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_philox<<<nblk(n, 256), 256, 0, s>>>(n, ctr, k0, k1, out);
+  return hipGetLastError();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+template hipError_t launch_init_lambda<float>(const Dev<float> &, const double *, const double *,
+                                              hipStream_t);
+template hipError_t launch_init_lambda<double>(const Dev<double> &, const double *, const double *,
+                                               hipStream_t);
+
+}  // namespace labf

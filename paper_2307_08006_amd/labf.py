@@ -1,0 +1,286 @@
+"""Python binding of the lambda-ABF C ABI (include/labf.h).
+
+Argument marshalling only: every step of the method runs in the gfx950 HIP
+library ``_build/liblabf.so``.  There is no CPU fallback; if the library is
+missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from .synth import LambdaSpec, SystemSpec
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "liblabf.so")
+
+LABF_FP32, LABF_FP64 = 0, 1
+LABF_DECOUPLE, LABF_COUPLE = 0, 1
+MODE_BATCHED, MODE_PLAIN = 0, 1
+WS_NONFINITE, WS_REFLECT, WS_SKIN, WS_CAPACITY = 1, 2, 4, 8
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NONFINITE",
+                -5: "E_SKIN", -6: "E_UNSUPPORTED", -7: "E_EMPTY_BIN", -8: "E_CAPACITY"}
+
+# every symbol include/labf.h declares
+EXPORTS = ["labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
+           "labf_read_abf_bins", "labf_free_energy", "labf_read_walker_state",
+           "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
+           "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
+           "labf_destroy_system",
+           "labf_last_error"]
+
+
+class LabfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [
+        ("n_walkers", C.c_int32), ("precision", C.c_int32),
+        ("atom_offset", C.c_void_p), ("box", C.c_void_p), ("pos", C.c_void_p),
+        ("vel", C.c_void_p), ("mass", C.c_void_p), ("charge", C.c_void_p),
+        ("sigma", C.c_void_p), ("epsilon", C.c_void_p), ("is_solute", C.c_void_p),
+        ("anchor", C.c_void_p), ("k0", C.c_void_p), ("k1", C.c_void_p),
+        ("r_cut", C.c_double), ("r_skin", C.c_double), ("kT", C.c_double),
+        ("gamma", C.c_double), ("dt", C.c_double), ("coulomb_k", C.c_double),
+        ("accel_unit", C.c_double), ("seed", C.c_uint64),
+        ("rebuild_interval", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class LambdaParams(C.Structure):
+    _fields_ = [
+        ("lambda0", C.c_void_p), ("p_lambda0", C.c_void_p),
+        ("m_lambda", C.c_double), ("gamma_lambda", C.c_double), ("kT_lambda", C.c_double),
+        ("elec_start", C.c_double), ("elec_end", C.c_double),
+        ("vdw_start", C.c_double), ("vdw_end", C.c_double),
+        ("direction", C.c_int32), ("sc_power", C.c_int32), ("sc_alpha", C.c_double),
+        ("n_bins", C.c_int32), ("share_interval", C.c_int32),
+        ("lo", C.c_double), ("hi", C.c_double), ("full_samples", C.c_int64),
+        ("fixed_lambda", C.c_int32), ("abf_on", C.c_int32),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("n_slots", C.c_int64), ("n_clusters", C.c_int64),
+                ("n_list_entries", C.c_int64), ("n_walkers", C.c_int32), ("list_cap", C.c_int32),
+                ("precision", C.c_int32), ("uniform_lj", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LabfError(-3, f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "labf_create_system": ([P, P, P], I32),
+            "labf_set_lambda_params": ([P, P, P], I32),
+            "labf_step_walkers": ([P, I64, I32, P], I32),
+            "labf_read_abf_bins": ([P, I32, I32, P, P, P, P], I32),
+            "labf_free_energy": ([P, P, P, P, P], I32),
+            "labf_read_walker_state": ([P, P, P, P, P, P, P, P], I32),
+            "labf_read_atoms": ([P, P, P, P], I32),
+            "labf_write_atoms": ([P, P, P, P], I32),
+            "labf_compute_forces": ([P, P, P, P, P], I32),
+            "labf_export_pairs": ([P, I32, I64, P, P, P], I32),
+            "labf_count_pairs": ([P, P, P, P], I32),
+            "labf_profile_steps": ([P, I64, P, P], I32),
+            "labf_philox": ([I64, P, P, P, P], I32),
+            "labf_get_info": ([P, P, P], I32),
+            "labf_destroy_system": ([P], None),
+            "labf_last_error": ([P], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return int(stream)
+
+
+class System:
+    """A batch of walkers living on the GPU (one labf_system handle)."""
+
+    def __init__(self, spec: SystemSpec, lam: Optional[LambdaSpec] = None, stream=None):
+        self.spec = spec
+        self.stream = _stream(stream)
+        self._h = None
+        keep = dict(
+            atom_offset=np.ascontiguousarray(spec.atom_offset, np.int64), box=_f64(spec.box, (-1, 3)),
+            pos=_f64(spec.pos, (-1, 3)), vel=_f64(spec.vel, (-1, 3)), mass=_f64(spec.mass),
+            charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
+            is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
+            k0=_f64(spec.k0), k1=_f64(spec.k1))
+        d = SystemDesc()
+        d.n_walkers = spec.n_walkers
+        d.precision = LABF_FP64 if spec.precision == "fp64" else LABF_FP32
+        for k, v in keep.items():
+            setattr(d, k, _p(v))
+        for k in ("r_cut", "r_skin", "kT", "gamma", "dt", "coulomb_k", "accel_unit"):
+            setattr(d, k, float(getattr(spec, k)))
+        d.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
+        d.rebuild_interval = int(spec.rebuild_interval)
+        d.reserved = 0
+        h = C.c_void_p()
+        rc = lib().labf_create_system(C.byref(d), self.stream, C.byref(h))
+        if rc != 0:
+            raise LabfError(rc, lib().labf_last_error(None).decode())
+        self._h = h
+        self.W, self.N = spec.n_walkers, spec.n_atoms
+        self.n_bins = None
+        if lam is not None:
+            self.set_lambda_params(lam)
+
+    # -- plumbing ---------------------------------------------------------------
+    def _chk(self, rc):
+        if rc != 0:
+            raise LabfError(rc, lib().labf_last_error(self._h).decode())
+
+    def close(self):
+        if self._h is not None:
+            lib().labf_destroy_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ------------------------------------------------------------------
+    def set_lambda_params(self, lam: LambdaSpec):
+        lam0 = np.ascontiguousarray(lam.lambda0, np.float64)
+        p0 = None if lam.p_lambda0 is None else np.ascontiguousarray(lam.p_lambda0, np.float64)
+        p = LambdaParams()
+        p.lambda0, p.p_lambda0 = _p(lam0), _p(p0)
+        p.m_lambda, p.gamma_lambda, p.kT_lambda = lam.m_lambda, lam.gamma_lambda, lam.kT_lambda
+        p.elec_start, p.elec_end, p.vdw_start, p.vdw_end = (lam.elec_start, lam.elec_end,
+                                                            lam.vdw_start, lam.vdw_end)
+        p.direction = LABF_COUPLE if lam.direction == "couple" else LABF_DECOUPLE
+        p.sc_power, p.sc_alpha = int(lam.sc_power), float(lam.sc_alpha)
+        p.n_bins, p.share_interval = int(lam.n_bins), int(lam.share_interval)
+        p.lo, p.hi, p.full_samples = float(lam.lo), float(lam.hi), int(lam.full_samples)
+        p.fixed_lambda, p.abf_on = int(lam.fixed_lambda), int(lam.abf_on)
+        self._chk(lib().labf_set_lambda_params(self._h, C.byref(p), self.stream))
+        self.n_bins = int(lam.n_bins)
+
+    def step(self, n_steps: int, mode: str = "batched"):
+        m = MODE_PLAIN if mode == "plain" else MODE_BATCHED
+        self._chk(lib().labf_step_walkers(self._h, int(n_steps), m, self.stream))
+
+    def read_abf_bins(self, include_unshared: bool = True):
+        c = np.zeros(self.n_bins, np.int64)
+        s1 = np.zeros(self.n_bins)
+        s2 = np.zeros(self.n_bins)
+        self._chk(lib().labf_read_abf_bins(self._h, self.n_bins, int(include_unshared), _p(c), _p(s1),
+                                           _p(s2), self.stream))
+        return c, s1, s2
+
+    def free_energy(self):
+        g, prof, da = np.zeros(self.n_bins), np.zeros(self.n_bins), np.zeros(1)
+        rc = lib().labf_free_energy(self._h, _p(g), _p(prof), _p(da), self.stream)
+        if rc not in (0, -7):
+            self._chk(rc)
+        return g, prof, float(da[0]), int(rc)
+
+    def read_walker_state(self):
+        W = self.W
+        lam, p, g, b = np.zeros(W), np.zeros(W), np.zeros(W), np.zeros(W)
+        st = np.zeros(W, np.uint32)
+        step = np.zeros(1, np.int64)
+        self._chk(lib().labf_read_walker_state(self._h, _p(lam), _p(p), _p(g), _p(b), _p(st),
+                                               _p(step), self.stream))
+        return dict(lam=lam, p_lambda=p, dudl=g, bias=b, status=st, step=int(step[0]))
+
+    def read_atoms(self):
+        pos = np.zeros((self.N, 3))
+        vel = np.zeros((self.N, 3))
+        self._chk(lib().labf_read_atoms(self._h, _p(pos), _p(vel), self.stream))
+        return pos, vel
+
+    def write_atoms(self, pos=None, vel=None):
+        pos = _f64(pos, (-1, 3))
+        vel = _f64(vel, (-1, 3))
+        self._chk(lib().labf_write_atoms(self._h, _p(pos), _p(vel), self.stream))
+
+    def compute_forces(self):
+        f = np.zeros((self.N, 3))
+        e = np.zeros((self.W, 5))
+        g = np.zeros(self.W)
+        self._chk(lib().labf_compute_forces(self._h, _p(f), _p(e), _p(g), self.stream))
+        return f, e, g
+
+    def export_pairs(self, walker: int) -> np.ndarray:
+        n = np.zeros(1, np.int64)
+        self._chk(lib().labf_export_pairs(self._h, int(walker), 0, None, _p(n), self.stream))
+        out = np.zeros((max(int(n[0]), 1), 2), np.int64)
+        self._chk(lib().labf_export_pairs(self._h, int(walker), out.shape[0], _p(out), _p(n),
+                                          self.stream))
+        return out[: int(n[0])]
+
+    def count_pairs(self, env_only: bool = False) -> np.ndarray:
+        """Pairs with r < r_cut per walker (all pairs, or environment pairs)."""
+        out = np.zeros(self.W, np.int64)
+        env = np.zeros(self.W, np.int64)
+        self._chk(lib().labf_count_pairs(self._h, _p(out), _p(env), self.stream))
+        return env if env_only else out
+
+    def profile_steps(self, n_steps: int) -> dict:
+        """Per-kernel times (ms) from HIP events around single launches."""
+        ms = np.zeros(3)
+        self._chk(lib().labf_profile_steps(self._h, int(n_steps), _p(ms), self.stream))
+        return dict(rebuild_ms=float(ms[0]), alch_ms=float(ms[1]), env_ms=float(ms[2]))
+
+    def info(self) -> dict:
+        inf = Info()
+        self._chk(lib().labf_get_info(self._h, C.byref(inf), self.stream))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+
+def philox(ctr, key, stream=None) -> np.ndarray:
+    """Philox4x32-10 of the device for counters ctr[n,4] and key[2]."""
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, np.uint32).reshape(2)
+    out = np.zeros_like(ctr)
+    rc = lib().labf_philox(ctr.shape[0], _p(ctr), _p(key), _p(out), _stream(stream))
+    if rc != 0:
+        raise LabfError(rc, lib().labf_last_error(None).decode())
+    return out
+
+
+def create_error() -> str:
+    return lib().labf_last_error(None).decode()

@@ -108,13 +108,14 @@ def _pow2_at_least(x: float) -> float:
 def quantize(pos: np.ndarray, box: np.ndarray, precision: str):
     """Round the box edges and positions (wrapped into [0, L)) to the values
     that ``(B + x) - B`` preserves in the given precision, B being the
-    smallest power of two >= L.  Returns (pos, box) as float64."""
+    smallest power of two >= 2L (the storage offset of the GPU layout).
+    Returns (pos, box) as float64."""
     pos = np.array(pos, dtype=np.float64, copy=True)
     box = np.array(box, dtype=np.float64, copy=True)
     ft = np.float32 if precision == "fp32" else np.float64
     for k in range(3):
         L = float(box[k])
-        B = _pow2_at_least(L)
+        B = _pow2_at_least(2.0 * L)
         Lq = float(ft(ft(B) + ft(L)) - ft(B))
         box[k] = Lq
         x = pos[:, k] - Lq * np.floor(pos[:, k] / Lq)
@@ -145,7 +146,7 @@ def _lattice_fcc(n_cell: int, L: float) -> np.ndarray:
 # reduced-unit LJ fluid with one decoupled solute
 # ----------------------------------------------------------------------------
 def lj_reduced(n_atoms: int = 512, density: float = 0.8, seed: int = BASE_SEED,
-               precision: str = "fp64", r_cut: float = 2.5, r_skin: float = 0.3,
+               precision: str = "fp64", r_cut: float = 2.5, r_skin: float = 0.5,
                n_walkers: int = 1, lambda0: float = 0.0, n_bins: int = 50,
                full_samples: int = 100, jitter: float = 0.05, charges: float = 0.0):
     """512 LJ particles (sigma = eps = m = 1), cubic periodic box at the given
@@ -207,7 +208,7 @@ def harmonic(n_walkers: int = 1, seed: int = BASE_SEED + 100, precision: str = "
     spec = SystemSpec(
         atom_offset=np.arange(n_walkers + 1, dtype=np.int64) * n, box=np.array(boxes),
         pos=np.concatenate(pos), mass=np.ones(N), charge=np.zeros(N), sigma=np.ones(N),
-        epsilon=np.zeros(N), is_solute=np.zeros(N, np.uint8), r_cut=2.5, r_skin=0.3, kT=1.0,
+        epsilon=np.zeros(N), is_solute=np.zeros(N, np.uint8), r_cut=2.5, r_skin=2.0, kT=1.0,
         gamma=1.0, dt=0.005, coulomb_k=1.0, accel_unit=1.0, seed=seed, precision=precision,
         anchor=anchor, k0=np.full(N, k0), k1=np.full(N, k1), name="harmonic")
     lam = LambdaSpec(lambda0=rng.uniform(0, 1, n_walkers), p_lambda0=None, m_lambda=10.0,
@@ -220,46 +221,91 @@ def harmonic(n_walkers: int = 1, seed: int = BASE_SEED + 100, precision: str = "
 # ----------------------------------------------------------------------------
 # charged LJ fluid in real units with a decoupled solute
 # ----------------------------------------------------------------------------
-SOLVENT_SIGMA = 3.15
+SOLVENT_SIGMA = 3.15        # the literal sigma of the workload description
+FLUID_SIGMA = 2.04          # sigma giving rho sigma^3 = 0.85 at 0.1 atoms/A^3
 SOLVENT_EPS = 0.15
 SOLVENT_Q = 0.4
 SOLVENT_MASS = 18.015
 SOLUTE_MASS = 12.011
 
 
-def _solute_params(rng, n_solute: int):
-    sig = rng.uniform(2.5, 3.8, n_solute)
+def _solute_params(rng, n_solute: int, scale: float = 1.0):
+    sig = rng.uniform(2.5, 3.8, n_solute) * scale
     eps = np.full(n_solute, 0.15)
     q = rng.uniform(-0.8, 0.8, n_solute)
-    q[-1] = -np.sum(q[:-1])
+    if n_solute:
+        q[-1] = -np.sum(q[:-1])
     return sig, eps, q
 
 
 def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
                seed: int = BASE_SEED + 1, precision: str = "fp32", r_cut: float = 12.0,
                r_skin: float = 1.0, temperature: float = 300.0, dt: float = 2.0,
-               gamma_ps: float = 1.0, jitter: float = 0.05, sigma: float = SOLVENT_SIGMA):
-    """One walker: n_atoms (solvent + solute) of a charged LJ fluid on a
-    seeded FCC lattice (vacancies chosen by a seeded permutation, +-jitter A),
-    solvent charges +-0.4 e alternating over a seeded permutation; the solute
-    is the n_solute occupied sites nearest the box centre with sigma ~
-    U(2.5, 3.8) A, eps 0.15, charges ~ U(-0.8, 0.8) summing to zero.
+               gamma_ps: float = 1.0, jitter: float = 0.05, sigma: float = FLUID_SIGMA,
+               lattice: str = "fcc_layered"):
+    """One walker: n_atoms (solvent + solute) of a charged LJ fluid at 0.1
+    atoms/A^3 on a seeded FCC lattice (vacancies chosen by a seeded
+    permutation, +-jitter A) with solvent charges +-0.4 e alternating between
+    lattice planes (lattice="fcc_layered"; "fcc" draws the signs by a seeded
+    permutation, "rocksalt" uses simple-cubic sites).  The solute is the
+    n_solute occupied sites nearest the box centre with sigma ~ U(2.5, 3.8) A
+    scaled by sigma/3.15, eps 0.15, charges ~ U(-0.8, 0.8) summing to zero.
+    The solvent sigma defaults to 2.04 A (rho sigma^3 = 0.85, a dense
+    supercritical LJ fluid): with the literal 3.15 A (rho sigma^3 = 3.1) the
+    lattice is a compressed solid whose relaxation heats the system to
+    ~10^4 K.  Pair counts depend on density and cutoff only.
     Lambda: electrostatics removed over [0, 0.5], soft-core vdW over
     [0.5, 1] (decoupling), m_lambda = 150000 kcal/mol fs^2,
     gamma_lambda = 1000 /ps, 100 bins, fullSamples 100."""
     rng = np.random.default_rng(seed)
     L = (n_atoms / density) ** (1.0 / 3.0)
-    n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
-    sites = _lattice_fcc(n_cell, L)
-    keep = np.sort(rng.permutation(sites.shape[0])[:n_atoms])
+    if lattice == "rocksalt":
+        # simple-cubic sites; charges alternate with the site parity (rock-salt
+        # order); vacancies drawn by a seeded permutation, half from each
+        # sublattice so that the two charge species stay balanced
+        n_side = int(math.ceil(n_atoms ** (1.0 / 3.0) - 1e-9))
+        n_side += n_side % 2
+        sites = _lattice_sc(n_side, L)
+        g = np.arange(n_side)
+        I, J, K = np.meshgrid(g, g, g, indexing="ij")
+        parity = ((I + J + K).ravel() % 2).astype(np.int64)
+        keep = []
+        for p_ in (0, 1):
+            idx = np.nonzero(parity == p_)[0]
+            take = n_atoms // 2 + (n_atoms % 2 if p_ == 0 else 0)
+            keep.append(idx[rng.permutation(idx.size)[:take]])
+        keep = np.sort(np.concatenate(keep))
+        site_q = np.where(parity[keep] == 0, SOLVENT_Q, -SOLVENT_Q)
+    elif lattice == "fcc_layered":
+        # FCC sites; charges alternate between the (001) planes of the basis
+        # (CuAu-like order: 8 unlike and 4 like nearest neighbours); vacancies
+        # by a seeded permutation, half from each charge species
+        n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
+        sites = _lattice_fcc(n_cell, L)
+        species = np.tile(np.array([0, 0, 1, 1]), n_cell ** 3)
+        keep = []
+        for p_ in (0, 1):
+            idx = np.nonzero(species == p_)[0]
+            take = n_atoms // 2 + (n_atoms % 2 if p_ == 0 else 0)
+            keep.append(idx[rng.permutation(idx.size)[:take]])
+        keep = np.sort(np.concatenate(keep))
+        site_q = np.where(species[keep] == 0, SOLVENT_Q, -SOLVENT_Q)
+    else:
+        n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
+        sites = _lattice_fcc(n_cell, L)
+        keep = np.sort(rng.permutation(sites.shape[0])[:n_atoms])
+        site_q = None
     pos = sites[keep] + rng.uniform(-jitter, jitter, size=(n_atoms, 3))
     pos, box = quantize(pos, np.array([L, L, L]), precision)
     d = np.linalg.norm(pos - L / 2, axis=1)
     order = np.lexsort((np.arange(n_atoms), d))
     solute = np.zeros(n_atoms, np.uint8)
     solute[order[:n_solute]] = 1
-    perm = rng.permutation(n_atoms - n_solute)
-    q_solv = np.where(perm % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
+    if site_q is not None:
+        q_solv = site_q[solute == 0]
+    else:
+        perm = rng.permutation(n_atoms - n_solute)
+        q_solv = np.where(perm % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
     charge = np.zeros(n_atoms)
     sig = np.full(n_atoms, sigma)
     eps = np.full(n_atoms, SOLVENT_EPS)
@@ -347,25 +393,31 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
     a_cl = (4.0 / 0.12) ** (1.0 / 3.0)
     ncl_side = int(math.ceil(2 * R / a_cl)) + 2
     cl_sites = _lattice_fcc(ncl_side, ncl_side * a_cl) - ncl_side * a_cl / 2 + c
+    cl_species = (np.arange(cl_sites.shape[0]) % 4) // 2
     dcl = np.linalg.norm(cl_sites - c, axis=1)
-    cl = cl_sites[np.argsort(dcl, kind="stable")[:n_cl]]
+    cl_pick = np.argsort(dcl, kind="stable")[:n_cl]
+    cl = cl_sites[cl_pick]
     R_eff = np.linalg.norm(cl - c, axis=1).max()
     # ligand: sites in a shell just outside the cluster, along a seeded direction
     u = rng.normal(size=3)
     u /= np.linalg.norm(u)
     solv_sites = _lattice_fcc(int(math.ceil(L / (4.0 / 0.1) ** (1.0 / 3.0))),
                               L)
+    sv_species = (np.arange(solv_sites.shape[0]) % 4) // 2
     ds = np.linalg.norm(solv_sites - c, axis=1)
-    outside = solv_sites[ds > R_eff + 1.0]
+    out_idx = np.nonzero(ds > R_eff + 1.0)[0]
+    outside = solv_sites[out_idx]
     lig_c = c + u * (R_eff + 3.0)
     dl = np.linalg.norm(outside - lig_c, axis=1)
     order = np.argsort(dl, kind="stable")
     lig = outside[order[:n_lig]]
-    rest = outside[order[n_lig:]]
+    rest_idx = out_idx[order[n_lig:]]
     n_solv = N - n_cl - n_lig
-    if rest.shape[0] < n_solv:
+    if rest_idx.shape[0] < n_solv:
         raise ValueError("solvent lattice too small")
-    solv = rest[np.sort(rng.permutation(rest.shape[0])[:n_solv])]
+    pick = rest_idx[np.sort(rng.permutation(rest_idx.shape[0])[:n_solv])]
+    solv = solv_sites[pick]
+    species = np.concatenate([cl_species[cl_pick], np.zeros(n_lig, np.int64), sv_species[pick]])
     pos = np.concatenate([cl, lig, solv]) + rng.uniform(-0.05, 0.05, size=(N, 3))
     pos, box = quantize(pos, np.array([L, L, L]), precision)
     anchor = pos.copy()
@@ -373,12 +425,11 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
     k[:n_cl] = 1.0
     solute = np.zeros(N, np.uint8)
     solute[n_cl:n_cl + n_lig] = 1
-    sig = np.full(N, SOLVENT_SIGMA)
+    sig = np.full(N, FLUID_SIGMA)
     eps = np.full(N, SOLVENT_EPS)
     mass = np.full(N, SOLVENT_MASS)
-    charge = np.zeros(N)
-    env = np.nonzero(solute == 0)[0]
-    charge[env] = np.where(rng.permutation(env.size) % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
+    charge = np.where(species == 0, SOLVENT_Q, -SOLVENT_Q).astype(np.float64)
+    charge[solute == 1] = 0.0
     s_sig, s_eps, s_q = _solute_params(rng, n_lig)
     li = np.arange(n_cl, n_cl + n_lig)
     sig[li], eps[li], charge[li], mass[li] = s_sig, s_eps, s_q, SOLUTE_MASS

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments on the host before any device
+work (these run without a GPU)."""
+import ctypes as C
+import dataclasses
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2307_08006_amd import labf, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ensure_built():
+    from paper_2307_08006_amd import build
+    if build.is_stale():
+        build.build(force=True)
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "labf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(labf_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    _ensure_built()
+    lib = labf.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(labf.EXPORTS) == names
+
+
+def _spec():
+    spec, lam = synth.lj_reduced(n_atoms=125, density=0.5, r_cut=2.0, r_skin=0.2)
+    return spec, lam
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda s: setattr(s, "r_cut", 10.0), "L/2"),
+    (lambda s: setattr(s, "dt", 0.0), "out of range"),
+    (lambda s: s.mass.__setitem__(3, 0.0), "mass"),
+    (lambda s: s.epsilon.__setitem__(3, -1.0), "epsilon"),
+    (lambda s: s.pos.__setitem__((2, 1), np.nan), "position"),
+    (lambda s: setattr(s, "atom_offset", np.array([0, 0, 125], np.int64)), "at least one atom"),
+    (lambda s: setattr(s, "anchor", np.zeros((125, 3))), "together"),
+    (lambda s: setattr(s, "rebuild_interval", 0), "rebuild_interval"),
+    (lambda s: setattr(s, "precision", "fp16"), None),
+])
+def test_invalid_descriptor_is_rejected_on_host(mutate, msg):
+    _ensure_built()
+    spec, lam = _spec()
+    if mutate is not None:
+        mutate(spec)
+    if spec.precision == "fp16":
+        # the binding maps unknown precisions to FP32; check the raw ABI instead
+        d = labf.SystemDesc()
+        d.n_walkers, d.precision = 1, 7
+        h = C.c_void_p()
+        assert labf.lib().labf_create_system(C.byref(d), None, C.byref(h)) == -1
+        assert h.value is None
+        return
+    with pytest.raises(labf.LabfError) as ei:
+        labf.System(spec)
+    assert ei.value.code == -1
+    assert msg in str(ei.value)
+
+
+def test_null_arguments_are_rejected():
+    _ensure_built()
+    L = labf.lib()
+    assert L.labf_create_system(None, None, None) == -1
+    h = C.c_void_p()
+    assert L.labf_create_system(None, None, C.byref(h)) == -1
+    assert L.labf_step_walkers(None, 1, 0, None) == -1
+    assert L.labf_read_atoms(None, None, None, None) == -1
+    assert L.labf_philox(-1, None, None, None, None) == -1
+    assert L.labf_philox(0, None, None, None, None) == 0
+    L.labf_destroy_system(None)
+    assert b"NULL" in L.labf_last_error(None) or L.labf_last_error(None) is not None
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(labf, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(labf, "_lib", None)
+    with pytest.raises(labf.LabfError):
+        labf.lib()

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64
+oracle on identical seeded inputs.
+
+Tolerances (from the arithmetic of each path):
+  * neighbour sets: bit-exact (same FP64 decision on identical positions);
+  * FP64 systems: forces, energies, dV/dlambda within 1e-10 relative
+    (differences only in summation order);
+  * FP32 systems: forces ||dF|| / ||F|| <= 1e-5 per walker (FP32 pair terms
+    on exact FP32 separations); dV/dlambda and every alchemical quantity
+    within 1e-9 relative (computed in FP64 on the FP32 positions);
+  * short FP64 trajectories with the same noise: lambda, p_lambda, ABF sums
+    and positions within 1e-9 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_08006_amd import labf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _small_charged(precision, n=3000, seed=synth.BASE_SEED + 11, n_solute=30):
+    return synth.charged_lj(n_atoms=n, n_solute=n_solute, precision=precision, seed=seed)
+
+
+def _uneven(precision):
+    a, lam = _small_charged(precision, n=2600, seed=31)
+    b, _ = _small_charged(precision, n=4100, seed=32, n_solute=12)
+    c, _ = synth.charged_lj(n_atoms=3300, n_solute=0, precision=precision, seed=33)
+    return synth.concat([a, b, c], lam, np.array([0.1, 0.45, 0.8]), seed=34, name="uneven3")
+
+
+SYSTEMS = {
+    "lj512_fp64": lambda: synth.lj_reduced(),
+    "charged3k_fp32": lambda: _small_charged("fp32"),
+    "charged3k_fp64": lambda: _small_charged("fp64"),
+    "uneven3_fp32": lambda: _uneven("fp32"),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(SYSTEMS))
+def case(request):
+    spec, lam = SYSTEMS[request.param]()
+    sys_ = labf.System(spec, lam)
+    yield request.param, spec, lam, sys_
+    sys_.close()
+
+
+def test_philox_stream_matches_oracle():
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2 ** 32, size=(512, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0x12345678, 0x9ABCDEF0], np.uint32)
+    got = labf.philox(ctr, key)
+    for i in range(ctr.shape[0]):
+        assert got[i].tolist() == oracle.philox4x32_10(ctr[i], key).tolist()
+
+
+def test_positions_round_trip(case):
+    name, spec, lam, s = case
+    pos, _ = s.read_atoms()
+    assert np.array_equal(pos, spec.pos), name
+
+
+def test_neighbour_set_is_bit_exact(case):
+    name, spec, lam, s = case
+    o = oracle.Oracle(spec, lam)
+    pos, _ = s.read_atoms()
+    for w in range(spec.n_walkers):
+        sl = spec.walker_slice(w)
+        got = s.export_pairs(w)
+        want = o.neighbor_pairs(w, pos[sl], spec.r_cut + spec.r_skin)
+        assert got.shape == want.shape and np.array_equal(got, want), (name, w, got.shape, want.shape)
+
+
+def test_pair_count_matches_oracle(case):
+    name, spec, lam, s = case
+    o = oracle.Oracle(spec, lam)
+    pos, _ = s.read_atoms()
+    got = s.count_pairs()
+    for w in range(spec.n_walkers):
+        want = o.neighbor_pairs(w, pos[spec.walker_slice(w)], spec.r_cut).shape[0]
+        assert got[w] == want, (name, w)
+
+
+@pytest.mark.parametrize("lam_value", [0.0, 0.3, 0.5, 0.77, 1.0])
+def test_forces_energy_dudl_match_oracle(case, lam_value):
+    name, spec, lam, s = case
+    lam2 = type(lam)(**{**lam.__dict__, "lambda0": np.full(spec.n_walkers, lam_value)})
+    s.set_lambda_params(lam2)
+    f, e, g = s.compute_forces()
+    o = oracle.Oracle(spec, lam2)
+    pos, _ = s.read_atoms()
+    fp64 = spec.precision == "fp64"
+    for w in range(spec.n_walkers):
+        sl = spec.walker_slice(w)
+        fo, uo, go = o.evaluate(w, pos[sl], lam_value)
+        ftol = 1e-10 if fp64 else 1e-5
+        assert _rel(f[sl], fo) <= ftol, (name, w, _rel(f[sl], fo))
+        assert abs(g[w] - go) <= 1e-9 * max(abs(go), 1e-3), (name, w, g[w], go)
+        # alchemical and restraint energies: FP64 on both sides
+        for k in (1, 2, 3, 4):
+            assert abs(e[w, k] - uo[k]) <= 1e-9 * max(abs(uo[k]), 1e-3), (name, w, k, e[w, k], uo[k])
+        etol = 1e-10 if fp64 else 2e-6
+        assert abs(e[w, 0] - uo[0]) <= etol * max(abs(uo[0]), 1.0), (name, w, e[w, 0], uo[0])
+
+
+def _state(s):
+    st = s.read_walker_state()
+    c, s1, s2 = s.read_abf_bins(True)
+    pos, vel = s.read_atoms()
+    return st, c, s1, s2, pos, vel
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_short_fp64_trajectory_matches_oracle(mode):
+    spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35)
+    lam.share_interval = 2
+    s = labf.System(spec, lam)
+    o = oracle.Oracle(spec, lam)
+    ost = o.init_state()
+    for n in (3, 7, 10, 20):
+        s.step(n, mode)
+        o.run(n)
+        st, c, s1, s2, pos, vel = _state(s)
+        ref_c = ost["bin_count"] + ost["loc_count"].sum(0)
+        ref_s = ost["bin_sum"] + ost["loc_sum"].sum(0)
+        assert np.array_equal(c, ref_c)
+        assert _rel(s1, ref_s) <= 1e-9
+        assert _rel(st["lam"], ost["lam"]) <= 1e-9, (st["lam"], ost["lam"])
+        assert _rel(st["p_lambda"], ost["p_lambda"]) <= 1e-9
+        assert _rel(st["dudl"], ost["dudl"]) <= 1e-9
+        d = pos - ost["x"]
+        L = spec.box[0, 0]
+        d -= L * np.rint(d / L)
+        assert np.abs(d).max() <= 1e-9
+        assert _rel(vel, ost["v"]) <= 1e-9
+        assert (st["status"] == 0).all()
+    s.close()
+
+
+def test_batched_and_plain_are_bitwise_identical():
+    spec, lam = _uneven("fp32")
+    a = labf.System(spec, lam)
+    b = labf.System(spec, lam)
+    a.step(25, "batched")
+    b.step(25, "plain")
+    sa, sb = _state(a), _state(b)
+    for k in ("lam", "p_lambda", "dudl", "bias"):
+        assert np.array_equal(sa[0][k], sb[0][k]), k
+    for x, y in zip(sa[1:], sb[1:]):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_repeated_runs_are_bitwise_identical():
+    spec, lam = _small_charged("fp32")
+    r = []
+    for _ in range(2):
+        s = labf.System(spec, lam)
+        s.step(20)
+        r.append(_state(s))
+        s.close()
+    for x, y in zip(r[0][1:], r[1][1:]):
+        assert np.array_equal(x, y)
+
+
+def test_harmonic_restraint_free_energy_closed_form():
+    spec, lam = synth.harmonic(n_walkers=512, seed=909)
+    s = labf.System(spec, lam)
+    s.step(100000)
+    g, prof, da, rc = s.free_energy()
+    assert rc == 0
+    exact = 4.5 * spec.kT * math.log(4.0)
+    assert abs(da - exact) < 0.05 * spec.kT, (da, exact)
+    st = s.read_walker_state()
+    assert (st["status"] == 0).all()
+    s.close()
+
+
+def test_full_size_single_walker_forces():
+    spec, lam = synth.charged_lj(n_atoms=30000, precision="fp32")
+    s = labf.System(spec, lam)
+    o = oracle.Oracle(spec, lam)
+    pos, _ = s.read_atoms()
+    for lv in (0.25, 0.75):
+        lam2 = type(lam)(**{**lam.__dict__, "lambda0": np.array([lv])})
+        s.set_lambda_params(lam2)
+        f, e, g = s.compute_forces()
+        fo, uo, go = o.evaluate(0, pos, lv)
+        assert _rel(f, fo) <= 1e-5, _rel(f, fo)
+        assert abs(g[0] - go) <= 1e-9 * abs(go)
+    cnt = s.count_pairs()
+    assert cnt[0] == o.neighbor_pairs(0, pos, spec.r_cut).shape[0]
+    s.close()
