@@ -10,8 +10,8 @@ walker: neighbour rebuild (every 10 steps), pair forces and dV/dlambda,
 BAOAB of atoms and lambda, ABF accumulation.
 
 Before timing, the seeded lattice is equilibrated on the GPU (untimed:
-500 steps at dt = 1 fs, gamma = 20/ps), then the production parameters are
-restored.  Pairs are counted exactly (FP64 decision) by a separate, untimed
+500 steps at dt = 1 fs, gamma = 20/ps, rebuild every step), then the
+production parameters are restored.  Pairs are counted exactly (FP64 decision) by a separate, untimed
 pass before and after the timed region.
 
 Prints ONE JSON line.
@@ -61,10 +61,12 @@ def _ensure_built():
 
 
 def equilibrate(spec, lam, steps):
-    """Untimed GPU equilibration of a one-walker system: strong friction and
-    a 1 fs step; returns the spec with the equilibrated coordinates."""
+    """Untimed GPU equilibration of a one-walker system: strong friction, a
+    1 fs step and a rebuild every step (the lattice relaxes by up to ~1.5 A
+    in the first steps); returns the spec with the equilibrated
+    coordinates."""
     from paper_2307_08006_amd import labf
-    eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0)
+    eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0, rebuild_interval=1)
     with labf.System(eq, lam) as s:
         s.step(steps)
         pos, _ = s.read_atoms()

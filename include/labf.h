@@ -39,9 +39,10 @@
  *     surface in labf_read_walker_state.  labf_last_error() describes the
  *     last failure of a handle (or of labf_create_system when passed NULL).
  *   - Positions are stored internally at the precision of the system
- *     (LABF_FP32 or LABF_FP64) offset by a power of two B >= L per box
- *     edge, so that every difference of two positions is exact.  Inputs are
- *     rounded to that grid; labf_read_atoms returns the stored values.
+ *     (LABF_FP32 or LABF_FP64) offset by a power of two B >= 2L per box
+ *     edge, so that every difference of two positions, and every image shift
+ *     by +-L, is exact.  Box edges and inputs are rounded to that grid;
+ *     labf_read_atoms returns the stored values wrapped into [0, L).
  */
 #ifndef LABF_H
 #define LABF_H
@@ -214,6 +215,7 @@ labf_status labf_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uin
 typedef struct labf_info {
   int64_t n_atoms, n_slots, n_clusters, n_list_entries;
   int32_t n_walkers, list_cap, precision, uniform_lj;
+  int32_t list_max_env, list_max_alch;   /* longest list of each cluster kind */
 } labf_info;
 labf_status labf_get_info(labf_system *sys, labf_info *info, void *stream);
 

@@ -416,7 +416,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     m.cw[0] = m.L[0] / m.ncx;
     m.cw[1] = m.L[1] / m.ncy;
     m.cap_env = (int32_t)((nenv + CL - 1) / CL + (int64_t)m.ncx * m.ncy);
-    m.n_acl = (int32_t)((na + CL - 1) / CL);
+    m.n_acl = (int32_t)na;  // one alchemical atom per cluster
     m.cl_begin = cl;
     m.col_begin = (int32_t)col;
     m.env_item_begin = (int32_t)env;
@@ -568,14 +568,22 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     std::vector<int32_t> cnt(s->C);
     HIPCHK(s, hipStreamSynchronize(st));
     HIPCHK(s, hipMemcpy(cnt.data(), d.list_count, sizeof(int32_t) * s->C, hipMemcpyDeviceToHost));
-    int mx = 0;
-    for (int32_t v : cnt) mx = std::max(mx, (int)v);
+    int mx_env = 0, mx_a = 0;
+    for (int w = 0; w < W; ++w) {
+      const WalkerMeta &m = s->meta[w];
+      for (int64_t c = m.cl_begin; c < m.cl_begin + m.cap_env; ++c) mx_env = std::max(mx_env, (int)cnt[c]);
+      for (int64_t c = m.cl_begin + m.cap_env; c < m.cl_begin + m.cap_env + m.n_acl; ++c)
+        mx_a = std::max(mx_a, (int)cnt[c]);
+    }
+    const int mx = std::max(mx_env, mx_a);
     if (mx >= s->list_cap) {
       s->list_cap *= 2;  // overflowed: grow and rebuild from the same positions
     } else {
       // headroom for denser regions and larger cluster boxes once the
-      // configuration relaxes (overflow is flagged in the walker status)
-      const int want = std::max(128, ((int)(2.0 * mx) + 64 + 31) / 32 * 32);
+      // configuration relaxes; alchemical clusters (a spread-out solute) get
+      // more (overflow is flagged in the walker status)
+      const int want = std::max({128, ((int)(2.0 * mx_env) + 64 + 31) / 32 * 32,
+                                 ((int)(3.0 * mx_a) + 128 + 31) / 32 * 32});
       if (want >= s->list_cap) break;
       s->list_cap = want;
     }
@@ -1068,12 +1076,21 @@ labf_status labf_get_info(labf_system *sys, labf_info *info, void *stream) {
   HIPCHK(sys, hipMemcpy(ne.data(), pne, sizeof(int32_t) * sys->W, hipMemcpyDeviceToHost));
   HIPCHK(sys, hipMemcpy(lc.data(), plc, sizeof(int32_t) * sys->C, hipMemcpyDeviceToHost));
   int64_t used = 0, entries = 0;
+  int32_t mx_env = 0, mx_a = 0;
   for (int w = 0; w < sys->W; ++w) {
     const WalkerMeta &m = sys->meta[w];
     used += ne[w] + m.n_acl;
-    for (int64_t c = m.cl_begin; c < m.cl_begin + ne[w]; ++c) entries += lc[c];
-    for (int64_t c = m.cl_begin + m.cap_env; c < m.cl_begin + m.cap_env + m.n_acl; ++c) entries += lc[c];
+    for (int64_t c = m.cl_begin; c < m.cl_begin + ne[w]; ++c) {
+      entries += lc[c];
+      mx_env = std::max(mx_env, lc[c]);
+    }
+    for (int64_t c = m.cl_begin + m.cap_env; c < m.cl_begin + m.cap_env + m.n_acl; ++c) {
+      entries += lc[c];
+      mx_a = std::max(mx_a, lc[c]);
+    }
   }
+  info->list_max_env = mx_env;
+  info->list_max_alch = mx_a;
   info->n_atoms = sys->N;
   info->n_slots = sys->S;
   info->n_clusters = used;

@@ -7,7 +7,8 @@
 //     [cl_begin, cl_begin + cap_env + n_acl): first its environment clusters
 //     (GROMACS-like columns on an x-y grid, each column sorted by z and padded
 //     to a multiple of 8), then its alchemical clusters (solute atoms and
-//     atoms whose restraint depends on lambda).  Per-slot arrays are SoA.
+//     atoms whose restraint depends on lambda), one atom per cluster in
+//     slot 0 so that their lists stay local.  Per-slot arrays are SoA.
 //   * per cluster: bounding box, a list of neighbour-cluster entries
 //     (cluster index | image-shift code << 26) with a fixed capacity per
 //     cluster, and flags.
@@ -34,7 +35,7 @@ struct WalkerMeta {
   int32_t n_atoms;
   int32_t n_a;            // alchemical atoms
   int32_t cap_env;        // environment cluster capacity
-  int32_t n_acl;          // alchemical clusters (static)
+  int32_t n_acl;          // alchemical clusters (= alchemical atoms; static)
   int32_t ncx, ncy;       // column grid
   int32_t col_begin;      // first entry in per-column arrays (ncx*ncy + 1 columns)
   int32_t item_begin;     // first alchemical work item

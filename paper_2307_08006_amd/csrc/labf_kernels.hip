@@ -263,8 +263,11 @@ __global__ void k_rank(Dev<T> d, Range r, int xb) {
   const int col = d.col_of[a];
   const int n = d.col_count[m.col_begin + col];
   const int64_t mb = m.atom_begin + d.col_atom0[m.col_begin + col];
+  // positions are wrapped into the box only at a rebuild: sort on the wrapped
+  // z, as the binning and the scatter use it
   const T *Z = d.X[xb][2];
-  const T z = Z[d.slot_of[a]];
+  const T Bz = (T)m.B[2], Lz = (T)m.L[2];
+  const T z = wrap_pos<T>(Z[d.slot_of[a]], Bz, Lz);
   const int me = (int)(a - m.atom_begin);
   const int kc = d.key_col[a];
   const bool alchcol = col == m.ncx * m.ncy;
@@ -272,7 +275,7 @@ __global__ void k_rank(Dev<T> d, Range r, int xb) {
   for (int t = 0; t < n; ++t) {
     const int bl = d.members[mb + t];
     const int64_t b = m.atom_begin + bl;
-    const T zb = Z[d.slot_of[b]];
+    const T zb = wrap_pos<T>(Z[d.slot_of[b]], Bz, Lz);
     bool less = zb < z || (zb == z && bl < me);
     if (alchcol) {
       const int kb = d.key_col[b];
@@ -280,7 +283,11 @@ __global__ void k_rank(Dev<T> d, Range r, int xb) {
     }
     rank += less ? 1 : 0;
   }
-  d.new_slot[a] = (int32_t)((m.cl_begin + d.col_cl0[m.col_begin + col]) * CL + rank);
+  // environment atoms fill their column's clusters; every alchemical atom
+  // gets a cluster of its own (its list then covers the neighbourhood of one
+  // point however far apart the solute atoms drift)
+  d.new_slot[a] = alchcol ? (int32_t)((m.cl_begin + m.cap_env + rank) * CL)
+                          : (int32_t)((m.cl_begin + d.col_cl0[m.col_begin + col]) * CL + rank);
 }
 
 template <typename T>

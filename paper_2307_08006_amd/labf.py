@@ -69,7 +69,8 @@ class LambdaParams(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("n_slots", C.c_int64), ("n_clusters", C.c_int64),
                 ("n_list_entries", C.c_int64), ("n_walkers", C.c_int32), ("list_cap", C.c_int32),
-                ("precision", C.c_int32), ("uniform_lj", C.c_int32)]
+                ("precision", C.c_int32), ("uniform_lj", C.c_int32),
+                ("list_max_env", C.c_int32), ("list_max_alch", C.c_int32)]
 
 
 _lib = None
