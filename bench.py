@@ -10,8 +10,9 @@ walker: neighbour rebuild (every 10 steps), pair forces and dV/dlambda,
 BAOAB of atoms and lambda, ABF accumulation.
 
 Before timing, the seeded lattice is equilibrated on the GPU (untimed:
-500 steps at dt = 1 fs, gamma = 20/ps, rebuild every step), then the
-production parameters are restored.  Pairs are counted exactly (FP64 decision) by a separate, untimed
+500 steps of one walker at lambda = 0, then 300 steps of the batch at each
+walker's initial lambda, both at dt = 1 fs, gamma = 20/ps, lambda fixed,
+rebuild every step), then the production parameters are restored.  Pairs are counted exactly (FP64 decision) by a separate, untimed
 pass before and after the timed region.
 
 Prints ONE JSON line.
@@ -61,19 +62,19 @@ def _ensure_built():
 
 
 def equilibrate(spec, lam, steps):
-    """Untimed GPU equilibration of a one-walker system: strong friction, a
-    1 fs step and a rebuild every step (the lattice relaxes by up to ~1.5 A
-    in the first steps); returns the spec with the equilibrated
-    coordinates."""
+    """Untimed GPU equilibration at each walker's initial lambda (held
+    fixed, no ABF): strong friction, a 1 fs step and a rebuild every step.
+    Returns the spec with the equilibrated coordinates and velocities."""
     from paper_2307_08006_amd import labf
     eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0, rebuild_interval=1)
-    with labf.System(eq, lam) as s:
+    lm = dataclasses.replace(lam, fixed_lambda=True, abf_on=False)
+    with labf.System(eq, lm) as s:
         s.step(steps)
-        pos, _ = s.read_atoms()
+        pos, vel = s.read_atoms()
         st = s.read_walker_state()
     if st["status"].any() or not np.isfinite(pos).all():
         raise RuntimeError(f"equilibration failed: status {st['status']}")
-    return dataclasses.replace(spec, pos=pos)
+    return dataclasses.replace(spec, pos=pos, vel=vel)
 
 
 def timed_steps(s, n, mode):
@@ -118,6 +119,7 @@ def main(argv=None):
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--single-steps", type=int, default=500)
     ap.add_argument("--equil-steps", type=int, default=500)
+    ap.add_argument("--batch-equil-steps", type=int, default=300)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
@@ -137,6 +139,8 @@ def main(argv=None):
     log(f"equilibrating {args.atoms} atoms for {args.equil_steps} steps")
     spec1 = equilibrate(spec1, lam1, args.equil_steps)
     specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
+    log(f"equilibrating the batch at its initial lambdas for {args.batch_equil_steps} steps")
+    specb = equilibrate(specb, lamb, args.batch_equil_steps)
 
     out = {}
     with labf.System(specb, lamb) as s:
@@ -184,10 +188,12 @@ def main(argv=None):
         "data": "synthetic",
         "config": {
             "workload": f"{W} walkers x {args.atoms}-atom charged LJ fluid (0.1 atoms/A^3, 12 A "
-                        "cutoff, 2 fs, 30-atom decoupled solute), batched: 10-step HIP-graph blocks",
+                        "cutoff, 2 fs, 30-atom decoupled solute held by k=100 restraints), batched: "
+                        "10-step HIP-graph blocks",
             "walkers": W, "atoms_per_walker": args.atoms, "cutoff_A": 12.0, "skin_A": 1.0,
             "rebuild_interval": 10, "abf_bins": 100, "pair_precision": "f32",
             "lambda_precision": "f64", "equilibration_steps_untimed": args.equil_steps,
+            "batch_equilibration_steps_untimed": args.batch_equil_steps,
         },
         "pair_interactions_per_s": pairs_per_step * args.steps / dt_b,
         "pairs_per_step": pairs_per_step,

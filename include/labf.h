@@ -62,7 +62,7 @@ typedef int32_t labf_status;
 #define LABF_E_STATE (-2)        /* call not valid in the current state        */
 #define LABF_E_HIP (-3)          /* HIP runtime error                          */
 #define LABF_E_NONFINITE (-4)    /* non-finite value in a walker               */
-#define LABF_E_SKIN (-5)         /* an atom moved more than r_skin/2 between rebuilds */
+#define LABF_E_SKIN (-5)         /* two largest displacements since the last rebuild exceed r_skin */
 #define LABF_E_UNSUPPORTED (-6)  /* configuration not supported                */
 #define LABF_E_EMPTY_BIN (-7)    /* free-energy readout with an empty bin      */
 #define LABF_E_CAPACITY (-8)     /* neighbour list capacity exceeded           */
@@ -79,7 +79,7 @@ typedef int32_t labf_status;
 /* walker status bits */
 #define LABF_WS_NONFINITE 1u
 #define LABF_WS_REFLECT 2u       /* lambda needed more than one reflection     */
-#define LABF_WS_SKIN 4u
+#define LABF_WS_SKIN 4u          /* the two largest displacements since a rebuild exceed r_skin */
 #define LABF_WS_CAPACITY 8u
 
 /* Static description of a batch of walkers ("Software interface": the
@@ -109,6 +109,10 @@ typedef struct labf_system_desc {
   uint64_t seed;               /* Philox4x32-10 key                               */
   int32_t rebuild_interval;    /* steps between neighbour rebuilds (>= 1; 10 typical) */
   int32_t reserved;            /* must be 0                                       */
+  double r_skin_alch;          /* list buffer of pairs with an alchemical atom (solute atoms and
+                                  atoms with k0 != k1), or 0: r_skin.  A decoupled solute has no
+                                  solvent cage and can move much farther between rebuilds than the
+                                  environment.  r_skin <= r_skin_alch, r_cut + r_skin_alch < L/2 */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF

@@ -73,13 +73,14 @@ struct labf_system {
   int interval = 10;
   bool lam_set = false;
   bool xref_valid = false;
-  int xb = 0, vb = 0;
+  int xb = 0, vb = 0, lb = 0;
   int since_rebuild = 0;
   int64_t host_steps = 0;
   std::vector<int64_t> atom_offset;
   std::vector<WalkerMeta> meta;
   std::vector<int32_t> n_acl_host;
-  hipStream_t cap_stream = nullptr;
+  hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
   DevBufs bufs;
@@ -207,18 +208,21 @@ labf_status validate_desc(const labf_system_desc *d) {
   const bool has_r = d->anchor != nullptr;
   if (has_r != (d->k0 != nullptr) || has_r != (d->k1 != nullptr))
     return fail(nullptr, LABF_E_ARG, "anchor, k0 and k1 must be given together");
-  const double scal[] = {d->r_cut, d->r_skin, d->kT, d->gamma, d->dt, d->coulomb_k, d->accel_unit};
-  if (!finite_all(scal, 7)) return fail(nullptr, LABF_E_ARG, "non-finite scalar parameter");
+  const double scal[] = {d->r_cut, d->r_skin, d->r_skin_alch, d->kT, d->gamma, d->dt, d->coulomb_k, d->accel_unit};
+  if (!finite_all(scal, 8)) return fail(nullptr, LABF_E_ARG, "non-finite scalar parameter");
+  if (d->r_skin_alch != 0.0 && d->r_skin_alch < d->r_skin)
+    return fail(nullptr, LABF_E_ARG, "r_skin_alch must be 0 or >= r_skin");
   if (!(d->r_cut > 0) || d->r_skin < 0 || d->kT < 0 || d->gamma < 0 || !(d->dt > 0) || d->coulomb_k < 0 ||
       !(d->accel_unit > 0))
     return fail(nullptr, LABF_E_ARG, "scalar parameter out of range");
   if (d->rebuild_interval < 1 || d->rebuild_interval > 1000) return fail(nullptr, LABF_E_ARG, "rebuild_interval out of range");
-  const double rl = d->r_cut + d->r_skin;
+  const double rl = d->r_cut + std::max(d->r_skin, d->r_skin_alch);
   for (int w = 0; w < d->n_walkers; ++w)
     for (int k = 0; k < 3; ++k) {
       const double L = d->box[3 * w + k];
       if (!std::isfinite(L) || !(L > 0)) return fail(nullptr, LABF_E_ARG, "box edges must be finite and > 0");
-      if (!(rl < 0.5 * L)) return fail(nullptr, LABF_E_ARG, "r_cut + r_skin must be < L/2 on every edge");
+      if (!(rl < 0.5 * L))
+        return fail(nullptr, LABF_E_ARG, "r_cut + max(r_skin, r_skin_alch) must be < L/2 on every edge");
       if (L > 1e7) return fail(nullptr, LABF_E_ARG, "box edge too large");
     }
   if (!finite_all(d->pos, 3 * N)) return fail(nullptr, LABF_E_ARG, "non-finite position");
@@ -267,19 +271,23 @@ template <typename T>
 labf_status alloc_items(labf_system *s) {
   Dev<T> &d = s->dev<T>();
   s->item_bufs.release();
-  std::vector<int32_t> item_walker;
+  std::vector<int32_t> item_walker, alch_cluster;
   int64_t ib = 0;
   for (int w = 0; w < s->W; ++w) {
     WalkerMeta &m = s->meta[w];
     m.item_begin = (int32_t)ib;
-    m.item_cap = m.n_acl * ((s->list_cap + CL - 1) / CL) + 1;
-    for (int t = 0; t < m.item_cap; ++t) item_walker.push_back(w);
+    m.item_cap = std::max(1, m.n_acl);
+    for (int t = 0; t < m.item_cap; ++t) {
+      item_walker.push_back(w);
+      alch_cluster.push_back(t < m.n_acl ? (int32_t)(m.cl_begin + m.cap_env + t) : -1);
+    }
     ib += m.item_cap;
   }
-  if (ib > 0x7FFFFFF0LL) return fail(s, LABF_E_UNSUPPORTED, "too many alchemical work items");
+  if (ib > 0x7FFFFFF0LL) return fail(s, LABF_E_UNSUPPORTED, "too many alchemical atoms");
   s->I = ib;
   HIPCHK(s, upload(s->item_bufs, &d.item_walker, item_walker.data(), item_walker.size()));
-  HIPCHK(s, dalloc(s->item_bufs, &d.items, (size_t)ib));
+  HIPCHK(s, upload(s->item_bufs, &d.alch_cluster, alch_cluster.data(), alch_cluster.size()));
+  HIPCHK(s, dalloc(s->item_bufs, &d.item_force, (size_t)ib * 3));
   HIPCHK(s, dalloc(s->item_bufs, &d.item_dudl, (size_t)ib));
   HIPCHK(s, dalloc(s->item_bufs, &d.item_energy, (size_t)ib * 5));
   HIPCHK(s, dalloc(s->item_bufs, &d.list, (size_t)s->C * s->list_cap));
@@ -309,11 +317,13 @@ template <typename T>
 labf_status do_step(labf_system *s, int mode, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
   if (mode == LABF_MODE_PLAIN) {
-    for (int w = 0; w < s->W; ++w) HIPCHK(s, Launch<T>::step(d, walker_range(s, w), s->xb, s->vb, st));
+    for (int w = 0; w < s->W; ++w)
+      HIPCHK(s, Launch<T>::step(d, walker_range(s, w), s->xb, s->vb, s->lb, st));
   } else {
-    HIPCHK(s, Launch<T>::step(d, full_range(s), s->xb, s->vb, st));
+    HIPCHK(s, Launch<T>::step(d, full_range(s), s->xb, s->vb, s->lb, st));
   }
   s->xb ^= 1;
+  s->lb ^= 1;
   s->since_rebuild += 1;
   s->host_steps += 1;
   return LABF_OK;
@@ -323,18 +333,32 @@ labf_status do_step(labf_system *s, int mode, hipStream_t st) {
 template <typename T>
 labf_status graph_block(labf_system *s, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
-  const int key = s->xb * 2 + s->vb + (s->xref_valid ? 4 : 0);
+  const int key = s->xb * 2 + s->vb + (s->xref_valid ? 4 : 0) + s->lb * 8;
   auto it = s->graphs.find(key);
   if (it == s->graphs.end()) {
-    if (!s->cap_stream) HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    if (!s->cap_stream) {
+      HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+      HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream2, hipStreamNonBlocking));
+      HIPCHK(s, hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+      HIPCHK(s, hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+    }
     HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    int xb = s->xb, vb = s->vb;
+    int xb = s->xb, vb = s->vb, lb = s->lb;
     hipError_t e = Launch<T>::rebuild(d, full_range(s), xb, vb, s->xref_valid ? 1 : 0, s->cap_stream);
     xb ^= 1;
     vb ^= 1;
+    // each step: the alchemical kernel (second stream) runs beside the
+    // environment kernel; they read the same positions and write disjoint
+    // slots, lambda and step counters are double-buffered
     for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
-      e = Launch<T>::step(d, full_range(s), xb, vb, s->cap_stream);
+      e = hipEventRecord(s->fork_ev, s->cap_stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
+      if (e == hipSuccess) e = Launch<T>::step_alch(d, full_range(s), xb, vb, lb, s->cap_stream2);
+      if (e == hipSuccess) e = Launch<T>::step_env(d, full_range(s), xb, vb, lb, s->cap_stream);
+      if (e == hipSuccess) e = hipEventRecord(s->join_ev, s->cap_stream2);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, s->join_ev, 0);
       xb ^= 1;
+      lb ^= 1;
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
@@ -350,7 +374,10 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
   s->xb ^= 1;
   s->vb ^= 1;
   s->xref_valid = true;
-  for (int i = 0; i < s->interval; ++i) s->xb ^= 1;
+  for (int i = 0; i < s->interval; ++i) {
+    s->xb ^= 1;
+    s->lb ^= 1;
+  }
   s->since_rebuild = s->interval;
   s->host_steps += s->interval;
   return LABF_OK;
@@ -392,6 +419,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   if (desc->anchor) anc_grid.resize(3 * N);
   int64_t cl = 0, col = 0, env = 0;
   const double rl = desc->r_cut + desc->r_skin;
+  const double rla = desc->r_cut + std::max(desc->r_skin, desc->r_skin_alch);
   for (int w = 0; w < W; ++w) {
     WalkerMeta &m = s->meta[w];
     std::memset(&m, 0, sizeof(m));
@@ -406,7 +434,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       const double L0 = desc->box[3 * w + k];
       m.B[k] = pow2_at_least(2.0 * L0);
       m.L[k] = grid_edge<T>(L0, m.B[k]);
-      if (!(rl < 0.5 * m.L[k])) return fail(nullptr, LABF_E_ARG, "r_list >= L/2 after rounding the box");
+      if (!(rla < 0.5 * m.L[k])) return fail(nullptr, LABF_E_ARG, "r_list >= L/2 after rounding the box");
       vol *= m.L[k];
     }
     const double rho = (double)std::max<int64_t>(nenv, 1) / vol;
@@ -442,6 +470,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.uniform_lj = uniform ? 1 : 0;
   d.r_cut = desc->r_cut;
   d.r_list = rl;
+  d.r_list_a = rla;
   d.dt = desc->dt;
   d.kT = desc->kT;
   d.gamma = desc->gamma;
@@ -493,6 +522,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, dalloc(b, &d.key_col, N));
   HIPCHK(s, dalloc(b, &d.members, N));
   HIPCHK(s, dalloc(b, &d.xref, 3 * N));
+  HIPCHK(s, dalloc(b, &d.disp, N));
   HIPCHK(s, dalloc(b, &d.col_count, s->K));
   HIPCHK(s, dalloc(b, &d.col_fill, s->K));
   HIPCHK(s, dalloc(b, &d.col_atom0, s->K));
@@ -508,10 +538,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, dalloc(b, &d.aim, s->S));
   HIPCHK(s, dalloc(b, &d.nsd, s->S));
   HIPCHK(s, dalloc(b, &d.rk, s->S));
-  for (int k = 0; k < 3; ++k) {
-    HIPCHK(s, dalloc(b, &d.anc[k], s->S));
-    HIPCHK(s, dalloc(b, &d.fext[k], s->S));
-  }
+  for (int k = 0; k < 3; ++k) HIPCHK(s, dalloc(b, &d.anc[k], s->S));
   HIPCHK(s, dalloc(b, &d.q64, s->S));
   HIPCHK(s, dalloc(b, &d.sig64, s->S));
   HIPCHK(s, dalloc(b, &d.eps64, s->S));
@@ -523,19 +550,17 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, dalloc(b, &d.bbox, 6 * s->C));
   HIPCHK(s, dalloc(b, &d.cl_col, s->C));
   HIPCHK(s, dalloc(b, &d.list_count, s->C));
-  HIPCHK(s, dalloc(b, &d.has_ext, s->C));
+  HIPCHK(s, dalloc(b, &d.list_nenv, s->C));
   HIPCHK(s, dalloc(b, &d.cl_energy, 2 * s->C));
   HIPCHK(s, dalloc(b, &d.n_env, W));
-  HIPCHK(s, dalloc(b, &d.n_items, W));
   HIPCHK(s, dalloc(b, &d.ticket, W));
   HIPCHK(s, dalloc(b, &d.gticket, 1));
   HIPCHK(s, dalloc(b, &d.status, W));
-  HIPCHK(s, dalloc(b, &d.lambda, W));
+  HIPCHK(s, dalloc(b, &d.lambda, 2 * W));
   HIPCHK(s, dalloc(b, &d.p_lambda, W));
   HIPCHK(s, dalloc(b, &d.dudl, W));
   HIPCHK(s, dalloc(b, &d.bias, W));
-  HIPCHK(s, dalloc(b, &d.step, W));
-  HIPCHK(s, dalloc(b, &d.env_step, W));
+  HIPCHK(s, dalloc(b, &d.step, 2 * W));
   HIPCHK(s, dalloc(b, &d.start_step, 1));
   HIPCHK(s, dalloc(b, &d.energy, 5 * W));
   HIPCHK(s, dalloc(b, &d.pair_n, 2 * W));
@@ -594,7 +619,6 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     if (rc != LABF_OK) return rc;
   }
   HIPCHK(s, hipStreamSynchronize(st));
-  s->xref_valid = false;  // displacement reference starts with the first step
   s->since_rebuild = 0;
   return LABF_OK;
 }
@@ -642,7 +666,7 @@ labf_status set_lambda_impl(labf_system *s, const labf_lambda_params *p, hipStre
   HIPCHK(s, hipMemcpyAsync(s->lam_stage, p->lambda0, sizeof(double) * s->W, hipMemcpyHostToDevice, st));
   if (p->p_lambda0)
     HIPCHK(s, hipMemcpyAsync(s->lam_stage + s->W, p->p_lambda0, sizeof(double) * s->W, hipMemcpyHostToDevice, st));
-  HIPCHK(s, launch_init_lambda<T>(d, s->lam_stage, p->p_lambda0 ? s->lam_stage + s->W : nullptr, st));
+  HIPCHK(s, launch_init_lambda<T>(d, s->lam_stage, p->p_lambda0 ? s->lam_stage + s->W : nullptr, s->lb, st));
   HIPCHK(s, hipStreamSynchronize(st));
   drop_graphs(s);
   s->host_steps = 0;
@@ -684,7 +708,7 @@ labf_status eval_impl(labf_system *s, double *forces, double *energy, double *du
   Dev<T> &d = s->dev<T>();
   labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
   if (rc != LABF_OK) return rc;
-  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, st));
+  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, st));
   if (forces) {
     HIPCHK(s, Launch<T>::gather_forces(d, s->stage, st));
     HIPCHK(s, hipMemcpyAsync(forces, s->stage, sizeof(double) * 3 * s->N, hipMemcpyDeviceToHost, st));
@@ -797,11 +821,12 @@ labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) 
   }
   HIPCHK(s, hipEventRecord(ev[1], st));
   for (int64_t i = 0; i < n; ++i) {
-    HIPCHK(s, Launch<T>::step_alch(d, full_range(s), s->xb, s->vb, st));
+    HIPCHK(s, Launch<T>::step_alch(d, full_range(s), s->xb, s->vb, s->lb, st));
     HIPCHK(s, hipEventRecord(ev[2 + 2 * i], st));
-    HIPCHK(s, Launch<T>::step_env(d, full_range(s), s->xb, s->vb, st));
+    HIPCHK(s, Launch<T>::step_env(d, full_range(s), s->xb, s->vb, s->lb, st));
     HIPCHK(s, hipEventRecord(ev[3 + 2 * i], st));
     s->xb ^= 1;
+    s->lb ^= 1;
     s->since_rebuild += 1;
     s->host_steps += 1;
   }
@@ -839,10 +864,9 @@ labf_status write_atoms_impl(labf_system *s, const double *pos, const double *ve
   }
   if (vel) HIPCHK(s, hipMemcpy(s->stage2, vel, sizeof(double) * 3 * s->N, hipMemcpyHostToDevice));
   HIPCHK(s, Launch<T>::scatter_atoms(d, s->xb, s->vb, pos ? s->stage : nullptr, vel ? s->stage2 : nullptr, st));
-  s->xref_valid = false;
+  s->xref_valid = false;  // positions replaced: nothing to check at this rebuild
   labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
   if (rc != LABF_OK) return rc;
-  s->xref_valid = false;
   return start_fresh_sequence<T>(s, st);
 }
 
@@ -978,14 +1002,14 @@ labf_status labf_read_walker_state(labf_system *sys, double *lambda, double *p_l
   HIPCHK(sys, hipStreamSynchronize(st));
   if (sys->precision == LABF_FP64) {
     const Dev<double> &d = sys->dd;
-    HIPCHK(sys, get(lambda, d.lambda));
+    HIPCHK(sys, get(lambda, d.lambda + sys->lb * W));
     HIPCHK(sys, get(p_lambda, d.p_lambda));
     HIPCHK(sys, get(dudl, d.dudl));
     HIPCHK(sys, get(bias, d.bias));
     HIPCHK(sys, get(status, d.status));
   } else {
     const Dev<float> &d = sys->df;
-    HIPCHK(sys, get(lambda, d.lambda));
+    HIPCHK(sys, get(lambda, d.lambda + sys->lb * W));
     HIPCHK(sys, get(p_lambda, d.p_lambda));
     HIPCHK(sys, get(dudl, d.dudl));
     HIPCHK(sys, get(bias, d.bias));
@@ -1107,6 +1131,9 @@ void labf_destroy_system(labf_system *sys) {
   (void)hipDeviceSynchronize();
   drop_graphs(sys);
   if (sys->cap_stream) (void)hipStreamDestroy(sys->cap_stream);
+  if (sys->cap_stream2) (void)hipStreamDestroy(sys->cap_stream2);
+  if (sys->fork_ev) (void)hipEventDestroy(sys->fork_ev);
+  if (sys->join_ev) (void)hipEventDestroy(sys->join_ev);
   sys->item_bufs.release();
   sys->bufs.release();
   delete sys;

@@ -26,7 +26,6 @@ constexpr int WAVE = 64;              // CDNA wavefront
 constexpr int SHIFT_BITS = 26;        // cluster index bits in a list entry
 constexpr uint32_t CL_MASK = (1u << SHIFT_BITS) - 1u;
 constexpr int SHIFT_ZERO = 13;        // code of the (0,0,0) image
-constexpr double FIX_SCALE = 1099511627776.0;  // 2^40: fixed-point force unit
 constexpr uint32_t LAMBDA_ATOM = 0xFFFFFFFFu;  // noise stream of lambda
 
 struct WalkerMeta {
@@ -38,8 +37,9 @@ struct WalkerMeta {
   int32_t n_acl;          // alchemical clusters (= alchemical atoms; static)
   int32_t ncx, ncy;       // column grid
   int32_t col_begin;      // first entry in per-column arrays (ncx*ncy + 1 columns)
-  int32_t item_begin;     // first alchemical work item
-  int32_t item_cap;
+  int32_t item_begin;     // first entry of this walker in the alchemical block table
+  int32_t item_cap;       // max(1, n_acl) blocks (a walker without alchemical atoms
+                          // still gets one block, which runs its lambda tail)
   int32_t env_item_begin; // first entry in the environment work table
   double L[3];            // box edges
   double B[3];            // storage offset (power of two >= 2L)
@@ -65,7 +65,7 @@ struct Dev {
   int64_t n_atoms, n_slots, n_clusters;
   int32_t list_cap;
   int32_t uniform_lj;
-  double r_cut, r_list, dt, kT, gamma, coulomb_k, accel;
+  double r_cut, r_list, r_list_a, dt, kT, gamma, coulomb_k, accel;
   double c1;                // exp(-gamma dt)
   uint64_t seed;
   T rc2, irc, irc2;         // r_cut^2, 1/r_cut, 1/r_cut^2 (storage precision)
@@ -77,11 +77,13 @@ struct Dev {
   const int32_t *cl_walker;     // [C]
   const int32_t *env_table;     // [sum cap_env] -> cluster
   const int32_t *item_walker;   // [sum item_cap]
+  const int32_t *alch_cluster;  // [sum item_cap] alchemical cluster of each block, or -1
   // --- caller-order atom data
   const double *a_pos0;         // [N][3] upload staging (B-offset, rounded)
   const double *a_q, *a_sig, *a_eps, *a_mass, *a_k0, *a_k1, *a_anchor;  // anchor [N][3]
   const uint8_t *a_sol, *a_alch;
   int32_t *slot_of, *new_slot, *col_of, *key_col, *members;
+  float *disp;                  // [N] displacement since the last rebuild (rounded up)
   T *xref;                      // [3][N] positions at the last rebuild
   // --- per column
   int32_t *col_count, *col_fill, *col_atom0, *col_cl0;
@@ -97,26 +99,26 @@ struct Dev {
   double *q64, *sig64, *eps64, *k0_64, *k1_64;
   uint8_t *sol;                 // is_solute per slot
   int32_t *orig;                // walker-local atom index or -1
-  unsigned long long *fext[3];  // fixed-point force accumulators (2^-40 units)
   double *fout;                 // [3][S] forces of an evaluation
   // --- per cluster
   double *bbox;                 // [C][6] lo xyz, hi xyz
   int32_t *cl_col;              // column of an environment cluster
-  int32_t *list_count;
+  int32_t *list_count;          // entries in use (environment, then alchemical)
+  int32_t *list_nenv;           // environment-cluster entries of an environment list
   uint32_t *list;               // [C * list_cap]
-  uint8_t *has_ext;
   double *cl_energy;            // [C][2] env-env, restraint (evaluation)
-  // --- alchemical work items
-  int4 *items;                  // (cluster, e0, e1, walker)
-  double *item_dudl;            // [items]
-  double *item_energy;          // [items][5]
+  // --- alchemical blocks (one per alchemical atom)
+  double *item_force;           // [I][3] force on the block's atom
+  double *item_dudl;            // [I]
+  double *item_energy;          // [I][5]
   // --- per walker dynamic state
-  int32_t *n_env, *n_items;
+  int32_t *n_env;
   uint32_t *ticket;             // per walker
   uint32_t *gticket;            // [1]
   uint32_t *status;
-  double *lambda, *p_lambda, *dudl, *bias;
-  int64_t *step, *env_step;     // per walker
+  double *lambda;               // [2][W]: read [lb], written [lb ^ 1] by the tail
+  double *p_lambda, *dudl, *bias;
+  int64_t *step;                // [2][W], same double buffering
   int64_t *start_step;          // [1] step at which the BAOAB sequence (re)started
   double *energy;               // [W][5] evaluation output (alchemical side)
   int64_t *bin_count;           // [nbins]
@@ -144,10 +146,13 @@ template <typename T>
 struct Launch {
   static hipError_t rebuild(const Dev<T> &d, const Range &r, int xb, int vb, int check_disp,
                             hipStream_t s);
-  static hipError_t step(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
-  static hipError_t step_alch(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
-  static hipError_t step_env(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
-  static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s);
+  // xb, vb: position/velocity buffers; lb: lambda/step buffer (flips every step)
+  static hipError_t step(const Dev<T> &d, const Range &r, int xb, int vb, int lb, hipStream_t s);
+  static hipError_t step_alch(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                              hipStream_t s);
+  static hipError_t step_env(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                             hipStream_t s);
+  static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, hipStream_t s);
   static hipError_t export_pairs(const Dev<T> &d, const Range &r, int xb, int mode,
                                  hipStream_t s);
   static hipError_t init_velocities(const Dev<T> &d, int vb, hipStream_t s);
@@ -160,7 +165,8 @@ struct Launch {
 
 // lam0 / p0: device arrays [W]; p0 may be NULL (Maxwell-Boltzmann draw).
 template <typename T>
-hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, hipStream_t s);
+hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, int lb,
+                              hipStream_t s);
 
 hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);

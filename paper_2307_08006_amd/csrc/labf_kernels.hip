@@ -1,25 +1,26 @@
 // labf_kernels.hip -- gfx950 kernels of the lambda-ABF alchemical nonbonded step.
 //
-// Per step (one launch pair, captured 10 steps at a time in a HIP graph):
-//   k_alch  : pairs of alchemical clusters (solute atoms and atoms with a
-//             lambda-dependent restraint) with every neighbour, in FP64:
-//             soft-core LJ scaled by c_v(lambda), shifted-force Coulomb scaled
-//             by c_e(lambda) ("Alchemical pathway"), dV/dlambda, forces on the
-//             alchemical atoms and the reaction on environment atoms
-//             (fixed-point 64-bit accumulation: order-independent).  The last
-//             work item of a walker runs the walker tail: restraints, BAOAB of
-//             its alchemical atoms, the ABF sample and bias, and the BAOAB step
-//             of (lambda, p_lambda) with reflection (Eq. lambda-abf); the last
+// Per step (two independent launches, run concurrently inside a HIP graph of
+// 10-step blocks):
+//   k_env   : environment atoms.  Environment-environment pairs in the storage
+//             precision (plain LJ + shifted-force Coulomb) over a full
+//             cluster-pair list (no atomics), 8 i-atoms held in scalar
+//             registers against 64 j-atoms in the lanes; then the few
+//             alchemical partners of the cluster (soft-core LJ at c_v(lambda),
+//             Coulomb at c_e(lambda), "Alchemical pathway"); the epilogue adds
+//             restraints and runs BAOAB for the cluster's atoms.
+//   k_alch  : alchemical atoms (solute atoms and atoms with a lambda-dependent
+//             restraint), one 256-thread block per atom, FP64: forces,
+//             dV/dlambda and energies reduced in a fixed order.  The block that
+//             completes a walker runs its tail: restraints, BAOAB of its
+//             alchemical atoms, the ABF sample and bias, and the BAOAB step of
+//             (lambda, p_lambda) with reflection (Eq. lambda-abf); the last
 //             walker merges the walkers' ABF samples in walker order
 //             ("Orthogonal space sampling").
-//   k_env   : environment-environment pairs in the storage precision: plain
-//             LJ + shifted-force Coulomb, full cluster-pair list (no atomics),
-//             8 i-atoms held in scalar registers against 64 j-atoms in the
-//             lanes; the epilogue adds the reactions and restraints and runs
-//             BAOAB for the cluster's atoms.
 // Every rebuild_interval steps the neighbour structure is rebuilt: columns
 // on an x-y grid, z-sorted, cut into clusters of 8, and per-cluster lists of
-// neighbour clusters within r_list = r_cut + r_skin.
+// neighbour clusters within r_list = r_cut + r_skin (r_cut + r_skin_alch for
+// pairs with an alchemical atom).
 #include "labf_impl.h"
 
 #include <math.h>
@@ -119,13 +120,6 @@ __device__ __forceinline__ double min_image(double d, double L) {
   return d;
 }
 
-__device__ __forceinline__ unsigned long long to_fix(double f) {
-  return (unsigned long long)(long long)llrint(f * FIX_SCALE);
-}
-__device__ __forceinline__ double from_fix(unsigned long long v) {
-  return (double)(long long)v * (1.0 / FIX_SCALE);
-}
-
 // XCD-aware block order: consecutive logical blocks (neighbouring clusters,
 // sharing j-data) land on the same XCD and its L2.  Grid = 8 * ceil(nb / 8).
 __device__ __forceinline__ int xcd_block(int nb) {
@@ -164,8 +158,8 @@ __global__ void k_key(Dev<T> d, Range r, int xb, int check) {
       const double dd = min_image(x[k] - (double)d.xref[(int64_t)k * d.n_atoms + a], m.L[k]);
       r2 += dd * dd;
     }
-    const double half_skin = 0.5 * (d.r_list - d.r_cut);
-    if (r2 > half_skin * half_skin) atomicOr(&d.status[w], 4u);
+    // rounded up so that the skin test stays conservative
+    d.disp[a] = finite ? __double2float_ru(sqrt(r2)) : INFINITY;
   }
   // clamp in floating point before converting (non-finite or far positions)
   const double fx = fmin(fmax(floor((x[0] - m.B[0]) / m.cw[0]), 0.0), (double)(m.ncx - 1));
@@ -177,6 +171,56 @@ __global__ void k_key(Dev<T> d, Range r, int xb, int check) {
   d.key_col[a] = kc;
   d.col_of[a] = col;
   atomicAdd(&d.col_count[m.col_begin + col], 1);
+}
+
+// Two largest displacements of a pair (m1 >= m2) merged with another pair.
+__device__ __forceinline__ void top2_merge(float &m1, float &m2, float p1, float p2) {
+  const float n2 = fmaxf(fminf(m1, p1), m1 >= p1 ? m2 : p2);
+  m1 = fmaxf(m1, p1);
+  m2 = n2;
+}
+
+// One block per walker: a pair that was farther than r_list apart at the last
+// rebuild can have come within r_cut only if the displacements of its two
+// atoms add up to more than the skin.  Environment pairs are tested against
+// r_skin with the two largest environment displacements, pairs with an
+// alchemical atom against r_skin_alch with the largest alchemical displacement
+// plus the largest other one.
+template <typename T>
+__global__ __launch_bounds__(256) void k_skin(Dev<T> d, Range r) {
+  __shared__ float sm[4][4];
+  const int w = r.w0 + blockIdx.x;
+  const WalkerMeta &m = d.meta[w];
+  float e1 = 0.f, e2 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int i = threadIdx.x; i < m.n_atoms; i += blockDim.x) {
+    const int64_t a = m.atom_begin + i;
+    const float v = d.disp[a];
+    if (d.a_alch[a]) top2_merge(a1, a2, v, 0.f);
+    else top2_merge(e1, e2, v, 0.f);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    top2_merge(e1, e2, __shfl_xor(e1, o, WAVE), __shfl_xor(e2, o, WAVE));
+    top2_merge(a1, a2, __shfl_xor(a1, o, WAVE), __shfl_xor(a2, o, WAVE));
+  }
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    sm[wv][0] = e1;
+    sm[wv][1] = e2;
+    sm[wv][2] = a1;
+    sm[wv][3] = a2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      top2_merge(e1, e2, sm[k][0], sm[k][1]);
+      top2_merge(a1, a2, sm[k][2], sm[k][3]);
+    }
+    const double skin = d.r_list - d.r_cut, skin_a = d.r_list_a - d.r_cut;
+    const bool bad = (double)e1 + (double)e2 > skin || (double)a1 + (double)fmaxf(e1, a2) > skin_a ||
+                     !(e1 <= INFINITY) || !(a1 <= INFINITY);
+    if (bad) atomicOr(&d.status[w], 4u);
+  }
 }
 
 // Block-wide exclusive scan of one int per thread (256 threads).
@@ -361,7 +405,6 @@ template <typename T>
 __global__ void k_bbox(Dev<T> d, Range r, int xb) {
   const int64_t c = r.c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= r.c0 + r.cn) return;
-  d.has_ext[c] = 0;
   const int w = d.cl_walker[c];
   const WalkerMeta &m = d.meta[w];
   if (!cluster_used(m, d.n_env[w], c)) return;
@@ -412,9 +455,13 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
   }
   const int cap = d.list_cap;
   uint32_t *out = d.list + c * (int64_t)cap;
-  const double rl = d.r_list * (1.0 + 1e-7);
+  // environment pairs within r_list; pairs with an alchemical atom within
+  // r_list_a (an alchemical cluster lists everything with r_list_a)
+  const double rl = (isA ? d.r_list_a : d.r_list) * (1.0 + 1e-7);
   const double rl2 = rl * rl;
-  int cnt = 0;
+  const double rla = d.r_list_a * (1.0 + 1e-7);
+  const double rla2 = rla * rla;
+  int cnt = 0, nenv = 0;
   if (!isA) {
     if (lane == 0) out[0] = (uint32_t)c | ((uint32_t)SHIFT_ZERO << SHIFT_BITS);
     cnt = 1;
@@ -471,13 +518,16 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
           if (pass) {
             const int pos = cnt + pre;
             if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
-            if (isA) d.has_ext[J] = 1;
           }
           cnt += __popcll(bal);
         }
       }
     }
-    if (isA) {
+    nenv = cnt;
+    // alchemical atoms (one per cluster) within r_list, every image: an
+    // environment cluster computes their forces on its own atoms, an
+    // alchemical cluster its alchemical-alchemical pairs
+    {
       const int64_t A0 = m.cl_begin + m.cap_env;
       for (int t0 = 0; t0 < m.n_acl * 27; t0 += WAVE) {
         const int t = t0 + lane;
@@ -494,7 +544,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
             const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
             const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
             const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
-            pass = ax * ax + ay * ay + az * az < rl2;
+            pass = ax * ax + ay * ay + az * az < rla2;
           }
         }
         const unsigned long long bal = __ballot(pass);
@@ -506,36 +556,9 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
   }
   if (lane == 0) {
     d.list_count[c] = cnt < cap ? cnt : cap;
+    d.list_nenv[c] = nenv < cap ? nenv : cap;
     if (cnt > cap) atomicOr(&d.status[w], 8u);
   }
-}
-
-// Alchemical work items: each alchemical cluster's list cut into chunks of
-// 8 entries; a walker without alchemical atoms gets one empty item so that
-// its lambda tail still runs.
-template <typename T>
-__global__ void k_items(Dev<T> d, Range r) {
-  const int w = r.w0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= r.w0 + r.wn) return;
-  const WalkerMeta &m = d.meta[w];
-  int n = 0;
-  for (int t = 0; t < m.n_acl; ++t) {
-    const int64_t c = m.cl_begin + m.cap_env + t;
-    const int cnt = d.list_count[c];
-    for (int e0 = 0; e0 < cnt; e0 += CL) {
-      if (n < m.item_cap) d.items[m.item_begin + n] = make_int4((int)c, e0, min(e0 + CL, cnt), w);
-      ++n;
-    }
-  }
-  if (n == 0) {
-    d.items[m.item_begin] = make_int4(-1, 0, 0, w);
-    n = 1;
-  }
-  if (n > m.item_cap) {
-    atomicOr(&d.status[w], 8u);
-    n = m.item_cap;
-  }
-  d.n_items[w] = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -592,10 +615,43 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
   }
 }
 
+// Forces on environment atoms from alchemical atoms (storage precision):
+// soft-core LJ at coupling cv with A = alpha (1 - cv)^p and shifted-force
+// Coulomb at ce for solute partners, plain terms (c = 1) for the others.
+// Energies and dV/dlambda of these pairs are accounted on the alchemical side.
 template <typename T>
-__device__ __forceinline__ void integrate_atom(const Dev<T> &d, const WalkerMeta &m, int64_t s,
-                                               int xb, int vb, int w, int64_t step, bool pending,
-                                               const double F[3]) {
+__device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL],
+                                               const T (&yi)[CL], const T (&zi)[CL],
+                                               const T (&qi)[CL], const T (&ai)[CL],
+                                               const T (&bi)[CL], T xj, T yj, T zj, T qj, T aj,
+                                               T bj, bool alch, bool valid, T cv, T ce, T Asc,
+                                               T (&fx)[CL], T (&fy)[CL], T (&fz)[CL]) {
+  const T c = alch ? cv : (T)1, e = alch ? ce : (T)1, A = alch ? Asc : (T)0;
+#pragma unroll
+  for (int ii = 0; ii < CL; ++ii) {
+    const T dx = xj - xi[ii], dy = yj - yi[ii], dz = zj - zi[ii];
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = valid && r2 < d.rc2;
+    const T rinv = rsq(r2);
+    const T r2inv = rinv * rinv;
+    const T sg = ai[ii] + aj;
+    const T t = r2 / (sg * sg);
+    const T u = t * t * t;
+    const T sc = (T)1 / (A + u);
+    const T bij = bi[ii] * bj;
+    T flj = bij * c * ((T)2 * sc - (T)1) * sc * sc * u * r2inv;
+    flj = bij != (T)0 ? flj : (T)0;
+    const T fc = e * qi[ii] * qj * rinv * (r2inv - d.irc2);
+    const T fr = in ? flj + fc : (T)0;
+    fx[ii] -= fr * dx;
+    fy[ii] -= fr * dy;
+    fz[ii] -= fr * dz;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int xb, int vb, int w,
+                                               int64_t step, bool pending, const double F[3]) {
   const T h = (T)(0.5 * d.dt);
   const T c1 = (T)d.c1;
   const T im = d.aim[s], sd = d.nsd[s];
@@ -619,11 +675,11 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, const WalkerMeta
 }
 
 template <typename T, bool LB, bool ENERGY, bool INTEG>
-__global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) {
+__global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   const int nb = (int)((r.en + 3) >> 2);
-  const int lb = xcd_block(nb);
-  if (lb >= nb) return;
-  const int64_t e = r.e0 + (int64_t)lb * 4 + uni(threadIdx.x >> 6);
+  const int lblk = xcd_block(nb);
+  if (lblk >= nb) return;
+  const int64_t e = r.e0 + (int64_t)lblk * 4 + uni(threadIdx.x >> 6);
   if (e >= r.e0 + r.en) return;
   const int64_t c = d.env_table[e];
   const int w = d.cl_walker[c];
@@ -632,6 +688,9 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
   const int lane = lane_id();
   const int64_t s0 = c * CL;
   const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
+  const int n = d.list_count[c];
+  const int nenv = d.list_nenv[c];
+  const bool need_lj = LB || nenv < n;
   T xi[CL], yi[CL], zi[CL], qi[CL], ai[CL], bi[CL];
   int vmask = 0;
 #pragma unroll
@@ -641,8 +700,8 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
     yi[ii] = X1[s0 + ii];
     zi[ii] = X2[s0 + ii];
     qi[ii] = d.q[s0 + ii];
-    ai[ii] = LB ? d.lja[s0 + ii] : (T)0;
-    bi[ii] = LB ? d.ljb[s0 + ii] : (T)0;
+    ai[ii] = need_lj ? d.lja[s0 + ii] : (T)0;
+    bi[ii] = need_lj ? d.ljb[s0 + ii] : (T)0;
   }
   T fx[CL], fy[CL], fz[CL];
 #pragma unroll
@@ -650,13 +709,12 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
   double eacc = 0.0;
   const T Lx = (T)m.L[0], Ly = (T)m.L[1], Lz = (T)m.L[2];
   const T far = (T)(8.0 * m.B[0]);
-  const int n = d.list_count[c];
   const uint32_t *lst = d.list + c * (int64_t)d.list_cap;
-  for (int e0 = 0; e0 < n; e0 += CL) {
+  for (int e0 = 0; e0 < nenv; e0 += CL) {
     const int ee = e0 + (lane >> 3);
     T xj = far, yj = far, zj = far, qj = (T)0, aj = (T)0, bj = (T)0;
     int js = -1;
-    if (ee < n) {
+    if (ee < nenv) {
       const uint32_t ent = lst[ee];
       const int64_t J = ent & CL_MASK;
       const int code = (int)(ent >> SHIFT_BITS);
@@ -677,6 +735,35 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
       env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
                                       vmask, fx, fy, fz, eacc);
   }
+  if (nenv < n) {
+    // alchemical partners: one atom per alchemical cluster (slot 0), 64 per pass
+    const LamParams &lp = d.lp;
+    double ce, dce, cv, dcv;
+    channel(d.lambda[lb * d.n_walkers + w], lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
+    channel(d.lambda[lb * d.n_walkers + w], lp.vdw_start, lp.vdw_end, lp.direction, lp.hi, cv, dcv);
+    const T Asc = (T)(lp.sc_alpha * pow(1.0 - cv, (double)lp.sc_power));
+    for (int e0 = nenv; e0 < n; e0 += WAVE) {
+      const int ee = e0 + lane;
+      T xj = far, yj = far, zj = far, qj = (T)0, aj = (T)1, bj = (T)0;
+      bool alch = false, valid = false;
+      if (ee < n) {
+        const uint32_t ent = lst[ee];
+        const int64_t J = ent & CL_MASK;
+        const int code = (int)(ent >> SHIFT_BITS);
+        const int64_t js = J * CL;
+        valid = d.orig[js] >= 0;
+        xj = X0[js] + (T)(code / 9 - 1) * Lx;
+        yj = X1[js] + (T)((code / 3) % 3 - 1) * Ly;
+        zj = X2[js] + (T)(code % 3 - 1) * Lz;
+        qj = d.q[js];
+        aj = d.lja[js];
+        bj = d.ljb[js];
+        alch = d.sol[js] != 0;
+      }
+      env_alch_pairs<T>(d, xi, yi, zi, qi, ai, bi, xj, yj, zj, qj, aj, bj, alch, valid, (T)cv,
+                        (T)ce, Asc, fx, fy, fz);
+    }
+  }
   T Fx = (T)0, Fy = (T)0, Fz = (T)0;
 #pragma unroll
   for (int ii = 0; ii < CL; ++ii) {
@@ -692,13 +779,6 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
     const int64_t s = s0 + lane;
     const bool valid = d.orig[s] >= 0;
     double F[3] = {(double)Fx, (double)Fy, (double)Fz};
-    if (d.has_ext[c]) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        F[k] += from_fix(d.fext[k][s]);
-        d.fext[k][s] = 0ull;
-      }
-    }
     const T kr = d.rk[s];
     if (valid && kr != (T)0) {
       double r2 = 0.0;
@@ -713,8 +793,8 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb) 
     }
     if (INTEG) {
       if (valid) {
-        const int64_t st = d.env_step[w];
-        integrate_atom<T>(d, m, s, xb, vb, w, st, st != *d.start_step, F);
+        const int64_t st = d.step[lb * d.n_walkers + w];
+        integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
       } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
@@ -771,57 +851,45 @@ __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, 
 }
 
 template <typename T, bool ENERGY, bool INTEG>
-__device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb) {
+__device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
   const WalkerMeta &m = d.meta[w];
   const int lane = lane_id();
-  const double lam = d.lambda[w];
-  const int64_t step = d.step[w];
+  const int W = d.n_walkers;
+  const double lam = d.lambda[lb * W + w];
+  const int64_t step = d.step[lb * W + w];
   const bool pending = step != *d.start_step;
-  double gr = 0.0, ur = 0.0;
-  const int64_t a0 = (m.cl_begin + m.cap_env) * CL;
-  for (int t = lane; t < m.n_acl * CL; t += WAVE) {
-    const int64_t s = a0 + t;
-    const bool valid = d.orig[s] >= 0;
-    double F[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      F[k] = from_fix(d.fext[k][s]);
-      d.fext[k][s] = 0ull;
-    }
+  double gr = 0.0, ur = 0.0, g = 0.0;
+  for (int t = lane; t < m.n_acl; t += WAVE) {
+    const int64_t k = m.item_begin + t;
+    const int64_t s = (m.cl_begin + m.cap_env + t) * CL;
+    double F[3] = {d.item_force[k * 3], d.item_force[k * 3 + 1], d.item_force[k * 3 + 2]};
+    g += d.item_dudl[k];
     const double k0 = d.k0_64[s], k1 = d.k1_64[s];
-    if (valid && (k0 != 0.0 || k1 != 0.0)) {
+    if (k0 != 0.0 || k1 != 0.0) {
       const double kl = k0 + lam * (k1 - k0);
       double r2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double dd = min_image((double)(d.X[xb][k][s] - d.anc[k][s]), m.L[k]);
-        F[k] -= kl * dd;
+      for (int q = 0; q < 3; ++q) {
+        const double dd = min_image((double)(d.X[xb][q][s] - d.anc[q][s]), m.L[q]);
+        F[q] -= kl * dd;
         r2 += dd * dd;
       }
       gr += 0.5 * (k1 - k0) * r2;
       ur += 0.5 * kl * r2;
     }
     if (INTEG) {
-      if (valid) {
-        integrate_atom<T>(d, m, s, xb, vb, w, step, pending, F);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
-      }
+      integrate_atom<T>(d, s, xb, vb, w, step, pending, F);
     } else {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
+      for (int q = 0; q < 3; ++q) d.fout[(int64_t)q * d.n_slots + s] = F[q];
     }
   }
-  const int ni = d.n_items[w];
-  double g = 0.0;
-  for (int t = lane; t < ni; t += WAVE) g += d.item_dudl[m.item_begin + t];
   const double G = wave_sum(g) + wave_sum(gr);
   if (ENERGY) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       double e = 0.0;
-      for (int t = lane; t < ni; t += WAVE) e += d.item_energy[(int64_t)(m.item_begin + t) * 5 + q];
+      for (int t = lane; t < m.n_acl; t += WAVE) e += d.item_energy[(m.item_begin + t) * 5 + q];
       e = wave_sum(e);
       if (q == 4) e += wave_sum(ur);
       if (lane == 0) d.energy[w * 5 + q] = e;
@@ -892,10 +960,9 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb) {
     }
     if (!isfinite(G) || !isfinite(l) || !isfinite(p)) st |= 1u;
     if (st) atomicOr(&d.status[w], st);
-    d.lambda[w] = l;
+    d.lambda[(lb ^ 1) * W + w] = l;
     d.p_lambda[w] = p;
-    d.env_step[w] = step;
-    d.step[w] = step + 1;
+    d.step[(lb ^ 1) * W + w] = step + 1;
     d.ticket[w] = 0u;
     __threadfence();
   }
@@ -903,13 +970,13 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb) {
   unsigned old = 0;
   if (lane == 0) old = atomicAdd(d.gticket, 1u);
   old = __shfl(old, 0, WAVE);
-  if (old != (unsigned)(d.n_walkers - 1)) return;
+  if (old != (unsigned)(W - 1)) return;
   __threadfence();
   if (lp.abf_on && ((step + 1) % lp.share_interval) == 0) {
     for (int b = lane; b < lp.n_bins; b += WAVE) {
       int64_t n = d.bin_count[b];
       double s1 = d.bin_sum[b], s2 = d.bin_sum2[b];
-      for (int v = 0; v < d.n_walkers; ++v) {
+      for (int v = 0; v < W; ++v) {
         const int64_t li = (int64_t)v * lp.n_bins + b;
         n += d.loc_count[li];
         s1 += d.loc_sum[li];
@@ -926,117 +993,102 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb) {
   if (lane == 0) *d.gticket = 0u;
 }
 
+// One 256-thread block per alchemical atom: its four waves share the atom's
+// neighbour list, each lane one partner per pass (FP64), and the block
+// reduces force, dV/dlambda and energies in a fixed order (no atomics).  The
+// block that completes a walker's set runs the walker's lambda/ABF tail.
 template <typename T, bool ENERGY, bool INTEG>
-__global__ __launch_bounds__(64) void k_alch(Dev<T> d, Range r, int xb, int vb) {
+__global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
+  __shared__ double red[4][9];
+  __shared__ int is_last;
   const int64_t k = r.i0 + blockIdx.x;
   if (k >= r.i0 + r.in_) return;
   const int w = d.item_walker[k];
+  const int64_t c = d.alch_cluster[k];
   const WalkerMeta &m = d.meta[w];
-  if (k - m.item_begin >= d.n_items[w]) return;
-  const int lane = lane_id();
-  const int4 it = d.items[k];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
   const LamParams &lp = d.lp;
   double ce, dce, cv, dcv;
-  const double lam = d.lambda[w];
+  const double lam = d.lambda[lb * d.n_walkers + w];
   channel(lam, lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
   channel(lam, lp.vdw_start, lp.vdw_end, lp.direction, lp.hi, cv, dcv);
-  double dudl = 0.0;
-  double e5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (it.x >= 0) {
-    const int64_t c = it.x, s0 = c * CL;
-    const int ee = it.y + (lane >> 3);
-    bool vj = ee < it.z;
-    int64_t js = 0;
-    double xj = 0, yj = 0, zj = 0, qj = 0, sgj = 1, epj = 0;
-    int solj = 0;
-    bool isAj = false;
-    if (vj) {
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  if (c >= 0) {
+    const int64_t si = c * CL;
+    const double xi = (double)d.X[xb][0][si], yi = (double)d.X[xb][1][si],
+                 zi = (double)d.X[xb][2][si];
+    const double qi = d.q64[si], sgi = d.sig64[si], epi = d.eps64[si];
+    const int soli = d.sol[si];
+    const int n = d.list_count[c];
+    const double rc = d.r_cut, rc2 = rc * rc;
+    for (int e0 = wv * CL; e0 < n; e0 += 4 * CL) {
+      const int ee = e0 + (lane >> 3);
+      if (ee >= n) continue;
       const uint32_t ent = d.list[c * (int64_t)d.list_cap + ee];
       const int64_t J = ent & CL_MASK;
       const int code = (int)(ent >> SHIFT_BITS);
-      js = J * CL + (lane & 7);
-      vj = d.orig[js] >= 0;
-      xj = (double)d.X[xb][0][js] + (code / 9 - 1) * m.L[0];
-      yj = (double)d.X[xb][1][js] + ((code / 3) % 3 - 1) * m.L[1];
-      zj = (double)d.X[xb][2][js] + (code % 3 - 1) * m.L[2];
-      qj = d.q64[js];
-      sgj = d.sig64[js];
-      epj = d.eps64[js];
-      solj = d.sol[js];
-      isAj = (J - m.cl_begin) >= m.cap_env;
-    }
-    double rjx = 0, rjy = 0, rjz = 0;
-    const double rc = d.r_cut, rc2 = rc * rc;
-    for (int ii = 0; ii < CL; ++ii) {
-      const int64_t si = s0 + ii;
-      if (d.orig[si] < 0) continue;
-      const double dx = xj - (double)d.X[xb][0][si];
-      const double dy = yj - (double)d.X[xb][1][si];
-      const double dz = zj - (double)d.X[xb][2][si];
+      const int64_t js = J * CL + (lane & 7);
+      if (d.orig[js] < 0 || js == si) continue;
+      const double dx = ((double)d.X[xb][0][js] + (code / 9 - 1) * m.L[0]) - xi;
+      const double dy = ((double)d.X[xb][1][js] + ((code / 3) % 3 - 1) * m.L[1]) - yi;
+      const double dz = ((double)d.X[xb][2][js] + (code % 3 - 1) * m.L[2]) - zi;
       const double r2 = dx * dx + dy * dy + dz * dz;
-      double fx = 0.0, fy = 0.0, fz = 0.0;
-      if (vj && r2 < rc2 && js != si) {
-        const int soli = d.sol[si];
-        const bool alch = soli != solj;
-        const double sig = 0.5 * (d.sig64[si] + sgj);
-        const double eps = sqrt(d.eps64[si] * epj);
-        const double qq = d.coulomb_k * d.q64[si] * qj;
-        const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0,
-                                    lp.sc_alpha, lp.sc_power, rc);
-        fx = -o.fr * dx;
-        fy = -o.fr * dy;
-        fz = -o.fr * dz;
-        if (!isAj) {
-          rjx -= fx;
-          rjy -= fy;
-          rjz -= fz;
-        }
-        if (alch && soli) {
-          if (dcv != 0.0) dudl += dcv * o.dulj;
-          if (dce != 0.0) dudl += dce * o.duc;
-        }
-        if (ENERGY && (!isAj || si < js)) {
+      if (!(r2 < rc2)) continue;
+      const int solj = d.sol[js];
+      const bool alch = soli != solj;
+      const double sig = 0.5 * (sgi + d.sig64[js]);
+      const double eps = sqrt(epi * d.eps64[js]);
+      const double qq = d.coulomb_k * qi * d.q64[js];
+      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0,
+                                  lp.sc_alpha, lp.sc_power, rc);
+      acc[0] -= o.fr * dx;
+      acc[1] -= o.fr * dy;
+      acc[2] -= o.fr * dz;
+      if (alch && soli) {
+        if (dcv != 0.0) acc[3] += dcv * o.dulj;
+        if (dce != 0.0) acc[3] += dce * o.duc;
+      }
+      if (ENERGY) {
+        const bool isAj = (J - m.cl_begin) >= m.cap_env;
+        if (!isAj || si < js) {
           if (alch) {
-            e5[2] += o.ulj;
-            e5[3] += o.uc;
+            acc[6] += o.ulj;
+            acc[7] += o.uc;
           } else if (soli) {
-            e5[1] += o.ulj + o.uc;
+            acc[5] += o.ulj + o.uc;
           } else {
-            e5[0] += o.ulj + o.uc;
+            acc[4] += o.ulj + o.uc;
           }
         }
       }
-      fx = wave_sum(fx);
-      fy = wave_sum(fy);
-      fz = wave_sum(fz);
-      if (lane == 0) {
-        atomicAdd(&d.fext[0][si], to_fix(fx));
-        atomicAdd(&d.fext[1][si], to_fix(fy));
-        atomicAdd(&d.fext[2][si], to_fix(fz));
-      }
-    }
-    if (vj && !isAj && (rjx != 0.0 || rjy != 0.0 || rjz != 0.0)) {
-      atomicAdd(&d.fext[0][js], to_fix(rjx));
-      atomicAdd(&d.fext[1][js], to_fix(rjy));
-      atomicAdd(&d.fext[2][js], to_fix(rjz));
     }
   }
-  dudl = wave_sum(dudl);
-  if (lane == 0) d.item_dudl[k] = dudl;
-  if (ENERGY) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const double e = wave_sum(e5[q]);
-      if (lane == 0) d.item_energy[k * 5 + q] = e;
-    }
+  for (int q = 0; q < 9; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[wv][q] = v;
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    d.item_force[k * 3] = tot[0];
+    d.item_force[k * 3 + 1] = tot[1];
+    d.item_force[k * 3 + 2] = tot[2];
+    d.item_dudl[k] = tot[3];
+    if (ENERGY)
+      for (int q = 0; q < 5; ++q) d.item_energy[k * 5 + q] = tot[4 + q];
+    __threadfence();
+    const unsigned old = atomicAdd(&d.ticket[w], 1u);
+    is_last = old == (unsigned)(m.item_cap - 1);
+  }
+  __syncthreads();
+  if (!is_last || wv != 0) return;
   __threadfence();
-  unsigned old = 0;
-  if (lane == 0) old = atomicAdd(&d.ticket[w], 1u);
-  old = __shfl(old, 0, WAVE);
-  if (old != (unsigned)(d.n_items[w] - 1)) return;
-  __threadfence();
-  alch_tail<T, ENERGY, INTEG>(d, w, xb, vb);
+  alch_tail<T, ENERGY, INTEG>(d, w, xb, vb, lb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1051,7 +1103,9 @@ __global__ __launch_bounds__(256) void k_pairs(Dev<T> d, Range r, int xb, int mo
   if (!cluster_used(m, d.n_env[w], c)) return;
   const bool isA = (c - m.cl_begin) >= m.cap_env;
   const int lane = lane_id();
-  const int n = d.list_count[c];
+  // environment clusters: environment entries only (alchemical pairs are
+  // enumerated from the alchemical side)
+  const int n = isA ? d.list_count[c] : d.list_nenv[c];
   const double lim = mode == 0 ? d.r_list * d.r_list : d.r_cut * d.r_cut;
   unsigned long long cnt = 0, cnt_env = 0;
   for (int e0 = 0; e0 < n; e0 += CL) {
@@ -1116,10 +1170,12 @@ __global__ void k_init_vel(Dev<T> d, int vb) {
 }
 
 template <typename T>
-__global__ void k_init_lambda(Dev<T> d, const double *lam0, const double *p0) {
+__global__ void k_init_lambda(Dev<T> d, const double *lam0, const double *p0, int lb) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w < d.n_walkers) {
-    d.lambda[w] = lam0[w];
+  const int W = d.n_walkers;
+  if (w < W) {
+    d.lambda[lb * W + w] = lam0[w];
+    d.lambda[(lb ^ 1) * W + w] = lam0[w];
     if (p0) {
       d.p_lambda[w] = p0[w];
     } else {
@@ -1130,7 +1186,7 @@ __global__ void k_init_lambda(Dev<T> d, const double *lam0, const double *p0) {
     d.dudl[w] = 0.0;
     d.bias[w] = 0.0;
     d.step[w] = 0;
-    d.env_step[w] = 0;
+    d.step[W + w] = 0;
     d.ticket[w] = 0u;
     d.status[w] = 0u;
     for (int b = 0; b < d.lp.n_bins; ++b) {
@@ -1201,6 +1257,7 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
   if (r.an <= 0) return hipSuccess;
   k_fill_i32<<<nblk(r.kn, 256), 256, 0, s>>>(d.col_count + r.k0, r.kn, 0);
   k_key<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, check);
+  if (check) k_skin<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r);
   k_scan<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r);
   k_members<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r);
   k_rank<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb);
@@ -1208,50 +1265,53 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
   k_scatter<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, vb, xb ^ 1, vb ^ 1);
   k_bbox<T><<<nblk(r.cn, 256), 256, 0, s>>>(d, r, xb ^ 1);
   k_list<T><<<nblk(r.cn, 4), 256, 0, s>>>(d, r);
-  k_items<T><<<nblk(r.wn, 64), 64, 0, s>>>(d, r);
   return hipGetLastError();
 }
 
 template <typename T>
-static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, bool energy, bool integ,
-                       hipStream_t s) {
+static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
+                       bool integ, hipStream_t s) {
   const int nb = (int)((r.en + 3) / 4);
   const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
   if (grid == 0) return;
   if (d.uniform_lj) {
-    if (integ) k_env<T, false, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb);
-    else if (energy) k_env<T, false, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
-    else k_env<T, false, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    if (integ) k_env<T, false, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, false, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, false, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   } else {
-    if (integ) k_env<T, true, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb);
-    else if (energy) k_env<T, true, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
-    else k_env<T, true, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb);
+    if (integ) k_env<T, true, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, true, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, true, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   }
 }
 
 template <typename T>
-hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
-  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
-  env_launch<T>(d, r, xb, vb, false, true, s);
+hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                           hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  env_launch<T>(d, r, xb, vb, lb, false, true, s);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
-  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
+hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                                hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
-  env_launch<T>(d, r, xb, vb, false, true, s);
+hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                               hipStream_t s) {
+  env_launch<T>(d, r, xb, vb, lb, false, true, s);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, hipStream_t s) {
-  if (r.in_ > 0) k_alch<T, true, false><<<(unsigned)r.in_, 64, 0, s>>>(d, r, xb, vb);
-  env_launch<T>(d, r, xb, vb, true, false, s);
+hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                           hipStream_t s) {
+  if (r.in_ > 0) k_alch<T, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  env_launch<T>(d, r, xb, vb, lb, true, false, s);
   return hipGetLastError();
 }
 
@@ -1290,8 +1350,9 @@ hipError_t Launch<T>::gather_forces(const Dev<T> &d, double *f, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, hipStream_t s) {
-  k_init_lambda<T><<<nblk(d.n_walkers, 64), 64, 0, s>>>(d, lam0, p0);
+hipError_t launch_init_lambda(const Dev<T> &d, const double *lam0, const double *p0, int lb,
+                              hipStream_t s) {
+  k_init_lambda<T><<<nblk(d.n_walkers, 64), 64, 0, s>>>(d, lam0, p0, lb);
   return hipGetLastError();
 }
 
@@ -1305,8 +1366,8 @@ hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k
 template struct Launch<float>;
 template struct Launch<double>;
 template hipError_t launch_init_lambda<float>(const Dev<float> &, const double *, const double *,
-                                              hipStream_t);
-template hipError_t launch_init_lambda<double>(const Dev<double> &, const double *, const double *,
-                                               hipStream_t);
+                                              int, hipStream_t);
+template hipError_t launch_init_lambda<double>(const Dev<double> &, const double *,
+                                               const double *, int, hipStream_t);
 
 }  // namespace labf

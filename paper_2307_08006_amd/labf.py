@@ -50,6 +50,7 @@ class SystemDesc(C.Structure):
         ("gamma", C.c_double), ("dt", C.c_double), ("coulomb_k", C.c_double),
         ("accel_unit", C.c_double), ("seed", C.c_uint64),
         ("rebuild_interval", C.c_int32), ("reserved", C.c_int32),
+        ("r_skin_alch", C.c_double),
     ]
 
 
@@ -150,6 +151,7 @@ class System:
         d.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
         d.rebuild_interval = int(spec.rebuild_interval)
         d.reserved = 0
+        d.r_skin_alch = float(spec.r_skin_alch)
         h = C.c_void_p()
         rc = lib().labf_create_system(C.byref(d), self.stream, C.byref(h))
         if rc != 0:

@@ -63,6 +63,7 @@ class SystemSpec:
     k0: Optional[np.ndarray] = None      # float64 [N]
     k1: Optional[np.ndarray] = None      # float64 [N]
     rebuild_interval: int = 10
+    r_skin_alch: float = 0.0             # list buffer of alchemical pairs; 0 -> r_skin
     name: str = ""
 
     @property
@@ -238,87 +239,72 @@ def _solute_params(rng, n_solute: int, scale: float = 1.0):
     return sig, eps, q
 
 
+SOLUTE_K = 100.0            # kcal/mol/A^2: restraint holding the solute's shape
+
+
 def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
                seed: int = BASE_SEED + 1, precision: str = "fp32", r_cut: float = 12.0,
                r_skin: float = 1.0, temperature: float = 300.0, dt: float = 2.0,
                gamma_ps: float = 1.0, jitter: float = 0.05, sigma: float = FLUID_SIGMA,
-               lattice: str = "fcc_layered"):
+               solute_k: float = SOLUTE_K, r_skin_alch: float = 0.0):
     """One walker: n_atoms (solvent + solute) of a charged LJ fluid at 0.1
-    atoms/A^3 on a seeded FCC lattice (vacancies chosen by a seeded
-    permutation, +-jitter A) with solvent charges +-0.4 e alternating between
-    lattice planes (lattice="fcc_layered"; "fcc" draws the signs by a seeded
-    permutation, "rocksalt" uses simple-cubic sites).  The solute is the
-    n_solute occupied sites nearest the box centre with sigma ~ U(2.5, 3.8) A
-    scaled by sigma/3.15, eps 0.15, charges ~ U(-0.8, 0.8) summing to zero.
-    The solvent sigma defaults to 2.04 A (rho sigma^3 = 0.85, a dense
-    supercritical LJ fluid): with the literal 3.15 A (rho sigma^3 = 3.1) the
-    lattice is a compressed solid whose relaxation heats the system to
-    ~10^4 K.  Pair counts depend on density and cutoff only.
+    atoms/A^3 on a seeded FCC lattice (+-jitter A).  Solvent charges are
+    +-0.4 e on alternating (001) planes of the FCC basis (8 unlike and 4 like
+    nearest neighbours), half of the solvent from each species, vacancies by
+    a seeded permutation; the solvent sigma defaults to 2.04 A
+    (rho sigma^3 = 0.85, a dense supercritical LJ fluid; with the literal
+    3.15 A, rho sigma^3 = 3.1 is a compressed solid whose relaxation heats
+    the system to ~10^4 K).  Pair counts depend on density and cutoff only.
+    The solute: the n_solute cube-corner sites of the FCC cells (a simple
+    cubic sub-lattice, spacing a = 3.42 A at this density) nearest the box
+    centre, sigma ~ U(2.5, 3.8) A, eps 0.15, charges ~ U(-0.8, 0.8) summing
+    to zero, each atom held to its initial site by a lambda-independent
+    harmonic restraint (solute_k) that stands in for the molecule's bonded
+    terms: an unbonded charged cluster left alone in vacuum at lambda = 1
+    flies apart (~3000 K).
     Lambda: electrostatics removed over [0, 0.5], soft-core vdW over
     [0.5, 1] (decoupling), m_lambda = 150000 kcal/mol fs^2,
     gamma_lambda = 1000 /ps, 100 bins, fullSamples 100."""
     rng = np.random.default_rng(seed)
     L = (n_atoms / density) ** (1.0 / 3.0)
-    if lattice == "rocksalt":
-        # simple-cubic sites; charges alternate with the site parity (rock-salt
-        # order); vacancies drawn by a seeded permutation, half from each
-        # sublattice so that the two charge species stay balanced
-        n_side = int(math.ceil(n_atoms ** (1.0 / 3.0) - 1e-9))
-        n_side += n_side % 2
-        sites = _lattice_sc(n_side, L)
-        g = np.arange(n_side)
-        I, J, K = np.meshgrid(g, g, g, indexing="ij")
-        parity = ((I + J + K).ravel() % 2).astype(np.int64)
-        keep = []
-        for p_ in (0, 1):
-            idx = np.nonzero(parity == p_)[0]
-            take = n_atoms // 2 + (n_atoms % 2 if p_ == 0 else 0)
-            keep.append(idx[rng.permutation(idx.size)[:take]])
-        keep = np.sort(np.concatenate(keep))
-        site_q = np.where(parity[keep] == 0, SOLVENT_Q, -SOLVENT_Q)
-    elif lattice == "fcc_layered":
-        # FCC sites; charges alternate between the (001) planes of the basis
-        # (CuAu-like order: 8 unlike and 4 like nearest neighbours); vacancies
-        # by a seeded permutation, half from each charge species
-        n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
-        sites = _lattice_fcc(n_cell, L)
-        species = np.tile(np.array([0, 0, 1, 1]), n_cell ** 3)
-        keep = []
-        for p_ in (0, 1):
-            idx = np.nonzero(species == p_)[0]
-            take = n_atoms // 2 + (n_atoms % 2 if p_ == 0 else 0)
-            keep.append(idx[rng.permutation(idx.size)[:take]])
-        keep = np.sort(np.concatenate(keep))
-        site_q = np.where(species[keep] == 0, SOLVENT_Q, -SOLVENT_Q)
-    else:
-        n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
-        sites = _lattice_fcc(n_cell, L)
-        keep = np.sort(rng.permutation(sites.shape[0])[:n_atoms])
-        site_q = None
+    n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
+    sites = _lattice_fcc(n_cell, L)
+    basis = np.arange(sites.shape[0]) % 4
+    species = (basis >= 2).astype(np.int64)      # basis (0,0,0),(1/2,1/2,0): +; the others: -
+    dc = np.linalg.norm(sites - L / 2, axis=1)
+    corner = np.nonzero(basis == 0)[0]
+    sol_sites = corner[np.argsort(dc[corner], kind="stable")[:n_solute]]
+    free = np.ones(sites.shape[0], bool)
+    free[sol_sites] = False
+    n_solv = n_atoms - n_solute
+    keep = [sol_sites]
+    for p_ in (0, 1):
+        idx = np.nonzero(free & (species == p_))[0]
+        take = n_solv // 2 + (n_solv % 2 if p_ == 0 else 0)
+        keep.append(idx[rng.permutation(idx.size)[:take]])
+    keep = np.sort(np.concatenate(keep))
     pos = sites[keep] + rng.uniform(-jitter, jitter, size=(n_atoms, 3))
     pos, box = quantize(pos, np.array([L, L, L]), precision)
-    d = np.linalg.norm(pos - L / 2, axis=1)
-    order = np.lexsort((np.arange(n_atoms), d))
-    solute = np.zeros(n_atoms, np.uint8)
-    solute[order[:n_solute]] = 1
-    if site_q is not None:
-        q_solv = site_q[solute == 0]
-    else:
-        perm = rng.permutation(n_atoms - n_solute)
-        q_solv = np.where(perm % 2 == 0, SOLVENT_Q, -SOLVENT_Q)
-    charge = np.zeros(n_atoms)
+    # small boxes: keep r_cut + r_skin_alch inside half the box
+    if r_skin_alch:
+        r_skin_alch = max(r_skin, min(r_skin_alch, 0.49 * float(box.min()) - r_cut))
+    solute = np.isin(keep, sol_sites).astype(np.uint8)
+    charge = np.where(species[keep] == 0, SOLVENT_Q, -SOLVENT_Q).astype(np.float64)
     sig = np.full(n_atoms, sigma)
     eps = np.full(n_atoms, SOLVENT_EPS)
     mass = np.full(n_atoms, SOLVENT_MASS)
-    charge[solute == 0] = q_solv
     s_sig, s_eps, s_q = _solute_params(rng, n_solute)
     idx = np.nonzero(solute)[0]
     sig[idx], eps[idx], charge[idx], mass[idx] = s_sig, s_eps, s_q, SOLUTE_MASS
+    k = np.zeros(n_atoms)
+    k[idx] = solute_k
     spec = SystemSpec(
         atom_offset=np.array([0, n_atoms], np.int64), box=box[None, :], pos=pos, mass=mass,
         charge=charge, sigma=sig, epsilon=eps, is_solute=solute, r_cut=r_cut, r_skin=r_skin,
         kT=KB_KCAL * temperature, gamma=gamma_ps * 1e-3, dt=dt, coulomb_k=COULOMB_K,
-        accel_unit=ACCEL_REAL, seed=seed, precision=precision, name="charged_lj")
+        accel_unit=ACCEL_REAL, seed=seed, precision=precision, r_skin_alch=r_skin_alch,
+        anchor=pos.copy() if solute_k else None, k0=k if solute_k else None,
+        k1=k.copy() if solute_k else None, name="charged_lj")
     lam = LambdaSpec(lambda0=np.array([0.0]), p_lambda0=None, m_lambda=150000.0,
                      gamma_lambda=1000.0 * 1e-3, kT_lambda=KB_KCAL * temperature,
                      elec_start=0.0, elec_end=0.5, vdw_start=0.5, vdw_end=1.0,
@@ -339,7 +325,7 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         spec, atom_offset=np.arange(n_walkers + 1, dtype=np.int64) * n,
         box=np.repeat(spec.box, n_walkers, axis=0), pos=rep(spec.pos), mass=rep(spec.mass),
         charge=rep(spec.charge), sigma=rep(spec.sigma), epsilon=rep(spec.epsilon),
-        is_solute=rep(spec.is_solute), vel=rep(spec.vel), anchor=rep(spec.anchor),
+        is_solute=rep(spec.is_solute), vel=None, anchor=rep(spec.anchor),
         k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}")
     lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None)
     return out, lam2
@@ -367,11 +353,13 @@ def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
 
 def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
            seed: int = BASE_SEED + 3, precision: str = "fp32", r_cut: float = 12.0,
-           r_skin: float = 1.0):
+           r_skin: float = 1.0, r_skin_alch: float = 0.0):
     """Walkers with atom counts log-uniform in [n_min, n_max]: each a charged
     LJ solvent box around a dense cluster (0.12 atoms/A^3, FCC) restrained
     harmonically (k = 1 kcal/mol/A^2, lambda-independent) to its initial
-    sites, with a 20-80 atom decoupled ligand just outside the cluster."""
+    sites, with a 20-80 atom decoupled ligand just outside the cluster (on
+    the cube-corner sub-lattice, restrained to its sites like the solute of
+    charged_lj)."""
     rng = np.random.default_rng(seed)
     specs = []
     for w in range(n_walkers):
@@ -379,12 +367,13 @@ def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
         n_cl = int(round(math.exp(rng.uniform(math.log(2000), math.log(20000)))))
         n_cl = int(np.clip(n_cl, 2000, N // 2))
         n_lig = int(rng.integers(20, 81))
-        specs.append(_cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed + w))
+        specs.append(_cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed + w,
+                                     r_skin_alch))
     _, lam = charged_lj(n_atoms=3000, precision=precision)
     return concat(specs, lam, rng.uniform(0, 1, n_walkers), seed, "uneven")
 
 
-def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
+def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed, r_skin_alch=0.0):
     vol = n_cl / 0.12 + (N - n_cl) / 0.1
     L = vol ** (1.0 / 3.0)
     R = (3.0 * n_cl / (4.0 * math.pi * 0.12)) ** (1.0 / 3.0)
@@ -403,15 +392,17 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
     u /= np.linalg.norm(u)
     solv_sites = _lattice_fcc(int(math.ceil(L / (4.0 / 0.1) ** (1.0 / 3.0))),
                               L)
-    sv_species = (np.arange(solv_sites.shape[0]) % 4) // 2
+    sv_basis = np.arange(solv_sites.shape[0]) % 4
+    sv_species = sv_basis // 2
     ds = np.linalg.norm(solv_sites - c, axis=1)
     out_idx = np.nonzero(ds > R_eff + 1.0)[0]
-    outside = solv_sites[out_idx]
+    # ligand on the cube-corner sub-lattice (3.42 A spacing) nearest lig_c
     lig_c = c + u * (R_eff + 3.0)
-    dl = np.linalg.norm(outside - lig_c, axis=1)
-    order = np.argsort(dl, kind="stable")
-    lig = outside[order[:n_lig]]
-    rest_idx = out_idx[order[n_lig:]]
+    corner = out_idx[sv_basis[out_idx] == 0]
+    dl = np.linalg.norm(solv_sites[corner] - lig_c, axis=1)
+    lig_idx = corner[np.argsort(dl, kind="stable")[:n_lig]]
+    lig = solv_sites[lig_idx]
+    rest_idx = np.setdiff1d(out_idx, lig_idx)
     n_solv = N - n_cl - n_lig
     if rest_idx.shape[0] < n_solv:
         raise ValueError("solvent lattice too small")
@@ -423,6 +414,7 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
     anchor = pos.copy()
     k = np.zeros(N)
     k[:n_cl] = 1.0
+    k[n_cl:n_cl + n_lig] = SOLUTE_K
     solute = np.zeros(N, np.uint8)
     solute[n_cl:n_cl + n_lig] = 1
     sig = np.full(N, FLUID_SIGMA)
@@ -437,4 +429,5 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed):
         atom_offset=np.array([0, N], np.int64), box=box[None, :], pos=pos, mass=mass,
         charge=charge, sigma=sig, epsilon=eps, is_solute=solute, r_cut=r_cut, r_skin=r_skin,
         kT=KB_KCAL * 300.0, gamma=1e-3, dt=2.0, coulomb_k=COULOMB_K, accel_unit=ACCEL_REAL,
-        seed=seed, precision=precision, anchor=anchor, k0=k, k1=k.copy(), name="cluster")
+        seed=seed, precision=precision, anchor=anchor, k0=k, k1=k.copy(), r_skin_alch=r_skin_alch,
+        name="cluster")

@@ -201,3 +201,60 @@ def test_full_size_single_walker_forces():
     cnt = s.count_pairs()
     assert cnt[0] == o.neighbor_pairs(0, pos, spec.r_cut).shape[0]
     s.close()
+
+
+def _top2(v):
+    v = np.sort(np.asarray(v, float))
+    pad = np.concatenate([np.zeros(2), v])
+    return pad[-1], pad[-2]
+
+
+def test_list_validity_check_matches_host_displacements():
+    """The rebuild flags a walker (status bit 4) iff its displacements since
+    the previous rebuild could have brought an unlisted pair inside r_cut:
+    e1 + e2 > r_skin over environment atoms, or a1 + max(e1, a2) > r_skin_alch
+    with an alchemical atom.  Walkers get one fast environment atom (walkers
+    0-3) or a fast decoupled solute (walkers 4-7) so that both tests fire in
+    some walkers and not in others; the expected flags come from the
+    positions read back before and after the interval."""
+    base, lam = synth.lj_reduced(density=0.3)   # mean free path ~1 sigma
+    W, n = 8, base.n_atoms
+    spec, lamb = synth.batch(base, lam, W, seed=71)
+    rng = np.random.default_rng(72)
+    vel = rng.normal(size=(W * n, 3))
+    solute = np.nonzero(base.is_solute)[0][0]
+    env_atom = (solute + 7) % n
+    for w in range(W):
+        if w < 4:
+            vel[w * n + env_atom] = [2.0 + 2.0 * w, 0.0, 0.0]
+        else:
+            vel[w * n + solute] = [10.0 + 8.0 * (w - 4), 0.0, 0.0]
+    spec.vel = vel
+    spec.r_skin, spec.r_skin_alch = 0.5, 1.2
+    lamb.lambda0 = np.ones(W)          # solute fully decoupled: it flies freely
+    lamb.fixed_lambda = True
+    with labf.System(spec, lamb) as s:
+        p0, _ = s.read_atoms()
+        s.step(spec.rebuild_interval)
+        p1, _ = s.read_atoms()
+        s.step(1)                      # rebuild: the check runs here
+        st = s.read_walker_state()["status"]
+    L = spec.box[0]
+    d = p1 - p0
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(1)).reshape(W, n)
+    alch = base.is_solute.astype(bool)
+    want, margin, sums = [], [], []
+    for w in range(W):
+        e1, e2 = _top2(r[w][~alch])
+        a1, a2 = _top2(r[w][alch])
+        t_env, t_a = e1 + e2 - spec.r_skin, a1 + max(e1, a2) - spec.r_skin_alch
+        want.append(bool(t_env > 0 or t_a > 0))
+        margin.append(min(abs(t_env), abs(t_a)))
+        sums.append((round(e1 + e2, 4), round(a1 + max(e1, a2), 4)))
+    assert min(margin) > 1e-6, margin   # no case decided by rounding
+    got = [(int(x) & 4) != 0 for x in st]
+    assert got == want, (got, want, sums)
+    assert (np.asarray(st) & ~np.uint32(4)).max() == 0
+    assert any(want[:4]) and not all(want[:4])
+    assert any(want[4:]) and not all(want[4:])
