@@ -188,6 +188,45 @@ labf_status labf_write_atoms(labf_system *sys, const double *pos, const double *
 labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy, double *dudl,
                                 void *stream);
 
+/* Differentiable potential energy ("Theory": the extended potential
+ * V(q; lambda) whose derivatives drive the dynamics and the ABF estimator;
+ * "Alchemical pathway": the lambda-scaled soft-core LJ and shifted-force
+ * Coulomb terms).  For automatic differentiation (a torch.autograd.Function
+ * sits on top); nothing computed by labf_energy is kept for the backward
+ * call, which recomputes every pair term.
+ *
+ * Every array argument of these two calls is a DEVICE pointer on the
+ * system's GPU, read and written in the order of `stream`; the caller owns
+ * them.  Each of pos, lambda, params may be NULL (keep the current value):
+ *   pos     [N][3] FP64, caller order; wrapped into the box and rounded to
+ *           the storage grid exactly as labf_write_atoms does
+ *   lambda  [W] FP64; a value outside [lo, hi] gets the schedule's clipped
+ *           couplings (no reflection is applied here)
+ *   params  [S][3] FP64 (epsilon, sigma, q) of the solute atoms in increasing
+ *           atom order (S = labf_info.n_solute); copied to the host and
+ *           validated (finite, epsilon >= 0, sigma > 0 where epsilon > 0;
+ *           LABF_E_ARG otherwise, nothing changed)
+ * The given values replace the system's (velocities, lambda momenta and the
+ * ABF accumulators are kept) and the neighbour structure is rebuilt
+ * (positions given: without the list-validity check).
+ *
+ * labf_energy: energy[W] = total potential energy of each walker (FP64
+ *   sums; environment pair terms in the storage precision).
+ * labf_energy_backward: for the upstream gradient grad_energy[W] = dL/dV_w,
+ *   grad_pos[N][3]    = g_w dV_w/dx_a = -g_w F_a      (or NULL)
+ *   grad_lambda[W]    = g_w dV_w/dlambda_w             (or NULL)
+ *   grad_params[S][3] = g_w dV_w/d(epsilon, sigma, q)_i of solute atom i
+ *                       (Lorentz-Berthelot mixing; FP64; or NULL)
+ * A non-finite position gives non-finite outputs and walker status bit 1.
+ * Errors: LABF_E_STATE before labf_set_lambda_params; LABF_E_ARG for NULL
+ * energy / grad_energy or invalid params. */
+labf_status labf_energy(labf_system *sys, const double *pos, const double *lambda,
+                        const double *params, double *energy, void *stream);
+labf_status labf_energy_backward(labf_system *sys, const double *pos, const double *lambda,
+                                 const double *params, const double *grad_energy,
+                                 double *grad_pos, double *grad_lambda, double *grad_params,
+                                 void *stream);
+
 /* The neighbour set of walker w held by the device list: every pair (i < j,
  * walker-local indices) with |x_j - x_i|^2 < r_list^2 under the minimum
  * image, decided in FP64 as (dx*dx + dy*dy) + dz*dz.  Writes up to
@@ -220,6 +259,7 @@ typedef struct labf_info {
   int64_t n_atoms, n_slots, n_clusters, n_list_entries;
   int32_t n_walkers, list_cap, precision, uniform_lj;
   int32_t list_max_env, list_max_alch;   /* longest list of each cluster kind */
+  int64_t n_solute;                      /* atoms with is_solute = 1 (S below) */
 } labf_info;
 labf_status labf_get_info(labf_system *sys, labf_info *info, void *stream);
 

@@ -69,6 +69,7 @@ struct labf_system {
   int precision = LABF_FP32;
   int W = 0;
   int64_t N = 0, C = 0, S = 0, E = 0, I = 0, K = 0;
+  int64_t n_solute = 0;
   int list_cap = 0;
   int interval = 10;
   bool lam_set = false;
@@ -290,6 +291,7 @@ labf_status alloc_items(labf_system *s) {
   HIPCHK(s, dalloc(s->item_bufs, &d.item_force, (size_t)ib * 3));
   HIPCHK(s, dalloc(s->item_bufs, &d.item_dudl, (size_t)ib));
   HIPCHK(s, dalloc(s->item_bufs, &d.item_energy, (size_t)ib * 5));
+  HIPCHK(s, dalloc(s->item_bufs, &d.item_pgrad, (size_t)ib * 3));
   HIPCHK(s, dalloc(s->item_bufs, &d.list, (size_t)s->C * s->list_cap));
   // metadata changed (item ranges)
   HIPCHK(s, hipMemcpy((void *)d.meta, s->meta.data(), sizeof(WalkerMeta) * s->W, hipMemcpyHostToDevice));
@@ -502,9 +504,19 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, upload(b, &d.atom_walker, atom_walker.data(), N));
   HIPCHK(s, upload(b, &d.cl_walker, cl_walker.data(), s->C));
   HIPCHK(s, upload(b, &d.env_table, env_table.data(), s->E));
-  HIPCHK(s, upload(b, &d.a_q, desc->charge, N));
-  HIPCHK(s, upload(b, &d.a_sig, desc->sigma, N));
-  HIPCHK(s, upload(b, &d.a_eps, desc->epsilon, N));
+  for (auto pr : {std::make_pair(&d.a_q, desc->charge), std::make_pair(&d.a_sig, desc->sigma),
+                  std::make_pair(&d.a_eps, desc->epsilon)}) {
+    HIPCHK(s, dalloc(b, pr.first, N));
+    HIPCHK(s, hipMemcpy(*pr.first, pr.second, sizeof(double) * N, hipMemcpyHostToDevice));
+  }
+  {
+    std::vector<int32_t> solute_atom;
+    for (int64_t i = 0; i < N; ++i)
+      if (sol[i]) solute_atom.push_back((int32_t)i);
+    s->n_solute = (int64_t)solute_atom.size();
+    d.n_solute = s->n_solute;
+    HIPCHK(s, upload(b, &d.solute_atom, solute_atom.data(), solute_atom.size()));
+  }
   HIPCHK(s, upload(b, &d.a_mass, desc->mass, N));
   HIPCHK(s, upload(b, &d.a_sol, sol.data(), N));
   HIPCHK(s, upload(b, &d.a_alch, alch.data(), N));
@@ -732,6 +744,48 @@ labf_status eval_impl(labf_system *s, double *forces, double *energy, double *du
   }
   if (energy) std::memcpy(energy, e.data(), sizeof(double) * 5 * s->W);
   if (dudl) std::memcpy(dudl, g.data(), sizeof(double) * s->W);
+  return LABF_OK;
+}
+
+// Differentiable energy: install the configuration (device arrays, each may
+// be NULL), rebuild, evaluate every pair term once.
+template <typename T>
+labf_status energy_eval(labf_system *s, const double *pos, const double *lam, const double *params,
+                        hipStream_t st) {
+  Dev<T> &d = s->dev<T>();
+  if (params && s->n_solute > 0) {
+    std::vector<double> p(3 * s->n_solute);
+    HIPCHK(s, hipMemcpyAsync(p.data(), params, sizeof(double) * p.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < s->n_solute; ++i) {
+      const double eps = p[3 * i], sig = p[3 * i + 1], q = p[3 * i + 2];
+      if (!std::isfinite(eps) || !std::isfinite(sig) || !std::isfinite(q) || eps < 0 || (eps > 0 && !(sig > 0)))
+        return fail(s, LABF_E_ARG, "solute parameters: need finite values, eps >= 0, sigma > 0 where eps > 0");
+    }
+  }
+  HIPCHK(s, Launch<T>::set_config(d, s->xb, s->lb, pos, lam, params, st));
+  if (pos) s->xref_valid = false;  // positions replaced: nothing to check at this rebuild
+  labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
+  if (rc != LABF_OK) return rc;
+  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, st));
+  return LABF_OK;
+}
+
+template <typename T>
+labf_status energy_impl(labf_system *s, const double *pos, const double *lam, const double *params,
+                        double *energy, hipStream_t st) {
+  labf_status rc = energy_eval<T>(s, pos, lam, params, st);
+  if (rc != LABF_OK) return rc;
+  HIPCHK(s, Launch<T>::energy_total(s->dev<T>(), energy, st));
+  return LABF_OK;
+}
+
+template <typename T>
+labf_status energy_backward_impl(labf_system *s, const double *pos, const double *lam, const double *params,
+                                 const double *g, double *gpos, double *glam, double *gpar, hipStream_t st) {
+  labf_status rc = energy_eval<T>(s, pos, lam, params, st);
+  if (rc != LABF_OK) return rc;
+  HIPCHK(s, Launch<T>::energy_grads(s->dev<T>(), g, gpos, glam, gpar, st));
   return LABF_OK;
 }
 
@@ -1044,6 +1098,30 @@ labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy
   });
 }
 
+labf_status labf_energy(labf_system *sys, const double *pos, const double *lambda, const double *params,
+                        double *energy, void *stream) {
+  if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
+  if (!energy) return fail(sys, LABF_E_ARG, "energy is NULL");
+  if (!sys->lam_set) return fail(sys, LABF_E_STATE, "labf_set_lambda_params must be called first");
+  return dispatch(sys, [&](auto *tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return energy_impl<T>(sys, pos, lambda, params, energy, (hipStream_t)stream);
+  });
+}
+
+labf_status labf_energy_backward(labf_system *sys, const double *pos, const double *lambda, const double *params,
+                                 const double *grad_energy, double *grad_pos, double *grad_lambda,
+                                 double *grad_params, void *stream) {
+  if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
+  if (!grad_energy) return fail(sys, LABF_E_ARG, "grad_energy is NULL");
+  if (!sys->lam_set) return fail(sys, LABF_E_STATE, "labf_set_lambda_params must be called first");
+  return dispatch(sys, [&](auto *tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return energy_backward_impl<T>(sys, pos, lambda, params, grad_energy, grad_pos, grad_lambda, grad_params,
+                                   (hipStream_t)stream);
+  });
+}
+
 labf_status labf_export_pairs(labf_system *sys, int32_t walker, int64_t max_pairs, int64_t *pairs, int64_t *n_pairs,
                               void *stream) {
   if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
@@ -1123,6 +1201,7 @@ labf_status labf_get_info(labf_system *sys, labf_info *info, void *stream) {
   info->list_cap = sys->list_cap;
   info->precision = sys->precision;
   info->uniform_lj = sys->precision == LABF_FP64 ? sys->dd.uniform_lj : sys->df.uniform_lj;
+  info->n_solute = sys->n_solute;
   return LABF_OK;
 }
 

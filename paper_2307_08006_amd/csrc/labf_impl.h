@@ -80,7 +80,10 @@ struct Dev {
   const int32_t *alch_cluster;  // [sum item_cap] alchemical cluster of each block, or -1
   // --- caller-order atom data
   const double *a_pos0;         // [N][3] upload staging (B-offset, rounded)
-  const double *a_q, *a_sig, *a_eps, *a_mass, *a_k0, *a_k1, *a_anchor;  // anchor [N][3]
+  double *a_q, *a_sig, *a_eps;  // charge, sigma, epsilon (solute entries replaceable)
+  const double *a_mass, *a_k0, *a_k1, *a_anchor;  // anchor [N][3]
+  const int32_t *solute_atom;   // [n_solute] atoms with is_solute = 1, increasing
+  int64_t n_solute;
   const uint8_t *a_sol, *a_alch;
   int32_t *slot_of, *new_slot, *col_of, *key_col, *members;
   float *disp;                  // [N] displacement since the last rebuild (rounded up)
@@ -111,6 +114,7 @@ struct Dev {
   double *item_force;           // [I][3] force on the block's atom
   double *item_dudl;            // [I]
   double *item_energy;          // [I][5]
+  double *item_pgrad;           // [I][3] dV/d(eps, sigma, q) of the block's atom (evaluation)
   // --- per walker dynamic state
   int32_t *n_env;
   uint32_t *ticket;             // per walker
@@ -161,6 +165,15 @@ struct Launch {
   static hipError_t scatter_atoms(const Dev<T> &d, int xb, int vb, const double *pos,
                                   const double *vel, hipStream_t s);
   static hipError_t gather_forces(const Dev<T> &d, double *f, hipStream_t s);
+  // differentiable energy: replace positions (caller order, unrounded),
+  // lambda and solute (eps, sigma, q) from device arrays (each may be NULL)
+  static hipError_t set_config(const Dev<T> &d, int xb, int lb, const double *pos,
+                               const double *lam, const double *params, hipStream_t s);
+  // total potential energy per walker after eval()
+  static hipError_t energy_total(const Dev<T> &d, double *out, hipStream_t s);
+  // upstream gradient g[W] times the derivatives of the last eval()
+  static hipError_t energy_grads(const Dev<T> &d, const double *g, double *gpos, double *glam,
+                                 double *gpar, hipStream_t s);
 };
 
 // lam0 / p0: device arrays [W]; p0 may be NULL (Maxwell-Boltzmann draw).

@@ -818,13 +818,15 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
 // ---------------------------------------------------------------------------
 struct PairOut {
   double fr, ulj, dulj, uc, duc;
+  double dsig;  // dV_LJ/d(sigma_ij), shift included
+  double g;     // shifted-force kernel 1/r - 1/rc + (r - rc)/rc^2
 };
 
 // Soft-core LJ (alpha (1-c)^p + (r/sig)^6 in the denominator, shift at r_cut
 // with the same c) and shifted-force Coulomb, both at coupling (cv, ce).
 __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq, double cv,
                                             double ce, double alpha, int p, double rc) {
-  PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0};
+  PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double r = sqrt(r2);
   if (eps != 0.0) {
     const double sig2 = sig * sig;
@@ -838,9 +840,12 @@ __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, 
     o.dulj = 4.0 * eps * (((s * s - s) + cv * dsc * (2.0 * s - 1.0) * s * s) -
                           ((sc * sc - sc) + cv * dsc * (2.0 * sc - 1.0) * sc * sc));
     o.fr = 24.0 * eps * cv * (2.0 * s - 1.0) * s * s * u / r2;
+    // u = (r/sig)^6 gives du/dsig = -6u/sig, hence ds/dsig = 6 u s^2 / sig
+    o.dsig = 24.0 * eps * cv * ((2.0 * s - 1.0) * s * s * u - (2.0 * sc - 1.0) * sc * sc * uc) / sig;
   }
   if (qq != 0.0) {
     const double g = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+    o.g = g;
     o.duc = qq * g;
     if (ce != 0.0) {
       o.uc = ce * qq * g;
@@ -999,7 +1004,8 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
 // block that completes a walker's set runs the walker's lambda/ABF tail.
 template <typename T, bool ENERGY, bool INTEG>
 __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
-  __shared__ double red[4][9];
+  constexpr int NACC = ENERGY ? 12 : 9;
+  __shared__ double red[4][NACC];
   __shared__ int is_last;
   const int64_t k = r.i0 + blockIdx.x;
   if (k >= r.i0 + r.in_) return;
@@ -1012,9 +1018,10 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
   const double lam = d.lambda[lb * d.n_walkers + w];
   channel(lam, lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
   channel(lam, lp.vdw_start, lp.vdw_end, lp.direction, lp.hi, cv, dcv);
-  double acc[9];
+  // 0-2 force, 3 dV/dlambda, 4-8 energies, 9-11 dV/d(eps, sigma, q) of atom i
+  double acc[NACC];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
   if (c >= 0) {
     const int64_t si = c * CL;
     const double xi = (double)d.X[xb][0][si], yi = (double)d.X[xb][1][si],
@@ -1051,6 +1058,10 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
         if (dce != 0.0) acc[3] += dce * o.duc;
       }
       if (ENERGY) {
+        // eps_ij = sqrt(eps_i eps_j), sig_ij = (sig_i + sig_j)/2, q_i q_j
+        if (epi != 0.0) acc[9] += o.ulj / (2.0 * epi);
+        acc[10] += 0.5 * o.dsig;
+        acc[11] += (alch ? ce : 1.0) * d.coulomb_k * d.q64[js] * o.g;
         const bool isAj = (J - m.cl_begin) >= m.cap_env;
         if (!isAj || si < js) {
           if (alch) {
@@ -1066,21 +1077,23 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     }
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
+  for (int q = 0; q < NACC; ++q) {
     const double v = wave_sum(acc[q]);
     if (lane == 0) red[wv][q] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tot[9];
+    double tot[NACC];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    for (int q = 0; q < NACC; ++q) tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
     d.item_force[k * 3] = tot[0];
     d.item_force[k * 3 + 1] = tot[1];
     d.item_force[k * 3 + 2] = tot[2];
     d.item_dudl[k] = tot[3];
-    if (ENERGY)
+    if (ENERGY) {
       for (int q = 0; q < 5; ++q) d.item_energy[k * 5 + q] = tot[4 + q];
+      for (int q = 0; q < 3; ++q) d.item_pgrad[k * 3 + q] = tot[9 + q];
+    }
     __threadfence();
     const unsigned old = atomicAdd(&d.ticket[w], 1u);
     is_last = old == (unsigned)(m.item_cap - 1);
@@ -1242,6 +1255,98 @@ __global__ void k_gather_forces(Dev<T> d, double *f) {
 }
 
 // ---------------------------------------------------------------------------
+// differentiable energy: configuration in, total energy and gradients out
+// ---------------------------------------------------------------------------
+// Positions are wrapped into [0, L) and rounded to the storage grid B + x
+// exactly as the host does for uploads; lambda goes to the buffer that the
+// next evaluation reads.
+template <typename T>
+__global__ void k_set_config(Dev<T> d, int xb, int lb, const double *pos, const double *lam) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos && i < d.n_atoms) {
+    const WalkerMeta &m = d.meta[d.atom_walker[i]];
+    const int s = d.slot_of[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double L = m.L[k], B = m.B[k];
+      double v = pos[3 * i + k];
+      v = v - L * floor(v / L);
+      if (v >= L) v -= L;
+      double X = (double)((T)B + (T)v);
+      if (X >= B + L) X -= L;
+      if (X < B) X += L;
+      d.X[xb][k][s] = (T)X;
+    }
+  }
+  if (lam && i < d.n_walkers) d.lambda[lb * d.n_walkers + i] = lam[i];
+}
+
+// Solute parameters (eps, sigma, q) into the caller-order atom arrays; the
+// rebuild that follows derives every per-slot copy from them.
+template <typename T>
+__global__ void k_set_params(Dev<T> d, const double *par) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n_solute) return;
+  const int a = d.solute_atom[i];
+  d.a_eps[a] = par[3 * i];
+  d.a_sig[a] = par[3 * i + 1];
+  d.a_q[a] = par[3 * i + 2];
+}
+
+// One block per walker: environment cluster energies summed in a fixed
+// order, then the alchemical-side parts.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_total(Dev<T> d, double *out) {
+  __shared__ double sm[4][2];
+  const int w = blockIdx.x;
+  const WalkerMeta &m = d.meta[w];
+  const int ne = d.n_env[w];
+  double ee = 0.0, er = 0.0;
+  for (int c = threadIdx.x; c < ne; c += blockDim.x) {
+    ee += d.cl_energy[2 * (m.cl_begin + c)];
+    er += d.cl_energy[2 * (m.cl_begin + c) + 1];
+  }
+  ee = wave_sum(ee);
+  er = wave_sum(er);
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    sm[wv][0] = ee;
+    sm[wv][1] = er;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double se = ((sm[0][0] + sm[1][0]) + sm[2][0]) + sm[3][0];
+    const double sr = ((sm[0][1] + sm[1][1]) + sm[2][1]) + sm[3][1];
+    const double *e = d.energy + 5 * w;
+    out[w] = ((((e[0] + se) + e[1]) + e[2]) + e[3]) + (e[4] + sr);
+  }
+}
+
+// gpos = g_w dV/dx = -g_w F, glam = g_w dV/dlambda, gpar = g_w dV/d(eps, sigma, q).
+template <typename T>
+__global__ void k_energy_grads(Dev<T> d, const double *g, double *gpos, double *glam,
+                               double *gpar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gpos && i < d.n_atoms) {
+    const double gw = g[d.atom_walker[i]];
+    const int s = d.slot_of[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gpos[3 * i + k] = -gw * d.fout[(int64_t)k * d.n_slots + s];
+  }
+  if (glam && i < d.n_walkers) glam[i] = g[i] * d.dudl[i];
+  if (gpar && i < d.n_solute) {
+    const int a = d.solute_atom[i];
+    const int w = d.atom_walker[a];
+    const WalkerMeta &m = d.meta[w];
+    // the t-th alchemical cluster of a walker is its t-th alchemical block
+    const int64_t c = d.slot_of[a] / CL;
+    const int64_t k = m.item_begin + (c - m.cl_begin - m.cap_env);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gpar[3 * i + q] = g[w] * d.item_pgrad[3 * k + q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1340,6 +1445,33 @@ template <typename T>
 hipError_t Launch<T>::scatter_atoms(const Dev<T> &d, int xb, int vb, const double *pos,
                                     const double *vel, hipStream_t s) {
   k_scatter_atoms<T><<<nblk(d.n_atoms, 256), 256, 0, s>>>(d, xb, vb, pos, vel);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::set_config(const Dev<T> &d, int xb, int lb, const double *pos,
+                                 const double *lam, const double *params, hipStream_t s) {
+  if (params && d.n_solute > 0) k_set_params<T><<<nblk(d.n_solute, 256), 256, 0, s>>>(d, params);
+  if (pos || lam) {
+    const int64_t n = pos ? (d.n_atoms > d.n_walkers ? d.n_atoms : d.n_walkers) : d.n_walkers;
+    k_set_config<T><<<nblk(n, 256), 256, 0, s>>>(d, xb, lb, pos, lam);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::energy_total(const Dev<T> &d, double *out, hipStream_t s) {
+  k_energy_total<T><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::energy_grads(const Dev<T> &d, const double *g, double *gpos, double *glam,
+                                   double *gpar, hipStream_t s) {
+  int64_t n = d.n_walkers;
+  if (gpos && d.n_atoms > n) n = d.n_atoms;
+  if (gpar && d.n_solute > n) n = d.n_solute;
+  k_energy_grads<T><<<nblk(n, 256), 256, 0, s>>>(d, g, gpos, glam, gpar);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ["labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
            "labf_read_abf_bins", "labf_free_energy", "labf_read_walker_state",
            "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
            "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
-           "labf_destroy_system",
+           "labf_energy", "labf_energy_backward", "labf_destroy_system",
            "labf_last_error"]
 
 
@@ -71,7 +71,8 @@ class Info(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("n_slots", C.c_int64), ("n_clusters", C.c_int64),
                 ("n_list_entries", C.c_int64), ("n_walkers", C.c_int32), ("list_cap", C.c_int32),
                 ("precision", C.c_int32), ("uniform_lj", C.c_int32),
-                ("list_max_env", C.c_int32), ("list_max_alch", C.c_int32)]
+                ("list_max_env", C.c_int32), ("list_max_alch", C.c_int32),
+                ("n_solute", C.c_int64)]
 
 
 _lib = None
@@ -100,6 +101,8 @@ def lib():
             "labf_profile_steps": ([P, I64, P, P], I32),
             "labf_philox": ([I64, P, P, P, P], I32),
             "labf_get_info": ([P, P, P], I32),
+            "labf_energy": ([P, P, P, P, P, P], I32),
+            "labf_energy_backward": ([P, P, P, P, P, P, P, P, P], I32),
             "labf_destroy_system": ([P], None),
             "labf_last_error": ([P], C.c_char_p),
         }
@@ -126,6 +129,23 @@ def _stream(stream):
     if stream is None:
         return None
     return int(stream)
+
+
+def _dev(t, shape, name):
+    """Device pointer of a contiguous float64 CUDA (HIP) tensor of the given
+    shape, or None."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise LabfError(-1, f"{name}: need a contiguous float64 GPU tensor of shape {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _torch_stream(stream):
+    import torch
+    return int(stream) if stream is not None else torch.cuda.current_stream().cuda_stream
 
 
 class System:
@@ -228,6 +248,42 @@ class System:
         self._chk(lib().labf_read_walker_state(self._h, _p(lam), _p(p), _p(g), _p(b), _p(st),
                                                _p(step), self.stream))
         return dict(lam=lam, p_lambda=p, dudl=g, bias=b, status=st, step=int(step[0]))
+
+    # -- differentiable energy (device tensors; see paper_2307_08006_amd.autograd)
+    @property
+    def n_solute(self) -> int:
+        return int(np.count_nonzero(self.spec.is_solute))
+
+    def solute_params(self):
+        """(epsilon, sigma, q) of the solute atoms in increasing atom order, [S][3]."""
+        m = np.asarray(self.spec.is_solute).astype(bool)
+        return np.stack([np.asarray(self.spec.epsilon)[m], np.asarray(self.spec.sigma)[m],
+                         np.asarray(self.spec.charge)[m]], axis=1)
+
+    def energy(self, pos=None, lam=None, params=None, out=None, stream=None):
+        """Total potential energy per walker [W] at the given configuration
+        (float64 GPU tensors, each optional); the configuration replaces the
+        system's."""
+        import torch
+        W, N, S = self.W, self.N, self.n_solute
+        if out is None:
+            out = torch.empty(W, dtype=torch.float64, device="cuda")
+        self._chk(lib().labf_energy(self._h, _dev(pos, (N, 3), "pos"), _dev(lam, (W,), "lambda"),
+                                    _dev(params, (S, 3), "params"), _dev(out, (W,), "energy"),
+                                    _torch_stream(stream)))
+        return out
+
+    def energy_backward(self, grad_energy, pos=None, lam=None, params=None, grad_pos=None,
+                        grad_lam=None, grad_params=None, stream=None):
+        """Recompute the pair terms at the given configuration and write
+        g_w dV/dx, g_w dV/dlambda and g_w dV/d(eps, sigma, q) of the solute
+        into the given output tensors (each optional)."""
+        W, N, S = self.W, self.N, self.n_solute
+        self._chk(lib().labf_energy_backward(
+            self._h, _dev(pos, (N, 3), "pos"), _dev(lam, (W,), "lambda"),
+            _dev(params, (S, 3), "params"), _dev(grad_energy, (W,), "grad_energy"),
+            _dev(grad_pos, (N, 3), "grad_pos"), _dev(grad_lam, (W,), "grad_lambda"),
+            _dev(grad_params, (S, 3), "grad_params"), _torch_stream(stream)))
 
     def read_atoms(self):
         pos = np.zeros((self.N, 3))

@@ -80,6 +80,8 @@ def test_null_arguments_are_rejected():
     h = C.c_void_p()
     assert L.labf_create_system(None, None, C.byref(h)) == -1
     assert L.labf_step_walkers(None, 1, 0, None) == -1
+    assert L.labf_energy(None, None, None, None, None, None) == -1
+    assert L.labf_energy_backward(None, None, None, None, None, None, None, None, None) == -1
     assert L.labf_read_atoms(None, None, None, None) == -1
     assert L.labf_philox(-1, None, None, None, None) == -1
     assert L.labf_philox(0, None, None, None, None) == 0
