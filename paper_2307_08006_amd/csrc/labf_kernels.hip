@@ -564,6 +564,32 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
 // ---------------------------------------------------------------------------
 // environment pair kernel
 // ---------------------------------------------------------------------------
+// Per-wave LDS ring of pruned j atoms (position, scaled charge; sigma/2 and
+// sqrt(24 eps) for per-atom mixing).  At most 63 + 64 entries are pending.
+constexpr int RING = 128;
+template <typename T, bool LB>
+struct Ring {
+  T x[RING], y[RING], z[RING], q[RING];
+  T a[LB ? RING : 1], b[LB ? RING : 1];
+  __device__ __forceinline__ void put(int k, T xj, T yj, T zj, T qj, T aj, T bj) {
+    x[k] = xj;
+    y[k] = yj;
+    z[k] = zj;
+    q[k] = qj;
+    if (LB) {
+      a[k] = aj;
+      b[k] = bj;
+    }
+  }
+  __device__ __forceinline__ void get(int k, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj) const {
+    xj = x[k];
+    yj = y[k];
+    zj = z[k];
+    qj = q[k];
+    aj = LB ? a[k] : (T)0;
+    bj = LB ? b[k] : (T)0;
+  }
+};
 template <typename T, bool LB, bool ENERGY, bool DIAG>
 __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], const T (&yi)[CL],
                                           const T (&zi)[CL], const T (&qi)[CL], const T (&ai)[CL],
@@ -574,7 +600,7 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
 #pragma unroll
   for (int ii = 0; ii < CL; ++ii) {
     const T dx = xj - xi[ii], dy = yj - yi[ii], dz = zj - zi[ii];
-    const T r2 = dx * dx + dy * dy + dz * dz;
+    const T r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     bool in = r2 < d.rc2;
     if (DIAG) in = in && (js != (int)(s0 + ii));
     const T rinv = rsq(r2);
@@ -710,10 +736,16 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
   const T Lx = (T)m.L[0], Ly = (T)m.L[1], Lz = (T)m.L[2];
   const T far = (T)(8.0 * m.B[0]);
   const uint32_t *lst = d.list + c * (int64_t)d.list_cap;
-  for (int e0 = 0; e0 < nenv; e0 += CL) {
+  // Candidate j atoms of list entries [e0, e0 + 8): lane -> (entry, atom).
+  auto load_j = [&](int e0, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj, int &js) {
     const int ee = e0 + (lane >> 3);
-    T xj = far, yj = far, zj = far, qj = (T)0, aj = (T)0, bj = (T)0;
-    int js = -1;
+    xj = far;
+    yj = far;
+    zj = far;
+    qj = (T)0;
+    aj = (T)0;
+    bj = (T)0;
+    js = -1;
     if (ee < nenv) {
       const uint32_t ent = lst[ee];
       const int64_t J = ent & CL_MASK;
@@ -728,12 +760,71 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         bj = d.ljb[js];
       }
     }
-    if (e0 == 0)
-      env_pairs<T, LB, ENERGY, true>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
-                                     vmask, fx, fy, fz, eacc);
-    else
-      env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
+  };
+  {
+    // first 8 entries (the cluster's own entry among them) unpruned, with
+    // the self pairs masked
+    T xj, yj, zj, qj, aj, bj;
+    int js;
+    load_j(0, xj, yj, zj, qj, aj, bj, js);
+    env_pairs<T, LB, ENERGY, true>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js, vmask,
+                                   fx, fy, fz, eacc);
+  }
+  if (nenv > CL) {
+    // Remaining entries: a j atom farther than r_cut from the box of the 8
+    // i atoms cannot interact with any of them, so it is dropped before the
+    // pair arithmetic; survivors are compacted through a per-wave LDS ring
+    // and evaluated 64 at a time.  Coordinates are exact multiples of the
+    // storage grid, so the box gaps are exact and, with the same fma order as
+    // r^2, the box distance never exceeds any member pair's r^2: no pair
+    // inside the cutoff is dropped.
+    __shared__ Ring<T, LB> ring[4];
+    Ring<T, LB> &rg = ring[threadIdx.x >> 6];
+    T lox = far, loy = far, loz = far, hix = -far, hiy = -far, hiz = -far;
+#pragma unroll
+    for (int ii = 0; ii < CL; ++ii) {
+      if (d.orig[s0 + ii] >= 0) {
+        lox = fmin(lox, xi[ii]);
+        loy = fmin(loy, yi[ii]);
+        loz = fmin(loz, zi[ii]);
+        hix = fmax(hix, xi[ii]);
+        hiy = fmax(hiy, yi[ii]);
+        hiz = fmax(hiz, zi[ii]);
+      }
+    }
+    int head = 0, cnt = 0;
+    for (int e0 = CL; e0 < nenv; e0 += CL) {
+      T xj, yj, zj, qj, aj, bj;
+      int js;
+      load_j(e0, xj, yj, zj, qj, aj, bj, js);
+      const T gx = fmax(fmax(lox - xj, xj - hix), (T)0);
+      const T gy = fmax(fmax(loy - yj, yj - hiy), (T)0);
+      const T gz = fmax(fmax(loz - zj, zj - hiz), (T)0);
+      const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < d.rc2;
+      const unsigned long long bal = __ballot(keep);
+      if (keep) {
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        rg.put((head + cnt + pre) & (RING - 1), xj, yj, zj, qj, aj, bj);
+      }
+      cnt += __popcll(bal);
+      if (cnt >= WAVE) {
+        __builtin_amdgcn_wave_barrier();
+        T x2, y2, z2, q2, a2, b2;
+        rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
+        __builtin_amdgcn_wave_barrier();
+        env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+                                        vmask, fx, fy, fz, eacc);
+        head = (head + WAVE) & (RING - 1);
+        cnt -= WAVE;
+      }
+    }
+    if (cnt > 0) {
+      __builtin_amdgcn_wave_barrier();
+      T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
+      if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
+      env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
                                       vmask, fx, fy, fz, eacc);
+    }
   }
   if (nenv < n) {
     // alchemical partners: one atom per alchemical cluster (slot 0), 64 per pass
