@@ -41,6 +41,25 @@ SLOTS_PER_PAIR = 31
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_env_charged_lj_16x30k_pmc.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2307_08006_amd", "csrc", "labf_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per batched k_env launch from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(PMC_SUMMARY).read()
+        want = txt.split("kernel_source_sha256:")[1].split()[0]
+        nbytes = int(txt.split("traffic_bytes_per_launch:")[1].split()[0])
+        have = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    return nbytes if have == want else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -211,12 +230,12 @@ def main(argv=None):
         },
         "pair_interactions_per_s": pairs_per_step * args.steps / dt_b,
         "pairs_per_step": pairs_per_step,
-        "plain": {
+        "plain": None if args.plain_steps <= 0 else {
             "walker_steps_per_s": W * args.plain_steps / dt_p,
             "pair_interactions_per_s": pairs_per_step * args.plain_steps / dt_p,
             "ms_per_step": 1e3 * dt_p / args.plain_steps, "steps": args.plain_steps,
         },
-        "single_walker": {
+        "single_walker": None if args.single_steps <= 0 else {
             "walker_steps_per_s": args.single_steps / dt_1,
             "pair_interactions_per_s": pairs_1 * args.single_steps / dt_1,
             "ms_per_step": 1e3 * dt_1 / args.single_steps, "steps": args.single_steps,
@@ -229,7 +248,8 @@ def main(argv=None):
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "per_unit": f"{SLOTS_PER_PAIR} FP32 VALU lane-ops per in-cutoff environment pair",
             "units_per_launch": env_pairs_per_step,
         },
