@@ -105,6 +105,45 @@ def timed_steps(s, n, mode):
     return time.perf_counter() - t0
 
 
+def run_uneven(args):
+    """64 walkers of 5k-60k atoms (log-uniform; restrained dense cluster,
+    decoupled ligand, solvent) in one batch, column widths from the
+    autotuner (tuned once per size class and cached), against the same batch
+    at the default width and in plain mode."""
+    from paper_2307_08006_amd import autotune, labf, synth
+    spec, lam = synth.uneven(precision="fp32")
+    widths = autotune.tune(spec, lam, log=log)
+    log(f"uneven: {spec.n_walkers} walkers, {spec.n_atoms} atoms; equilibrating")
+    spec = equilibrate(spec, lam, args.uneven_equil_steps)
+    out = {"walkers": spec.n_walkers, "atoms": spec.n_atoms,
+           "size_classes": [list(c) for c in autotune.CLASSES],
+           "column_width_per_class": {}}
+    n = np.diff(spec.atom_offset)
+    for lo, hi in autotune.CLASSES:
+        m = (n >= lo) & (n < hi)
+        out["column_width_per_class"][f"{lo}-{hi}"] = float(widths[m][0]) if m.any() else None
+    for label, wd in (("tuned", widths), ("default_width", np.ones(spec.n_walkers))):
+        sp = dataclasses.replace(spec, column_width=wd)
+        with labf.System(sp, lam) as s:
+            pairs0 = float(s.count_pairs().sum())
+            s.step(args.warmup)
+            dt = timed_steps(s, args.uneven_steps, "batched")
+            pairs1 = float(s.count_pairs().sum())
+            st = s.read_walker_state()
+            rec = {"walker_steps_per_s": spec.n_walkers * args.uneven_steps / dt,
+                   "pair_interactions_per_s": 0.5 * (pairs0 + pairs1) * args.uneven_steps / dt,
+                   "ms_per_step": 1e3 * dt / args.uneven_steps, "steps": args.uneven_steps,
+                   "walker_status": int(np.bitwise_or.reduce(st["status"]))}
+            if label == "tuned" and args.uneven_plain_steps > 0:
+                dtp = timed_steps(s, args.uneven_plain_steps, "plain")
+                out["plain"] = {"walker_steps_per_s": spec.n_walkers * args.uneven_plain_steps / dtp,
+                                "ms_per_step": 1e3 * dtp / args.uneven_plain_steps,
+                                "steps": args.uneven_plain_steps}
+        log(f"uneven {label}: {rec['ms_per_step']:.3f} ms/step")
+        out[label] = rec
+    return out
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -142,6 +181,10 @@ def main(argv=None):
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--uneven-steps", type=int, default=200,
+                    help="timed steps of the 64-walker uneven batch (0: skip it)")
+    ap.add_argument("--uneven-plain-steps", type=int, default=20)
+    ap.add_argument("--uneven-equil-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -258,6 +301,8 @@ def main(argv=None):
                           "single": int(np.bitwise_or.reduce(st_1["status"]))},
         "layout": info,
     }
+    if args.uneven_steps > 0:
+        out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle)")
         v, cores, secs = cpu_baseline(specb, lamb, W, args.cpu_steps)

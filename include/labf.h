@@ -113,6 +113,10 @@ typedef struct labf_system_desc {
                                   atoms with k0 != k1), or 0: r_skin.  A decoupled solute has no
                                   solvent cage and can move much farther between rebuilds than the
                                   environment.  r_skin <= r_skin_alch, r_cut + r_skin_alch < L/2 */
+  const double *column_width;  /* [W] x-y width of the cluster columns in units of (8/rho)^(1/3)
+                                  (rho: the walker's environment atom density; 1 gives cubic
+                                  8-atom clusters), or NULL: 1 for every walker; 0.5 .. 2.
+                                  The tile shape that an autotuner chooses per size class */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF

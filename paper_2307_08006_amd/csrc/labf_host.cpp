@@ -217,6 +217,10 @@ labf_status validate_desc(const labf_system_desc *d) {
       !(d->accel_unit > 0))
     return fail(nullptr, LABF_E_ARG, "scalar parameter out of range");
   if (d->rebuild_interval < 1 || d->rebuild_interval > 1000) return fail(nullptr, LABF_E_ARG, "rebuild_interval out of range");
+  if (d->column_width)
+    for (int w = 0; w < d->n_walkers; ++w)
+      if (!(d->column_width[w] >= 0.5 && d->column_width[w] <= 2.0))
+        return fail(nullptr, LABF_E_ARG, "column_width must be in [0.5, 2]");
   const double rl = d->r_cut + std::max(d->r_skin, d->r_skin_alch);
   for (int w = 0; w < d->n_walkers; ++w)
     for (int k = 0; k < 3; ++k) {
@@ -440,7 +444,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       vol *= m.L[k];
     }
     const double rho = (double)std::max<int64_t>(nenv, 1) / vol;
-    const double target = std::cbrt((double)CL / rho);
+    const double target = std::cbrt((double)CL / rho) * (desc->column_width ? desc->column_width[w] : 1.0);
     m.ncx = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[0] / target)));
     m.ncy = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[1] / target)));
     m.cw[0] = m.L[0] / m.ncx;
@@ -504,6 +508,14 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, upload(b, &d.atom_walker, atom_walker.data(), N));
   HIPCHK(s, upload(b, &d.cl_walker, cl_walker.data(), s->C));
   HIPCHK(s, upload(b, &d.env_table, env_table.data(), s->E));
+  {
+    std::vector<int32_t> col_walker(s->K);
+    for (int w = 0; w < W; ++w) {
+      const WalkerMeta &m = s->meta[w];
+      for (int64_t k = m.col_begin; k < (int64_t)m.col_begin + (int64_t)m.ncx * m.ncy + 1; ++k) col_walker[k] = w;
+    }
+    HIPCHK(s, upload(b, &d.col_walker, col_walker.data(), col_walker.size()));
+  }
   for (auto pr : {std::make_pair(&d.a_q, desc->charge), std::make_pair(&d.a_sig, desc->sigma),
                   std::make_pair(&d.a_eps, desc->epsilon)}) {
     HIPCHK(s, dalloc(b, pr.first, N));
@@ -535,6 +547,7 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   HIPCHK(s, dalloc(b, &d.members, N));
   HIPCHK(s, dalloc(b, &d.xref, 3 * N));
   HIPCHK(s, dalloc(b, &d.disp, N));
+  HIPCHK(s, dalloc(b, &d.skin_part, (size_t)W * SKIN_PARTS * 4));
   HIPCHK(s, dalloc(b, &d.col_count, s->K));
   HIPCHK(s, dalloc(b, &d.col_fill, s->K));
   HIPCHK(s, dalloc(b, &d.col_atom0, s->K));
@@ -588,6 +601,13 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     for (int64_t i = 0; i < s->meta[w].n_atoms; ++i)
       slot0[s->meta[w].atom_begin + i] = (int32_t)(s->meta[w].cl_begin * CL + i);
   HIPCHK(s, hipMemcpy(d.slot_of, slot0.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+  {
+    // slot -> walker-local atom (-1: empty); the rebuilds keep it current
+    std::vector<int32_t> orig0(s->S, -1);
+    for (int w = 0; w < W; ++w)
+      for (int64_t i = 0; i < s->meta[w].n_atoms; ++i) orig0[slot0[s->meta[w].atom_begin + i]] = (int32_t)i;
+    HIPCHK(s, hipMemcpy(d.orig, orig0.data(), sizeof(int32_t) * s->S, hipMemcpyHostToDevice));
+  }
   HIPCHK(s, hipMemcpy(s->stage, pos_grid.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice));
   if (desc->vel) HIPCHK(s, hipMemcpy(s->stage2, desc->vel, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
   s->xb = 0;

@@ -22,6 +22,7 @@
 namespace labf {
 
 constexpr int CL = 8;                 // atoms per cluster
+constexpr int SKIN_PARTS = 8;         // blocks per walker of the list-validity reduction
 constexpr int WAVE = 64;              // CDNA wavefront
 constexpr int SHIFT_BITS = 26;        // cluster index bits in a list entry
 constexpr uint32_t CL_MASK = (1u << SHIFT_BITS) - 1u;
@@ -78,6 +79,7 @@ struct Dev {
   const int32_t *env_table;     // [sum cap_env] -> cluster
   const int32_t *item_walker;   // [sum item_cap]
   const int32_t *alch_cluster;  // [sum item_cap] alchemical cluster of each block, or -1
+  const int32_t *col_walker;    // [K] walker of each column (all walkers' columns concatenated)
   // --- caller-order atom data
   const double *a_pos0;         // [N][3] upload staging (B-offset, rounded)
   double *a_q, *a_sig, *a_eps;  // charge, sigma, epsilon (solute entries replaceable)
@@ -87,6 +89,7 @@ struct Dev {
   const uint8_t *a_sol, *a_alch;
   int32_t *slot_of, *new_slot, *col_of, *key_col, *members;
   float *disp;                  // [N] displacement since the last rebuild (rounded up)
+  float *skin_part;             // [W][SKIN_PARTS][4] partial top-two displacements
   T *xref;                      // [3][N] positions at the last rebuild
   // --- per column
   int32_t *col_count, *col_fill, *col_atom0, *col_cl0;

@@ -135,42 +135,69 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Adds one per lane to ctr[K] (lanes with K < 0 add nothing) with one atomic
+// per distinct K in the wave; returns the lane's offset among the additions
+// to its counter (old value + rank among the wave's lanes with the same K).
+// Slot order keeps a wave within one or two columns.
+__device__ __forceinline__ int wave_agg_add(int32_t *ctr, int64_t K) {
+  const int lane = lane_id();
+  unsigned long long todo = __ballot(K >= 0);
+  int result = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int64_t KL = __shfl(K, leader, WAVE);
+    const unsigned long long same = __ballot(K == KL) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[KL], __popcll(same));
+    base = __shfl(base, leader, WAVE);
+    if (K == KL) result = base + __popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return result;
+}
+
+// One thread per slot of the range (atoms in cluster order): wrap, finite
+// check, displacement since the last rebuild, column key and column counts.
 template <typename T>
 __global__ void k_key(Dev<T> d, Range r, int xb, int check) {
-  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= r.a0 + r.an) return;
-  const int w = d.atom_walker[a];
-  const WalkerMeta &m = d.meta[w];
-  const int s = d.slot_of[a];
-  double x[3];
-  bool finite = true;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const T xw = wrap_pos<T>(d.X[xb][k][s], (T)m.B[k], (T)m.L[k]);
-    x[k] = (double)xw;
-    finite = finite && isfinite(x[k]);
-  }
-  if (!finite) atomicOr(&d.status[w], 1u);
-  if (check) {
-    double r2 = 0.0;
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = s < (r.c0 + r.cn) * CL ? d.orig[s] : -1;
+  int64_t K = -1;
+  if (o >= 0) {
+    const int w = d.cl_walker[s / CL];
+    const WalkerMeta &m = d.meta[w];
+    const int64_t a = m.atom_begin + o;
+    double x[3];
+    bool finite = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double dd = min_image(x[k] - (double)d.xref[(int64_t)k * d.n_atoms + a], m.L[k]);
-      r2 += dd * dd;
+      const T xw = wrap_pos<T>(d.X[xb][k][s], (T)m.B[k], (T)m.L[k]);
+      x[k] = (double)xw;
+      finite = finite && isfinite(x[k]);
     }
-    // rounded up so that the skin test stays conservative
-    d.disp[a] = finite ? __double2float_ru(sqrt(r2)) : INFINITY;
+    if (!finite) atomicOr(&d.status[w], 1u);
+    if (check) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double dd = min_image(x[k] - (double)d.xref[(int64_t)k * d.n_atoms + a], m.L[k]);
+        r2 += dd * dd;
+      }
+      // rounded up so that the skin test stays conservative
+      d.disp[a] = finite ? __double2float_ru(sqrt(r2)) : INFINITY;
+    }
+    // clamp in floating point before converting (non-finite or far positions)
+    const double fx = fmin(fmax(floor((x[0] - m.B[0]) / m.cw[0]), 0.0), (double)(m.ncx - 1));
+    const double fy = fmin(fmax(floor((x[1] - m.B[1]) / m.cw[1]), 0.0), (double)(m.ncy - 1));
+    const int cx = finite ? (int)fx : 0;
+    const int cy = finite ? (int)fy : 0;
+    const int kc = cx * m.ncy + cy;
+    const int col = d.a_alch[a] ? m.ncx * m.ncy : kc;
+    d.key_col[a] = kc;
+    d.col_of[a] = col;
+    K = m.col_begin + col;
   }
-  // clamp in floating point before converting (non-finite or far positions)
-  const double fx = fmin(fmax(floor((x[0] - m.B[0]) / m.cw[0]), 0.0), (double)(m.ncx - 1));
-  const double fy = fmin(fmax(floor((x[1] - m.B[1]) / m.cw[1]), 0.0), (double)(m.ncy - 1));
-  const int cx = finite ? (int)fx : 0;
-  const int cy = finite ? (int)fy : 0;
-  const int kc = cx * m.ncy + cy;
-  const int col = d.a_alch[a] ? m.ncx * m.ncy : kc;
-  d.key_col[a] = kc;
-  d.col_of[a] = col;
-  atomicAdd(&d.col_count[m.col_begin + col], 1);
+  (void)wave_agg_add(d.col_count, K);
 }
 
 // Two largest displacements of a pair (m1 >= m2) merged with another pair.
@@ -180,19 +207,22 @@ __device__ __forceinline__ void top2_merge(float &m1, float &m2, float p1, float
   m2 = n2;
 }
 
-// One block per walker: a pair that was farther than r_list apart at the last
-// rebuild can have come within r_cut only if the displacements of its two
-// atoms add up to more than the skin.  Environment pairs are tested against
-// r_skin with the two largest environment displacements, pairs with an
-// alchemical atom against r_skin_alch with the largest alchemical displacement
-// plus the largest other one.
+// A pair that was farther than r_list apart at the last rebuild can have
+// come within r_cut only if the displacements of its two atoms add up to
+// more than the skin.  Environment pairs are tested against r_skin with the
+// two largest environment displacements, pairs with an alchemical atom
+// against r_skin_alch with the largest alchemical displacement plus the
+// largest other one.  SKIN_PARTS blocks per walker each reduce a slice of
+// its atoms to (e1, e2, a1, a2); the column scan of the walker merges them.
 template <typename T>
 __global__ __launch_bounds__(256) void k_skin(Dev<T> d, Range r) {
   __shared__ float sm[4][4];
-  const int w = r.w0 + blockIdx.x;
+  const int w = r.w0 + blockIdx.x / SKIN_PARTS, part = blockIdx.x % SKIN_PARTS;
   const WalkerMeta &m = d.meta[w];
+  const int chunk = (m.n_atoms + SKIN_PARTS - 1) / SKIN_PARTS;
+  const int i0 = part * chunk, i1 = min(m.n_atoms, i0 + chunk);
   float e1 = 0.f, e2 = 0.f, a1 = 0.f, a2 = 0.f;
-  for (int i = threadIdx.x; i < m.n_atoms; i += blockDim.x) {
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
     const int64_t a = m.atom_begin + i;
     const float v = d.disp[a];
     if (d.a_alch[a]) top2_merge(a1, a2, v, 0.f);
@@ -216,11 +246,27 @@ __global__ __launch_bounds__(256) void k_skin(Dev<T> d, Range r) {
       top2_merge(e1, e2, sm[k][0], sm[k][1]);
       top2_merge(a1, a2, sm[k][2], sm[k][3]);
     }
-    const double skin = d.r_list - d.r_cut, skin_a = d.r_list_a - d.r_cut;
-    const bool bad = (double)e1 + (double)e2 > skin || (double)a1 + (double)fmaxf(e1, a2) > skin_a ||
-                     !(e1 <= INFINITY) || !(a1 <= INFINITY);
-    if (bad) atomicOr(&d.status[w], 4u);
+    float *p = d.skin_part + ((int64_t)w * SKIN_PARTS + part) * 4;
+    p[0] = e1;
+    p[1] = e2;
+    p[2] = a1;
+    p[3] = a2;
   }
+}
+
+// Merge of a walker's partial maxima and the validity flag (one thread).
+template <typename T>
+__device__ void skin_flag(const Dev<T> &d, int w) {
+  float e1 = 0.f, e2 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int part = 0; part < SKIN_PARTS; ++part) {
+    const float *p = d.skin_part + ((int64_t)w * SKIN_PARTS + part) * 4;
+    top2_merge(e1, e2, p[0], p[1]);
+    top2_merge(a1, a2, p[2], p[3]);
+  }
+  const double skin = d.r_list - d.r_cut, skin_a = d.r_list_a - d.r_cut;
+  const bool bad = (double)e1 + (double)e2 > skin || (double)a1 + (double)fmaxf(e1, a2) > skin_a ||
+                   !(e1 <= INFINITY) || !(a1 <= INFINITY);
+  if (bad) atomicOr(&d.status[w], 4u);
 }
 
 // Block-wide exclusive scan of one int per thread (256 threads).
@@ -245,7 +291,7 @@ __device__ int block_excl_scan(int v, int *sm, int &total) {
 // multiple of 8 atoms), atom starts of the member lists; the alchemical
 // column starts at cap_env.
 template <typename T>
-__global__ __launch_bounds__(256) void k_scan(Dev<T> d, Range r) {
+__global__ __launch_bounds__(256) void k_scan(Dev<T> d, Range r, int check) {
   __shared__ int sm[8];
   __shared__ int run_a, run_c;
   const int w = r.w0 + blockIdx.x;
@@ -276,6 +322,7 @@ __global__ __launch_bounds__(256) void k_scan(Dev<T> d, Range r) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    if (check) skin_flag(d, w);
     int ne = run_c;
     if (ne > m.cap_env) {
       atomicOr(&d.status[w], 8u);
@@ -285,53 +332,81 @@ __global__ __launch_bounds__(256) void k_scan(Dev<T> d, Range r) {
   }
 }
 
+// Member lists of the columns (slot order, one atomic per column and wave).
 template <typename T>
 __global__ void k_members(Dev<T> d, Range r) {
-  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= r.a0 + r.an) return;
-  const int w = d.atom_walker[a];
-  const WalkerMeta &m = d.meta[w];
-  const int col = d.col_of[a];
-  const int pos = d.col_atom0[m.col_begin + col] + atomicAdd(&d.col_fill[m.col_begin + col], 1);
-  d.members[m.atom_begin + pos] = (int32_t)(a - m.atom_begin);
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = s < (r.c0 + r.cn) * CL ? d.orig[s] : -1;
+  int64_t K = -1, a = 0;
+  const WalkerMeta *m = nullptr;
+  if (o >= 0) {
+    m = &d.meta[d.cl_walker[s / CL]];
+    a = m->atom_begin + o;
+    K = m->col_begin + d.col_of[a];
+  }
+  const int pos = wave_agg_add(d.col_fill, K);
+  if (o >= 0) d.members[m->atom_begin + d.col_atom0[K] + pos] = o;
 }
 
-// Rank of an atom inside its column by (z, index); alchemical atoms by
-// (x-y column, z, index).  Deterministic whatever the member order.
+// One block per column: rank of each member by (z, index), alchemical atoms
+// by (x-y column, z, index), computed against the column held in LDS.
+// Deterministic whatever the member order.
+constexpr int RANK_LDS = 1024;
 template <typename T>
-__global__ void k_rank(Dev<T> d, Range r, int xb) {
-  const int64_t a = r.a0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= r.a0 + r.an) return;
-  const int w = d.atom_walker[a];
-  const WalkerMeta &m = d.meta[w];
-  const int col = d.col_of[a];
-  const int n = d.col_count[m.col_begin + col];
-  const int64_t mb = m.atom_begin + d.col_atom0[m.col_begin + col];
+__global__ __launch_bounds__(256) void k_rank(Dev<T> d, Range r, int xb) {
+  __shared__ T sz[RANK_LDS];
+  __shared__ int sidx[RANK_LDS], skc[RANK_LDS];
+  const int64_t K = r.k0 + blockIdx.x;
+  if (K >= r.k0 + r.kn) return;
+  const WalkerMeta &m = d.meta[d.col_walker[K]];
+  const int col = (int)(K - m.col_begin);
+  const int n = d.col_count[K];
+  const int64_t mb = m.atom_begin + d.col_atom0[K];
+  const bool alchcol = col == m.ncx * m.ncy;
   // positions are wrapped into the box only at a rebuild: sort on the wrapped
   // z, as the binning and the scatter use it
   const T *Z = d.X[xb][2];
   const T Bz = (T)m.B[2], Lz = (T)m.L[2];
-  const T z = wrap_pos<T>(Z[d.slot_of[a]], Bz, Lz);
-  const int me = (int)(a - m.atom_begin);
-  const int kc = d.key_col[a];
-  const bool alchcol = col == m.ncx * m.ncy;
-  int rank = 0;
-  for (int t = 0; t < n; ++t) {
-    const int bl = d.members[mb + t];
-    const int64_t b = m.atom_begin + bl;
-    const T zb = wrap_pos<T>(Z[d.slot_of[b]], Bz, Lz);
-    bool less = zb < z || (zb == z && bl < me);
-    if (alchcol) {
-      const int kb = d.key_col[b];
-      less = kb < kc || (kb == kc && less);
+  auto member = [&](int t, T &z, int &idx, int &kc) {
+    idx = d.members[mb + t];
+    const int64_t b = m.atom_begin + idx;
+    z = wrap_pos<T>(Z[d.slot_of[b]], Bz, Lz);
+    kc = alchcol ? d.key_col[b] : 0;
+  };
+  const bool fits = n <= RANK_LDS;
+  if (fits)
+    for (int t = threadIdx.x; t < n; t += blockDim.x) member(t, sz[t], sidx[t], skc[t]);
+  __syncthreads();
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    T z;
+    int me, kc;
+    if (fits) {
+      z = sz[t];
+      me = sidx[t];
+      kc = skc[t];
+    } else {
+      member(t, z, me, kc);
     }
-    rank += less ? 1 : 0;
+    int rank = 0;
+    for (int u = 0; u < n; ++u) {
+      T zb;
+      int bl, kb;
+      if (fits) {
+        zb = sz[u];
+        bl = sidx[u];
+        kb = skc[u];
+      } else {
+        member(u, zb, bl, kb);
+      }
+      const bool less = kb < kc || (kb == kc && (zb < z || (zb == z && bl < me)));
+      rank += less ? 1 : 0;
+    }
+    // environment atoms fill their column's clusters; every alchemical atom
+    // gets a cluster of its own (its list then covers the neighbourhood of
+    // one point however far apart the solute atoms drift)
+    d.new_slot[m.atom_begin + me] = alchcol ? (int32_t)((m.cl_begin + m.cap_env + rank) * CL)
+                                            : (int32_t)((m.cl_begin + d.col_cl0[K]) * CL + rank);
   }
-  // environment atoms fill their column's clusters; every alchemical atom
-  // gets a cluster of its own (its list then covers the neighbourhood of one
-  // point however far apart the solute atoms drift)
-  d.new_slot[a] = alchcol ? (int32_t)((m.cl_begin + m.cap_env + rank) * CL)
-                          : (int32_t)((m.cl_begin + d.col_cl0[m.col_begin + col]) * CL + rank);
 }
 
 template <typename T>
@@ -434,10 +509,33 @@ __device__ __forceinline__ double gap1(double lo_i, double hi_i, double lo_j, do
   return fmax(0.0, fmax(lo_j - hi_i, lo_i - hi_j));
 }
 
-// One wave per cluster.  Environment clusters list environment clusters
-// (their own (I, I, 0) entry first); alchemical clusters list every cluster.
+// Exclusive prefix sum across the wave and the wave total.
+__device__ __forceinline__ int wave_excl_scan(int v, int &total) {
+  const int lane = lane_id();
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += t;
+  }
+  total = __shfl(inc, WAVE - 1, WAVE);
+  return inc - v;
+}
+
+// One wave per cluster.  An environment cluster lists the environment
+// clusters within r_list (its own (I, I, 0) entry first), then the
+// alchemical clusters within r_list_a; an alchemical cluster lists every
+// cluster within r_list_a.  The columns in range are enumerated 64 at a
+// time (one lane per column, x-y gap test, cluster counts scanned across the
+// wave); their clusters are then flattened into passes of 64 lanes, each
+// lane testing the three z images of one cluster, so that a pass loads 64
+// cluster boxes however the columns are filled.  Alchemical partners take
+// one lane each, testing their 27 images in registers.
 template <typename T>
 __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
+  __shared__ int s_pre[4][WAVE + 1];
+  __shared__ int s_j0[4][WAVE];
+  __shared__ int s_sxy[4][WAVE];
   const int64_t c = r.c0 + (int64_t)blockIdx.x * 4 + uni(threadIdx.x >> 6);
   if (c >= r.c0 + r.cn) return;
   const int w = d.cl_walker[c];
@@ -446,7 +544,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
   const int64_t loc = c - m.cl_begin;
   if (!cluster_used(m, ne, c)) return;
   const bool isA = loc >= m.cap_env;
-  const int lane = lane_id();
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
   double lo[3], hi[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -468,7 +566,6 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
   }
   const bool box_ok = lo[0] <= hi[0] && isfinite(lo[0] + lo[1] + lo[2] + hi[0] + hi[1] + hi[2]);
   if (box_ok) {
-    // environment columns within r_list (raw column index carries the image)
     const double tolx = 1e-9 * m.L[0] + 1e-12, toly = 1e-9 * m.L[1] + 1e-12;
     // raw column indices carry the image (-1, 0, +1 box shifts only); clamp in
     // floating point so that far or non-finite boxes cannot produce huge ranges
@@ -479,79 +576,112 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
     const int rx1 = raw((hi[0] + rl - m.B[0]) / m.cw[0] + 1e-9, m.ncx);
     const int ry0 = raw((lo[1] - rl - m.B[1]) / m.cw[1] - 1e-9, m.ncy);
     const int ry1 = raw((hi[1] + rl - m.B[1]) / m.cw[1] + 1e-9, m.ncy);
-    for (int rx = rx0; rx <= rx1; ++rx) {
-      const int cx = ((rx % m.ncx) + m.ncx) % m.ncx;
-      const int sx = (rx - cx) / m.ncx;
-      if (sx < -1 || sx > 1) continue;
-      const double cxl = m.B[0] + rx * m.cw[0] - tolx, cxh = m.B[0] + (rx + 1) * m.cw[0] + tolx;
-      const double gx = gap1(lo[0], hi[0], cxl, cxh);
-      if (gx >= rl) continue;
-      for (int ry = ry0; ry <= ry1; ++ry) {
-        const int cy = ((ry % m.ncy) + m.ncy) % m.ncy;
-        const int sy = (ry - cy) / m.ncy;
-        if (sy < -1 || sy > 1) continue;
-        const double cyl = m.B[1] + ry * m.cw[1] - toly, cyh = m.B[1] + (ry + 1) * m.cw[1] + toly;
-        const double gy = gap1(lo[1], hi[1], cyl, cyh);
-        if (gx * gx + gy * gy >= rl2) continue;
-        const int col = cx * m.ncy + cy;
-        const int ncl = (d.col_count[m.col_begin + col] + CL - 1) / CL;
-        const int64_t J0 = m.cl_begin + d.col_cl0[m.col_begin + col];
-        for (int t0 = 0; t0 < ncl * 3; t0 += WAVE) {
-          const int t = t0 + lane;
-          bool pass = false;
-          int64_t J = 0;
-          int code = 0;
-          if (t < ncl * 3) {
-            J = J0 + t / 3;
-            const int sz = t % 3 - 1;
-            const double ox = sx * m.L[0], oy = sy * m.L[1], oz = sz * m.L[2];
-            const double *bj = d.bbox + J * 6;
-            const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
-            const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
-            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
-            code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1);
-            pass = ax * ax + ay * ay + az * az < rl2;
-            if (!isA && J == c && code == SHIFT_ZERO) pass = false;
+    const int nry = ry1 - ry0 + 1;
+    const int ncols = (rx1 - rx0 + 1) * nry;
+    for (int q0 = 0; q0 < ncols; q0 += WAVE) {
+      // one lane per column: x-y gap test, cluster count and first cluster
+      const int q = q0 + lane;
+      int ncl = 0, j0 = 0, sxy = 0;
+      if (q < ncols) {
+        const int rx = rx0 + q / nry, ry = ry0 + q % nry;
+        const int cx = ((rx % m.ncx) + m.ncx) % m.ncx, cy = ((ry % m.ncy) + m.ncy) % m.ncy;
+        const int sx = (rx - cx) / m.ncx, sy = (ry - cy) / m.ncy;
+        if (sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1) {
+          const double cxl = m.B[0] + rx * m.cw[0] - tolx, cxh = m.B[0] + (rx + 1) * m.cw[0] + tolx;
+          const double cyl = m.B[1] + ry * m.cw[1] - toly, cyh = m.B[1] + (ry + 1) * m.cw[1] + toly;
+          const double gx = gap1(lo[0], hi[0], cxl, cxh), gy = gap1(lo[1], hi[1], cyl, cyh);
+          if (gx * gx + gy * gy < rl2) {
+            const int col = cx * m.ncy + cy;
+            ncl = (d.col_count[m.col_begin + col] + CL - 1) / CL;
+            j0 = d.col_cl0[m.col_begin + col];
+            sxy = (sx + 1) * 3 + (sy + 1);
           }
+        }
+      }
+      int tot;
+      const int pre = wave_excl_scan(ncl, tot);
+      s_pre[wv][lane] = pre;
+      s_j0[wv][lane] = j0;
+      s_sxy[wv][lane] = sxy;
+      if (lane == 0) s_pre[wv][WAVE] = tot;
+      __builtin_amdgcn_wave_barrier();
+      for (int f0 = 0; f0 < tot; f0 += WAVE) {
+        const int f = f0 + lane;
+        unsigned mask = 0u;
+        int64_t J = 0;
+        int sx = 0, sy = 0;
+        if (f < tot) {
+          // the last column slot whose prefix is <= f (that column has clusters)
+          int a = 0, b = WAVE - 1;
+          while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (s_pre[wv][mid] <= f) a = mid;
+            else b = mid - 1;
+          }
+          J = m.cl_begin + s_j0[wv][a] + (f - s_pre[wv][a]);
+          const int code_xy = s_sxy[wv][a];
+          sx = code_xy / 3 - 1;
+          sy = code_xy % 3 - 1;
+          const double *bj = d.bbox + J * 6;
+          const double ox = sx * m.L[0], oy = sy * m.L[1];
+          const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
+          const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
+          const double axy = ax * ax + ay * ay;
+#pragma unroll
+          for (int sz = -1; sz <= 1; ++sz) {
+            const double oz = sz * m.L[2];
+            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
+            bool pass = axy + az * az < rl2;
+            if (!isA && J == c && sx == 0 && sy == 0 && sz == 0) pass = false;
+            mask |= (pass ? 1u : 0u) << (sz + 1);
+          }
+        }
+#pragma unroll
+        for (int zs = 0; zs < 3; ++zs) {
+          const bool pass = (mask >> zs) & 1u;
           const unsigned long long bal = __ballot(pass);
-          const int pre = __popcll(bal & ((1ull << lane) - 1ull));
           if (pass) {
-            const int pos = cnt + pre;
+            const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+            const int code = (sx + 1) * 9 + (sy + 1) * 3 + zs;
             if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
           }
           cnt += __popcll(bal);
         }
       }
+      __builtin_amdgcn_wave_barrier();
     }
     nenv = cnt;
-    // alchemical atoms (one per cluster) within r_list, every image: an
+    // alchemical atoms (one per cluster), every image within r_list_a: an
     // environment cluster computes their forces on its own atoms, an
     // alchemical cluster its alchemical-alchemical pairs
-    {
-      const int64_t A0 = m.cl_begin + m.cap_env;
-      for (int t0 = 0; t0 < m.n_acl * 27; t0 += WAVE) {
-        const int t = t0 + lane;
-        bool pass = false;
-        int64_t J = 0;
-        int code = 0;
-        if (t < m.n_acl * 27) {
-          J = A0 + t / 27;
-          code = t % 27;
-          const double ox = (code / 9 - 1) * m.L[0], oy = ((code / 3) % 3 - 1) * m.L[1],
-                       oz = (code % 3 - 1) * m.L[2];
-          const double *bj = d.bbox + J * 6;
-          if (bj[0] <= bj[3]) {
+    const int64_t A0 = m.cl_begin + m.cap_env;
+    for (int t0 = 0; t0 < m.n_acl; t0 += WAVE) {
+      const int t = t0 + lane;
+      unsigned mask = 0u;
+      int64_t J = 0;
+      if (t < m.n_acl) {
+        J = A0 + t;
+        const double *bj = d.bbox + J * 6;
+        if (bj[0] <= bj[3]) {
+          for (int code = 0; code < 27; ++code) {
+            const double ox = (code / 9 - 1) * m.L[0], oy = ((code / 3) % 3 - 1) * m.L[1],
+                         oz = (code % 3 - 1) * m.L[2];
             const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
             const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
             const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
-            pass = ax * ax + ay * ay + az * az < rla2;
+            if (ax * ax + ay * ay + az * az < rla2) mask |= 1u << code;
           }
         }
-        const unsigned long long bal = __ballot(pass);
-        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        if (pass && cnt + pre < cap) out[cnt + pre] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
-        cnt += __popcll(bal);
       }
+      int tot;
+      int pos = cnt + wave_excl_scan(__popc(mask), tot);
+      for (int code = 0; code < 27; ++code) {
+        if ((mask >> code) & 1u) {
+          if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
+          ++pos;
+        }
+      }
+      cnt += tot;
     }
   }
   if (lane == 0) {
@@ -1452,11 +1582,11 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
                               hipStream_t s) {
   if (r.an <= 0) return hipSuccess;
   k_fill_i32<<<nblk(r.kn, 256), 256, 0, s>>>(d.col_count + r.k0, r.kn, 0);
-  k_key<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, check);
-  if (check) k_skin<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r);
-  k_scan<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r);
-  k_members<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r);
-  k_rank<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb);
+  k_key<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r, xb, check);
+  if (check) k_skin<T><<<(unsigned)(r.wn * SKIN_PARTS), 256, 0, s>>>(d, r);
+  k_scan<T><<<(unsigned)r.wn, 256, 0, s>>>(d, r, check);
+  k_members<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r);
+  k_rank<T><<<(unsigned)r.kn, 256, 0, s>>>(d, r, xb);
   k_clear_slots<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r, xb ^ 1, vb ^ 1);
   k_scatter<T><<<nblk(r.an, 256), 256, 0, s>>>(d, r, xb, vb, xb ^ 1, vb ^ 1);
   k_bbox<T><<<nblk(r.cn, 256), 256, 0, s>>>(d, r, xb ^ 1);

@@ -50,7 +50,7 @@ class SystemDesc(C.Structure):
         ("gamma", C.c_double), ("dt", C.c_double), ("coulomb_k", C.c_double),
         ("accel_unit", C.c_double), ("seed", C.c_uint64),
         ("rebuild_interval", C.c_int32), ("reserved", C.c_int32),
-        ("r_skin_alch", C.c_double),
+        ("r_skin_alch", C.c_double), ("column_width", C.c_void_p),
     ]
 
 
@@ -84,6 +84,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LabfError(-3, f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        # torch carries its own HIP runtime; it must be loaded before this
+        # library starts HIP, or torch finds no GPU later in the process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
@@ -160,7 +166,7 @@ class System:
             pos=_f64(spec.pos, (-1, 3)), vel=_f64(spec.vel, (-1, 3)), mass=_f64(spec.mass),
             charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
             is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
-            k0=_f64(spec.k0), k1=_f64(spec.k1))
+            k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width))
         d = SystemDesc()
         d.n_walkers = spec.n_walkers
         d.precision = LABF_FP64 if spec.precision == "fp64" else LABF_FP32

@@ -64,6 +64,7 @@ class SystemSpec:
     k1: Optional[np.ndarray] = None      # float64 [N]
     rebuild_interval: int = 10
     r_skin_alch: float = 0.0             # list buffer of alchemical pairs; 0 -> r_skin
+    column_width: Optional[np.ndarray] = None  # float64 [W] cluster column width factor; None -> 1
     name: str = ""
 
     @property
@@ -326,8 +327,28 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         box=np.repeat(spec.box, n_walkers, axis=0), pos=rep(spec.pos), mass=rep(spec.mass),
         charge=rep(spec.charge), sigma=rep(spec.sigma), epsilon=rep(spec.epsilon),
         is_solute=rep(spec.is_solute), vel=None, anchor=rep(spec.anchor),
-        k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}")
+        k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}",
+        column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers))
     lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None)
+    return out, lam2
+
+
+def subset(spec: SystemSpec, lam: LambdaSpec, walkers) -> tuple:
+    """The given walkers of a batch as a batch of their own."""
+    walkers = [int(w) for w in walkers]
+    sl = [spec.walker_slice(w) for w in walkers]
+    pick = lambda a: None if a is None else np.concatenate([a[s] for s in sl])
+    off = np.zeros(len(walkers) + 1, np.int64)
+    off[1:] = np.cumsum([s.stop - s.start for s in sl])
+    out = dataclasses.replace(
+        spec, atom_offset=off, box=spec.box[walkers], pos=pick(spec.pos), vel=pick(spec.vel),
+        mass=pick(spec.mass), charge=pick(spec.charge), sigma=pick(spec.sigma),
+        epsilon=pick(spec.epsilon), is_solute=pick(spec.is_solute), anchor=pick(spec.anchor),
+        k0=pick(spec.k0), k1=pick(spec.k1),
+        column_width=None if spec.column_width is None else spec.column_width[walkers])
+    lam2 = dataclasses.replace(lam, lambda0=np.asarray(lam.lambda0)[walkers],
+                               p_lambda0=None if lam.p_lambda0 is None
+                               else np.asarray(lam.p_lambda0)[walkers])
     return out, lam2
 
 
@@ -346,7 +367,9 @@ def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
         mass=cat("mass"), charge=cat("charge"), sigma=cat("sigma"), epsilon=cat("epsilon"),
         is_solute=cat("is_solute"), vel=None,
         anchor=cat("anchor") if has_r else None, k0=cat("k0") if has_r else None,
-        k1=cat("k1") if has_r else None, seed=seed, name=name)
+        k1=cat("k1") if has_r else None, seed=seed, name=name,
+        column_width=np.concatenate([np.ones(1) if s.column_width is None else s.column_width
+                                     for s in specs]))
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lambda0, np.float64), p_lambda0=None)
     return out, lam2
 
@@ -359,7 +382,8 @@ def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
     harmonically (k = 1 kcal/mol/A^2, lambda-independent) to its initial
     sites, with a 20-80 atom decoupled ligand just outside the cluster (on
     the cube-corner sub-lattice, restrained to its sites like the solute of
-    charged_lj)."""
+    charged_lj).  Solvent sites start SHELL and the ligand LIG_GAP outside
+    the cluster so that no pair starts deep inside the LJ core."""
     rng = np.random.default_rng(seed)
     specs = []
     for w in range(n_walkers):
@@ -371,6 +395,10 @@ def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
                                      r_skin_alch))
     _, lam = charged_lj(n_atoms=3000, precision=precision)
     return concat(specs, lam, rng.uniform(0, 1, n_walkers), seed, "uneven")
+
+
+SHELL = 2.2     # A: solvent sites start this far outside the cluster (about one sigma)
+LIG_GAP = 3.5   # A: and the ligand this far (its sigma reaches 3.8 A)
 
 
 def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed, r_skin_alch=0.0):
@@ -390,22 +418,28 @@ def _cluster_walker(rng, N, n_cl, n_lig, precision, r_cut, r_skin, seed, r_skin_
     # ligand: sites in a shell just outside the cluster, along a seeded direction
     u = rng.normal(size=3)
     u /= np.linalg.norm(u)
-    solv_sites = _lattice_fcc(int(math.ceil(L / (4.0 / 0.1) ** (1.0 / 3.0))),
-                              L)
-    sv_basis = np.arange(solv_sites.shape[0]) % 4
-    sv_species = sv_basis // 2
-    ds = np.linalg.norm(solv_sites - c, axis=1)
-    out_idx = np.nonzero(ds > R_eff + 1.0)[0]
-    # ligand on the cube-corner sub-lattice (3.42 A spacing) nearest lig_c
-    lig_c = c + u * (R_eff + 3.0)
-    corner = out_idx[sv_basis[out_idx] == 0]
-    dl = np.linalg.norm(solv_sites[corner] - lig_c, axis=1)
-    lig_idx = corner[np.argsort(dl, kind="stable")[:n_lig]]
-    lig = solv_sites[lig_idx]
-    rest_idx = np.setdiff1d(out_idx, lig_idx)
+    # solvent: FCC sites outside R + 1 A; the 1 A shell costs sites, so the
+    # lattice is refined until enough remain (vacancies keep 0.1 atoms/A^3)
     n_solv = N - n_cl - n_lig
-    if rest_idx.shape[0] < n_solv:
-        raise ValueError("solvent lattice too small")
+    n_side = int(math.ceil(L / (4.0 / 0.1) ** (1.0 / 3.0)))
+    while True:
+        solv_sites = _lattice_fcc(n_side, L)
+        sv_basis = np.arange(solv_sites.shape[0]) % 4
+        sv_species = sv_basis // 2
+        ds = np.linalg.norm(solv_sites - c, axis=1)
+        out_idx = np.nonzero(ds > R_eff + SHELL)[0]
+        # ligand: the cube-corner sites (3.42 A apart) nearest a centre placed
+        # so that the ligand ball starts LIG_GAP outside the cluster
+        r_lig = (3.0 * n_lig * (4.0 / 0.1) / (4.0 * math.pi)) ** (1.0 / 3.0)
+        lig_c = c + u * (R_eff + LIG_GAP + r_lig)
+        corner = out_idx[(sv_basis[out_idx] == 0) & (ds[out_idx] > R_eff + LIG_GAP)]
+        dl = np.linalg.norm(solv_sites[corner] - lig_c, axis=1)
+        lig_idx = corner[np.argsort(dl, kind="stable")[:n_lig]]
+        lig = solv_sites[lig_idx]
+        rest_idx = np.setdiff1d(out_idx, lig_idx)
+        if rest_idx.shape[0] >= n_solv:
+            break
+        n_side += 1
     pick = rest_idx[np.sort(rng.permutation(rest_idx.shape[0])[:n_solv])]
     solv = solv_sites[pick]
     species = np.concatenate([cl_species[cl_pick], np.zeros(n_lig, np.int64), sv_species[pick]])

@@ -52,6 +52,7 @@ def _spec():
     (lambda s: setattr(s, "rebuild_interval", 0), "rebuild_interval"),
     (lambda s: setattr(s, "r_skin_alch", 0.1), "r_skin_alch"),
     (lambda s: setattr(s, "r_skin_alch", 1.5), "L/2"),
+    (lambda s: setattr(s, "column_width", np.array([0.3])), "column_width"),
     (lambda s: setattr(s, "precision", "fp16"), None),
 ])
 def test_invalid_descriptor_is_rejected_on_host(mutate, msg):

@@ -258,3 +258,30 @@ def test_list_validity_check_matches_host_displacements():
     assert (np.asarray(st) & ~np.uint32(4)).max() == 0
     assert any(want[:4]) and not all(want[:4])
     assert any(want[4:]) and not all(want[4:])
+
+
+def test_uneven_64_walkers_full_size_sampled():
+    """The 64-walker uneven batch (5k-60k atoms per walker, 1.34 M atoms) in
+    the launch configuration the benchmark times (autotuned column widths
+    from the cache): forces and dV/dlambda of the smallest, the largest and
+    two other walkers against the oracle, the pair count of the smallest."""
+    from paper_2307_08006_amd import autotune
+    spec, lam = synth.uneven(precision="fp32")
+    spec.column_width = autotune.cached_widths(spec)
+    n = np.diff(spec.atom_offset)
+    sample = sorted({int(np.argmin(n)), int(np.argmax(n)), 7, 40})
+    with labf.System(spec, lam) as s:
+        f, e, g = s.compute_forces()
+        pos, _ = s.read_atoms()
+        cnt = s.count_pairs()
+        st = s.read_walker_state()
+    assert (st["status"] & ~np.uint32(4)).max() == 0, st["status"]
+    o = oracle.Oracle(spec, lam)
+    for w in sample:
+        sl = spec.walker_slice(w)
+        fo, uo, go = o.evaluate(w, pos[sl], float(lam.lambda0[w]))
+        assert _rel(f[sl], fo) <= 1e-5, (w, _rel(f[sl], fo))
+        assert abs(g[w] - go) <= 1e-9 * max(abs(go), 1e-12), (w, g[w], go)
+    w = int(np.argmin(n))
+    sl = spec.walker_slice(w)
+    assert cnt[w] == len(o.neighbor_pairs(w, pos[sl], spec.r_cut))
