@@ -184,7 +184,7 @@ def main(argv=None):
     ap.add_argument("--uneven-steps", type=int, default=200,
                     help="timed steps of the 64-walker uneven batch (0: skip it)")
     ap.add_argument("--uneven-plain-steps", type=int, default=20)
-    ap.add_argument("--uneven-equil-steps", type=int, default=300)
+    ap.add_argument("--uneven-equil-steps", type=int, default=1500)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -26,7 +26,11 @@ constexpr int SKIN_PARTS = 8;         // blocks per walker of the list-validity 
 constexpr int WAVE = 64;              // CDNA wavefront
 constexpr int SHIFT_BITS = 26;        // cluster index bits in a list entry
 constexpr uint32_t CL_MASK = (1u << SHIFT_BITS) - 1u;
-constexpr int SHIFT_ZERO = 13;        // code of the (0,0,0) image
+// Image code of a list entry: two bits per axis holding s + 1 for the box
+// shift s in {-1, 0, 1} (x in bits 0-1, y in 2-3, z in 4-5).
+constexpr int image_code(int sx, int sy, int sz) { return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4); }
+constexpr int SHIFT_ZERO = image_code(0, 0, 0);  // code of the (0,0,0) image
+constexpr int IMG_CODES = 64;                    // table size indexed by code
 constexpr uint32_t LAMBDA_ATOM = 0xFFFFFFFFu;  // noise stream of lambda
 
 struct WalkerMeta {

@@ -32,6 +32,14 @@ namespace labf {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// box shift of each axis encoded in a list entry's image code
+__device__ __forceinline__ int img_x(int code) { return (code & 3) - 1; }
+__device__ __forceinline__ int img_y(int code) { return ((code >> 2) & 3) - 1; }
+__device__ __forceinline__ int img_z(int code) { return ((code >> 4) & 3) - 1; }
+// number of lanes below this one whose bit is set in a ballot
+__device__ __forceinline__ int lanes_below(unsigned long long bal) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+}
 
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v) {
@@ -642,7 +650,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
           const unsigned long long bal = __ballot(pass);
           if (pass) {
             const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
-            const int code = (sx + 1) * 9 + (sy + 1) * 3 + zs;
+            const int code = image_code(sx, sy, zs - 1);
             if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
           }
           cnt += __popcll(bal);
@@ -663,20 +671,21 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
         J = A0 + t;
         const double *bj = d.bbox + J * 6;
         if (bj[0] <= bj[3]) {
-          for (int code = 0; code < 27; ++code) {
-            const double ox = (code / 9 - 1) * m.L[0], oy = ((code / 3) % 3 - 1) * m.L[1],
-                         oz = (code % 3 - 1) * m.L[2];
+          for (int t27 = 0; t27 < 27; ++t27) {
+            const double ox = (t27 / 9 - 1) * m.L[0], oy = ((t27 / 3) % 3 - 1) * m.L[1],
+                         oz = (t27 % 3 - 1) * m.L[2];
             const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
             const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
             const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
-            if (ax * ax + ay * ay + az * az < rla2) mask |= 1u << code;
+            if (ax * ax + ay * ay + az * az < rla2) mask |= 1u << t27;
           }
         }
       }
       int tot;
       int pos = cnt + wave_excl_scan(__popc(mask), tot);
-      for (int code = 0; code < 27; ++code) {
-        if ((mask >> code) & 1u) {
+      for (int t27 = 0; t27 < 27; ++t27) {
+        if ((mask >> t27) & 1u) {
+          const int code = image_code(t27 / 9 - 1, (t27 / 3) % 3 - 1, t27 % 3 - 1);
           if (pos < cap) out[pos] = (uint32_t)J | ((uint32_t)code << SHIFT_BITS);
           ++pos;
         }
@@ -863,9 +872,15 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
 #pragma unroll
   for (int ii = 0; ii < CL; ++ii) fx[ii] = fy[ii] = fz[ii] = (T)0;
   double eacc = 0.0;
-  const T Lx = (T)m.L[0], Ly = (T)m.L[1], Lz = (T)m.L[2];
   const T far = (T)(8.0 * m.B[0]);
   const uint32_t *lst = d.list + c * (int64_t)d.list_cap;
+  // box shift of every image code for this wave's walker (lane = code)
+  __shared__ T shtab[4][3][IMG_CODES];
+  T *shx = shtab[threadIdx.x >> 6][0], *shy = shtab[threadIdx.x >> 6][1], *shz = shtab[threadIdx.x >> 6][2];
+  shx[lane] = (T)img_x(lane) * (T)m.L[0];
+  shy[lane] = (T)img_y(lane) * (T)m.L[1];
+  shz[lane] = (T)img_z(lane) * (T)m.L[2];
+  __builtin_amdgcn_wave_barrier();
   // Candidate j atoms of list entries [e0, e0 + 8): lane -> (entry, atom).
   auto load_j = [&](int e0, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj, int &js) {
     const int ee = e0 + (lane >> 3);
@@ -881,9 +896,9 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
       const int64_t J = ent & CL_MASK;
       const int code = (int)(ent >> SHIFT_BITS);
       js = (int)(J * CL + (lane & 7));
-      xj = X0[js] + (T)(code / 9 - 1) * Lx;
-      yj = X1[js] + (T)((code / 3) % 3 - 1) * Ly;
-      zj = X2[js] + (T)(code % 3 - 1) * Lz;
+      xj = X0[js] + shx[code];
+      yj = X1[js] + shy[code];
+      zj = X2[js] + shz[code];
       qj = d.q[js];
       if (LB) {
         aj = d.lja[js];
@@ -932,10 +947,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
       const T gz = fmax(fmax(loz - zj, zj - hiz), (T)0);
       const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < d.rc2;
       const unsigned long long bal = __ballot(keep);
-      if (keep) {
-        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        rg.put((head + cnt + pre) & (RING - 1), xj, yj, zj, qj, aj, bj);
-      }
+      if (keep) rg.put((head + cnt + lanes_below(bal)) & (RING - 1), xj, yj, zj, qj, aj, bj);
       cnt += __popcll(bal);
       if (cnt >= WAVE) {
         __builtin_amdgcn_wave_barrier();
@@ -973,9 +985,9 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         const int code = (int)(ent >> SHIFT_BITS);
         const int64_t js = J * CL;
         valid = d.orig[js] >= 0;
-        xj = X0[js] + (T)(code / 9 - 1) * Lx;
-        yj = X1[js] + (T)((code / 3) % 3 - 1) * Ly;
-        zj = X2[js] + (T)(code % 3 - 1) * Lz;
+        xj = X0[js] + shx[code];
+        yj = X1[js] + shy[code];
+        zj = X2[js] + shz[code];
         qj = d.q[js];
         aj = d.lja[js];
         bj = d.ljb[js];
@@ -1259,9 +1271,9 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
       const int code = (int)(ent >> SHIFT_BITS);
       const int64_t js = J * CL + (lane & 7);
       if (d.orig[js] < 0 || js == si) continue;
-      const double dx = ((double)d.X[xb][0][js] + (code / 9 - 1) * m.L[0]) - xi;
-      const double dy = ((double)d.X[xb][1][js] + ((code / 3) % 3 - 1) * m.L[1]) - yi;
-      const double dz = ((double)d.X[xb][2][js] + (code % 3 - 1) * m.L[2]) - zi;
+      const double dx = ((double)d.X[xb][0][js] + img_x(code) * m.L[0]) - xi;
+      const double dy = ((double)d.X[xb][1][js] + img_y(code) * m.L[1]) - yi;
+      const double dz = ((double)d.X[xb][2][js] + img_z(code) * m.L[2]) - zi;
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (!(r2 < rc2)) continue;
       const int solj = d.sol[js];
@@ -1352,9 +1364,9 @@ __global__ __launch_bounds__(256) void k_pairs(Dev<T> d, Range r, int xb, int mo
     const int oj = d.orig[js];
     if (oj < 0) continue;
     const bool isAj = (J - m.cl_begin) >= m.cap_env;
-    const double xj = __dadd_rn((double)d.X[xb][0][js], (code / 9 - 1) * m.L[0]);
-    const double yj = __dadd_rn((double)d.X[xb][1][js], ((code / 3) % 3 - 1) * m.L[1]);
-    const double zj = __dadd_rn((double)d.X[xb][2][js], (code % 3 - 1) * m.L[2]);
+    const double xj = __dadd_rn((double)d.X[xb][0][js], img_x(code) * m.L[0]);
+    const double yj = __dadd_rn((double)d.X[xb][1][js], img_y(code) * m.L[1]);
+    const double zj = __dadd_rn((double)d.X[xb][2][js], img_z(code) * m.L[2]);
     for (int ii = 0; ii < CL; ++ii) {
       const int64_t si = c * CL + ii;
       const int oi = d.orig[si];
