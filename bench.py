@@ -80,20 +80,27 @@ def _ensure_built():
         build.build(force=True)
 
 
-def equilibrate(spec, lam, steps):
-    """Untimed GPU equilibration at each walker's initial lambda (held
-    fixed, no ABF): strong friction, a 1 fs step and a rebuild every step.
-    Returns the spec with the equilibrated coordinates and velocities."""
+def equilibrate(spec, lam, steps, lambda_dynamics=False):
+    """Untimed GPU equilibration: strong atom friction, a 1 fs step and a
+    rebuild every step, no ABF.  With lambda_dynamics the extended system
+    (atoms and lambda) is equilibrated together, so that lambda has settled
+    where the unbiased dV/dlambda drives it before timing starts (otherwise
+    it falls there in the first ~100 timed steps, a sudden recoupling that
+    heats the solute); without, lambda stays at its initial value.
+    Returns (spec, lam) with the equilibrated coordinates, velocities and,
+    with lambda_dynamics, lambda (its momentum is drawn afresh)."""
     from paper_2307_08006_amd import labf
     eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0, rebuild_interval=1)
-    lm = dataclasses.replace(lam, fixed_lambda=True, abf_on=False)
+    lm = dataclasses.replace(lam, fixed_lambda=not lambda_dynamics, abf_on=False)
     with labf.System(eq, lm) as s:
         s.step(steps)
         pos, vel = s.read_atoms()
         st = s.read_walker_state()
     if st["status"].any() or not np.isfinite(pos).all():
         raise RuntimeError(f"equilibration failed: status {st['status']}")
-    return dataclasses.replace(spec, pos=pos, vel=vel)
+    if lambda_dynamics:
+        lam = dataclasses.replace(lam, lambda0=st["lam"].copy(), p_lambda0=None)
+    return dataclasses.replace(spec, pos=pos, vel=vel), lam
 
 
 def timed_steps(s, n, mode):
@@ -114,7 +121,7 @@ def run_uneven(args):
     spec, lam = synth.uneven(precision="fp32")
     widths = autotune.tune(spec, lam, log=log)
     log(f"uneven: {spec.n_walkers} walkers, {spec.n_atoms} atoms; equilibrating")
-    spec = equilibrate(spec, lam, args.uneven_equil_steps)
+    spec, lam = equilibrate(spec, lam, args.uneven_equil_steps, lambda_dynamics=True)
     out = {"walkers": spec.n_walkers, "atoms": spec.n_atoms,
            "size_classes": [list(c) for c in autotune.CLASSES],
            "column_width_per_class": {}}
@@ -213,10 +220,10 @@ def main(argv=None):
 
     spec1, lam1 = synth.charged_lj(n_atoms=args.atoms, precision="fp32")
     log(f"equilibrating {args.atoms} atoms for {args.equil_steps} steps")
-    spec1 = equilibrate(spec1, lam1, args.equil_steps)
+    spec1, _ = equilibrate(spec1, lam1, args.equil_steps)
     specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
     log(f"equilibrating the batch at its initial lambdas for {args.batch_equil_steps} steps")
-    specb = equilibrate(specb, lamb, args.batch_equil_steps)
+    specb, lamb = equilibrate(specb, lamb, args.batch_equil_steps, lambda_dynamics=True)
 
     out = {}
     with labf.System(specb, lamb) as s:
