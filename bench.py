@@ -151,6 +151,25 @@ def run_uneven(args):
     return out
 
 
+def run_ti(args, spec1, lam1):
+    """Fixed-lambda TI mode on the same 30k-atom system: 16 windows (lambda
+    frozen at the centres of 16 bins), one walker each, in one batch."""
+    from paper_2307_08006_amd import labf, synth
+    spec, lamw = synth.ti_windows(spec1, lam1, n_windows=16, replicas=1, seed=synth.BASE_SEED + 5)
+    spec, _ = equilibrate(spec, lamw, args.ti_equil_steps)
+    with labf.System(spec, lamw) as s:
+        s.step(args.warmup)
+        dt = timed_steps(s, args.ti_steps, "batched")
+        st = s.read_walker_state()
+        g, prof, da, rc = s.free_energy()
+    log(f"ti: {args.ti_steps} steps in {dt:.3f} s")
+    return {"windows": 16, "walker_steps_per_s": 16 * args.ti_steps / dt,
+            "ms_per_step": 1e3 * dt / args.ti_steps, "steps": args.ti_steps,
+            "walker_status": int(np.bitwise_or.reduce(st["status"])),
+            "dA_kcal_mol_so_far": da if rc == 0 else None,
+            "note": "throughput of the TI mode; the free energy after so few steps is not converged"}
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -192,6 +211,8 @@ def main(argv=None):
                     help="timed steps of the 64-walker uneven batch (0: skip it)")
     ap.add_argument("--uneven-plain-steps", type=int, default=20)
     ap.add_argument("--uneven-equil-steps", type=int, default=1500)
+    ap.add_argument("--ti-steps", type=int, default=200, help="timed fixed-lambda TI steps (0: skip)")
+    ap.add_argument("--ti-equil-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -308,6 +329,8 @@ def main(argv=None):
                           "single": int(np.bitwise_or.reduce(st_1["status"]))},
         "layout": info,
     }
+    if args.ti_steps > 0:
+        out["ti"] = run_ti(args, spec1, lam1)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:

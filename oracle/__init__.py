@@ -56,6 +56,7 @@ class OrcSys(C.Structure):
         ("sc_alpha", C.c_double), ("n_bins", C.c_int32), ("share_interval", C.c_int32),
         ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("full_samples", C.c_int64),
         ("fixed_lambda", C.c_int32), ("abf_on", C.c_int32),
+        ("sc_form", C.c_int32), ("pad1", C.c_int32), ("sc_shift", C.c_double),
     ]
 
 
@@ -79,6 +80,8 @@ def lib():
             L.orc_schedule.restype = None
             L.orc_pair_terms.argtypes = [D, D, D, D, D, D, D, I32, D, I32, P]
             L.orc_pair_terms.restype = None
+            L.orc_pair_terms_shifted.argtypes = [D, D, D, D, D, D, D, D, I32, P]
+            L.orc_pair_terms_shifted.restype = None
             L.orc_neighbor_pairs.argtypes = [P, I32, P, D, I32, I64, P]
             L.orc_neighbor_pairs.restype = I64
             L.orc_evaluate.argtypes = [P, I32, P, D, I32, P, P, P]
@@ -145,6 +148,8 @@ class Oracle:
         s.n_bins, s.lam_lo, s.lam_hi = lam.n_bins, lam.lo, lam.hi
         s.full_samples, s.share_interval = lam.full_samples, lam.share_interval
         s.fixed_lambda, s.abf_on = int(lam.fixed_lambda), int(lam.abf_on)
+        s.sc_form = 1 if lam.sc_form == "shifted" else 0
+        s.sc_shift = float(lam.sc_shift)
         self.sys = s
         self.st = None
 
@@ -237,6 +242,14 @@ def pair_terms(r, sig, eps, qq, cv, ce, alpha=0.5, p=1, r_cut=1e300, shift=False
     out = np.zeros(6)
     lib().orc_pair_terms(float(r), float(sig), float(eps), float(qq), float(cv), float(ce),
                          float(alpha), int(p), float(r_cut), int(shift), _p(out))
+    return out
+
+
+def pair_terms_shifted(r, sig, eps, qq, cv, ce, delta=5.0, r_cut=1e300, shift=False):
+    """Single-pair terms with the separation-shifted soft-core."""
+    out = np.zeros(6)
+    lib().orc_pair_terms_shifted(float(r), float(sig), float(eps), float(qq), float(cv), float(ce),
+                                 float(delta), float(r_cut), int(shift), _p(out))
     return out
 
 

@@ -139,6 +139,39 @@ void orc_pair_terms(double r, double sig, double eps, double qq, double cv, doub
   }
 }
 
+/* Separation-shifted soft-core (Zacharias, Straatsma and McCammon 1994;
+ * NAMD's alchVdwShiftCoeff): the LJ distance r^2 is replaced by
+ * s = r^2 + delta (1 - c) and the whole term is scaled by c,
+ *   phi(r, c) = 4 eps c (sig^12 / s^6 - sig^6 / s^3),
+ * i.e. c times the plain LJ at the effective distance sqrt(s).  Potential
+ * shift at r_cut with the same c.  Coulomb as in orc_pair_terms.
+ *   (F/r)  = -(1/r) dphi/dr = 4 eps c (12 sig^12 / s^7 - 6 sig^6 / s^4)
+ *   dphi/dc = 4 eps (sig^12/s^6 - sig^6/s^3) + 4 eps c delta (6 sig^12/s^7 - 3 sig^6/s^4) */
+static void shifted_lj(double r, double sig, double eps, double c, double delta, double out[3]) {
+  double s = r * r + delta * (1.0 - c);
+  double s6 = pow(sig, 6.0), s12 = s6 * s6;
+  out[0] = 4.0 * eps * c * (s12 / pow(s, 6.0) - s6 / pow(s, 3.0));
+  out[1] = 4.0 * eps * (s12 / pow(s, 6.0) - s6 / pow(s, 3.0)) +
+           4.0 * eps * c * delta * (6.0 * s12 / pow(s, 7.0) - 3.0 * s6 / pow(s, 4.0));
+  out[2] = 4.0 * eps * c * (12.0 * s12 / pow(s, 7.0) - 6.0 * s6 / pow(s, 4.0));
+}
+
+void orc_pair_terms_shifted(double r, double sig, double eps, double qq, double cv, double ce,
+                            double delta, double r_cut, int32_t shift, double out[6]) {
+  double t[3], tc[3];
+  int k;
+  orc_pair_terms(r, sig, 0.0, qq, cv, ce, 0.0, 1, r_cut, shift, out); /* Coulomb part */
+  if (eps == 0.0) return;
+  shifted_lj(r, sig, eps, cv, delta, t);
+  if (shift) {
+    shifted_lj(r_cut, sig, eps, cv, delta, tc);
+    for (k = 0; k < 2; ++k) t[k] -= tc[k];
+  }
+  out[0] = t[0];
+  out[1] = t[1];
+  out[2] = t[2];
+}
+
 /* ---------------------------------------------------------------------------
  * Minimum-image separation d = x_j - x_i (the neighbour-set definition):
  * d_k -= L_k * rint(d_k * (1/L_k)), 1/L_k evaluated once in FP64, rint is
@@ -340,7 +373,10 @@ static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], doubl
   qq = s->coulomb_k * s->charge[gi] * s->charge[gj];
   cv = alch ? c->cv : 1.0;
   ce = alch ? c->ce : 1.0;
-  orc_pair_terms(r, sig, eps, qq, cv, ce, s->sc_alpha, s->sc_power, rc, 1, t);
+  if (s->sc_form == 1)
+    orc_pair_terms_shifted(r, sig, eps, qq, cv, ce, s->sc_shift, rc, 1, t);
+  else
+    orc_pair_terms(r, sig, eps, qq, cv, ce, s->sc_alpha, s->sc_power, rc, 1, t);
   fr = t[2] + t[5];
   if (c->f) {
     /* d = x_j - x_i; a repulsive pair pushes i along -d */
@@ -366,7 +402,12 @@ static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], doubl
      *     dphi/dsig = 24 eps c (2s-1) s^2 (r/sig)^6 / sig (shift included)
      *   U_C = ce k q_i q_j g(r): dU/dq_i = ce k q_j g(r)                     */
     double dsig = 0.0;
-    if (eps != 0.0) {
+    if (eps != 0.0 && s->sc_form == 1) {
+      /* d/dsig of 4 eps c (sig^12 s^-6 - sig^6 s^-3) = 4 eps c (12 sig^11 s^-6 - 6 sig^5 s^-3) */
+      double sa = r * r + s->sc_shift * (1.0 - cv), sb = rc * rc + s->sc_shift * (1.0 - cv);
+      dsig = 4.0 * eps * cv * ((12.0 * pow(sig, 11.0) / pow(sa, 6.0) - 6.0 * pow(sig, 5.0) / pow(sa, 3.0)) -
+                               (12.0 * pow(sig, 11.0) / pow(sb, 6.0) - 6.0 * pow(sig, 5.0) / pow(sb, 3.0)));
+    } else if (eps != 0.0) {
       double a = s->sc_alpha * pow(1.0 - cv, (double)s->sc_power);
       double u1 = pow(r / sig, 6.0), u2 = pow(rc / sig, 6.0);
       double s1 = 1.0 / (a + u1), s2 = 1.0 / (a + u2);

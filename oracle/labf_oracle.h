@@ -50,6 +50,10 @@ typedef struct orc_sys {
   int64_t full_samples;
   int32_t fixed_lambda;         /* 1: lambda frozen (fixed-lambda TI)      */
   int32_t abf_on;               /* 0: no samples and no bias               */
+  int32_t sc_form;              /* 0: alpha (1-c)^p + (r/sig)^6 in the denominator;
+                                   1: separation-shifted, r^2 -> r^2 + delta (1-c) */
+  int32_t pad1;
+  double sc_shift;              /* delta of the separation-shifted form (length^2) */
 } orc_sys;
 
 /* Dynamic state.  x, v: [N][3]; per-walker arrays: [W]; bins: [nbins];
@@ -74,6 +78,8 @@ enum { ORC_U_ENV = 0, ORC_U_SOLUTE = 1, ORC_U_ALCH_LJ = 2, ORC_U_ALCH_C = 3, ORC
 void orc_schedule(const orc_sys *s, double lam, double out[4]);
 void orc_pair_terms(double r, double sig, double eps, double qq, double cv, double ce,
                     double alpha, int32_t p, double r_cut, int32_t shift, double out[6]);
+void orc_pair_terms_shifted(double r, double sig, double eps, double qq, double cv, double ce,
+                            double delta, double r_cut, int32_t shift, double out[6]);
 int64_t orc_neighbor_pairs(const orc_sys *s, int32_t w, const double *x, double r_list,
                            int32_t brute, int64_t max_pairs, int64_t *pairs);
 int32_t orc_evaluate(const orc_sys *s, int32_t w, const double *x, double lam,

@@ -101,6 +101,8 @@ class LambdaSpec:
     share_interval: int = 1
     fixed_lambda: bool = False
     abf_on: bool = True
+    sc_form: str = "beutler"         # "beutler": alpha (1-c)^p + (r/sig)^6; "shifted": r^2 + delta (1-c)
+    sc_shift: float = 5.0            # delta of the separation-shifted form (length^2)
 
 
 def _pow2_at_least(x: float) -> float:
@@ -330,6 +332,20 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}",
         column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers))
     lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None)
+    return out, lam2
+
+
+def ti_windows(spec: SystemSpec, lam: LambdaSpec, n_windows: int, replicas: int, seed: int):
+    """Fixed-lambda thermodynamic integration: n_windows x replicas copies of
+    a one-walker system, lambda frozen at the centres of n_windows equal bins
+    on [lo, hi] (window-major order).  The per-bin mean of dV/dlambda is then
+    the window average and the bin readout (Riemann sum) is the midpoint-rule
+    TI estimate of the free-energy difference."""
+    out, lam2 = batch(spec, lam, n_windows * replicas, seed=seed)
+    w = (lam.hi - lam.lo) / n_windows
+    centres = lam.lo + (np.arange(n_windows) + 0.5) * w
+    lam2 = dataclasses.replace(lam2, lambda0=np.repeat(centres, replicas), n_bins=n_windows,
+                               fixed_lambda=True, abf_on=True, p_lambda0=None)
     return out, lam2
 
 

@@ -119,9 +119,15 @@ def _state(s):
     return st, c, s1, s2, pos, vel
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "fixed_lambda"])
 def test_short_fp64_trajectory_matches_oracle(mode):
-    spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35)
+    if mode == "fixed_lambda":
+        # fixed-lambda TI windows: lambda frozen at 4 window centres
+        base, lam0 = synth.lj_reduced(n_walkers=1)
+        spec, lam = synth.ti_windows(base, lam0, n_windows=4, replicas=1, seed=77)
+        mode = "batched"
+    else:
+        spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35)
     lam.share_interval = 2
     s = labf.System(spec, lam)
     o = oracle.Oracle(spec, lam)
@@ -184,6 +190,24 @@ def test_harmonic_restraint_free_energy_closed_form():
     st = s.read_walker_state()
     assert (st["status"] == 0).all()
     s.close()
+
+
+def test_fixed_lambda_ti_harmonic_closed_form():
+    """Fixed-lambda TI on the GPU: 50 windows x 16 replicas of the 3-particle
+    harmonic system, lambda frozen at the window centres; the midpoint sum
+    of the window means reproduces (9/2) kT ln(k1/k0) within 0.05 kT."""
+    base, lam = synth.harmonic(n_walkers=1, seed=911)
+    spec, lamw = synth.ti_windows(base, lam, n_windows=50, replicas=16, seed=912)
+    with labf.System(spec, lamw) as s:
+        s.step(40000)
+        g, prof, da, rc = s.free_energy()
+        st = s.read_walker_state()
+        cnt, _, _ = s.read_abf_bins()
+    assert rc == 0
+    assert np.array_equal(st["lam"], lamw.lambda0) and (st["status"] == 0).all()
+    assert (cnt == 16 * 40000).all()
+    exact = 4.5 * spec.kT * math.log(4.0)
+    assert abs(da - exact) < 0.05 * spec.kT, (da, exact)
 
 
 def test_full_size_single_walker_forces():

@@ -164,9 +164,10 @@ def test_neighbor_boundary_pairs_are_strict():
 # --------------------------------------------------------------------------
 # forces, dU/dlambda, endpoints
 # --------------------------------------------------------------------------
-def _charged_small(seed=7, n_sol=3):
+def _charged_small(seed=7, n_sol=3, form="beutler"):
     spec, lam = synth.lj_reduced(n_atoms=125, density=0.5, seed=seed, jitter=0.15, charges=0.5,
                                  r_cut=2.5)
+    lam.sc_form, lam.sc_shift = form, 0.5
     spec.is_solute[:] = 0
     spec.is_solute[:n_sol] = 1
     spec.sigma[:n_sol] = [0.9, 1.2, 1.05][:n_sol]
@@ -441,3 +442,110 @@ def test_harmonic_restraint_free_energy_closed_form():
     # the lambda histogram is flat under the converged bias
     frac = cnt / cnt.sum()
     assert frac.min() > 0.5 / 50 and frac.max() < 1.6 / 50
+
+
+@pytest.mark.slow
+def test_fixed_lambda_ti_harmonic_closed_form():
+    """Fixed-lambda TI (lambda frozen at 50 window centres, 16 replicas each):
+    the midpoint sum of the window means of dV/dlambda reproduces
+    (9/2) kT ln(k1/k0); every sample of a walker lands in its own window."""
+    base, lam = synth.harmonic(n_walkers=1, seed=911)
+    spec, lamw = synth.ti_windows(base, lam, n_windows=50, replicas=16, seed=912)
+    o = oracle.Oracle(spec, lamw)
+    st = o.init_state()
+    o.run(40000)
+    assert np.array_equal(st["lam"], lamw.lambda0)          # frozen
+    cnt = st["bin_count"] + st["loc_count"].sum(0)
+    tot = st["bin_sum"] + st["loc_sum"].sum(0)
+    assert (cnt == 16 * 40000).all()
+    g, prof, da, rc = oracle.abf_readout(cnt, tot, 0.0, 1.0)
+    assert rc == 0
+    exact = 4.5 * spec.kT * math.log(4.0)
+    assert abs(da - exact) < 0.05 * spec.kT, (da, exact)
+    # window means against the closed form <dV/dlambda> = (9/2)(k1 - k0) kT / k(lambda)
+    lc = (np.arange(50) + 0.5) / 50
+    want = 4.5 * 3.0 / (1.0 + 3.0 * lc)
+    # statistical error of a window mean: dV/dlambda = (3/2) sum of 9 x^2 with
+    # var(x^2) = 2 (kT/k)^2 and ~200 independent samples per walker-window
+    # (40000 steps of 0.005 over a unit correlation time): sigma ~ 0.11 / k
+    sigma = 0.11 / (1.0 + 3.0 * lc)
+    assert (np.abs(g - want) < 4.5 * sigma).all(), np.max(np.abs(g - want) / sigma)
+
+
+# --------------------------------------------------------------------------
+# separation-shifted (Zacharias) soft-core variant
+# --------------------------------------------------------------------------
+def test_shifted_softcore_is_lj_at_the_effective_distance():
+    """s = r^2 + delta (1 - c) makes the term c times the plain LJ at distance
+    sqrt(s): energy, F/r (times the chain factor) and the shift at r_cut all
+    follow from the textbook LJ pinned above."""
+    rng = np.random.default_rng(21)
+    for _ in range(50):
+        r, sig, eps = rng.uniform(0.3, 2.4), rng.uniform(0.8, 1.3), rng.uniform(0.2, 2.0)
+        c, delta, rc = rng.uniform(0.0, 1.0), rng.uniform(0.1, 6.0), 2.5
+        reff, rceff = math.sqrt(r * r + delta * (1 - c)), math.sqrt(rc * rc + delta * (1 - c))
+        z = oracle.pair_terms_shifted(r, sig, eps, 0.0, c, 1.0, delta=delta, r_cut=rc, shift=True)
+        lj = oracle.pair_terms(reff, sig, eps, 0.0, 1.0, 1.0)
+        ljc = oracle.pair_terms(rceff, sig, eps, 0.0, 1.0, 1.0)
+        assert z[0] == pytest.approx(c * (lj[0] - ljc[0]), rel=1e-11, abs=1e-14)
+        # -(1/r) dU/dr = c (F/r)_LJ(r_eff), since d r_eff / d r = r / r_eff
+        assert z[2] == pytest.approx(c * lj[2], rel=1e-11, abs=1e-14)
+
+
+def test_shifted_softcore_full_coupling_is_textbook_lj():
+    for r in (0.9, 1.12, 1.7, 2.4):
+        z = oracle.pair_terms_shifted(r, 1.1, 0.7, 0.0, 1.0, 1.0, delta=3.0, r_cut=2.5, shift=True)
+        t = 4 * 0.7 * ((1.1 / r) ** 12 - (1.1 / r) ** 6) - 4 * 0.7 * ((1.1 / 2.5) ** 12 - (1.1 / 2.5) ** 6)
+        assert z[0] == pytest.approx(t, rel=1e-12)
+    # finite at r = 0 below full coupling
+    z0 = oracle.pair_terms_shifted(0.0, 1.0, 1.0, 0.0, 0.5, 1.0, delta=2.0)
+    assert z0[0] == pytest.approx(4 * 0.5 * (1.0 / 1.0 ** 6 - 1.0 / 1.0 ** 3), abs=1e-15)
+
+
+@pytest.mark.parametrize("c", [1.0, 0.7, 0.3, 0.02])
+def test_shifted_softcore_pair_fd(c):
+    h = 1e-6
+    for r in (0.6, 1.0, 1.6, 2.3):
+        z = oracle.pair_terms_shifted(r, 1.05, 0.9, 0.0, c, 1.0, delta=0.5, r_cut=2.5, shift=True)
+        up = oracle.pair_terms_shifted(r + h, 1.05, 0.9, 0.0, c, 1.0, delta=0.5, r_cut=2.5, shift=True)
+        dn = oracle.pair_terms_shifted(r - h, 1.05, 0.9, 0.0, c, 1.0, delta=0.5, r_cut=2.5, shift=True)
+        assert z[2] * r == pytest.approx(-(up[0] - dn[0]) / (2 * h), rel=1e-6, abs=1e-9)
+        if 0.0 < c < 1.0:
+            cp = oracle.pair_terms_shifted(r, 1.05, 0.9, 0.0, c + h, 1.0, delta=0.5, r_cut=2.5, shift=True)
+            cm = oracle.pair_terms_shifted(r, 1.05, 0.9, 0.0, c - h, 1.0, delta=0.5, r_cut=2.5, shift=True)
+            assert z[1] == pytest.approx((cp[0] - cm[0]) / (2 * h), rel=1e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("l", [0.0, 0.3, 0.62, 0.8, 0.97])
+def test_shifted_softcore_system_derivatives_match_fd(l):
+    """Forces, dV/dlambda and dV/d(eps, sigma, q) of a small charged system
+    with the separation-shifted form against central differences."""
+    spec, lam = _charged_small(form="shifted")
+    o = oracle.Oracle(spec, lam)
+    x = spec.pos.copy()
+    f, _, g = o.evaluate(0, x, l)
+    h = 1e-6
+    for i in (0, 1, 2, 40):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = -(_energy(o, xp, l) - _energy(o, xm, l)) / (2 * h)
+            assert abs(f[i, k] - fd) < 1e-6 * max(1.0, abs(fd)), (i, k, f[i, k], fd)
+    hl = 1e-4
+    if l == 0.0:
+        fd = (-3 * _energy(o, x, 0) + 4 * _energy(o, x, hl) - _energy(o, x, 2 * hl)) / (2 * hl)
+    else:
+        fd = (_energy(o, x, l + hl) - _energy(o, x, l - hl)) / (2 * hl)
+    assert abs(g - fd) < 1e-7 * max(1.0, abs(g)), (g, fd)
+    pg = o.param_grad(0, x, l)
+    hp = 1e-5
+    for i in (0, 1, 2):
+        for k, field in enumerate(["epsilon", "sigma", "charge"]):
+            vals = []
+            for sgn in (+1, -1):
+                sp, _ = _charged_small(form="shifted")
+                getattr(sp, field)[i] += sgn * hp
+                vals.append(oracle.Oracle(sp, lam).evaluate(0, x, l)[1].sum())
+            fd = (vals[0] - vals[1]) / (2 * hp)
+            assert abs(pg[i, k] - fd) < 1e-6 * max(1.0, abs(fd)), (i, field, pg[i, k], fd)
