@@ -170,6 +170,25 @@ def run_ti(args, spec1, lam1):
             "note": "throughput of the TI mode; the free energy after so few steps is not converged"}
 
 
+def run_shifted(args, specb, lamb):
+    """The 16-walker batch with the separation-shifted soft-core (delta =
+    5 A^2) and the staggered schedule of the NAMD setup (electrostatics over
+    [0, 0.5], vdW over [0, 1]), after a short re-equilibration under it."""
+    from paper_2307_08006_amd import labf
+    lam = dataclasses.replace(lamb, sc_form="shifted", sc_shift=5.0, elec_start=0.0, elec_end=0.5,
+                              vdw_start=0.0, vdw_end=1.0)
+    spec, lam = equilibrate(specb, lam, args.variant_equil_steps, lambda_dynamics=True)
+    with labf.System(spec, lam) as s:
+        s.step(args.warmup)
+        dt = timed_steps(s, args.variant_steps, "batched")
+        st = s.read_walker_state()
+        prof = s.profile_steps(args.profile_steps)
+    log(f"shifted soft-core: {args.variant_steps} steps in {dt:.3f} s")
+    return {"walker_steps_per_s": spec.n_walkers * args.variant_steps / dt,
+            "ms_per_step": 1e3 * dt / args.variant_steps, "steps": args.variant_steps,
+            "kernels_ms": prof, "walker_status": int(np.bitwise_or.reduce(st["status"]))}
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -213,6 +232,9 @@ def main(argv=None):
     ap.add_argument("--uneven-equil-steps", type=int, default=1500)
     ap.add_argument("--ti-steps", type=int, default=200, help="timed fixed-lambda TI steps (0: skip)")
     ap.add_argument("--ti-equil-steps", type=int, default=300)
+    ap.add_argument("--variant-steps", type=int, default=200,
+                    help="timed steps of the separation-shifted soft-core variant (0: skip)")
+    ap.add_argument("--variant-equil-steps", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -331,6 +353,8 @@ def main(argv=None):
     }
     if args.ti_steps > 0:
         out["ti"] = run_ti(args, spec1, lam1)
+    if args.variant_steps > 0:
+        out["shifted_softcore"] = run_shifted(args, specb, lamb)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:

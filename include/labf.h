@@ -73,6 +73,11 @@ typedef int32_t labf_status;
 #define LABF_DECOUPLE 0          /* c_x = 1 - ramp_x(lambda) (NAMD convention)  */
 #define LABF_COUPLE 1            /* c_x = ramp_x(lambda) (Tinker-HP convention) */
 
+/* soft-core form of the lambda-scaled LJ ("Alchemical pathway"; the
+ * separation-shifted form is the one of the NAMD setup of the SI) */
+#define LABF_SC_BEUTLER 0        /* 4 eps c (y^2 - y), y = 1/(alpha (1-c)^p + (r/sig)^6) */
+#define LABF_SC_SHIFTED 1        /* 4 eps c (sig^12/s^6 - sig^6/s^3), s = r^2 + sc_shift (1-c) */
+
 #define LABF_MODE_BATCHED 0      /* all walkers per launch, 10-step blocks replayed as HIP graphs */
 #define LABF_MODE_PLAIN 1        /* one walker per launch sequence, no graph    */
 
@@ -138,6 +143,9 @@ typedef struct labf_lambda_params {
   int64_t full_samples;        /* bias ramp length (>= 1)                         */
   int32_t fixed_lambda;        /* 1: lambda frozen (samples still accumulated)   */
   int32_t abf_on;              /* 0: no ABF samples and no bias                   */
+  int32_t sc_form;             /* LABF_SC_BEUTLER | LABF_SC_SHIFTED               */
+  int32_t reserved2;           /* must be 0                                       */
+  double sc_shift;             /* delta of LABF_SC_SHIFTED (length^2, >= 0)       */
 } labf_lambda_params;
 
 /* Create a system: validates the descriptor on the host, allocates device

@@ -259,6 +259,10 @@ labf_status validate_lambda(const labf_system *s, const labf_lambda_params *p) {
   if (!(p->elec_start < p->elec_end) || !(p->vdw_start < p->vdw_end)) return bad("schedule ramps need start < end");
   if (p->direction != LABF_DECOUPLE && p->direction != LABF_COUPLE) return bad("bad direction");
   if (p->sc_power < 1 || p->sc_power > 8 || p->sc_alpha < 0) return bad("soft-core parameters out of range");
+  if ((p->sc_form != LABF_SC_BEUTLER && p->sc_form != LABF_SC_SHIFTED) || !std::isfinite(p->sc_shift) ||
+      p->sc_shift < 0)
+    return bad("sc_form must be LABF_SC_BEUTLER or LABF_SC_SHIFTED, sc_shift finite and >= 0");
+  if (p->reserved2 != 0) return bad("reserved2 must be 0");
   if (p->n_bins < 1 || p->n_bins > 4096) return bad("n_bins out of range");
   if (p->share_interval < 1) return bad("share_interval must be >= 1");
   if (!(p->lo < p->hi)) return bad("lo must be < hi");
@@ -675,6 +679,8 @@ labf_status set_lambda_impl(labf_system *s, const labf_lambda_params *p, hipStre
   lp.full_samples = p->full_samples;
   lp.direction = p->direction;
   lp.sc_power = p->sc_power;
+  lp.sc_form = p->sc_form;
+  lp.sc_shift = p->sc_shift;
   lp.n_bins = p->n_bins;
   lp.share_interval = p->share_interval;
   lp.fixed_lambda = p->fixed_lambda;

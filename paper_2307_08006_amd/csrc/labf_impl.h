@@ -55,11 +55,12 @@ struct WalkerMeta {
 struct LamParams {
   double m_lambda, gamma_lambda, kT_lambda;
   double elec_start, elec_end, vdw_start, vdw_end;
-  double sc_alpha;
+  double sc_alpha, sc_shift;   // sc_shift: delta of the separation-shifted form
   double lo, hi, bin_w;
   double c1l, sdl;          // exp(-gamma_l dt), sqrt((1 - c1l^2) kT_l m_l)
   int64_t full_samples;
   int32_t direction, sc_power, n_bins, share_interval, fixed_lambda, abf_on;
+  int32_t sc_form;             // 0: alpha (1-c)^p + (r/sig)^6; 1: r^2 + delta (1-c)
 };
 
 // Everything the kernels touch.  Pointers are device pointers.

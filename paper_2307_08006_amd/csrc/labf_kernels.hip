@@ -784,14 +784,17 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
 // soft-core LJ at coupling cv with A = alpha (1 - cv)^p and shifted-force
 // Coulomb at ce for solute partners, plain terms (c = 1) for the others.
 // Energies and dV/dlambda of these pairs are accounted on the alchemical side.
-template <typename T>
+template <typename T, bool SHIFTED>
 __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL],
                                                const T (&yi)[CL], const T (&zi)[CL],
                                                const T (&qi)[CL], const T (&ai)[CL],
                                                const T (&bi)[CL], T xj, T yj, T zj, T qj, T aj,
                                                T bj, bool alch, bool valid, T cv, T ce, T Asc,
-                                               T (&fx)[CL], T (&fy)[CL], T (&fz)[CL]) {
-  const T c = alch ? cv : (T)1, e = alch ? ce : (T)1, A = alch ? Asc : (T)0;
+                                               T Dsc, T (&fx)[CL], T (&fy)[CL], T (&fz)[CL]) {
+  // soft-core: y = 1/(A + (r/sig)^6) or y = (sig^2 / (r^2 + D))^3 (separation
+  // shifted, D = delta (1 - c)); F/r of the LJ part = 24 eps c (2y - 1) y g with
+  // g = y (r/sig)^6 / r^2 or 1 / (r^2 + D); c = 1, A = D = 0 for plain pairs
+  const T c = alch ? cv : (T)1, e = alch ? ce : (T)1, A = alch ? Asc : (T)0, D = alch ? Dsc : (T)0;
 #pragma unroll
   for (int ii = 0; ii < CL; ++ii) {
     const T dx = xj - xi[ii], dy = yj - yi[ii], dz = zj - zi[ii];
@@ -800,11 +803,20 @@ __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL
     const T rinv = rsq(r2);
     const T r2inv = rinv * rinv;
     const T sg = ai[ii] + aj;
-    const T t = r2 / (sg * sg);
-    const T u = t * t * t;
-    const T sc = (T)1 / (A + u);
+    T y, g;
+    if (SHIFTED) {
+      const T sinv = (T)1 / (r2 + D);
+      const T w = sg * sg * sinv;
+      y = w * w * w;
+      g = sinv;
+    } else {
+      const T t = r2 / (sg * sg);
+      const T u = t * t * t;
+      y = (T)1 / (A + u);
+      g = y * u * r2inv;
+    }
     const T bij = bi[ii] * bj;
-    T flj = bij * c * ((T)2 * sc - (T)1) * sc * sc * u * r2inv;
+    T flj = bij * c * ((T)2 * y - (T)1) * y * g;
     flj = bij != (T)0 ? flj : (T)0;
     const T fc = e * qi[ii] * qj * rinv * (r2inv - d.irc2);
     const T fr = in ? flj + fc : (T)0;
@@ -839,7 +851,9 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
   }
 }
 
-template <typename T, bool LB, bool ENERGY, bool INTEG>
+// SHIFTED selects the soft-core form of the alchemical segment at compile time
+// (both forms in one instantiation double the register allocation).
+template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED>
 __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   const int nb = (int)((r.en + 3) >> 2);
   const int lblk = xcd_block(nb);
@@ -975,6 +989,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
     channel(d.lambda[lb * d.n_walkers + w], lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
     channel(d.lambda[lb * d.n_walkers + w], lp.vdw_start, lp.vdw_end, lp.direction, lp.hi, cv, dcv);
     const T Asc = (T)(lp.sc_alpha * pow(1.0 - cv, (double)lp.sc_power));
+    const T Dsc = (T)(lp.sc_shift * (1.0 - cv));
     for (int e0 = nenv; e0 < n; e0 += WAVE) {
       const int ee = e0 + lane;
       T xj = far, yj = far, zj = far, qj = (T)0, aj = (T)1, bj = (T)0;
@@ -993,8 +1008,8 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         bj = d.ljb[js];
         alch = d.sol[js] != 0;
       }
-      env_alch_pairs<T>(d, xi, yi, zi, qi, ai, bi, xj, yj, zj, qj, aj, bj, alch, valid, (T)cv,
-                        (T)ce, Asc, fx, fy, fz);
+      env_alch_pairs<T, SHIFTED>(d, xi, yi, zi, qi, ai, bi, xj, yj, zj, qj, aj, bj, alch, valid,
+                                 (T)cv, (T)ce, Asc, Dsc, fx, fy, fz);
     }
   }
   T Fx = (T)0, Fy = (T)0, Fz = (T)0;
@@ -1055,26 +1070,54 @@ struct PairOut {
   double g;     // shifted-force kernel 1/r - 1/rc + (r - rc)/rc^2
 };
 
-// Soft-core LJ (alpha (1-c)^p + (r/sig)^6 in the denominator, shift at r_cut
-// with the same c) and shifted-force Coulomb, both at coupling (cv, ce).
+// Soft-core LJ at coupling c, written for both forms as phi = 4 eps c (y^2 - y):
+//   form 0: y = 1 / (alpha (1-c)^p + (r/sig)^6)
+//   form 1: y = sig^6 / s^3 with s = r^2 + delta (1 - c) (separation-shifted)
+// so that F/r = -2 dphi/d(r^2) = 24 eps c (2y - 1) y (-dln y / d r^2) with
+// -dln y/dr^2 = 3 u y / r^2 (form 0, u = (r/sig)^6) or 3 / s (form 1),
+// dphi/dc = 4 eps ((y^2 - y) + c (2y - 1) dy/dc) with dy/dc = alpha p (1-c)^(p-1) y^2
+// or 3 y delta / s, and dphi/dsig = 4 eps c (2y - 1) dy/dsig with
+// dy/dsig = 6 u y^2 / sig or 6 y / sig.  Potential shift at r_cut with the same
+// c.  Shifted-force Coulomb at ce.
+struct SoftCore {
+  int form, p;
+  double alpha, delta;
+};
+
+__device__ __forceinline__ void softcore_y(const SoftCore &sc, double r2, double sig2, double c,
+                                           double &y, double &dydc, double &fy, double &dys) {
+  if (sc.form == 1) {
+    const double s = r2 + sc.delta * (1.0 - c);
+    const double w = sig2 / s;
+    y = w * w * w;
+    dydc = 3.0 * y * sc.delta / s;
+    fy = 3.0 * y / s;      // y (-dln y / d r^2)
+    dys = 6.0 * y;         // sig dy/dsig
+  } else {
+    const double t = r2 / sig2;
+    const double u = t * t * t;
+    const double A = sc.alpha * pow(1.0 - c, (double)sc.p);
+    y = 1.0 / (A + u);
+    dydc = sc.p >= 1 ? sc.alpha * (double)sc.p * pow(1.0 - c, (double)(sc.p - 1)) * y * y : 0.0;
+    fy = 3.0 * u * y * y / r2;
+    dys = 6.0 * u * y * y;
+  }
+}
+
 __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq, double cv,
-                                            double ce, double alpha, int p, double rc) {
+                                            double ce, const SoftCore &scf, double rc) {
   PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double r = sqrt(r2);
   if (eps != 0.0) {
     const double sig2 = sig * sig;
-    const double u = (r2 / sig2) * (r2 / sig2) * (r2 / sig2);
-    const double uc0 = (rc * rc / sig2);
-    const double uc = uc0 * uc0 * uc0;
-    const double A = alpha * pow(1.0 - cv, (double)p);
-    const double dsc = p >= 1 ? alpha * (double)p * pow(1.0 - cv, (double)(p - 1)) : 0.0;
-    const double s = 1.0 / (A + u), sc = 1.0 / (A + uc);
-    o.ulj = 4.0 * eps * cv * ((s * s - s) - (sc * sc - sc));
-    o.dulj = 4.0 * eps * (((s * s - s) + cv * dsc * (2.0 * s - 1.0) * s * s) -
-                          ((sc * sc - sc) + cv * dsc * (2.0 * sc - 1.0) * sc * sc));
-    o.fr = 24.0 * eps * cv * (2.0 * s - 1.0) * s * s * u / r2;
-    // u = (r/sig)^6 gives du/dsig = -6u/sig, hence ds/dsig = 6 u s^2 / sig
-    o.dsig = 24.0 * eps * cv * ((2.0 * s - 1.0) * s * s * u - (2.0 * sc - 1.0) * sc * sc * uc) / sig;
+    double y, dydc, fy, dys, yc, dycc, fyc, dysc;
+    softcore_y(scf, r2, sig2, cv, y, dydc, fy, dys);
+    softcore_y(scf, rc * rc, sig2, cv, yc, dycc, fyc, dysc);
+    o.ulj = 4.0 * eps * cv * ((y * y - y) - (yc * yc - yc));
+    o.dulj = 4.0 * eps * (((y * y - y) + cv * (2.0 * y - 1.0) * dydc) -
+                          ((yc * yc - yc) + cv * (2.0 * yc - 1.0) * dycc));
+    o.fr = 8.0 * eps * cv * (2.0 * y - 1.0) * fy;
+    o.dsig = 4.0 * eps * cv * ((2.0 * y - 1.0) * dys - (2.0 * yc - 1.0) * dysc) / sig;
   }
   if (qq != 0.0) {
     const double g = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
@@ -1263,6 +1306,7 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     const int soli = d.sol[si];
     const int n = d.list_count[c];
     const double rc = d.r_cut, rc2 = rc * rc;
+    const SoftCore scf = {lp.sc_form, lp.sc_power, lp.sc_alpha, lp.sc_shift};
     for (int e0 = wv * CL; e0 < n; e0 += 4 * CL) {
       const int ee = e0 + (lane >> 3);
       if (ee >= n) continue;
@@ -1281,8 +1325,7 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
       const double sig = 0.5 * (sgi + d.sig64[js]);
       const double eps = sqrt(epi * d.eps64[js]);
       const double qq = d.coulomb_k * qi * d.q64[js];
-      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0,
-                                  lp.sc_alpha, lp.sc_power, rc);
+      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0, scf, rc);
       acc[0] -= o.fr * dx;
       acc[1] -= o.fr * dy;
       acc[2] -= o.fr * dz;
@@ -1606,21 +1649,28 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
   return hipGetLastError();
 }
 
+template <typename T, bool SH>
+static void env_launch_form(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
+                            bool integ, unsigned grid, hipStream_t s) {
+  if (d.uniform_lj) {
+    if (integ) k_env<T, false, false, true, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, false, true, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, false, false, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+  } else {
+    if (integ) k_env<T, true, false, true, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, true, true, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, true, false, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+  }
+}
+
 template <typename T>
 static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
                        bool integ, hipStream_t s) {
   const int nb = (int)((r.en + 3) / 4);
   const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
   if (grid == 0) return;
-  if (d.uniform_lj) {
-    if (integ) k_env<T, false, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, false, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else k_env<T, false, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-  } else {
-    if (integ) k_env<T, true, false, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, true, true, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else k_env<T, true, false, false><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-  }
+  if (d.lp.sc_form == 1) env_launch_form<T, true>(d, r, xb, vb, lb, energy, integ, grid, s);
+  else env_launch_form<T, false>(d, r, xb, vb, lb, energy, integ, grid, s);
 }
 
 template <typename T>

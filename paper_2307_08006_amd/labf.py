@@ -64,6 +64,7 @@ class LambdaParams(C.Structure):
         ("n_bins", C.c_int32), ("share_interval", C.c_int32),
         ("lo", C.c_double), ("hi", C.c_double), ("full_samples", C.c_int64),
         ("fixed_lambda", C.c_int32), ("abf_on", C.c_int32),
+        ("sc_form", C.c_int32), ("reserved2", C.c_int32), ("sc_shift", C.c_double),
     ]
 
 
@@ -224,6 +225,8 @@ class System:
         p.n_bins, p.share_interval = int(lam.n_bins), int(lam.share_interval)
         p.lo, p.hi, p.full_samples = float(lam.lo), float(lam.hi), int(lam.full_samples)
         p.fixed_lambda, p.abf_on = int(lam.fixed_lambda), int(lam.abf_on)
+        p.sc_form = 1 if lam.sc_form == "shifted" else 0
+        p.sc_shift = float(lam.sc_shift)
         self._chk(lib().labf_set_lambda_params(self._h, C.byref(p), self.stream))
         self.n_bins = int(lam.n_bins)
 

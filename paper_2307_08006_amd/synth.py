@@ -392,14 +392,17 @@ def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
 
 def uneven(n_walkers: int = 64, n_min: int = 5000, n_max: int = 60000,
            seed: int = BASE_SEED + 3, precision: str = "fp32", r_cut: float = 12.0,
-           r_skin: float = 1.0, r_skin_alch: float = 0.0):
+           r_skin: float = 1.2, r_skin_alch: float = 0.0):
     """Walkers with atom counts log-uniform in [n_min, n_max]: each a charged
     LJ solvent box around a dense cluster (0.12 atoms/A^3, FCC) restrained
     harmonically (k = 1 kcal/mol/A^2, lambda-independent) to its initial
     sites, with a 20-80 atom decoupled ligand just outside the cluster (on
     the cube-corner sub-lattice, restrained to its sites like the solute of
     charged_lj).  Solvent sites start SHELL and the ligand LIG_GAP outside
-    the cluster so that no pair starts deep inside the LJ core."""
+    the cluster so that no pair starts deep inside the LJ core.  The list
+    buffer is 1.2 A: over ~1.4 M atoms the two largest displacements in 10
+    steps reach 0.85-1.0 A (ballistic estimate and measurement), too close
+    to a 1 A buffer."""
     rng = np.random.default_rng(seed)
     specs = []
     for w in range(n_walkers):

@@ -28,10 +28,17 @@ def _charged(precision, n=3000, seed=synth.BASE_SEED + 11):
     return synth.charged_lj(n_atoms=n, precision=precision, seed=seed)
 
 
+def _shifted(spec, lam):
+    lam.sc_form, lam.sc_shift = "shifted", 5.0
+    lam.elec_start, lam.elec_end, lam.vdw_start, lam.vdw_end = 0.0, 0.5, 0.0, 1.0
+    return spec, lam
+
+
 CASES = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp64": lambda: _charged("fp64"),
     "charged3k_fp32": lambda: _charged("fp32"),
+    "charged3k_fp64_shifted": lambda: _shifted(*_charged("fp64")),
 }
 LAMS = [0.35, 0.75]   # inside the electrostatics and the soft-core vdW ramps
 

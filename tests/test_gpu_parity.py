@@ -38,11 +38,22 @@ def _uneven(precision):
     return synth.concat([a, b, c], lam, np.array([0.1, 0.45, 0.8]), seed=34, name="uneven3")
 
 
+def _shifted(precision):
+    """Separation-shifted soft-core (delta = 5 A^2) with the staggered schedule
+    of the NAMD setup: electrostatics over [0, 0.5], vdW over [0, 1]."""
+    spec, lam = _small_charged(precision)
+    lam.sc_form, lam.sc_shift = "shifted", 5.0
+    lam.elec_start, lam.elec_end, lam.vdw_start, lam.vdw_end = 0.0, 0.5, 0.0, 1.0
+    return spec, lam
+
+
 SYSTEMS = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp32": lambda: _small_charged("fp32"),
     "charged3k_fp64": lambda: _small_charged("fp64"),
     "uneven3_fp32": lambda: _uneven("fp32"),
+    "charged3k_fp32_shifted": lambda: _shifted("fp32"),
+    "charged3k_fp64_shifted": lambda: _shifted("fp64"),
 }
 
 
