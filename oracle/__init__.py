@@ -57,6 +57,8 @@ class OrcSys(C.Structure):
         ("lam_lo", C.c_double), ("lam_hi", C.c_double), ("full_samples", C.c_int64),
         ("fixed_lambda", C.c_int32), ("abf_on", C.c_int32),
         ("sc_form", C.c_int32), ("pad1", C.c_int32), ("sc_shift", C.c_double),
+        ("dr_pairs", C.c_void_p), ("dr_delta", C.c_double), ("dr_k", C.c_double),
+        ("dr_freq", C.c_int32), ("pad2", C.c_int32),
     ]
 
 
@@ -82,6 +84,8 @@ def lib():
             L.orc_pair_terms.restype = None
             L.orc_pair_terms_shifted.argtypes = [D, D, D, D, D, D, D, D, I32, P]
             L.orc_pair_terms_shifted.restype = None
+            L.orc_dmin.argtypes = [P, D, P]
+            L.orc_dmin.restype = None
             L.orc_neighbor_pairs.argtypes = [P, I32, P, D, I32, I64, P]
             L.orc_neighbor_pairs.restype = I64
             L.orc_evaluate.argtypes = [P, I32, P, D, I32, P, P, P]
@@ -150,6 +154,10 @@ class Oracle:
         s.fixed_lambda, s.abf_on = int(lam.fixed_lambda), int(lam.abf_on)
         s.sc_form = 1 if lam.sc_form == "shifted" else 0
         s.sc_shift = float(lam.sc_shift)
+        if lam.dr_pairs is not None:
+            self._dr = np.ascontiguousarray(lam.dr_pairs, np.int32).reshape(-1, 2)
+            s.dr_pairs = self._dr.ctypes.data
+            s.dr_delta, s.dr_k, s.dr_freq = float(lam.dr_delta), float(lam.dr_k), int(lam.dr_freq)
         self.sys = s
         self.st = None
 
@@ -187,6 +195,12 @@ class Oracle:
         if rc != 0:
             raise ValueError("invalid evaluation request")
         return g
+
+    def dmin(self, lam: float):
+        """(d_min(lambda), d d_min / d lambda) of the distance restraint."""
+        out = np.zeros(2)
+        lib().orc_dmin(C.byref(self.sys), float(lam), _p(out))
+        return out
 
     def bin_of(self, lam: float) -> int:
         return int(lib().orc_bin_of(C.byref(self.sys), float(lam)))

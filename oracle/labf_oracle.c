@@ -466,10 +466,37 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
         for (k = 0; k < 3; ++k) f[3 * i + k] -= kl * d[k];
     }
   }
+  if (s->dr_pairs) {
+    /* lambda-dependent distance restraint ("Dealing with metastabilities
+     * related to counterions"): acts only while d < d_min(lambda) */
+    int32_t ia = s->dr_pairs[2 * w], ib = s->dr_pairs[2 * w + 1];
+    double dm[2], d[3], r2, r;
+    orc_dmin(s, lam, dm);
+    r2 = min_image(x + 3 * ia, x + 3 * ib, L, invL, d); /* d = x_b - x_a */
+    r = sqrt(r2);
+    if (r < dm[0]) {
+      double e = r - dm[0];
+      c.u[ORC_U_RESTR] += 0.5 * s->dr_k * e * e;
+      c.dudl += -s->dr_k * e * dm[1];
+      if (f && r > 0.0)
+        for (k = 0; k < 3; ++k) {
+          /* dV/dx_b = k e d/r, dV/dx_a = -k e d/r */
+          f[3 * ib + k] -= s->dr_k * e * d[k] / r;
+          f[3 * ia + k] += s->dr_k * e * d[k] / r;
+        }
+    }
+  }
   if (u_parts)
     for (k = 0; k < 5; ++k) u_parts[k] = c.u[k];
   if (dudl) *dudl = c.dudl;
   return 0;
+}
+
+void orc_dmin(const orc_sys *s, double lam, double out[2]) {
+  const double two_pi = 6.283185307179586;
+  double n = (double)s->dr_freq;
+  out[0] = 0.5 * s->dr_delta * (1.0 - cos(two_pi * n * lam));
+  out[1] = 0.5 * s->dr_delta * two_pi * n * sin(two_pi * n * lam);
 }
 
 int32_t orc_evaluate(const orc_sys *s, int32_t w, const double *x, double lam, int32_t brute,

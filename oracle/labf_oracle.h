@@ -54,7 +54,17 @@ typedef struct orc_sys {
                                    1: separation-shifted, r^2 -> r^2 + delta (1-c) */
   int32_t pad1;
   double sc_shift;              /* delta of the separation-shifted form (length^2) */
+  /* lambda-dependent distance restraint between two atoms of each walker:
+   * V = k/2 (d - d_min)^2 for d < d_min(lambda), 0 otherwise, with
+   * d_min = (delta/2)(1 - cos(2 pi n lambda)); NULL pairs: none */
+  const int32_t *dr_pairs;      /* [W][2] walker-local atom indices or NULL */
+  double dr_delta, dr_k;
+  int32_t dr_freq;              /* n (1: the text's form; 2: lambda doubled) */
+  int32_t pad2;
 } orc_sys;
+
+/* d_min(lambda) and its derivative for the distance restraint. */
+void orc_dmin(const orc_sys *s, double lam, double out[2]);
 
 /* Dynamic state.  x, v: [N][3]; per-walker arrays: [W]; bins: [nbins];
  * local (not yet shared) ABF deltas: [W][nbins].  `pending` = 1 when the

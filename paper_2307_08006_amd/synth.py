@@ -103,6 +103,12 @@ class LambdaSpec:
     abf_on: bool = True
     sc_form: str = "beutler"         # "beutler": alpha (1-c)^p + (r/sig)^6; "shifted": r^2 + delta (1-c)
     sc_shift: float = 5.0            # delta of the separation-shifted form (length^2)
+    # lambda-dependent distance restraint between two atoms per walker:
+    # V = k/2 (d - d_min)^2 for d < d_min = (delta/2)(1 - cos(2 pi n lambda))
+    dr_pairs: Optional[np.ndarray] = None   # int [W][2] walker-local atom indices
+    dr_delta: float = 20.0
+    dr_k: float = 5.0
+    dr_freq: int = 1
 
 
 def _pow2_at_least(x: float) -> float:
@@ -331,7 +337,9 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         is_solute=rep(spec.is_solute), vel=None, anchor=rep(spec.anchor),
         k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}",
         column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers))
-    lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None)
+    lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None,
+                               dr_pairs=None if lam.dr_pairs is None
+                               else np.tile(np.asarray(lam.dr_pairs).reshape(1, 2), (n_walkers, 1)))
     return out, lam2
 
 
@@ -364,7 +372,9 @@ def subset(spec: SystemSpec, lam: LambdaSpec, walkers) -> tuple:
         column_width=None if spec.column_width is None else spec.column_width[walkers])
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lam.lambda0)[walkers],
                                p_lambda0=None if lam.p_lambda0 is None
-                               else np.asarray(lam.p_lambda0)[walkers])
+                               else np.asarray(lam.p_lambda0)[walkers],
+                               dr_pairs=None if lam.dr_pairs is None
+                               else np.asarray(lam.dr_pairs).reshape(-1, 2)[walkers])
     return out, lam2
 
 

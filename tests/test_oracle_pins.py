@@ -549,3 +549,97 @@ def test_shifted_softcore_system_derivatives_match_fd(l):
                 vals.append(oracle.Oracle(sp, lam).evaluate(0, x, l)[1].sum())
             fd = (vals[0] - vals[1]) / (2 * hp)
             assert abs(pg[i, k] - fd) < 1e-6 * max(1.0, abs(fd)), (i, field, pg[i, k], fd)
+
+
+# --------------------------------------------------------------------------
+# lambda-dependent distance restraint ("Dealing with metastabilities")
+# --------------------------------------------------------------------------
+def _dr_sys(n=1, delta=2.0, k=5.0, pair=(0, 6)):
+    spec, lam = _charged_small()
+    lam.dr_pairs = np.array([pair], np.int32)
+    lam.dr_delta, lam.dr_k, lam.dr_freq = delta, k, n
+    return spec, lam
+
+
+def _pair_distance(spec, a, b):
+    d = spec.pos[b] - spec.pos[a]
+    L = spec.box[0]
+    d -= L * np.round(d / L)
+    return float(np.linalg.norm(d))
+
+
+def test_dmin_is_zero_at_the_end_states_and_delta_midway():
+    """The properties the paper states: d_min(0) = d_min(1) = 0 and
+    d_min(0.5) = delta (n = 1); with lambda doubled (n = 2, the SI script)
+    the peaks move to 1/4 and 3/4."""
+    o1 = oracle.Oracle(*_dr_sys(n=1, delta=20.0))
+    assert o1.dmin(0.0)[0] == 0.0 and abs(o1.dmin(1.0)[0]) < 1e-12
+    assert o1.dmin(0.5)[0] == pytest.approx(20.0, rel=1e-15)
+    o2 = oracle.Oracle(*_dr_sys(n=2, delta=10.0))
+    for l, want in [(0.25, 10.0), (0.75, 10.0), (0.5, 0.0), (0.0, 0.0)]:
+        assert o2.dmin(l)[0] == pytest.approx(want, abs=1e-12)
+
+
+def test_distance_restraint_leaves_the_end_states_and_far_pairs_alone():
+    spec, lam = _dr_sys(delta=2.0)
+    base, lam0 = _charged_small()
+    o, o0 = oracle.Oracle(spec, lam), oracle.Oracle(base, lam0)
+    for l in (0.0, 1.0):
+        f, u, g = o.evaluate(0, spec.pos, l)
+        f0, u0, g0 = o0.evaluate(0, spec.pos, l)
+        assert np.array_equal(f, f0) and np.array_equal(u, u0) and g == g0
+    # midway: acts iff d < delta
+    d = _pair_distance(spec, 0, 6)
+    f, u, g = o.evaluate(0, spec.pos, 0.5)
+    f0, u0, g0 = o0.evaluate(0, spec.pos, 0.5)
+    if d < 2.0:
+        assert u[4] - u0[4] == pytest.approx(0.5 * 5.0 * (d - 2.0) ** 2, rel=1e-12)
+    spec2, lam2 = _dr_sys(delta=0.5 * d)    # d_min(0.5) below d: inert everywhere
+    for l in (0.3, 0.5, 0.8):
+        f2, u2, g2 = oracle.Oracle(spec2, lam2).evaluate(0, spec.pos, l)
+        f0, u0, g0 = o0.evaluate(0, spec.pos, l)
+        assert np.array_equal(f2, f0) and g2 == g0
+
+
+def test_distance_restraint_lambda_force_matches_the_si_expression():
+    """With lambda doubled (n = 2) the force on lambda is
+    -F_d delta pi sin(2 pi l1) 2 with l1 = 2 lambda and F_d = -k (d - d_min)."""
+    spec, lam = _dr_sys(n=2, delta=2.5, k=10.0)
+    base, lam0 = _charged_small()
+    o, o0 = oracle.Oracle(spec, lam), oracle.Oracle(base, lam0)
+    d = _pair_distance(spec, 0, 6)
+    hit = 0
+    for l in (0.1, 0.2, 0.3, 0.4, 0.6, 0.7):
+        l1 = 2.0 * l
+        dmin = 2.5 / 2.0 * (1 - math.cos(2 * math.pi * l1))
+        g = o.evaluate(0, spec.pos, l)[2] - o0.evaluate(0, spec.pos, l)[2]
+        if d < dmin:
+            fd = -10.0 * (d - dmin)
+            want = -(-fd * 2.5 * math.pi * math.sin(2 * math.pi * l1) * 2.0)   # dV/dlambda
+            assert g == pytest.approx(want, rel=1e-12)
+            hit += 1
+        else:
+            assert g == 0.0
+    assert hit >= 2
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_distance_restraint_derivatives_match_fd(n):
+    spec, lam = _dr_sys(n=n, delta=2.5, k=5.0)
+    o = oracle.Oracle(spec, lam)
+    x = spec.pos.copy()
+    for l in (0.2, 0.45, 0.7):
+        if o.dmin(l)[0] <= _pair_distance(spec, 0, 6):
+            continue
+        f, _, g = o.evaluate(0, x, l)
+        h = 1e-6
+        for i in (0, 6):
+            for k in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[i, k] += h
+                xm[i, k] -= h
+                fd = -(_energy(o, xp, l) - _energy(o, xm, l)) / (2 * h)
+                assert abs(f[i, k] - fd) < 1e-6 * max(1.0, abs(fd)), (i, k, f[i, k], fd)
+        hl = 1e-5
+        fd = (_energy(o, x, l + hl) - _energy(o, x, l - hl)) / (2 * hl)
+        assert abs(g - fd) < 1e-6 * max(1.0, abs(g)), (l, g, fd)
