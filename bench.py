@@ -189,6 +189,30 @@ def run_shifted(args, specb, lamb):
             "kernels_ms": prof, "walker_status": int(np.bitwise_or.reduce(st["status"]))}
 
 
+def run_restrained(args, specb, lamb):
+    """The 16-walker batch with the lambda-dependent distance restraint of
+    the text (delta = 20 A, k = 5 kcal/mol/A^2) between the first solute
+    atom and an environment atom about 4 A away in each walker."""
+    from paper_2307_08006_amd import labf
+    n = int(specb.atom_offset[1])
+    a = int(np.nonzero(specb.is_solute[:n])[0][0])
+    d = specb.pos[:n] - specb.pos[a]
+    d -= specb.box[0] * np.round(d / specb.box[0])
+    r = np.linalg.norm(d, axis=1)
+    r[specb.is_solute[:n].astype(bool)] = np.inf
+    b = int(np.argmin(np.abs(r - 4.0)))
+    lam = dataclasses.replace(lamb, dr_pairs=np.tile([[a, b]], (specb.n_walkers, 1)).astype(np.int32),
+                              dr_delta=20.0, dr_k=5.0, dr_freq=1)
+    with labf.System(specb, lam) as s:
+        s.step(args.warmup)
+        dt = timed_steps(s, args.variant_steps, "batched")
+        st = s.read_walker_state()
+    log(f"distance restraint: {args.variant_steps} steps in {dt:.3f} s")
+    return {"walker_steps_per_s": specb.n_walkers * args.variant_steps / dt,
+            "ms_per_step": 1e3 * dt / args.variant_steps, "steps": args.variant_steps,
+            "walker_status": int(np.bitwise_or.reduce(st["status"]))}
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -355,6 +379,7 @@ def main(argv=None):
         out["ti"] = run_ti(args, spec1, lam1)
     if args.variant_steps > 0:
         out["shifted_softcore"] = run_shifted(args, specb, lamb)
+        out["distance_restraint"] = run_restrained(args, specb, lamb)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:

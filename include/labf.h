@@ -200,6 +200,21 @@ labf_status labf_write_atoms(labf_system *sys, const double *pos, const double *
 labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy, double *dudl,
                                 void *stream);
 
+/* Lambda-dependent distance restraint ("Dealing with metastabilities
+ * related to counterions"): between two atoms a, b of each walker,
+ *   V = k/2 (d - d_min)^2  if d < d_min(lambda),  0 otherwise,
+ *   d_min(lambda) = (delta/2)(1 - cos(2 pi freq lambda)),
+ * d the minimum-image distance; it vanishes at lambda = 0 and 1 (freq = 1:
+ * the form of the text, d_min(1/2) = delta; freq = 2: lambda doubled, as in
+ * the SI script).  Adds its forces to both atoms, -k (d - d_min) d_min' to
+ * dV/dlambda and its energy to the restraint part.
+ *   pairs  host [W][2] walker-local atom indices, (-1, -1) for no restraint
+ *          in that walker; NULL removes the restraint everywhere
+ *   delta  >= 0 and < L/2 on every edge; k >= 0; freq 1 or 2
+ * Errors: LABF_E_ARG (nothing changed). */
+labf_status labf_set_distance_restraint(labf_system *sys, const int32_t *pairs, double delta,
+                                        double k, int32_t freq, void *stream);
+
 /* Differentiable potential energy ("Theory": the extended potential
  * V(q; lambda) whose derivatives drive the dynamics and the ABF estimator;
  * "Alchemical pathway": the lambda-scaled soft-core LJ and shifted-force

@@ -95,6 +95,8 @@ struct labf_system {
   double *lam_stage = nullptr;   // [2W]
   int64_t *pairs_dev = nullptr;
   int64_t pairs_cap = 0;
+  int32_t *dr_partner_dev = nullptr;  // distance-restraint tables (allocated on first use)
+  int32_t *dr_pair_dev = nullptr;
 
   template <typename T>
   Dev<T> &dev();
@@ -816,6 +818,50 @@ labf_status energy_backward_impl(labf_system *s, const double *pos, const double
 }
 
 template <typename T>
+labf_status dr_impl(labf_system *s, const int32_t *pairs, double delta, double k, int32_t freq,
+                    hipStream_t st) {
+  Dev<T> &d = s->dev<T>();
+  if (!pairs) {
+    d.dr_partner = nullptr;
+    d.dr_pair = nullptr;
+    drop_graphs(s);
+    return LABF_OK;
+  }
+  if (freq != 1 && freq != 2) return fail(s, LABF_E_ARG, "freq must be 1 or 2");
+  if (!std::isfinite(delta) || delta < 0 || !std::isfinite(k) || k < 0)
+    return fail(s, LABF_E_ARG, "delta and k must be finite and >= 0");
+  std::vector<int32_t> partner(s->N, -1), pair(2 * s->W, -1);
+  for (int w = 0; w < s->W; ++w) {
+    const WalkerMeta &m = s->meta[w];
+    const int32_t a = pairs[2 * w], b = pairs[2 * w + 1];
+    if (a == -1 && b == -1) continue;
+    if (a < 0 || b < 0 || a >= m.n_atoms || b >= m.n_atoms || a == b)
+      return fail(s, LABF_E_ARG, "restrained pair: two distinct atoms of the walker (or -1, -1)");
+    for (int q = 0; q < 3; ++q)
+      if (!(delta < 0.5 * m.L[q])) return fail(s, LABF_E_ARG, "delta must be < L/2");
+    const int64_t ga = m.atom_begin + a, gb = m.atom_begin + b;
+    partner[ga] = (int32_t)gb;
+    partner[gb] = (int32_t)ga;
+    pair[2 * w] = (int32_t)ga;
+    pair[2 * w + 1] = (int32_t)gb;
+  }
+  if (!s->dr_partner_dev) {
+    HIPCHK(s, dalloc(s->bufs, &s->dr_partner_dev, s->N));
+    HIPCHK(s, dalloc(s->bufs, &s->dr_pair_dev, 2 * s->W));
+  }
+  HIPCHK(s, hipMemcpyAsync(s->dr_partner_dev, partner.data(), sizeof(int32_t) * s->N, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync(s->dr_pair_dev, pair.data(), sizeof(int32_t) * 2 * s->W, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  d.dr_partner = s->dr_partner_dev;
+  d.dr_pair = s->dr_pair_dev;
+  d.dr_delta = delta;
+  d.dr_k = k;
+  d.dr_freq = freq;
+  drop_graphs(s);
+  return LABF_OK;
+}
+
+template <typename T>
 labf_status ensure_pairs_buf(labf_system *s, int64_t n) {
   Dev<T> &d = s->dev<T>();
   if (n <= s->pairs_cap) return LABF_OK;
@@ -1145,6 +1191,15 @@ labf_status labf_energy_backward(labf_system *sys, const double *pos, const doub
     using T = std::remove_pointer_t<decltype(tag)>;
     return energy_backward_impl<T>(sys, pos, lambda, params, grad_energy, grad_pos, grad_lambda, grad_params,
                                    (hipStream_t)stream);
+  });
+}
+
+labf_status labf_set_distance_restraint(labf_system *sys, const int32_t *pairs, double delta, double k,
+                                        int32_t freq, void *stream) {
+  if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
+  return dispatch(sys, [&](auto *tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return dr_impl<T>(sys, pairs, delta, k, freq, (hipStream_t)stream);
   });
 }
 

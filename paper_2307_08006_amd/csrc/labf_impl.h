@@ -91,6 +91,11 @@ struct Dev {
   const double *a_mass, *a_k0, *a_k1, *a_anchor;  // anchor [N][3]
   const int32_t *solute_atom;   // [n_solute] atoms with is_solute = 1, increasing
   int64_t n_solute;
+  // lambda-dependent distance restraint (NULL tables: none)
+  const int32_t *dr_partner;    // [N] the other atom of the atom's restrained pair, or -1
+  const int32_t *dr_pair;       // [W][2] the walker's pair (global atom indices), or -1
+  double dr_delta, dr_k;
+  int32_t dr_freq;
   const uint8_t *a_sol, *a_alch;
   int32_t *slot_of, *new_slot, *col_of, *key_col, *members;
   float *disp;                  // [N] displacement since the last rebuild (rounded up)

@@ -826,6 +826,40 @@ __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL
   }
 }
 
+// Lambda-dependent distance restraint between atoms a and b (global indices):
+// V = k/2 e^2 with e = d - d_min while d < d_min(lambda) = (delta/2)(1 - cos(2 pi n
+// lambda)), zero otherwise ("Dealing with metastabilities related to
+// counterions").  u = (x_b - x_a)/d under the minimum image; the force on a is
+// k e u, on b -k e u; dV/dlambda = -k e d_min'.
+struct DrTerm {
+  bool on;
+  double e, dm1, u[3];
+};
+
+template <typename T>
+__device__ __forceinline__ DrTerm dr_term(const Dev<T> &d, const WalkerMeta &m, int xb, int64_t a,
+                                          int64_t b, double lam) {
+  DrTerm t = {false, 0.0, 0.0, {0.0, 0.0, 0.0}};
+  const int sa = d.slot_of[a], sb = d.slot_of[b];
+  double v[3], r2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    v[q] = min_image((double)(d.X[xb][q][sb] - d.X[xb][q][sa]), m.L[q]);
+    r2 += v[q] * v[q];
+  }
+  const double r = sqrt(r2);
+  const double ph = 6.283185307179586 * (double)d.dr_freq * lam;
+  const double dmin = 0.5 * d.dr_delta * (1.0 - cos(ph));
+  if (r < dmin) {
+    t.on = true;
+    t.e = r - dmin;
+    t.dm1 = 0.5 * d.dr_delta * 6.283185307179586 * (double)d.dr_freq * sin(ph);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) t.u[q] = r > 0.0 ? v[q] / r : 0.0;
+  }
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int xb, int vb, int w,
                                                int64_t step, bool pending, const double F[3]) {
@@ -1039,6 +1073,16 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
       }
       eres = 0.5 * (double)kr * r2;
     }
+    if (valid && d.dr_partner) {
+      const int64_t a = m.atom_begin + d.orig[s];
+      const int64_t b = d.dr_partner[a];
+      if (b >= 0) {
+        const DrTerm t = dr_term(d, m, xb, a, b, d.lambda[lb * d.n_walkers + w]);
+        if (t.on)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) F[k] += d.dr_k * t.e * t.u[k];
+      }
+    }
     if (INTEG) {
       if (valid) {
         const int64_t st = d.step[lb * d.n_walkers + w];
@@ -1158,6 +1202,16 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
       gr += 0.5 * (k1 - k0) * r2;
       ur += 0.5 * kl * r2;
     }
+    if (d.dr_partner) {
+      const int64_t a = m.atom_begin + d.orig[s];
+      const int64_t b = d.dr_partner[a];
+      if (b >= 0) {
+        const DrTerm t = dr_term(d, m, xb, a, b, lam);
+        if (t.on)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) F[q] += d.dr_k * t.e * t.u[q];
+      }
+    }
     if (INTEG) {
       integrate_atom<T>(d, s, xb, vb, w, step, pending, F);
     } else {
@@ -1165,14 +1219,22 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
       for (int q = 0; q < 3; ++q) d.fout[(int64_t)q * d.n_slots + s] = F[q];
     }
   }
-  const double G = wave_sum(g) + wave_sum(gr);
+  double G = wave_sum(g) + wave_sum(gr);
+  double udr = 0.0;
+  if (d.dr_pair && d.dr_pair[2 * w] >= 0) {
+    const DrTerm t = dr_term(d, m, xb, d.dr_pair[2 * w], d.dr_pair[2 * w + 1], lam);
+    if (t.on) {
+      G += -d.dr_k * t.e * t.dm1;
+      udr = 0.5 * d.dr_k * t.e * t.e;
+    }
+  }
   if (ENERGY) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       double e = 0.0;
       for (int t = lane; t < m.n_acl; t += WAVE) e += d.item_energy[(m.item_begin + t) * 5 + q];
       e = wave_sum(e);
-      if (q == 4) e += wave_sum(ur);
+      if (q == 4) e += wave_sum(ur) + udr;
       if (lane == 0) d.energy[w * 5 + q] = e;
     }
   }

@@ -29,7 +29,8 @@ EXPORTS = ["labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
            "labf_read_abf_bins", "labf_free_energy", "labf_read_walker_state",
            "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
            "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
-           "labf_energy", "labf_energy_backward", "labf_destroy_system",
+           "labf_energy", "labf_energy_backward", "labf_set_distance_restraint",
+           "labf_destroy_system",
            "labf_last_error"]
 
 
@@ -110,6 +111,7 @@ def lib():
             "labf_get_info": ([P, P, P], I32),
             "labf_energy": ([P, P, P, P, P, P], I32),
             "labf_energy_backward": ([P, P, P, P, P, P, P, P, P], I32),
+            "labf_set_distance_restraint": ([P, P, C.c_double, C.c_double, I32, P], I32),
             "labf_destroy_system": ([P], None),
             "labf_last_error": ([P], C.c_char_p),
         }
@@ -228,11 +230,20 @@ class System:
         p.sc_form = 1 if lam.sc_form == "shifted" else 0
         p.sc_shift = float(lam.sc_shift)
         self._chk(lib().labf_set_lambda_params(self._h, C.byref(p), self.stream))
+        if lam.dr_pairs is not None:
+            self.set_distance_restraint(lam.dr_pairs, lam.dr_delta, lam.dr_k, lam.dr_freq)
         self.n_bins = int(lam.n_bins)
 
     def step(self, n_steps: int, mode: str = "batched"):
         m = MODE_PLAIN if mode == "plain" else MODE_BATCHED
         self._chk(lib().labf_step_walkers(self._h, int(n_steps), m, self.stream))
+
+    def set_distance_restraint(self, pairs, delta: float, k: float, freq: int = 1):
+        """Lambda-dependent distance restraint between two atoms per walker
+        (pairs [W][2] walker-local indices, (-1, -1) for none; None removes it)."""
+        pr = None if pairs is None else np.ascontiguousarray(pairs, np.int32).reshape(self.W, 2)
+        self._chk(lib().labf_set_distance_restraint(self._h, _p(pr), float(delta), float(k), int(freq),
+                                                    self.stream))
 
     def read_abf_bins(self, include_unshared: bool = True):
         c = np.zeros(self.n_bins, np.int64)

@@ -34,11 +34,24 @@ def _shifted(spec, lam):
     return spec, lam
 
 
+def _restrained(spec, lam):
+    a = int(np.nonzero(spec.is_solute)[0][0])
+    d = spec.pos - spec.pos[a]
+    d -= spec.box[0] * np.round(d / spec.box[0])
+    r = np.linalg.norm(d, axis=1)
+    r[spec.is_solute.astype(bool)] = np.inf
+    b = int(np.argmin(np.abs(r - 4.0)))
+    lam.dr_pairs = np.array([[a, b]], np.int32)
+    lam.dr_delta, lam.dr_k, lam.dr_freq = 10.0, 5.0, 1
+    return spec, lam
+
+
 CASES = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp64": lambda: _charged("fp64"),
     "charged3k_fp32": lambda: _charged("fp32"),
     "charged3k_fp64_shifted": lambda: _shifted(*_charged("fp64")),
+    "charged3k_fp64_restrained": lambda: _restrained(*_charged("fp64")),
 }
 LAMS = [0.35, 0.75]   # inside the electrostatics and the soft-core vdW ramps
 

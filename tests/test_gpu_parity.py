@@ -47,6 +47,22 @@ def _shifted(precision):
     return spec, lam
 
 
+def _restrained(precision, freq=1):
+    """Distance restraint between the first solute atom and the environment
+    atom nearest to 4 A from it (delta = 10 A, k = 5): active at
+    intermediate lambda."""
+    spec, lam = _small_charged(precision)
+    a = int(np.nonzero(spec.is_solute)[0][0])
+    d = spec.pos - spec.pos[a]
+    d -= spec.box[0] * np.round(d / spec.box[0])
+    r = np.linalg.norm(d, axis=1)
+    r[spec.is_solute.astype(bool)] = np.inf
+    b = int(np.argmin(np.abs(r - 4.0)))
+    lam.dr_pairs = np.array([[a, b]], np.int32)
+    lam.dr_delta, lam.dr_k, lam.dr_freq = 10.0, 5.0, freq
+    return spec, lam
+
+
 SYSTEMS = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp32": lambda: _small_charged("fp32"),
@@ -54,6 +70,8 @@ SYSTEMS = {
     "uneven3_fp32": lambda: _uneven("fp32"),
     "charged3k_fp32_shifted": lambda: _shifted("fp32"),
     "charged3k_fp64_shifted": lambda: _shifted("fp64"),
+    "charged3k_fp64_restrained": lambda: _restrained("fp64"),
+    "charged3k_fp32_restrained2": lambda: _restrained("fp32", freq=2),
 }
 
 
@@ -201,6 +219,27 @@ def test_harmonic_restraint_free_energy_closed_form():
     st = s.read_walker_state()
     assert (st["status"] == 0).all()
     s.close()
+
+
+def test_distance_restraint_energy_at_half_lambda():
+    """At lambda = 1/2, d_min = delta: the restraint part of the energy is
+    k/2 (d - delta)^2 from the positions read back (the solute carries no
+    other restraint)."""
+    spec, lam = _restrained("fp64")
+    spec.anchor = spec.k0 = spec.k1 = None
+    lam.lambda0 = np.array([0.5])
+    with labf.System(spec, lam) as s:
+        f, e, g = s.compute_forces()
+        pos, _ = s.read_atoms()
+    a, b = lam.dr_pairs[0]
+    d = pos[b] - pos[a]
+    d -= spec.box[0] * np.round(d / spec.box[0])
+    r = float(np.linalg.norm(d))
+    assert r < 10.0
+    assert e[0, 4] == pytest.approx(0.5 * 5.0 * (r - 10.0) ** 2, rel=1e-12)
+    # forces on the pair include -dV/dx = k (d - delta) (x_b - x_a)/d on a
+    fo, _, _ = oracle.Oracle(spec, lam).evaluate(0, pos, 0.5)
+    assert _rel(f, fo) <= 1e-10
 
 
 def test_fixed_lambda_ti_harmonic_closed_form():
