@@ -58,7 +58,8 @@ class OrcSys(C.Structure):
         ("fixed_lambda", C.c_int32), ("abf_on", C.c_int32),
         ("sc_form", C.c_int32), ("pad1", C.c_int32), ("sc_shift", C.c_double),
         ("dr_pairs", C.c_void_p), ("dr_delta", C.c_double), ("dr_k", C.c_double),
-        ("dr_freq", C.c_int32), ("pad2", C.c_int32),
+        ("dr_freq", C.c_int32), ("pme_on", C.c_int32), ("pme_dims", C.c_void_p),
+        ("ewald_beta", C.c_double), ("pme_order", C.c_int32), ("pad3", C.c_int32),
     ]
 
 
@@ -106,6 +107,10 @@ def lib():
             L.orc_abf_readout.restype = I32
             L.orc_bin_of.argtypes = [P, D]
             L.orc_bin_of.restype = I32
+            L.orc_ewald_exact.argtypes = [I64, P, P, P, D, D, I32, D, P]
+            L.orc_ewald_exact.restype = D
+            L.orc_spme_energy.argtypes = [I64, P, P, P, D, P, I32, D, P]
+            L.orc_spme_energy.restype = D
             _lib = L
     return _lib
 
@@ -158,6 +163,10 @@ class Oracle:
             self._dr = np.ascontiguousarray(lam.dr_pairs, np.int32).reshape(-1, 2)
             s.dr_pairs = self._dr.ctypes.data
             s.dr_delta, s.dr_k, s.dr_freq = float(lam.dr_delta), float(lam.dr_k), int(lam.dr_freq)
+        if getattr(spec, "pme_dims", None) is not None:
+            self._pme = np.ascontiguousarray(spec.pme_dims, np.int32).reshape(-1, 3)
+            s.pme_on, s.pme_dims = 1, self._pme.ctypes.data
+            s.ewald_beta, s.pme_order = float(spec.ewald_beta), int(spec.pme_order)
         self.sys = s
         self.st = None
 
@@ -290,3 +299,28 @@ def abf_readout(count, total, lo, hi):
     g, prof, da = np.zeros(n), np.zeros(n), np.zeros(1)
     rc = lib().orc_abf_readout(n, float(lo), float(hi), _p(count), _p(total), _p(g), _p(prof), _p(da))
     return g, prof, float(da[0]), int(rc)
+
+
+def ewald_exact(x, q, box, beta, r_real, kmax, coulomb_k=1.0):
+    """Plain Ewald sum (real-space images within r_real, |m_a| <= kmax,
+    self and neutralising-background terms): (energy, forces)."""
+    x = _f64(x, (-1, 3))
+    q = _f64(q)
+    L = _f64(box)
+    f = np.zeros_like(x)
+    e = lib().orc_ewald_exact(x.shape[0], _p(x), _p(q), _p(L), float(beta), float(r_real), int(kmax),
+                              float(coulomb_k), _p(f))
+    return float(e), f
+
+
+def spme_energy(x, q, box, beta, dims, order=4, coulomb_k=1.0):
+    """Smooth-PME reciprocal energy and forces of one charge set (no self
+    or background term)."""
+    x = _f64(x, (-1, 3))
+    q = _f64(q)
+    L = _f64(box)
+    K = np.ascontiguousarray(dims, np.int32)
+    f = np.zeros_like(x)
+    e = lib().orc_spme_energy(x.shape[0], _p(x), _p(q), _p(L), float(beta), _p(K), int(order),
+                              float(coulomb_k), _p(f))
+    return float(e), f

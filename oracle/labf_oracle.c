@@ -173,6 +173,258 @@ void orc_pair_terms_shifted(double r, double sig, double eps, double qq, double 
 }
 
 /* ---------------------------------------------------------------------------
+ * Ewald electrostatics.  The Ewald split (erfc(beta r)/r pairs in real
+ * space, Gaussian-screened charges in reciprocal space, minus the self
+ * interaction, minus a neutralising background for a net charge) and its
+ * smooth particle-mesh evaluation (Essmann, Perera, Berkowitz, Darden,
+ * Lee, Pedersen 1995): charges spread on a K0 x K1 x K2 grid with cardinal
+ * B-splines of order p, FFT, influence function
+ *   G(m) = kC exp(-pi^2 |m~|^2 / beta^2) / (pi V |m~|^2) |b0(m0)|^2 |b1(m1)|^2 |b2(m2)|^2,
+ * m~_a = m_a / L_a (m_a wrapped to [-K_a/2, K_a/2)), the grid potential
+ * phi(k) = sum_m G(m) F(m) exp(+2 pi i m.k/K), energy 1/2 sum_k Q(k) phi(k),
+ * force -q_i sum_k dW_i(k)/dx phi(k).
+ * ------------------------------------------------------------------------- */
+static const double ORC_PI = 3.14159265358979323846;
+
+/* in-place radix-2 complex FFT of n points spaced by stride; sign -1: forward
+ * (exp(-2 pi i j k / n)), +1: inverse without the 1/n factor */
+static void fft1(double *re, double *im, int n, int64_t stride, int sign) {
+  int i, j = 0, k, len;
+  for (i = 1; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) {
+      double t = re[i * stride];
+      re[i * stride] = re[j * stride];
+      re[j * stride] = t;
+      t = im[i * stride];
+      im[i * stride] = im[j * stride];
+      im[j * stride] = t;
+    }
+  }
+  for (len = 2; len <= n; len <<= 1) {
+    double ang = sign * 2.0 * ORC_PI / len;
+    for (i = 0; i < n; i += len)
+      for (k = 0; k < len / 2; ++k) {
+        double wr = cos(ang * k), wi = sin(ang * k);
+        int64_t a = (int64_t)(i + k) * stride, b = (int64_t)(i + k + len / 2) * stride;
+        double vr = re[b] * wr - im[b] * wi, vi = re[b] * wi + im[b] * wr;
+        double ur = re[a], ui = im[a];
+        re[a] = ur + vr;
+        im[a] = ui + vi;
+        re[b] = ur - vr;
+        im[b] = ui - vi;
+      }
+  }
+}
+
+/* 3-D FFT of an array indexed (i K1 + j) K2 + k */
+static void fft3(double *re, double *im, const int32_t K[3], int sign) {
+  int64_t i, j;
+  for (i = 0; i < K[0]; ++i)
+    for (j = 0; j < K[1]; ++j) fft1(re + (i * K[1] + j) * K[2], im + (i * K[1] + j) * K[2], K[2], 1, sign);
+  for (i = 0; i < K[0]; ++i)
+    for (j = 0; j < K[2]; ++j) fft1(re + i * K[1] * K[2] + j, im + i * K[1] * K[2] + j, K[1], K[2], sign);
+  for (i = 0; i < K[1]; ++i)
+    for (j = 0; j < K[2]; ++j) fft1(re + i * K[2] + j, im + i * K[2] + j, K[0], (int64_t)K[1] * K[2], sign);
+}
+
+/* cardinal B-spline M_p(u) (support (0, p)) and its derivative */
+static double bspline(double u, int p) {
+  if (u <= 0.0 || u >= (double)p) return 0.0;
+  if (p == 2) return 1.0 - fabs(u - 1.0);
+  return (u * bspline(u, p - 1) + ((double)p - u) * bspline(u - 1.0, p - 1)) / (double)(p - 1);
+}
+static double dbspline(double u, int p) { return bspline(u, p - 1) - bspline(u - 1.0, p - 1); }
+
+/* |b(m)|^2 of one axis: 1 / |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2 (p even) */
+static double bmod2(int m, int K, int p) {
+  double sr = 0.0, si = 0.0;
+  int k;
+  for (k = 0; k <= p - 2; ++k) {
+    double a = 2.0 * ORC_PI * (double)m * (double)k / (double)K, M = bspline((double)(k + 1), p);
+    sr += M * cos(a);
+    si += M * sin(a);
+  }
+  return 1.0 / (sr * sr + si * si);
+}
+
+/* spline weights of one atom: grid indices idx[a][j] and weights
+ * w[a][j], dw[a][j] (d/du) for j = 0..p-1 on each axis a */
+static void spline_weights(const double *x, const double *L, const int32_t K[3], int p, int idx[3][8],
+                           double w[3][8], double dw[3][8]) {
+  int a, j;
+  for (a = 0; a < 3; ++a) {
+    double f = x[a] / L[a];
+    double u, fr;
+    int k0;
+    f -= floor(f);
+    u = f * K[a];
+    k0 = (int)floor(u);
+    fr = u - k0;
+    for (j = 0; j < p; ++j) {
+      int k = k0 - j;
+      idx[a][j] = ((k % K[a]) + K[a]) % K[a];
+      w[a][j] = bspline(fr + j, p);
+      dw[a][j] = dbspline(fr + j, p);
+    }
+  }
+}
+
+/* influence function on the grid (index as the data) */
+static void influence(const double *L, const int32_t K[3], int p, double beta, double coulomb_k, double *G) {
+  double V = L[0] * L[1] * L[2];
+  int i, j, k;
+  for (i = 0; i < K[0]; ++i)
+    for (j = 0; j < K[1]; ++j)
+      for (k = 0; k < K[2]; ++k) {
+        int m0 = i < K[0] / 2 ? i : i - K[0], m1 = j < K[1] / 2 ? j : j - K[1], m2 = k < K[2] / 2 ? k : k - K[2];
+        double a0 = m0 / L[0], a1 = m1 / L[1], a2 = m2 / L[2];
+        double m2n = a0 * a0 + a1 * a1 + a2 * a2;
+        int64_t t = ((int64_t)i * K[1] + j) * K[2] + k;
+        if (m2n == 0.0) {
+          G[t] = 0.0;
+          continue;
+        }
+        G[t] = coulomb_k * exp(-ORC_PI * ORC_PI * m2n / (beta * beta)) / (ORC_PI * V * m2n) *
+               bmod2(i, K[0], p) * bmod2(j, K[1], p) * bmod2(k, K[2], p);
+      }
+}
+
+/* grid potential phi of charges q (mask: atoms with sel[i] == want, NULL: all) */
+static void spme_potential(int64_t n, const double *x, const double *q, const uint8_t *sel, int want,
+                           const double *L, const int32_t K[3], int p, const double *G, double *phi,
+                           double *work_im) {
+  int64_t N = (int64_t)K[0] * K[1] * K[2], i, t;
+  int idx[3][8];
+  double w[3][8], dw[3][8];
+  int a, b, c;
+  memset(phi, 0, sizeof(double) * N);
+  memset(work_im, 0, sizeof(double) * N);
+  for (i = 0; i < n; ++i) {
+    if (sel && (sel[i] != 0) != want) continue;
+    if (q[i] == 0.0) continue;
+    spline_weights(x + 3 * i, L, K, p, idx, w, dw);
+    for (a = 0; a < p; ++a)
+      for (b = 0; b < p; ++b)
+        for (c = 0; c < p; ++c)
+          phi[((int64_t)idx[0][a] * K[1] + idx[1][b]) * K[2] + idx[2][c]] += q[i] * w[0][a] * w[1][b] * w[2][c];
+  }
+  fft3(phi, work_im, K, -1);
+  for (t = 0; t < N; ++t) {
+    phi[t] *= G[t];
+    work_im[t] *= G[t];
+  }
+  fft3(phi, work_im, K, +1);
+}
+
+/* sum_k W_i(k) phi(k) and its gradient for atom i */
+static double spme_interp(const double *xi, const double *L, const int32_t K[3], int p, const double *phi,
+                          double grad[3]) {
+  int idx[3][8];
+  double w[3][8], dw[3][8], v = 0.0;
+  int a, b, c;
+  spline_weights(xi, L, K, p, idx, w, dw);
+  grad[0] = grad[1] = grad[2] = 0.0;
+  for (a = 0; a < p; ++a)
+    for (b = 0; b < p; ++b)
+      for (c = 0; c < p; ++c) {
+        double ph = phi[((int64_t)idx[0][a] * K[1] + idx[1][b]) * K[2] + idx[2][c]];
+        v += w[0][a] * w[1][b] * w[2][c] * ph;
+        grad[0] += dw[0][a] * w[1][b] * w[2][c] * ph * K[0] / L[0];
+        grad[1] += w[0][a] * dw[1][b] * w[2][c] * ph * K[1] / L[1];
+        grad[2] += w[0][a] * w[1][b] * dw[2][c] * ph * K[2] / L[2];
+      }
+  return v;
+}
+
+double orc_spme_energy(int64_t n, const double *x, const double *q, const double *L, double beta,
+                       const int32_t K[3], int32_t p, double coulomb_k, double *f) {
+  int64_t N = (int64_t)K[0] * K[1] * K[2], i;
+  double *G = (double *)malloc(sizeof(double) * N), *phi = (double *)malloc(sizeof(double) * N),
+         *im = (double *)malloc(sizeof(double) * N);
+  double e = 0.0, g[3];
+  influence(L, K, p, beta, coulomb_k, G);
+  spme_potential(n, x, q, NULL, 0, L, K, p, G, phi, im);
+  for (i = 0; i < n; ++i) {
+    double v = spme_interp(x + 3 * i, L, K, p, phi, g);
+    e += 0.5 * q[i] * v;
+    if (f) {
+      f[3 * i] -= q[i] * g[0];
+      f[3 * i + 1] -= q[i] * g[1];
+      f[3 * i + 2] -= q[i] * g[2];
+    }
+  }
+  free(G);
+  free(phi);
+  free(im);
+  return e;
+}
+
+double orc_ewald_exact(int64_t n, const double *x, const double *q, const double *L, double beta,
+                       double r_real, int32_t kmax, double coulomb_k, double *f) {
+  double V = L[0] * L[1] * L[2], e = 0.0, Q = 0.0;
+  int64_t i, j;
+  int nx[3], a, b, c;
+  for (a = 0; a < 3; ++a) nx[a] = (int)ceil(r_real / L[a]);
+  /* real space: all images within r_real */
+  for (i = 0; i < n; ++i)
+    for (j = 0; j < n; ++j)
+      for (a = -nx[0]; a <= nx[0]; ++a)
+        for (b = -nx[1]; b <= nx[1]; ++b)
+          for (c = -nx[2]; c <= nx[2]; ++c) {
+            double d[3], r2, r, fr;
+            if (i == j && a == 0 && b == 0 && c == 0) continue;
+            d[0] = x[3 * j] + a * L[0] - x[3 * i];
+            d[1] = x[3 * j + 1] + b * L[1] - x[3 * i + 1];
+            d[2] = x[3 * j + 2] + c * L[2] - x[3 * i + 2];
+            r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 < r_real * r_real)) continue;
+            r = sqrt(r2);
+            e += 0.5 * coulomb_k * q[i] * q[j] * erfc(beta * r) / r;
+            if (f) {
+              fr = coulomb_k * q[i] * q[j] * (erfc(beta * r) / r + 2.0 * beta / sqrt(ORC_PI) * exp(-beta * beta * r2)) / r2;
+              f[3 * i] -= fr * d[0];
+              f[3 * i + 1] -= fr * d[1];
+              f[3 * i + 2] -= fr * d[2];
+            }
+          }
+  /* reciprocal space */
+  for (a = -kmax; a <= kmax; ++a)
+    for (b = -kmax; b <= kmax; ++b)
+      for (c = -kmax; c <= kmax; ++c) {
+        double m[3], m2n, A, sr = 0.0, si = 0.0;
+        if (a == 0 && b == 0 && c == 0) continue;
+        m[0] = a / L[0];
+        m[1] = b / L[1];
+        m[2] = c / L[2];
+        m2n = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+        A = exp(-ORC_PI * ORC_PI * m2n / (beta * beta)) / m2n;
+        for (j = 0; j < n; ++j) {
+          double ph = 2.0 * ORC_PI * (m[0] * x[3 * j] + m[1] * x[3 * j + 1] + m[2] * x[3 * j + 2]);
+          sr += q[j] * cos(ph);
+          si += q[j] * sin(ph);
+        }
+        e += coulomb_k / (2.0 * ORC_PI * V) * A * (sr * sr + si * si);
+        if (f)
+          for (i = 0; i < n; ++i) {
+            double ph = 2.0 * ORC_PI * (m[0] * x[3 * i] + m[1] * x[3 * i + 1] + m[2] * x[3 * i + 2]);
+            /* Im[conj(S) exp(2 pi i m.r_i)] */
+            double s = sr * sin(ph) - si * cos(ph);
+            int k;
+            for (k = 0; k < 3; ++k) f[3 * i + k] += coulomb_k * 2.0 * q[i] / V * A * m[k] * s;
+          }
+      }
+  for (i = 0; i < n; ++i) {
+    e -= coulomb_k * beta / sqrt(ORC_PI) * q[i] * q[i];
+    Q += q[i];
+  }
+  e -= coulomb_k * ORC_PI * Q * Q / (2.0 * V * beta * beta);
+  return e;
+}
+
+/* ---------------------------------------------------------------------------
  * Minimum-image separation d = x_j - x_i (the neighbour-set definition):
  * d_k -= L_k * rint(d_k * (1/L_k)), 1/L_k evaluated once in FP64, rint is
  * round-half-even; r^2 = (dx*dx + dy*dy) + dz*dz with no fused operations
@@ -377,6 +629,13 @@ static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], doubl
     orc_pair_terms_shifted(r, sig, eps, qq, cv, ce, s->sc_shift, rc, 1, t);
   else
     orc_pair_terms(r, sig, eps, qq, cv, ce, s->sc_alpha, s->sc_power, rc, 1, t);
+  if (s->pme_on) {
+    /* Ewald real-space pair: qq erfc(beta r)/r, cut at r_cut, linear in ce */
+    double b = s->ewald_beta, ge = erfc(b * r) / r;
+    t[3] = ce * qq * ge;
+    t[4] = qq * ge;
+    t[5] = ce * qq * (ge + 2.0 * b / sqrt(ORC_PI) * exp(-b * b * r2)) / r2;
+  }
   fr = t[2] + t[5];
   if (c->f) {
     /* d = x_j - x_i; a repulsive pair pushes i along -d */
@@ -418,11 +677,75 @@ static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], doubl
     c->g[3 * i + 1] += 0.5 * dsig;
     c->g[3 * j + 1] += 0.5 * dsig;
     if (ce != 0.0) {
-      double gfun = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+      double gfun = s->pme_on ? erfc(s->ewald_beta * r) / r : 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
       c->g[3 * i + 2] += ce * s->coulomb_k * s->charge[gj] * gfun;
       c->g[3 * j + 2] += ce * s->coulomb_k * s->charge[gi] * gfun;
     }
   }
+}
+
+/* Reciprocal, self and background Ewald terms of walker w with the
+ * decoupled group's electrostatics scaled linearly by ce.  With E the
+ * environment charges and S the alchemical group's, the Ewald energy is
+ * the quadratic form V[E+S] = V[E] + V[S] + V_x; the two end states
+ * (ce = 1: V[E+S]; ce = 0: V[E] + V[S], the group decoupled but keeping
+ * its own interactions) are well defined, and the energy in between is
+ * their linear interpolation V[E] + V[S] + ce V_x (Section 2, alchemical
+ * pathway: many-body terms interpolated between the electrostatic end
+ * values).  The same split applies to the reciprocal, self (no cross part)
+ * and neutralising-background terms. */
+static void ewald_walker(const orc_sys *s, int32_t w, const double *x, int64_t n, double ce, double dce,
+                         eval_ctx *c) {
+  const double *L = s->box + 3 * w;
+  const int32_t *K = s->pme_dims + 3 * w;
+  int p = s->pme_order;
+  int64_t N = (int64_t)K[0] * K[1] * K[2], i;
+  const uint8_t *sel = s->is_solute + c->base;
+  const double *q = s->charge + c->base;
+  double *G = (double *)malloc(sizeof(double) * N), *phiE = (double *)malloc(sizeof(double) * N),
+         *phiS = (double *)malloc(sizeof(double) * N), *im = (double *)malloc(sizeof(double) * N);
+  double V = L[0] * L[1] * L[2], beta = s->ewald_beta, kC = s->coulomb_k;
+  double vE = 0.0, vS = 0.0, vX = 0.0, QE = 0.0, QS = 0.0, selfE = 0.0, selfS = 0.0, bgE, bgS, bgX;
+  influence(L, K, p, beta, kC, G);
+  spme_potential(n, x, q, sel, 0, L, K, p, G, phiE, im);
+  spme_potential(n, x, q, sel, 1, L, K, p, G, phiS, im);
+  for (i = 0; i < n; ++i) {
+    int solute = sel[i] != 0;
+    double gE[3], gS[3], pE, pS, pown, poth;
+    int k;
+    pE = spme_interp(x + 3 * i, L, K, p, phiE, gE);
+    pS = spme_interp(x + 3 * i, L, K, p, phiS, gS);
+    if (solute) {
+      vS += 0.5 * q[i] * pS;
+      vX += q[i] * pE;
+      QS += q[i];
+      selfS += q[i] * q[i];
+    } else {
+      vE += 0.5 * q[i] * pE;
+      QE += q[i];
+      selfE += q[i] * q[i];
+    }
+    pown = solute ? pS : pE;
+    poth = solute ? pE : pS;
+    if (c->f)
+      for (k = 0; k < 3; ++k) c->f[3 * i + k] -= q[i] * ((solute ? gS[k] : gE[k]) + ce * (solute ? gE[k] : gS[k]));
+    if (c->g) c->g[3 * i + 2] += pown + ce * poth - 2.0 * kC * beta / sqrt(ORC_PI) * q[i];
+  }
+  bgE = -ORC_PI * kC * QE * QE / (2.0 * V * beta * beta);
+  bgS = -ORC_PI * kC * QS * QS / (2.0 * V * beta * beta);
+  bgX = -ORC_PI * kC * QE * QS / (V * beta * beta);
+  if (c->g)
+    for (i = 0; i < n; ++i)
+      c->g[3 * i + 2] += sel[i] ? -ORC_PI * kC * (QS + ce * QE) / (V * beta * beta)
+                                : -ORC_PI * kC * (QE + ce * QS) / (V * beta * beta);
+  c->u[ORC_U_ENV] += vE - kC * beta / sqrt(ORC_PI) * selfE + bgE;
+  c->u[ORC_U_SOLUTE] += vS - kC * beta / sqrt(ORC_PI) * selfS + bgS;
+  c->u[ORC_U_ALCH_C] += ce * (vX + bgX);
+  c->dudl += dce * (vX + bgX);
+  free(G);
+  free(phiE);
+  free(phiS);
+  free(im);
 }
 
 static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam, int brute,
@@ -439,6 +762,13 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
     invL[k] = 1.0 / L[k];
   }
   n = s->atom_offset[w + 1] - s->atom_offset[w];
+  if (s->pme_on) {
+    if (!s->pme_dims || s->pme_order < 3 || s->pme_order > 8 || !(s->ewald_beta > 0.0)) return -1;
+    for (k = 0; k < 3; ++k) {
+      int32_t d = s->pme_dims[3 * w + k];
+      if (d < s->pme_order || (d & (d - 1)) != 0) return -1;
+    }
+  }
   memset(&c, 0, sizeof(c));
   c.s = s;
   c.base = s->atom_offset[w];
@@ -452,6 +782,7 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
   if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
   if (g) memset(g, 0, sizeof(double) * 3 * (size_t)n);
   for_each_pair(x, n, L, s->r_cut, brute, eval_pair, &c);
+  if (s->pme_on) ewald_walker(s, w, x, n, c.ce, c.dce, &c);
   if (s->anchor && s->k0 && s->k1) {
     for (i = 0; i < n; ++i) {
       int64_t gi = c.base + i;

@@ -60,8 +60,23 @@ typedef struct orc_sys {
   const int32_t *dr_pairs;      /* [W][2] walker-local atom indices or NULL */
   double dr_delta, dr_k;
   int32_t dr_freq;              /* n (1: the text's form; 2: lambda doubled) */
-  int32_t pad2;
+  int32_t pme_on;               /* 1: Ewald electrostatics (smooth PME) instead of shifted force */
+  const int32_t *pme_dims;      /* [W][3] PME grid points per edge (powers of two) */
+  double ewald_beta;            /* Ewald splitting parameter (1/length)    */
+  int32_t pme_order;            /* B-spline order (4..8)                   */
+  int32_t pad3;
 } orc_sys;
+
+/* Exact Ewald sum of point charges in an orthorhombic box (tests): real
+ * space over all images within r_real, reciprocal space over all
+ * |m_k| <= kmax, self and neutralising-background terms; energy and forces
+ * (f may be NULL).  Units: coulomb_k q_i q_j / r. */
+double orc_ewald_exact(int64_t n, const double *x, const double *q, const double *L, double beta,
+                       double r_real, int32_t kmax, double coulomb_k, double *f);
+/* Smooth PME reciprocal energy of one charge set (tests): order p,
+ * grid K[3] (powers of two), forces added to f (may be NULL). */
+double orc_spme_energy(int64_t n, const double *x, const double *q, const double *L, double beta,
+                       const int32_t K[3], int32_t p, double coulomb_k, double *f);
 
 /* d_min(lambda) and its derivative for the distance restraint. */
 void orc_dmin(const orc_sys *s, double lam, double out[2]);

@@ -65,6 +65,9 @@ class SystemSpec:
     rebuild_interval: int = 10
     r_skin_alch: float = 0.0             # list buffer of alchemical pairs; 0 -> r_skin
     column_width: Optional[np.ndarray] = None  # float64 [W] cluster column width factor; None -> 1
+    pme_dims: Optional[np.ndarray] = None  # int32 [W,3] PME grid (powers of two); None -> no PME
+    ewald_beta: float = 0.0              # Ewald splitting parameter (1/A) when pme_dims is set
+    pme_order: int = 4                   # B-spline order of the PME charge assignment
     name: str = ""
 
     @property
@@ -322,6 +325,31 @@ def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
     return spec, lam
 
 
+def with_pme(spec: SystemSpec, spacing: float = 1.1, tolerance: float = 1e-6, order: int = 4,
+             dims=None) -> SystemSpec:
+    """The same system with Ewald electrostatics: per walker the smallest
+    power-of-two PME grid with spacing <= `spacing` A on each edge (or the
+    given dims), the splitting parameter beta with erfc(beta r_cut) =
+    tolerance, and B-spline order `order`."""
+    if dims is None:
+        dims = np.array([[_grid_pow2(L / spacing, order) for L in b] for b in spec.box], np.int32)
+    else:
+        dims = np.broadcast_to(np.asarray(dims, np.int32), (spec.n_walkers, 3)).copy()
+    lo, hi = 0.0, 10.0 / spec.r_cut
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if math.erfc(mid * spec.r_cut) > tolerance else (lo, mid)
+    return dataclasses.replace(spec, pme_dims=dims, ewald_beta=0.5 * (lo + hi), pme_order=order,
+                               name=spec.name + "_pme")
+
+
+def _grid_pow2(x: float, floor: int) -> int:
+    k = 1
+    while k < x or k < floor:
+        k *= 2
+    return k
+
+
 def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
     """n_walkers copies of a one-walker system (same coordinates and
     parameters, independent velocity streams through the walker index),
@@ -336,7 +364,8 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         charge=rep(spec.charge), sigma=rep(spec.sigma), epsilon=rep(spec.epsilon),
         is_solute=rep(spec.is_solute), vel=None, anchor=rep(spec.anchor),
         k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}",
-        column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers))
+        column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers),
+        pme_dims=None if spec.pme_dims is None else np.repeat(spec.pme_dims, n_walkers, axis=0))
     lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None,
                                dr_pairs=None if lam.dr_pairs is None
                                else np.tile(np.asarray(lam.dr_pairs).reshape(1, 2), (n_walkers, 1)))
@@ -369,7 +398,8 @@ def subset(spec: SystemSpec, lam: LambdaSpec, walkers) -> tuple:
         mass=pick(spec.mass), charge=pick(spec.charge), sigma=pick(spec.sigma),
         epsilon=pick(spec.epsilon), is_solute=pick(spec.is_solute), anchor=pick(spec.anchor),
         k0=pick(spec.k0), k1=pick(spec.k1),
-        column_width=None if spec.column_width is None else spec.column_width[walkers])
+        column_width=None if spec.column_width is None else spec.column_width[walkers],
+        pme_dims=None if spec.pme_dims is None else spec.pme_dims[walkers])
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lam.lambda0)[walkers],
                                p_lambda0=None if lam.p_lambda0 is None
                                else np.asarray(lam.p_lambda0)[walkers],
@@ -395,7 +425,8 @@ def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
         anchor=cat("anchor") if has_r else None, k0=cat("k0") if has_r else None,
         k1=cat("k1") if has_r else None, seed=seed, name=name,
         column_width=np.concatenate([np.ones(1) if s.column_width is None else s.column_width
-                                     for s in specs]))
+                                     for s in specs]),
+        pme_dims=None if s0.pme_dims is None else np.concatenate([s.pme_dims for s in specs]))
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lambda0, np.float64), p_lambda0=None)
     return out, lam2
 
