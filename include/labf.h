@@ -113,7 +113,14 @@ typedef struct labf_system_desc {
   double accel_unit;           /* force/mass -> acceleration factor               */
   uint64_t seed;               /* Philox4x32-10 key                               */
   int32_t rebuild_interval;    /* steps between neighbour rebuilds (>= 1; 10 typical) */
-  int32_t reserved;            /* must be 0                                       */
+  int32_t pme_order;           /* 0: shifted-force Coulomb cut at r_cut.  4, 6 or 8: Ewald
+                                  electrostatics, real-space erfc(beta r)/r pairs cut at r_cut
+                                  plus smooth-PME reciprocal space with B-splines of this order
+                                  (Essmann et al. 1995), self and neutralising-background terms.
+                                  The alchemical group's electrostatic coupling scales the
+                                  group-environment real-space pairs and the cross part of the
+                                  reciprocal and background terms linearly (Section 2, alchemical
+                                  pathway: many-body terms interpolated between the end values) */
   double r_skin_alch;          /* list buffer of pairs with an alchemical atom (solute atoms and
                                   atoms with k0 != k1), or 0: r_skin.  A decoupled solute has no
                                   solvent cage and can move much farther between rebuilds than the
@@ -122,6 +129,9 @@ typedef struct labf_system_desc {
                                   (rho: the walker's environment atom density; 1 gives cubic
                                   8-atom clusters), or NULL: 1 for every walker; 0.5 .. 2.
                                   The tile shape that an autotuner chooses per size class */
+  const int32_t *pme_dims;     /* [W][3] PME grid points per edge when pme_order > 0: powers of
+                                  two in [16, 256]; ignored (may be NULL) otherwise */
+  double ewald_beta;           /* Ewald splitting parameter (1/length) > 0 when pme_order > 0 */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF
@@ -270,9 +280,10 @@ labf_status labf_count_pairs(labf_system *sys, int64_t *pairs_all, int64_t *pair
 
 /* Timing pass (for roofline reporting): rebuilds the list, then runs
  * n_steps >= 1 batched steps launched one kernel at a time with HIP events
- * around each launch on `stream`.  ms[0] = rebuild, ms[1] = alchemical
- * kernel (average per step), ms[2] = environment kernel (average per step).
- * Advances the dynamics by n_steps like labf_step_walkers. */
+ * around each launch on `stream`.  ms[4]: ms[0] = rebuild, ms[1] = alchemical
+ * kernel (average per step), ms[2] = environment kernel (average per step),
+ * ms[3] = PME reciprocal space (spread, transforms, gather; average per step,
+ * 0 without PME).  Advances the dynamics by n_steps like labf_step_walkers. */
 labf_status labf_profile_steps(labf_system *sys, int64_t n_steps, double *ms, void *stream);
 
 /* Philox4x32-10 on the device (test hook): out[n][4] for counters ctr[n][4]

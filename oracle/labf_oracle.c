@@ -763,7 +763,8 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
   }
   n = s->atom_offset[w + 1] - s->atom_offset[w];
   if (s->pme_on) {
-    if (!s->pme_dims || s->pme_order < 3 || s->pme_order > 8 || !(s->ewald_beta > 0.0)) return -1;
+    if (!s->pme_dims || (s->pme_order != 4 && s->pme_order != 6 && s->pme_order != 8) || !(s->ewald_beta > 0.0))
+      return -1;
     for (k = 0; k < 3; ++k) {
       int32_t d = s->pme_dims[3 * w + k];
       if (d < s->pme_order || (d & (d - 1)) != 0) return -1;

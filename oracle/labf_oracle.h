@@ -63,7 +63,7 @@ typedef struct orc_sys {
   int32_t pme_on;               /* 1: Ewald electrostatics (smooth PME) instead of shifted force */
   const int32_t *pme_dims;      /* [W][3] PME grid points per edge (powers of two) */
   double ewald_beta;            /* Ewald splitting parameter (1/length)    */
-  int32_t pme_order;            /* B-spline order (4..8)                   */
+  int32_t pme_order;            /* B-spline order (4, 6 or 8)              */
   int32_t pad3;
 } orc_sys;
 

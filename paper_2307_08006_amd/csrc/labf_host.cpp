@@ -79,6 +79,8 @@ struct labf_system {
   int64_t host_steps = 0;
   std::vector<int64_t> atom_offset;
   std::vector<WalkerMeta> meta;
+  std::vector<PmeWalker> pme;    // host copy (FFT block ranges of the launches)
+  int32_t pme_nblk[3] = {0, 0, 0};
   std::vector<int32_t> n_acl_host;
   hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -166,6 +168,10 @@ Range full_range(const labf_system *s) {
   r.kn = s->K;
   r.w0 = 0;
   r.wn = s->W;
+  for (int a = 0; a < 3; ++a) {
+    r.pb0[a] = 0;
+    r.pbn[a] = s->pme_nblk[a];
+  }
   return r;
 }
 
@@ -184,6 +190,10 @@ Range walker_range(const labf_system *s, int w) {
   r.kn = (int64_t)m.ncx * m.ncy + 1;
   r.w0 = w;
   r.wn = 1;
+  for (int a = 0; a < 3; ++a) {
+    r.pb0[a] = s->pme.empty() ? 0 : s->pme[w].blk_begin[a];
+    r.pbn[a] = s->pme.empty() ? 0 : s->pme[w].blk[a];
+  }
   return r;
 }
 
@@ -199,7 +209,18 @@ labf_status validate_desc(const labf_system_desc *d) {
   if (!d) return fail(nullptr, LABF_E_ARG, "desc is NULL");
   if (d->n_walkers < 1 || d->n_walkers > (1 << 20)) return fail(nullptr, LABF_E_ARG, "n_walkers out of range");
   if (d->precision != LABF_FP32 && d->precision != LABF_FP64) return fail(nullptr, LABF_E_ARG, "bad precision");
-  if (d->reserved != 0) return fail(nullptr, LABF_E_ARG, "reserved must be 0");
+  if (d->pme_order != 0 && d->pme_order != 4 && d->pme_order != 6 && d->pme_order != 8)
+    return fail(nullptr, LABF_E_ARG, "pme_order must be 0, 4, 6 or 8");
+  if (d->pme_order) {
+    if (!d->pme_dims) return fail(nullptr, LABF_E_ARG, "pme_dims is NULL");
+    if (!std::isfinite(d->ewald_beta) || !(d->ewald_beta > 0)) return fail(nullptr, LABF_E_ARG, "ewald_beta must be > 0");
+    for (int w = 0; w < d->n_walkers; ++w)
+      for (int k = 0; k < 3; ++k) {
+        const int32_t K = d->pme_dims[3 * w + k];
+        if (K < 16 || K > PME_KMAX || (K & (K - 1)) != 0)
+          return fail(nullptr, LABF_E_ARG, "pme_dims must be powers of two in [16, 256]");
+      }
+  }
   if (!d->atom_offset || !d->box || !d->pos || !d->mass || !d->charge || !d->sigma || !d->epsilon || !d->is_solute)
     return fail(nullptr, LABF_E_ARG, "required array is NULL");
   if (d->atom_offset[0] != 0) return fail(nullptr, LABF_E_ARG, "atom_offset[0] must be 0");
@@ -363,7 +384,8 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
     // environment kernel; they read the same positions and write disjoint
     // slots, lambda and step counters are double-buffered
     for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
-      e = hipEventRecord(s->fork_ev, s->cap_stream);
+      e = Launch<T>::pme(d, full_range(s), xb, lb, s->cap_stream);
+      if (e == hipSuccess) e = hipEventRecord(s->fork_ev, s->cap_stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
       if (e == hipSuccess) e = Launch<T>::step_alch(d, full_range(s), xb, vb, lb, s->cap_stream2);
       if (e == hipSuccess) e = Launch<T>::step_env(d, full_range(s), xb, vb, lb, s->cap_stream);
@@ -544,6 +566,56 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     HIPCHK(s, upload(b, &d.a_anchor, anc_grid.data(), 3 * N));
   } else {
     d.a_k0 = d.a_k1 = d.a_anchor = nullptr;
+  }
+  // smooth PME: per-walker grids, FFT block tables, influence-function tables
+  d.pme_on = desc->pme_order ? 1 : 0;
+  d.pme_order = desc->pme_order;
+  d.ewald_beta = desc->pme_order ? desc->ewald_beta : 0.0;
+  d.ewb = (T)d.ewald_beta;
+  d.ewc = (T)(d.ewald_beta * 1.1283791670955126);  // 2 beta / sqrt(pi)
+  s->pme.clear();
+  for (int a = 0; a < 3; ++a) s->pme_nblk[a] = 0;
+  if (d.pme_on) {
+    s->pme.resize(W);
+    int64_t goff = 0, toff = 0;
+    std::vector<int32_t> bw[3];
+    for (int w = 0; w < W; ++w) {
+      PmeWalker &p = s->pme[w];
+      std::memset(&p, 0, sizeof(p));
+      for (int a = 0; a < 3; ++a) {
+        p.K[a] = desc->pme_dims[3 * w + a];
+        while ((1 << p.lg[a]) < p.K[a]) ++p.lg[a];
+      }
+      p.nl[2] = PME_TILE / p.K[2];
+      p.nl[1] = std::min(PME_TILE / p.K[1], p.K[2]);
+      p.nl[0] = std::min(PME_TILE / p.K[0], p.K[2]);
+      p.blk[2] = p.K[0] * p.K[1] / p.nl[2];
+      p.blk[1] = p.K[0] * (p.K[2] / p.nl[1]);
+      p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
+      for (int a = 0; a < 3; ++a) {
+        p.blk_begin[a] = s->pme_nblk[a];
+        s->pme_nblk[a] += p.blk[a];
+        bw[a].insert(bw[a].end(), (size_t)p.blk[a], w);
+      }
+      p.goff = goff;
+      goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
+      p.toff = toff;
+      toff += p.K[0] + p.K[1] + p.K[2];
+      const WalkerMeta &m = s->meta[w];
+      p.pref = desc->coulomb_k / (3.14159265358979323846 * m.L[0] * m.L[1] * m.L[2]);
+    }
+    HIPCHK(s, upload(b, &d.pme, s->pme.data(), W));
+    for (int a = 0; a < 3; ++a) HIPCHK(s, upload(b, &d.pme_bw[a], bw[a].data(), bw[a].size()));
+    HIPCHK(s, dalloc(b, &d.pme_grid, goff));
+    HIPCHK(s, dalloc(b, &d.pme_acc, 2 * goff));
+    double *tab = nullptr;
+    HIPCHK(s, dalloc(b, &tab, 2 * toff));
+    d.pme_tab = tab;
+    HIPCHK(s, dalloc(b, &d.pme_frc, 3 * s->S));
+    HIPCHK(s, dalloc(b, &d.pme_phi, 2 * s->S));
+    HIPCHK(s, dalloc(b, &d.pme_qs, 4 * W));
+    HIPCHK(s, Launch<T>::pme_tables(d, st));
+    HIPCHK(s, Launch<T>::pme_charges(d, st));
   }
   d.a_pos0 = nullptr;
   HIPCHK(s, dalloc(b, &d.slot_of, N));
@@ -934,7 +1006,7 @@ labf_status count_impl(labf_system *s, int64_t *pairs, int64_t *pairs_env, hipSt
 template <typename T>
 labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
-  std::vector<hipEvent_t> ev(2 + 2 * n + 1);
+  std::vector<hipEvent_t> ev(2 + 3 * n + 1);
   for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
   auto cleanup = [&]() {
     for (auto &e : ev) (void)hipEventDestroy(e);
@@ -947,28 +1019,33 @@ labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) 
   }
   HIPCHK(s, hipEventRecord(ev[1], st));
   for (int64_t i = 0; i < n; ++i) {
+    HIPCHK(s, Launch<T>::pme(d, full_range(s), s->xb, s->lb, st));
+    HIPCHK(s, hipEventRecord(ev[2 + 3 * i], st));
     HIPCHK(s, Launch<T>::step_alch(d, full_range(s), s->xb, s->vb, s->lb, st));
-    HIPCHK(s, hipEventRecord(ev[2 + 2 * i], st));
+    HIPCHK(s, hipEventRecord(ev[3 + 3 * i], st));
     HIPCHK(s, Launch<T>::step_env(d, full_range(s), s->xb, s->vb, s->lb, st));
-    HIPCHK(s, hipEventRecord(ev[3 + 2 * i], st));
+    HIPCHK(s, hipEventRecord(ev[4 + 3 * i], st));
     s->xb ^= 1;
     s->lb ^= 1;
     s->since_rebuild += 1;
     s->host_steps += 1;
   }
-  HIPCHK(s, hipEventSynchronize(ev[1 + 2 * n]));
+  HIPCHK(s, hipEventSynchronize(ev[1 + 3 * n]));
   float t = 0.f;
   HIPCHK(s, hipEventElapsedTime(&t, ev[0], ev[1]));
   ms[0] = t;
-  double a = 0.0, e = 0.0;
+  double a = 0.0, e = 0.0, p = 0.0;
   for (int64_t i = 0; i < n; ++i) {
-    HIPCHK(s, hipEventElapsedTime(&t, ev[2 * i + 1], ev[2 * i + 2]));
+    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 1], ev[3 * i + 2]));
+    p += t;
+    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 2], ev[3 * i + 3]));
     a += t;
-    HIPCHK(s, hipEventElapsedTime(&t, ev[2 * i + 2], ev[2 * i + 3]));
+    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 3], ev[3 * i + 4]));
     e += t;
   }
   ms[1] = a / n;
   ms[2] = e / n;
+  ms[3] = d.pme_on ? p / n : 0.0;
   cleanup();
   return LABF_OK;
 }

@@ -51,6 +51,24 @@ struct WalkerMeta {
   double cw[2];           // column widths
 };
 
+// Smooth PME of one walker.  The complex grid holds the environment's charge
+// density in the real part and the alchemical group's in the imaginary part,
+// so that one complex transform serves both; z is the fastest index.
+constexpr int PME_TILE = 2048;  // complex points per FFT block
+constexpr int PME_KMAX = 256;   // largest grid edge
+constexpr int PME_PMAX = 8;     // largest B-spline order
+struct PmeWalker {
+  int32_t K[3];           // grid points per edge (powers of two, 16 .. PME_KMAX)
+  int32_t lg[3];          // log2 K
+  int32_t nl[3];          // FFT lines per block along each axis
+  int32_t blk[3];         // FFT blocks along each axis
+  int32_t blk_begin[3];   // first FFT block of the walker along each axis
+  int32_t pad;
+  int64_t goff;           // first grid point
+  int64_t toff;           // first entry of the per-axis tables (K0 + K1 + K2 entries)
+  double pref;            // coulomb_k / (pi V)
+};
+
 // Extended-lambda / ABF parameters as the kernels need them.
 struct LamParams {
   double m_lambda, gamma_lambda, kT_lambda;
@@ -142,6 +160,18 @@ struct Dev {
   double *bin_sum, *bin_sum2;
   int64_t *loc_count;           // [W][nbins]
   double *loc_sum, *loc_sum2;
+  // --- smooth PME (pme_on = 0: shifted-force Coulomb, the rest unused)
+  int32_t pme_on, pme_order;
+  double ewald_beta;
+  T ewb, ewc;                   // beta, 2 beta / sqrt(pi) (storage precision)
+  const PmeWalker *pme;         // [W]
+  const int32_t *pme_bw[3];     // walker of every FFT block along each axis
+  double2 *pme_grid;            // [sum K0 K1 K2] complex grid
+  unsigned long long *pme_acc;  // [sum K0 K1 K2][2] fixed-point charge spread (E, S)
+  const double *pme_tab;        // [sum (K0+K1+K2)][2] exp(-pi^2 m~^2 / beta^2) |b(m)|^2, m~^2
+  double *pme_frc;              // [3][S] reciprocal force per slot
+  double *pme_phi;              // [2][S] reciprocal potential: own group, other group
+  double *pme_qs;               // [W][4] Q_E, Q_S, sum_E q^2, sum_S q^2
   // --- export / counting
   int64_t *pair_out;            // [max][2]
   unsigned long long *pair_n;   // [W] counters
@@ -156,6 +186,7 @@ struct Range {
   int64_t i0, in_;     // alchemical item slots
   int64_t k0, kn;      // per-column entries
   int32_t w0, wn;      // walkers
+  int32_t pb0[3], pbn[3];  // PME FFT blocks along each axis
 };
 
 // Host-side launchers (defined in labf_kernels.hip).
@@ -182,6 +213,12 @@ struct Launch {
   // lambda and solute (eps, sigma, q) from device arrays (each may be NULL)
   static hipError_t set_config(const Dev<T> &d, int xb, int lb, const double *pos,
                                const double *lam, const double *params, hipStream_t s);
+  // reciprocal-space PME: spread, transforms and convolution, gather
+  static hipError_t pme(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s);
+  // per-walker charge sums of the two groups (after a charge change)
+  static hipError_t pme_charges(const Dev<T> &d, hipStream_t s);
+  // influence-function tables (once, at creation)
+  static hipError_t pme_tables(const Dev<T> &d, hipStream_t s);
   // total potential energy per walker after eval()
   static hipError_t energy_total(const Dev<T> &d, double *out, hipStream_t s);
   // upstream gradient g[W] times the derivatives of the last eval()

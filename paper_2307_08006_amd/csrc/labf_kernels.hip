@@ -729,7 +729,17 @@ struct Ring {
     bj = LB ? b[k] : (T)0;
   }
 };
-template <typename T, bool LB, bool ENERGY, bool DIAG>
+// Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut): F/r and, with
+// ENERGY, the energy.  Storage precision.
+template <typename T>
+__device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
+  const T br = d.ewb * (r2 * rinv);
+  const T ec = qq * erfc(br) * rinv;
+  ue = ec;
+  return (ec + qq * d.ewc * exp(-br * br)) * r2inv;
+}
+
+template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
 __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], const T (&yi)[CL],
                                           const T (&zi)[CL], const T (&qi)[CL], const T (&ai)[CL],
                                           const T (&bi)[CL], int64_t s0, T xj, T yj, T zj, T qj,
@@ -756,7 +766,8 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
       flj = bij * t3 * ((T)2 * t3 - (T)1);
     }
     const T qq = qi[ii] * qj;
-    const T fc = qq * rinv * (r2inv - d.irc2);
+    T uew = (T)0;
+    const T fc = EW ? ewald_fr(d, qq, r2, rinv, r2inv, uew) : qq * rinv * (r2inv - d.irc2);
     T fr = flj * r2inv + fc;
     fr = in ? fr : (T)0;
     fx[ii] -= fr * dx;
@@ -773,7 +784,7 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
         el = bij / (T)6 * ((t3 * t3 - t3) - (tc3 * tc3 - tc3));
       }
       const T rr = r2 * rinv;
-      const T ec = qq * (rinv - d.irc + (rr - (T)d.r_cut) * d.irc2);
+      const T ec = EW ? uew : qq * (rinv - d.irc + (rr - (T)d.r_cut) * d.irc2);
       // padded i-slots share the sentinel position with padded j-slots
       eacc += (in && ((vmask >> ii) & 1)) ? 0.5 * ((double)el + (double)ec) : 0.0;
     }
@@ -784,7 +795,7 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
 // soft-core LJ at coupling cv with A = alpha (1 - cv)^p and shifted-force
 // Coulomb at ce for solute partners, plain terms (c = 1) for the others.
 // Energies and dV/dlambda of these pairs are accounted on the alchemical side.
-template <typename T, bool SHIFTED>
+template <typename T, bool SHIFTED, bool EW>
 __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL],
                                                const T (&yi)[CL], const T (&zi)[CL],
                                                const T (&qi)[CL], const T (&ai)[CL],
@@ -818,7 +829,9 @@ __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL
     const T bij = bi[ii] * bj;
     T flj = bij * c * ((T)2 * y - (T)1) * y * g;
     flj = bij != (T)0 ? flj : (T)0;
-    const T fc = e * qi[ii] * qj * rinv * (r2inv - d.irc2);
+    T uew;
+    const T fc = EW ? ewald_fr(d, e * qi[ii] * qj, r2, rinv, r2inv, uew)
+                    : e * qi[ii] * qj * rinv * (r2inv - d.irc2);
     const T fr = in ? flj + fc : (T)0;
     fx[ii] -= fr * dx;
     fy[ii] -= fr * dy;
@@ -887,7 +900,7 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
 
 // SHIFTED selects the soft-core form of the alchemical segment at compile time
 // (both forms in one instantiation double the register allocation).
-template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED>
+template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED, bool EW>
 __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   const int nb = (int)((r.en + 3) >> 2);
   const int lblk = xcd_block(nb);
@@ -960,7 +973,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
     T xj, yj, zj, qj, aj, bj;
     int js;
     load_j(0, xj, yj, zj, qj, aj, bj, js);
-    env_pairs<T, LB, ENERGY, true>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js, vmask,
+    env_pairs<T, LB, ENERGY, true, EW>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js, vmask,
                                    fx, fy, fz, eacc);
   }
   if (nenv > CL) {
@@ -1002,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         T x2, y2, z2, q2, a2, b2;
         rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
         __builtin_amdgcn_wave_barrier();
-        env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+        env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
                                         vmask, fx, fy, fz, eacc);
         head = (head + WAVE) & (RING - 1);
         cnt -= WAVE;
@@ -1012,7 +1025,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
       __builtin_amdgcn_wave_barrier();
       T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
       if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
-      env_pairs<T, LB, ENERGY, false>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+      env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
                                       vmask, fx, fy, fz, eacc);
     }
   }
@@ -1042,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         bj = d.ljb[js];
         alch = d.sol[js] != 0;
       }
-      env_alch_pairs<T, SHIFTED>(d, xi, yi, zi, qi, ai, bi, xj, yj, zj, qj, aj, bj, alch, valid,
+      env_alch_pairs<T, SHIFTED, EW>(d, xi, yi, zi, qi, ai, bi, xj, yj, zj, qj, aj, bj, alch, valid,
                                  (T)cv, (T)ce, Asc, Dsc, fx, fy, fz);
     }
   }
@@ -1081,6 +1094,16 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
         if (t.on)
 #pragma unroll
           for (int k = 0; k < 3; ++k) F[k] += d.dr_k * t.e * t.u[k];
+      }
+    }
+    if (EW && valid) {
+      // reciprocal-space force; energy: half the atom's own-group potential
+      // times its charge, minus the Ewald self term
+#pragma unroll
+      for (int k = 0; k < 3; ++k) F[k] += d.pme_frc[(int64_t)k * d.n_slots + s];
+      if (ENERGY) {
+        const double q = d.q64[s];
+        eacc += 0.5 * q * d.pme_phi[s] - d.coulomb_k * d.ewald_beta * 0.56418958354775628 * q * q;
       }
     }
     if (INTEG) {
@@ -1149,7 +1172,8 @@ __device__ __forceinline__ void softcore_y(const SoftCore &sc, double r2, double
 }
 
 __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq, double cv,
-                                            double ce, const SoftCore &scf, double rc) {
+                                            double ce, const SoftCore &scf, double rc,
+                                            double beta) {
   PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double r = sqrt(r2);
   if (eps != 0.0) {
@@ -1164,12 +1188,14 @@ __device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, 
     o.dsig = 4.0 * eps * cv * ((2.0 * y - 1.0) * dys - (2.0 * yc - 1.0) * dysc) / sig;
   }
   if (qq != 0.0) {
-    const double g = 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
+    // beta > 0: real-space Ewald kernel erfc(beta r)/r cut at rc
+    const double g = beta > 0.0 ? erfc(beta * r) / r : 1.0 / r - 1.0 / rc + (r - rc) / (rc * rc);
     o.g = g;
     o.duc = qq * g;
     if (ce != 0.0) {
       o.uc = ce * qq * g;
-      o.fr += ce * qq * (1.0 / r2 - 1.0 / (rc * rc)) / r;
+      o.fr += beta > 0.0 ? ce * qq * (g + 1.1283791670955126 * beta * exp(-beta * beta * r2)) / r2
+                         : ce * qq * (1.0 / r2 - 1.0 / (rc * rc)) / r;
     }
   }
   return o;
@@ -1220,6 +1246,20 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
     }
   }
   double G = wave_sum(g) + wave_sum(gr);
+  // neutralising background of the Ewald sum: -pi k Q^2 / (2 V beta^2) split
+  // as E-E, S-S and the cross part, which is scaled by ce like V_x
+  double bg[3] = {0.0, 0.0, 0.0}, bce = 1.0;
+  if (d.pme_on) {
+    const double *qs = d.pme_qs + 4 * w;
+    const double f = -3.14159265358979323846 * d.coulomb_k /
+                     (m.L[0] * m.L[1] * m.L[2] * d.ewald_beta * d.ewald_beta);
+    bg[0] = 0.5 * f * qs[0] * qs[0];
+    bg[1] = 0.5 * f * qs[1] * qs[1];
+    bg[2] = f * qs[0] * qs[1];
+    double dbce;
+    channel(lam, d.lp.elec_start, d.lp.elec_end, d.lp.direction, d.lp.hi, bce, dbce);
+    G += dbce * bg[2];
+  }
   double udr = 0.0;
   if (d.dr_pair && d.dr_pair[2 * w] >= 0) {
     const DrTerm t = dr_term(d, m, xb, d.dr_pair[2 * w], d.dr_pair[2 * w + 1], lam);
@@ -1235,6 +1275,9 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
       for (int t = lane; t < m.n_acl; t += WAVE) e += d.item_energy[(m.item_begin + t) * 5 + q];
       e = wave_sum(e);
       if (q == 4) e += wave_sum(ur) + udr;
+      if (q == 0) e += bg[0];
+      if (q == 1) e += bg[1];
+      if (q == 3) e += bce * bg[2];
       if (lane == 0) d.energy[w * 5 + q] = e;
     }
   }
@@ -1387,7 +1430,8 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
       const double sig = 0.5 * (sgi + d.sig64[js]);
       const double eps = sqrt(epi * d.eps64[js]);
       const double qq = d.coulomb_k * qi * d.q64[js];
-      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0, scf, rc);
+      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0, scf, rc,
+                                  d.pme_on ? d.ewald_beta : 0.0);
       acc[0] -= o.fr * dx;
       acc[1] -= o.fr * dy;
       acc[2] -= o.fr * dz;
@@ -1424,6 +1468,26 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     double tot[NACC];
 #pragma unroll
     for (int q = 0; q < NACC; ++q) tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    if (d.pme_on && c >= 0) {
+      // reciprocal space: force from the gather; dV/dlambda of the cross
+      // term dce q phi_E for group atoms; energies and dV/dq with the self term
+      const int64_t si = c * CL;
+      const double q = d.q64[si], po = d.pme_phi[si], pt = d.pme_phi[d.n_slots + si];
+      const bool so = d.sol[si] != 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) tot[a] += d.pme_frc[(int64_t)a * d.n_slots + si];
+      if (so) tot[3] += dce * q * pt;
+      if (ENERGY) {
+        const double kb = d.coulomb_k * d.ewald_beta * 0.56418958354775628;  // k beta / sqrt(pi)
+        tot[so ? 5 : 4] += 0.5 * q * po - kb * q * q;
+        if (so) tot[7] += ce * q * pt;
+        const double *qs = d.pme_qs + 4 * w;
+        const double V = m.L[0] * m.L[1] * m.L[2];
+        const double qo = so ? qs[1] : qs[0], qt = so ? qs[0] : qs[1];
+        tot[11] += (po + ce * pt) - 2.0 * kb * q -
+                   3.14159265358979323846 * d.coulomb_k * (qo + ce * qt) / (V * d.ewald_beta * d.ewald_beta);
+      }
+    }
     d.item_force[k * 3] = tot[0];
     d.item_force[k * 3 + 1] = tot[1];
     d.item_force[k * 3 + 2] = tot[2];
@@ -1685,6 +1749,368 @@ __global__ void k_energy_grads(Dev<T> d, const double *g, double *gpos, double *
 }
 
 // ---------------------------------------------------------------------------
+// smooth particle-mesh Ewald: reciprocal space
+// ---------------------------------------------------------------------------
+// The environment (E) and the alchemical group (S) each have their own
+// charge density; with G the (real, even) influence function their grid
+// potentials are phi_E = G * Q_E and phi_S = G * Q_S, and the decoupled
+// reciprocal energy at electrostatic coupling ce is
+// V_E + V_S + ce V_x, V_x = sum_k Q_S phi_E (Section 2, alchemical pathway:
+// the many-body term interpolated between its electrostatic end values).
+// Both densities ride in one complex grid (E real, S imaginary): one forward
+// transform, the multiplication by G, one inverse transform give
+// phi_E + i phi_S.  Charges are spread with B-splines of order P
+// (Essmann et al. 1995) as 2^-40 fixed-point integers, so the grid does not
+// depend on the order of the atomic additions.
+
+// w[j] = M_P(f + j), dw[j] = M_P'(f + j) for j = 0..P-1 (grid point k0 - j,
+// f in [0, 1)), from M_2 through M_n(u) = (u M_{n-1}(u) + (n - u) M_{n-1}(u-1)) / (n-1)
+// and M_n'(u) = M_{n-1}(u) - M_{n-1}(u - 1).
+template <int P>
+__device__ __forceinline__ void bspline_w(double f, double (&w)[P], double (&dw)[P]) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) w[j] = 0.0;
+  w[0] = f;
+  w[1] = 1.0 - f;
+#pragma unroll
+  for (int n = 3; n <= P; ++n) {
+    if (n == P) {
+      dw[0] = w[0];
+#pragma unroll
+      for (int j = 1; j < P; ++j) dw[j] = w[j] - w[j - 1];
+    }
+    const double inv = 1.0 / (double)(n - 1);
+#pragma unroll
+    for (int j = n - 1; j >= 0; --j) {
+      const double u = f + (double)j;
+      const double a = j < n - 1 ? w[j] : 0.0;
+      const double b = j > 0 ? w[j - 1] : 0.0;
+      w[j] = (u * a + ((double)n - u) * b) * inv;
+    }
+  }
+}
+
+// Grid base point k0 and offset f of one coordinate (positions are stored
+// relative to B and may lie up to a list buffer outside [0, L)).
+__device__ __forceinline__ int pme_axis(double x, double L, int K, double &f) {
+  double g = x / L;
+  g -= floor(g);
+  const double u = g * (double)K;
+  const double k0 = floor(u);
+  f = u - k0;
+  return (int)k0;
+}
+
+// One thread per slot: B-spline spread of the slot's charge into its group's
+// half of the fixed-point accumulator.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= (r.c0 + r.cn) * CL || d.orig[s] < 0) return;
+  const double q = d.q64[s];
+  if (q == 0.0) return;
+  const int w = d.cl_walker[s / CL];
+  const WalkerMeta &m = d.meta[w];
+  const PmeWalker &pw = d.pme[w];
+  double wt[3][P], dw[3][P];
+  int k0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double f;
+    k0[a] = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
+    bspline_w<P>(f, wt[a], dw[a]);
+  }
+  unsigned long long *acc = d.pme_acc + 2 * pw.goff + (d.sol[s] ? 1 : 0);
+  const int m0 = pw.K[0] - 1, m1 = pw.K[1] - 1, m2 = pw.K[2] - 1;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int64_t ix = (int64_t)((k0[0] - i) & m0) * pw.K[1];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int64_t ixy = (ix + ((k0[1] - j) & m1)) * pw.K[2];
+      const double qw = q * wt[0][i] * wt[1][j];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const long long v = __double2ll_rn(qw * wt[2][k] * 0x1p40);
+        atomicAdd(acc + 2 * (ixy + ((k0[2] - k) & m2)), (unsigned long long)v);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One block transforms NL grid lines of length K along axis AX in LDS.
+// MODE 0: forward, reading (and clearing) the fixed-point accumulator;
+// 1: forward; 2: forward, times the influence function, inverse (x lines);
+// 3: inverse.  The forward transform is decimation in frequency (natural in,
+// bit-reversed out), the inverse decimation in time (bit-reversed in, natural
+// out), so the grid holds bit-reversed frequency indices between the passes
+// and no permutation is ever done.  Lines along z are contiguous; lines
+// along y and x are taken NL at a time from consecutive z so that every
+// load and store is a run of NL contiguous points.
+template <int AX, int MODE>
+__global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
+                                                 double2 *grid, unsigned long long *acc,
+                                                 const double *tab, int b0) {
+  __shared__ double2 buf[PME_TILE];
+  __shared__ double2 tw[PME_KMAX / 2];
+  const int bid = b0 + (int)blockIdx.x;
+  const PmeWalker &pw = pme[bw[bid]];
+  const int K = pw.K[AX], lg = pw.lg[AX], NL = pw.nl[AX];
+  const int g = bid - pw.blk_begin[AX];
+  const int64_t K1 = pw.K[1], K2 = pw.K[2];
+  int64_t base, sp;
+  int lgnl = 0;
+  while ((1 << lgnl) < NL) ++lgnl;
+  if (AX == 2) {
+    base = (int64_t)g * NL * K;
+    sp = 1;
+  } else {
+    const int gz = (int)(K2 >> lgnl);
+    const int64_t outer = g / gz, iz0 = (int64_t)(g % gz) * NL;
+    base = (AX == 1 ? outer * K1 * K2 : outer * K2) + iz0;
+    sp = AX == 1 ? K2 : K1 * K2;
+  }
+  base += pw.goff;
+  for (int k = threadIdx.x; k < (K >> 1); k += 256) {
+    double sn, cs;
+    sincospi(-2.0 * (double)k / (double)K, &sn, &cs);
+    tw[k] = make_double2(cs, sn);
+  }
+  const int n = NL << lg;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    int t, pos;
+    int64_t gi;
+    if (AX == 2) {
+      t = i >> lg;
+      pos = i & (K - 1);
+      gi = base + i;
+    } else {
+      t = i & (NL - 1);
+      pos = i >> lgnl;
+      gi = base + t + pos * sp;
+    }
+    double2 v;
+    if (MODE == 0) {
+      unsigned long long *a = acc + 2 * gi;
+      v = make_double2((double)(long long)a[0] * 0x1p-40, (double)(long long)a[1] * 0x1p-40);
+      a[0] = 0ull;
+      a[1] = 0ull;
+    } else {
+      v = grid[gi];
+    }
+    buf[(t << lg) + pos] = v;
+  }
+  __syncthreads();
+  const int nb = n >> 1, hl = lg - 1;
+  if (MODE <= 2) {
+    for (int l = lg; l >= 1; --l) {  // span 2^l
+      const int half = 1 << (l - 1), ts = 1 << (lg - l);
+      for (int b = threadIdx.x; b < nb; b += 256) {
+        const int t = b >> hl, j = b & ((1 << hl) - 1);
+        const int k = j & (half - 1);
+        const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+        const double2 u = buf[i0], v = buf[i1];
+        buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+        buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[k * ts]);
+      }
+      __syncthreads();
+    }
+  }
+  if (MODE == 2) {
+    // x lines (AX == 0): line t is grid column (iy, iz0 + t); every index
+    // is a bit-reversed frequency
+    const int gz = (int)(K2 >> lgnl);
+    const int iy = g / gz, iz0 = (g % gz) * NL;
+    const int lg1 = pw.lg[1], lg2 = pw.lg[2];
+    const double *tx = tab + 2 * pw.toff, *ty = tx + 2 * pw.K[0], *tz = ty + 2 * pw.K[1];
+    const int fy = (int)(__brev((unsigned)iy) >> (32 - lg1));
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int t = i >> lg, pos = i & (K - 1);
+      const int fx = (int)(__brev((unsigned)pos) >> (32 - lg));
+      const int fz = (int)(__brev((unsigned)(iz0 + t)) >> (32 - lg2));
+      const double m2 = (tx[2 * fx + 1] + ty[2 * fy + 1]) + tz[2 * fz + 1];
+      const double G = (fx | fy | fz) == 0 ? 0.0 : pw.pref * (tx[2 * fx] * ty[2 * fy] * tz[2 * fz]) / m2;
+      const double2 v = buf[i];
+      buf[i] = make_double2(v.x * G, v.y * G);
+    }
+    __syncthreads();
+  }
+  if (MODE >= 2) {
+    for (int l = 1; l <= lg; ++l) {
+      const int half = 1 << (l - 1), ts = 1 << (lg - l);
+      for (int b = threadIdx.x; b < nb; b += 256) {
+        const int t = b >> hl, j = b & ((1 << hl) - 1);
+        const int k = j & (half - 1);
+        const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+        const double2 u = buf[i0], w0 = tw[k * ts];
+        const double2 v = cmul(buf[i1], make_double2(w0.x, -w0.y));
+        buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+        buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += 256) {
+    int t, pos;
+    int64_t gi;
+    if (AX == 2) {
+      t = i >> lg;
+      pos = i & (K - 1);
+      gi = base + i;
+    } else {
+      t = i & (NL - 1);
+      pos = i >> lgnl;
+      gi = base + t + pos * sp;
+    }
+    grid[gi] = buf[(t << lg) + pos];
+  }
+}
+
+// One thread per slot: potentials of both groups and their gradients at the
+// atom; force -q (grad phi_own + ce grad phi_other).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_pme_gather(Dev<T> d, Range r, int xb, int lb) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= (r.c0 + r.cn) * CL) return;
+  const int64_t S = d.n_slots;
+  if (d.orig[s] < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.pme_frc[a * S + s] = 0.0;
+    d.pme_phi[s] = 0.0;
+    d.pme_phi[S + s] = 0.0;
+    return;
+  }
+  const int w = d.cl_walker[s / CL];
+  const WalkerMeta &m = d.meta[w];
+  const PmeWalker &pw = d.pme[w];
+  double wt[3][P], dw[3][P];
+  int k0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double f;
+    k0[a] = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
+    bspline_w<P>(f, wt[a], dw[a]);
+  }
+  const double2 *gr = d.pme_grid + pw.goff;
+  const int m0 = pw.K[0] - 1, m1 = pw.K[1] - 1, m2 = pw.K[2] - 1;
+  double pe = 0.0, ps = 0.0, ge[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
+  // one grid row (P points along z) per iteration keeps the loads in flight
+  // few enough to avoid spilling; the x and y weights of the current row are
+  // rotated into element 0 so that every array index is static
+#pragma unroll 1
+  for (int i = 0; i < P; ++i) {
+    const int64_t ix = (int64_t)((k0[0] - i) & m0) * pw.K[1];
+    double wy[P], dy[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      wy[t] = wt[1][t];
+      dy[t] = dw[1][t];
+    }
+#pragma unroll 1
+    for (int j = 0; j < P; ++j) {
+      const int64_t ixy = (ix + ((k0[1] - j) & m1)) * pw.K[2];
+      const double wxy = wt[0][0] * wy[0], dxy = dw[0][0] * wy[0], xdy = wt[0][0] * dy[0];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const double2 v = gr[ixy + ((k0[2] - k) & m2)];
+        const double a = wxy * wt[2][k], bx = dxy * wt[2][k], by = xdy * wt[2][k], bz = wxy * dw[2][k];
+        pe += a * v.x;
+        ps += a * v.y;
+        ge[0] += bx * v.x;
+        gs[0] += bx * v.y;
+        ge[1] += by * v.x;
+        gs[1] += by * v.y;
+        ge[2] += bz * v.x;
+        gs[2] += bz * v.y;
+      }
+#pragma unroll
+      for (int t = 0; t + 1 < P; ++t) {
+        wy[t] = wy[t + 1];
+        dy[t] = dy[t + 1];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t + 1 < P; ++t) {
+      wt[0][t] = wt[0][t + 1];
+      dw[0][t] = dw[0][t + 1];
+    }
+  }
+  double ce, dce;
+  const LamParams &lp = d.lp;
+  channel(d.lambda[lb * d.n_walkers + w], lp.elec_start, lp.elec_end, lp.direction, lp.hi, ce, dce);
+  const bool so = d.sol[s] != 0;
+  const double q = d.q64[s];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double sc = (double)pw.K[a] / m.L[a];
+    const double own = so ? gs[a] : ge[a], oth = so ? ge[a] : gs[a];
+    d.pme_frc[a * S + s] = -q * sc * (own + ce * oth);
+  }
+  d.pme_phi[s] = so ? ps : pe;
+  d.pme_phi[S + s] = so ? pe : ps;
+}
+
+// Per-axis influence-function factors of every walker (one block per
+// walker): A(m) = exp(-pi^2 m~^2 / beta^2) |b(m)|^2 and m~^2, m~ = m / L for the
+// signed frequency m of natural index f, with the Euler exponential spline
+// modulus |b(m)|^2 = 1 / |sum_{k=0}^{P-2} M_P(k+1) exp(2 pi i m k / K)|^2.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_pme_tables(Dev<T> d, double *tab) {
+  const int w = blockIdx.x;
+  const WalkerMeta &m = d.meta[w];
+  const PmeWalker &pw = d.pme[w];
+  double mp[P], dmp[P];
+  bspline_w<P>(0.0, mp, dmp);  // mp[j] = M_P(j)
+  const int n = pw.K[0] + pw.K[1] + pw.K[2];
+  const double pb = 3.14159265358979323846 / d.ewald_beta;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int a = e < pw.K[0] ? 0 : (e < pw.K[0] + pw.K[1] ? 1 : 2);
+    const int f = e - (a > 0 ? pw.K[0] : 0) - (a > 1 ? pw.K[1] : 0);
+    const int K = pw.K[a];
+    const int mm = f < K / 2 ? f : f - K;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k <= P - 2; ++k) {
+      double sn, cs;
+      sincospi(2.0 * (double)mm * (double)k / (double)K, &sn, &cs);
+      re += mp[k + 1] * cs;
+      im += mp[k + 1] * sn;
+    }
+    const double mt = (double)mm / m.L[a];
+    tab[2 * (pw.toff + e)] = exp(-pb * pb * mt * mt) / (re * re + im * im);
+    tab[2 * (pw.toff + e) + 1] = mt * mt;
+  }
+}
+
+// Per-walker charge sums of both groups in a fixed order (one block per
+// walker): Q_E, Q_S, sum_E q^2, sum_S q^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pme_charges(Dev<T> d) {
+  __shared__ double red[4][4];
+  const int w = blockIdx.x;
+  const WalkerMeta &m = d.meta[w];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < m.n_atoms; i += 256) {
+    const double q = d.a_q[m.atom_begin + i];
+    const int so = d.a_sol[m.atom_begin + i] ? 1 : 0;
+    v[so] += q;
+    v[2 + so] += q * q;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double t = wave_sum(v[k]);
+    if (lane_id() == 0) red[threadIdx.x >> 6][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4)
+    d.pme_qs[4 * w + threadIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1711,17 +2137,17 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
   return hipGetLastError();
 }
 
-template <typename T, bool SH>
+template <typename T, bool SH, bool EW>
 static void env_launch_form(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
                             bool integ, unsigned grid, hipStream_t s) {
   if (d.uniform_lj) {
-    if (integ) k_env<T, false, false, true, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, false, true, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else k_env<T, false, false, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    if (integ) k_env<T, false, false, true, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, false, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, false, false, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   } else {
-    if (integ) k_env<T, true, false, true, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, true, true, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else k_env<T, true, false, false, SH><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    if (integ) k_env<T, true, false, true, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy) k_env<T, true, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else k_env<T, true, false, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   }
 }
 
@@ -1731,13 +2157,22 @@ static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, 
   const int nb = (int)((r.en + 3) / 4);
   const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
   if (grid == 0) return;
-  if (d.lp.sc_form == 1) env_launch_form<T, true>(d, r, xb, vb, lb, energy, integ, grid, s);
-  else env_launch_form<T, false>(d, r, xb, vb, lb, energy, integ, grid, s);
+  if (d.pme_on) {
+    if (d.lp.sc_form == 1) env_launch_form<T, true, true>(d, r, xb, vb, lb, energy, integ, grid, s);
+    else env_launch_form<T, false, true>(d, r, xb, vb, lb, energy, integ, grid, s);
+  } else {
+    if (d.lp.sc_form == 1) env_launch_form<T, true, false>(d, r, xb, vb, lb, energy, integ, grid, s);
+    else env_launch_form<T, false, false>(d, r, xb, vb, lb, energy, integ, grid, s);
+  }
 }
 
 template <typename T>
 hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                            hipStream_t s) {
+  if (d.pme_on) {
+    const hipError_t e = pme(d, r, xb, lb, s);
+    if (e != hipSuccess) return e;
+  }
   if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   env_launch<T>(d, r, xb, vb, lb, false, true, s);
   return hipGetLastError();
@@ -1760,6 +2195,10 @@ hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, 
 template <typename T>
 hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                            hipStream_t s) {
+  if (d.pme_on) {
+    const hipError_t e = pme(d, r, xb, lb, s);
+    if (e != hipSuccess) return e;
+  }
   if (r.in_ > 0) k_alch<T, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   env_launch<T>(d, r, xb, vb, lb, true, false, s);
   return hipGetLastError();
@@ -1796,7 +2235,10 @@ hipError_t Launch<T>::scatter_atoms(const Dev<T> &d, int xb, int vb, const doubl
 template <typename T>
 hipError_t Launch<T>::set_config(const Dev<T> &d, int xb, int lb, const double *pos,
                                  const double *lam, const double *params, hipStream_t s) {
-  if (params && d.n_solute > 0) k_set_params<T><<<nblk(d.n_solute, 256), 256, 0, s>>>(d, params);
+  if (params && d.n_solute > 0) {
+    k_set_params<T><<<nblk(d.n_solute, 256), 256, 0, s>>>(d, params);
+    if (d.pme_on) k_pme_charges<T><<<(unsigned)d.n_walkers, 256, 0, s>>>(d);
+  }
   if (pos || lam) {
     const int64_t n = pos ? (d.n_atoms > d.n_walkers ? d.n_atoms : d.n_walkers) : d.n_walkers;
     k_set_config<T><<<nblk(n, 256), 256, 0, s>>>(d, xb, lb, pos, lam);
@@ -1837,6 +2279,45 @@ hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_philox<<<nblk(n, 256), 256, 0, s>>>(n, ctr, k0, k1, out);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
+  const unsigned ns = nblk(r.cn * CL, 256);
+  k_pme_spread<T, P><<<ns, 256, 0, s>>>(d, r, xb);
+  double *tab = const_cast<double *>(d.pme_tab);
+  if (r.pbn[2] > 0) k_pme_fft<2, 0><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, d.pme_acc, tab, r.pb0[2]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, d.pme_acc, tab, r.pb0[1]);
+  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 256, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, d.pme_acc, tab, r.pb0[0]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, d.pme_acc, tab, r.pb0[1]);
+  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, d.pme_acc, tab, r.pb0[2]);
+  k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
+}
+
+template <typename T>
+hipError_t Launch<T>::pme(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
+  if (!d.pme_on || r.cn <= 0) return hipSuccess;
+  if (d.pme_order == 4) pme_order_launch<T, 4>(d, r, xb, lb, s);
+  else if (d.pme_order == 6) pme_order_launch<T, 6>(d, r, xb, lb, s);
+  else pme_order_launch<T, 8>(d, r, xb, lb, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::pme_charges(const Dev<T> &d, hipStream_t s) {
+  if (!d.pme_on) return hipSuccess;
+  k_pme_charges<T><<<(unsigned)d.n_walkers, 256, 0, s>>>(d);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::pme_tables(const Dev<T> &d, hipStream_t s) {
+  if (!d.pme_on) return hipSuccess;
+  double *tab = const_cast<double *>(d.pme_tab);
+  if (d.pme_order == 4) k_pme_tables<T, 4><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, tab);
+  else if (d.pme_order == 6) k_pme_tables<T, 6><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, tab);
+  else k_pme_tables<T, 8><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, tab);
   return hipGetLastError();
 }
 

@@ -50,8 +50,9 @@ class SystemDesc(C.Structure):
         ("r_cut", C.c_double), ("r_skin", C.c_double), ("kT", C.c_double),
         ("gamma", C.c_double), ("dt", C.c_double), ("coulomb_k", C.c_double),
         ("accel_unit", C.c_double), ("seed", C.c_uint64),
-        ("rebuild_interval", C.c_int32), ("reserved", C.c_int32),
+        ("rebuild_interval", C.c_int32), ("pme_order", C.c_int32),
         ("r_skin_alch", C.c_double), ("column_width", C.c_void_p),
+        ("pme_dims", C.c_void_p), ("ewald_beta", C.c_double),
     ]
 
 
@@ -169,7 +170,8 @@ class System:
             pos=_f64(spec.pos, (-1, 3)), vel=_f64(spec.vel, (-1, 3)), mass=_f64(spec.mass),
             charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
             is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
-            k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width))
+            k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width),
+            pme_dims=None if spec.pme_dims is None else np.ascontiguousarray(spec.pme_dims, np.int32))
         d = SystemDesc()
         d.n_walkers = spec.n_walkers
         d.precision = LABF_FP64 if spec.precision == "fp64" else LABF_FP32
@@ -179,7 +181,8 @@ class System:
             setattr(d, k, float(getattr(spec, k)))
         d.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
         d.rebuild_interval = int(spec.rebuild_interval)
-        d.reserved = 0
+        d.pme_order = 0 if spec.pme_dims is None else int(spec.pme_order)
+        d.ewald_beta = float(spec.ewald_beta) if spec.pme_dims is not None else 0.0
         d.r_skin_alch = float(spec.r_skin_alch)
         h = C.c_void_p()
         rc = lib().labf_create_system(C.byref(d), self.stream, C.byref(h))
@@ -340,9 +343,10 @@ class System:
 
     def profile_steps(self, n_steps: int) -> dict:
         """Per-kernel times (ms) from HIP events around single launches."""
-        ms = np.zeros(3)
+        ms = np.zeros(4)
         self._chk(lib().labf_profile_steps(self._h, int(n_steps), _p(ms), self.stream))
-        return dict(rebuild_ms=float(ms[0]), alch_ms=float(ms[1]), env_ms=float(ms[2]))
+        return dict(rebuild_ms=float(ms[0]), alch_ms=float(ms[1]), env_ms=float(ms[2]),
+                    pme_ms=float(ms[3]))
 
     def info(self) -> dict:
         inf = Info()

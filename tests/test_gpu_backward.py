@@ -46,12 +46,20 @@ def _restrained(spec, lam):
     return spec, lam
 
 
+def _pme(spec, lam):
+    spec = synth.with_pme(spec)
+    spec.charge[np.nonzero(spec.is_solute)[0][:3]] += 0.3
+    return spec, lam
+
+
 CASES = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp64": lambda: _charged("fp64"),
     "charged3k_fp32": lambda: _charged("fp32"),
     "charged3k_fp64_shifted": lambda: _shifted(*_charged("fp64")),
     "charged3k_fp64_restrained": lambda: _restrained(*_charged("fp64")),
+    "charged3k_fp64_pme": lambda: _pme(*_charged("fp64")),
+    "charged3k_fp32_pme": lambda: _pme(*_charged("fp32")),
 }
 LAMS = [0.35, 0.75]   # inside the electrostatics and the soft-core vdW ramps
 

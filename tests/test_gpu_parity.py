@@ -63,6 +63,22 @@ def _restrained(precision, freq=1):
     return spec, lam
 
 
+def _pme(precision):
+    """Smooth-PME electrostatics (grid spacing <= 1.1 A, order 4,
+    erfc(beta r_cut) = 1e-6) with a net-charged group, so that the
+    neutralising-background cross term enters dV/dlambda."""
+    spec, lam = _small_charged(precision)
+    spec = synth.with_pme(spec)
+    spec.charge[np.nonzero(spec.is_solute)[0][:3]] += 0.3
+    return spec, lam
+
+
+def _uneven_pme(precision):
+    """Three uneven walkers with differently shaped PME grids (order 6)."""
+    spec, lam = _uneven(precision)
+    return synth.with_pme(spec, dims=[[32, 32, 32], [16, 32, 64], [64, 16, 16]], order=6), lam
+
+
 SYSTEMS = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp32": lambda: _small_charged("fp32"),
@@ -72,6 +88,9 @@ SYSTEMS = {
     "charged3k_fp64_shifted": lambda: _shifted("fp64"),
     "charged3k_fp64_restrained": lambda: _restrained("fp64"),
     "charged3k_fp32_restrained2": lambda: _restrained("fp32", freq=2),
+    "charged3k_fp32_pme": lambda: _pme("fp32"),
+    "charged3k_fp64_pme": lambda: _pme("fp64"),
+    "uneven3_fp32_pme": lambda: _uneven_pme("fp32"),
 }
 
 
@@ -148,13 +167,18 @@ def _state(s):
     return st, c, s1, s2, pos, vel
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "fixed_lambda"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "fixed_lambda", "pme_batched", "pme_plain"])
 def test_short_fp64_trajectory_matches_oracle(mode):
     if mode == "fixed_lambda":
         # fixed-lambda TI windows: lambda frozen at 4 window centres
         base, lam0 = synth.lj_reduced(n_walkers=1)
         spec, lam = synth.ti_windows(base, lam0, n_windows=4, replicas=1, seed=77)
         mode = "batched"
+    elif mode.startswith("pme"):
+        # charged fluid with Ewald electrostatics on a 16 x 16 x 32 grid
+        spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35, charges=0.5)
+        spec = synth.with_pme(spec, dims=(16, 16, 32))
+        mode = mode[4:]
     else:
         spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35)
     lam.share_interval = 2
@@ -181,8 +205,9 @@ def test_short_fp64_trajectory_matches_oracle(mode):
     s.close()
 
 
-def test_batched_and_plain_are_bitwise_identical():
-    spec, lam = _uneven("fp32")
+@pytest.mark.parametrize("pme", [False, True])
+def test_batched_and_plain_are_bitwise_identical(pme):
+    spec, lam = _uneven_pme("fp32") if pme else _uneven("fp32")
     a = labf.System(spec, lam)
     b = labf.System(spec, lam)
     a.step(25, "batched")

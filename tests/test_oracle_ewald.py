@@ -114,9 +114,9 @@ def test_spme_is_translation_invariant_on_grid_shifts():
     forces unchanged (the B-spline weights are the same, shifted)."""
     x, q, L = _random_charges(n=15)
     dims = (16, 32, 16)
-    e0, f0 = oracle.spme_energy(x, q, L, 2.5, dims, 5)
+    e0, f0 = oracle.spme_energy(x, q, L, 2.5, dims, 6)
     x1 = x + np.array([3, 5, 15]) * L / np.array(dims)
-    e1, f1 = oracle.spme_energy(x1, q, L, 2.5, dims, 5)
+    e1, f1 = oracle.spme_energy(x1, q, L, 2.5, dims, 6)
     assert abs(e1 - e0) < 1e-12 * abs(e0)
     assert np.abs(f1 - f0).max() < 1e-10 * np.abs(f0).max()
 
@@ -220,7 +220,7 @@ def test_pme_walker_charge_gradient_matches_finite_difference():
 
 def test_pme_rejects_bad_grids():
     spec, lam = _pme_small(dims=(16, 16, 16), order=4)
-    for dims, order in (((16, 24, 16), 4), ((16, 16, 16), 9), ((2, 16, 16), 4)):
+    for dims, order in (((16, 24, 16), 4), ((16, 16, 16), 5), ((16, 16, 16), 10), ((2, 16, 16), 4)):
         sp = dataclasses.replace(spec, pme_dims=np.array([dims], np.int32), pme_order=order)
         with pytest.raises(ValueError):
             oracle.Oracle(sp, lam).evaluate(0, sp.pos, 0.1)
