@@ -213,6 +213,31 @@ def run_restrained(args, specb, lamb):
             "walker_status": int(np.bitwise_or.reduce(st["status"]))}
 
 
+def run_pme(args, specb, lamb):
+    """The 16-walker batch with Ewald electrostatics: real-space erfc pairs
+    cut at 12 A (erfc(beta r_cut) = 1e-6) and smooth-PME reciprocal space
+    on a 64^3 grid per walker (1.05 A spacing, B-spline order 4), the
+    reciprocal term interpolated linearly in the electrostatic coupling,
+    after a short re-equilibration under it."""
+    from paper_2307_08006_amd import labf, synth
+    spec = synth.with_pme(specb, spacing=1.1, order=4)
+    spec, lam = equilibrate(spec, lamb, args.variant_equil_steps, lambda_dynamics=True)
+    with labf.System(spec, lam) as s:
+        s.step(args.warmup)
+        dt = timed_steps(s, args.variant_steps, "batched")
+        st = s.read_walker_state()
+        prof = s.profile_steps(args.profile_steps)
+    log(f"pme: {args.variant_steps} steps in {dt:.3f} s")
+    K = [int(k) for k in spec.pme_dims[0]]
+    npts = spec.n_walkers * K[0] * K[1] * K[2]
+    return {"walker_steps_per_s": spec.n_walkers * args.variant_steps / dt,
+            "ms_per_step": 1e3 * dt / args.variant_steps, "steps": args.variant_steps,
+            "grid": K, "order": int(spec.pme_order), "ewald_beta": float(spec.ewald_beta),
+            "kernels_ms": prof,
+            "reciprocal_grid_points_per_s": npts / (1e-3 * prof["pme_ms"]) if prof["pme_ms"] > 0 else None,
+            "walker_status": int(np.bitwise_or.reduce(st["status"]))}
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -380,6 +405,7 @@ def main(argv=None):
     if args.variant_steps > 0:
         out["shifted_softcore"] = run_shifted(args, specb, lamb)
         out["distance_restraint"] = run_restrained(args, specb, lamb)
+        out["pme"] = run_pme(args, specb, lamb)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:

@@ -85,7 +85,7 @@ typedef int32_t labf_status;
 #define LABF_WS_NONFINITE 1u
 #define LABF_WS_REFLECT 2u       /* lambda needed more than one reflection     */
 #define LABF_WS_SKIN 4u          /* the two largest displacements since a rebuild exceed r_skin */
-#define LABF_WS_CAPACITY 8u
+#define LABF_WS_CAPACITY 8u       /* a neighbour list or a PME charge-spread brick list overflowed */
 
 /* Static description of a batch of walkers ("Software interface": the
  * engine side).  All pointers are host pointers. */

@@ -81,6 +81,7 @@ struct labf_system {
   std::vector<WalkerMeta> meta;
   std::vector<PmeWalker> pme;    // host copy (FFT block ranges of the launches)
   int32_t pme_nblk[3] = {0, 0, 0};
+  int32_t pme_bricks = 0;
   std::vector<int32_t> n_acl_host;
   hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -172,6 +173,8 @@ Range full_range(const labf_system *s) {
     r.pb0[a] = 0;
     r.pbn[a] = s->pme_nblk[a];
   }
+  r.bb0 = 0;
+  r.bbn = s->pme_bricks;
   return r;
 }
 
@@ -194,6 +197,8 @@ Range walker_range(const labf_system *s, int w) {
     r.pb0[a] = s->pme.empty() ? 0 : s->pme[w].blk_begin[a];
     r.pbn[a] = s->pme.empty() ? 0 : s->pme[w].blk[a];
   }
+  r.bb0 = s->pme.empty() ? 0 : s->pme[w].br_begin;
+  r.bbn = s->pme.empty() ? 0 : s->pme[w].nbr[0] * s->pme[w].nbr[1] * s->pme[w].nbr[2];
   return r;
 }
 
@@ -577,8 +582,9 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   for (int a = 0; a < 3; ++a) s->pme_nblk[a] = 0;
   if (d.pme_on) {
     s->pme.resize(W);
-    int64_t goff = 0, toff = 0;
-    std::vector<int32_t> bw[3];
+    int64_t goff = 0, toff = 0, loff = 0;
+    int32_t nbr = 0;
+    std::vector<int32_t> bw[3], brw;
     for (int w = 0; w < W; ++w) {
       PmeWalker &p = s->pme[w];
       std::memset(&p, 0, sizeof(p));
@@ -597,6 +603,16 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
         s->pme_nblk[a] += p.blk[a];
         bw[a].insert(bw[a].end(), (size_t)p.blk[a], w);
       }
+      // spread bricks; list capacity: three times the mean atom count of a
+      // brick plus 64 (overflow is flagged in the walker status)
+      const int32_t nb = (p.K[0] / PME_BR) * (p.K[1] / PME_BR) * (p.K[2] / PME_BR);
+      for (int a = 0; a < 3; ++a) p.nbr[a] = p.K[a] / PME_BR;
+      p.br_begin = nbr;
+      nbr += nb;
+      brw.insert(brw.end(), (size_t)nb, w);
+      p.br_cap = (int32_t)(((3 * (int64_t)s->meta[w].n_atoms) / nb + 64 + 31) / 32 * 32);
+      p.loff = loff;
+      loff += (int64_t)nb * p.br_cap;
       p.goff = goff;
       goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
       p.toff = toff;
@@ -607,7 +623,11 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     HIPCHK(s, upload(b, &d.pme, s->pme.data(), W));
     for (int a = 0; a < 3; ++a) HIPCHK(s, upload(b, &d.pme_bw[a], bw[a].data(), bw[a].size()));
     HIPCHK(s, dalloc(b, &d.pme_grid, goff));
-    HIPCHK(s, dalloc(b, &d.pme_acc, 2 * goff));
+    HIPCHK(s, upload(b, &d.pme_brw, brw.data(), brw.size()));
+    HIPCHK(s, dalloc(b, &d.pme_bcnt, nbr));
+    HIPCHK(s, dalloc(b, &d.pme_blist, loff));
+    d.pme_nbr = nbr;
+    s->pme_bricks = nbr;
     double *tab = nullptr;
     HIPCHK(s, dalloc(b, &tab, 2 * toff));
     d.pme_tab = tab;

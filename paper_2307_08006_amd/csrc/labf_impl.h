@@ -57,13 +57,18 @@ struct WalkerMeta {
 constexpr int PME_TILE = 2048;  // complex points per FFT block
 constexpr int PME_KMAX = 256;   // largest grid edge
 constexpr int PME_PMAX = 8;     // largest B-spline order
+constexpr int PME_BR = 8;       // grid brick edge of the charge spread (>= PME_PMAX)
 struct PmeWalker {
   int32_t K[3];           // grid points per edge (powers of two, 16 .. PME_KMAX)
   int32_t lg[3];          // log2 K
   int32_t nl[3];          // FFT lines per block along each axis
   int32_t blk[3];         // FFT blocks along each axis
   int32_t blk_begin[3];   // first FFT block of the walker along each axis
+  int32_t nbr[3];         // grid bricks per edge (K / PME_BR)
+  int32_t br_begin;       // first brick of the walker
+  int32_t br_cap;         // atom capacity of one brick's list
   int32_t pad;
+  int64_t loff;           // first brick-list entry of the walker
   int64_t goff;           // first grid point
   int64_t toff;           // first entry of the per-axis tables (K0 + K1 + K2 entries)
   double pref;            // coulomb_k / (pi V)
@@ -167,7 +172,10 @@ struct Dev {
   const PmeWalker *pme;         // [W]
   const int32_t *pme_bw[3];     // walker of every FFT block along each axis
   double2 *pme_grid;            // [sum K0 K1 K2] complex grid
-  unsigned long long *pme_acc;  // [sum K0 K1 K2][2] fixed-point charge spread (E, S)
+  const int32_t *pme_brw;       // [bricks] walker of every grid brick
+  int32_t *pme_bcnt;            // [bricks] atoms whose base grid point lies in the brick
+  int32_t *pme_blist;           // [bricks][br_cap] their slots
+  int64_t pme_nbr;              // bricks in all
   const double *pme_tab;        // [sum (K0+K1+K2)][2] exp(-pi^2 m~^2 / beta^2) |b(m)|^2, m~^2
   double *pme_frc;              // [3][S] reciprocal force per slot
   double *pme_phi;              // [2][S] reciprocal potential: own group, other group
@@ -187,6 +195,7 @@ struct Range {
   int64_t k0, kn;      // per-column entries
   int32_t w0, wn;      // walkers
   int32_t pb0[3], pbn[3];  // PME FFT blocks along each axis
+  int32_t bb0, bbn;        // PME grid bricks
 };
 
 // Host-side launchers (defined in labf_kernels.hip).

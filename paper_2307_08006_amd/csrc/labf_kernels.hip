@@ -730,13 +730,30 @@ struct Ring {
   }
 };
 // Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut): F/r and, with
-// ENERGY, the energy.  Storage precision.
+// ENERGY, the energy.  FP64: the library erfc.  FP32: erfc(x) =
+// t P(t) exp(-x^2), t = 1 / (1 + p x), with the five-term polynomial of
+// Abramowitz and Stegun 7.1.26 (Hastings), absolute error <= 1.5e-7, so that
+// exp(-x^2) is shared with the force term.
 template <typename T>
 __device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
   const T br = d.ewb * (r2 * rinv);
   const T ec = qq * erfc(br) * rinv;
   ue = ec;
   return (ec + qq * d.ewc * exp(-br * br)) * r2inv;
+}
+
+template <>
+__device__ __forceinline__ float ewald_fr<float>(const Dev<float> &d, float qq, float r2, float rinv,
+                                                 float r2inv, float &ue) {
+  const float x = d.ewb * (r2 * rinv);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+               0.254829592f);
+  const float e = __expf(-x * x);
+  const float ec = qq * rinv * (poly * e);
+  ue = ec;
+  return fmaf(qq * d.ewc, e, ec) * r2inv;
 }
 
 template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
@@ -1801,40 +1818,119 @@ __device__ __forceinline__ int pme_axis(double x, double L, int K, double &f) {
   return (int)k0;
 }
 
-// One thread per slot: B-spline spread of the slot's charge into its group's
-// half of the fixed-point accumulator.
+// Charge spread, step 1 (one thread per slot): every charged atom joins the
+// list of the grid brick that holds its base grid point k0.
+// The lanes of a wave (slot order: a few neighbouring bricks) add to each
+// brick counter once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pme_bin(Dev<T> d, Range r, int xb) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t key = -1;
+  int w = 0, b = 0;
+  if (s < (r.c0 + r.cn) * CL && d.orig[s] >= 0 && d.q64[s] != 0.0) {
+    w = d.cl_walker[s / CL];
+    const WalkerMeta &m = d.meta[w];
+    const PmeWalker &pw = d.pme[w];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double f;
+      const int k0 = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
+      b = b * pw.nbr[a] + k0 / PME_BR;
+    }
+    key = pw.br_begin + b;
+  }
+  const int pos = wave_agg_add(d.pme_bcnt, key);
+  if (key < 0) return;
+  const PmeWalker &pw = d.pme[w];
+  if (pos < pw.br_cap) d.pme_blist[pw.loff + (int64_t)b * pw.br_cap + pos] = (int32_t)s;
+  else atomicOr(&d.status[w], 8u);
+}
+
+// Charge spread, step 2 (one block per brick of PME_BR^3 grid points): an
+// atom with base point k0 reaches k0 - j, j < P <= PME_BR, so the brick
+// receives charge only from atoms listed in itself and in the next brick
+// along each axis.  Their B-spline contributions are summed in LDS as
+// 2^-40 fixed-point integers (exact and order-independent) and the brick is
+// written to the grid once, with no global atomics.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
-  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s >= (r.c0 + r.cn) * CL || d.orig[s] < 0) return;
-  const double q = d.q64[s];
-  if (q == 0.0) return;
-  const int w = d.cl_walker[s / CL];
+  constexpr int NP = PME_BR * PME_BR * PME_BR;
+  __shared__ unsigned long long acc[2][NP];
+  const int bi = r.bb0 + (int)blockIdx.x;
+  const int w = d.pme_brw[bi];
   const WalkerMeta &m = d.meta[w];
   const PmeWalker &pw = d.pme[w];
-  double wt[3][P], dw[3][P];
-  int k0[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double f;
-    k0[a] = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
-    bspline_w<P>(f, wt[a], dw[a]);
+  const int nbx = pw.nbr[0], nby = pw.nbr[1], nbz = pw.nbr[2];
+  const int lb = bi - pw.br_begin;
+  const int bz = lb % nbz, by = (lb / nbz) % nby, bx = lb / (nbz * nby);
+  for (int i = threadIdx.x; i < NP; i += 256) {
+    acc[0][i] = 0ull;
+    acc[1][i] = 0ull;
   }
-  unsigned long long *acc = d.pme_acc + 2 * pw.goff + (d.sol[s] ? 1 : 0);
+  __syncthreads();
   const int m0 = pw.K[0] - 1, m1 = pw.K[1] - 1, m2 = pw.K[2] - 1;
+  const int ox = bx * PME_BR, oy = by * PME_BR, oz = bz * PME_BR;
+  // the eight source lists as one index range
+  __shared__ int sbase[9], sidx[8];
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int sb = 0; sb < 8; ++sb) {
+      const int sx = (bx + (sb >> 2)) % nbx, sy = (by + ((sb >> 1) & 1)) % nby, sz = (bz + (sb & 1)) % nbz;
+      const int sbi = (sx * nby + sy) * nbz + sz;
+      const int n = d.pme_bcnt[pw.br_begin + sbi];
+      sidx[sb] = sbi;
+      sbase[sb] = tot;
+      tot += n < pw.br_cap ? n : pw.br_cap;
+    }
+    sbase[8] = tot;
+  }
+  __syncthreads();
+  const int ntot = sbase[8];
+  {
+    for (int t = threadIdx.x; t < ntot; t += 256) {
+      int sb = 0;
+      while (t >= sbase[sb + 1]) ++sb;
+      const int64_t s = d.pme_blist[pw.loff + (int64_t)sidx[sb] * pw.br_cap + (t - sbase[sb])];
+      double f[3];
+      int k0[3];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int64_t ix = (int64_t)((k0[0] - i) & m0) * pw.K[1];
+      for (int a = 0; a < 3; ++a) k0[a] = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f[a]);
+      // the footprint k0 - P + 1 .. k0 misses this brick unless the base point
+      // is at most P - 2 points past its upper edge on every axis
+      if (((k0[0] - ox) & m0) > PME_BR + P - 2 || ((k0[1] - oy) & m1) > PME_BR + P - 2 ||
+          ((k0[2] - oz) & m2) > PME_BR + P - 2)
+        continue;
+      double wt[3][P], dw[3][P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int64_t ixy = (ix + ((k0[1] - j) & m1)) * pw.K[2];
-      const double qw = q * wt[0][i] * wt[1][j];
+      for (int a = 0; a < 3; ++a) bspline_w<P>(f[a], wt[a], dw[a]);
+      const double q = d.q64[s];
+      unsigned long long *ah = acc[d.sol[s] ? 1 : 0];
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        const long long v = __double2ll_rn(qw * wt[2][k] * 0x1p40);
-        atomicAdd(acc + 2 * (ixy + ((k0[2] - k) & m2)), (unsigned long long)v);
+      for (int i = 0; i < P; ++i) {
+        const int lx = ((k0[0] - i) - ox) & m0;
+        if (lx >= PME_BR) continue;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int ly = ((k0[1] - j) - oy) & m1;
+          if (ly >= PME_BR) continue;
+          const double qw = q * wt[0][i] * wt[1][j];
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const int lz = ((k0[2] - k) - oz) & m2;
+            if (lz >= PME_BR) continue;
+            const long long v = __double2ll_rn(qw * wt[2][k] * 0x1p40);
+            atomicAdd(ah + (lx * PME_BR + ly) * PME_BR + lz, (unsigned long long)v);
+          }
+        }
       }
     }
+  }
+  __syncthreads();
+  const int64_t K1 = pw.K[1], K2 = pw.K[2];
+  for (int i = threadIdx.x; i < NP; i += 256) {
+    const int lx = i / (PME_BR * PME_BR), ly = (i / PME_BR) % PME_BR, lz = i % PME_BR;
+    const int64_t g = pw.goff + ((int64_t)(ox + lx) * K1 + (oy + ly)) * K2 + (oz + lz);
+    d.pme_grid[g] = make_double2((double)(long long)acc[0][i] * 0x1p-40, (double)(long long)acc[1][i] * 0x1p-40);
   }
 }
 
@@ -1843,9 +1939,8 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // One block transforms NL grid lines of length K along axis AX in LDS.
-// MODE 0: forward, reading (and clearing) the fixed-point accumulator;
-// 1: forward; 2: forward, times the influence function, inverse (x lines);
-// 3: inverse.  The forward transform is decimation in frequency (natural in,
+// MODE 1: forward; 2: forward, times the influence function, inverse
+// (x lines); 3: inverse.  The forward transform is decimation in frequency (natural in,
 // bit-reversed out), the inverse decimation in time (bit-reversed in, natural
 // out), so the grid holds bit-reversed frequency indices between the passes
 // and no permutation is ever done.  Lines along z are contiguous; lines
@@ -1853,8 +1948,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // load and store is a run of NL contiguous points.
 template <int AX, int MODE>
 __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
-                                                 double2 *grid, unsigned long long *acc,
-                                                 const double *tab, int b0) {
+                                                 double2 *grid, const double *tab, int b0) {
   __shared__ double2 buf[PME_TILE];
   __shared__ double2 tw[PME_KMAX / 2];
   const int bid = b0 + (int)blockIdx.x;
@@ -1893,16 +1987,7 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
       pos = i >> lgnl;
       gi = base + t + pos * sp;
     }
-    double2 v;
-    if (MODE == 0) {
-      unsigned long long *a = acc + 2 * gi;
-      v = make_double2((double)(long long)a[0] * 0x1p-40, (double)(long long)a[1] * 0x1p-40);
-      a[0] = 0ull;
-      a[1] = 0ull;
-    } else {
-      v = grid[gi];
-    }
-    buf[(t << lg) + pos] = v;
+    buf[(t << lg) + pos] = grid[gi];
   }
   __syncthreads();
   const int nb = n >> 1, hl = lg - 1;
@@ -2285,13 +2370,15 @@ hipError_t launch_philox(int64_t n, const uint32_t *ctr, uint32_t k0, uint32_t k
 template <typename T, int P>
 static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
   const unsigned ns = nblk(r.cn * CL, 256);
-  k_pme_spread<T, P><<<ns, 256, 0, s>>>(d, r, xb);
-  double *tab = const_cast<double *>(d.pme_tab);
-  if (r.pbn[2] > 0) k_pme_fft<2, 0><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, d.pme_acc, tab, r.pb0[2]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, d.pme_acc, tab, r.pb0[1]);
-  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 256, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, d.pme_acc, tab, r.pb0[0]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, d.pme_acc, tab, r.pb0[1]);
-  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, d.pme_acc, tab, r.pb0[2]);
+  k_fill_i32<<<nblk(r.bbn, 256), 256, 0, s>>>(d.pme_bcnt + r.bb0, r.bbn, 0);
+  k_pme_bin<T><<<ns, 256, 0, s>>>(d, r, xb);
+  k_pme_spread<T, P><<<(unsigned)r.bbn, 256, 0, s>>>(d, r, xb);
+  const double *tab = d.pme_tab;
+  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 256, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
   k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
 }
 
