@@ -82,6 +82,7 @@ struct labf_system {
   std::vector<PmeWalker> pme;    // host copy (FFT block ranges of the launches)
   int32_t pme_nblk[3] = {0, 0, 0};
   int32_t pme_bricks = 0;
+  int32_t pme_planes = 0;
   std::vector<int32_t> n_acl_host;
   hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -175,6 +176,8 @@ Range full_range(const labf_system *s) {
   }
   r.bb0 = 0;
   r.bbn = s->pme_bricks;
+  r.pl0 = 0;
+  r.pln = s->pme_planes;
   return r;
 }
 
@@ -199,6 +202,8 @@ Range walker_range(const labf_system *s, int w) {
   }
   r.bb0 = s->pme.empty() ? 0 : s->pme[w].br_begin;
   r.bbn = s->pme.empty() ? 0 : s->pme[w].nbr[0] * s->pme[w].nbr[1] * s->pme[w].nbr[2];
+  r.pl0 = s->pme.empty() ? 0 : s->pme[w].pl_begin;
+  r.pln = s->pme.empty() || s->pme_planes == 0 ? 0 : s->pme[w].K[0];
   return r;
 }
 
@@ -583,8 +588,8 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   if (d.pme_on) {
     s->pme.resize(W);
     int64_t goff = 0, toff = 0, loff = 0;
-    int32_t nbr = 0;
-    std::vector<int32_t> bw[3], brw;
+    int32_t nbr = 0, npl = 0, maxyz = 0;
+    std::vector<int32_t> bw[3], brw, plw;
     for (int w = 0; w < W; ++w) {
       PmeWalker &p = s->pme[w];
       std::memset(&p, 0, sizeof(p));
@@ -613,6 +618,10 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       p.br_cap = (int32_t)(((3 * (int64_t)s->meta[w].n_atoms) / nb + 64 + 31) / 32 * 32);
       p.loff = loff;
       loff += (int64_t)nb * p.br_cap;
+      p.pl_begin = npl;
+      npl += p.K[0];
+      plw.insert(plw.end(), (size_t)p.K[0], w);
+      maxyz = std::max(maxyz, p.K[1] * p.K[2]);
       p.goff = goff;
       goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
       p.toff = toff;
@@ -628,6 +637,15 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     HIPCHK(s, dalloc(b, &d.pme_blist, loff));
     d.pme_nbr = nbr;
     s->pme_bricks = nbr;
+    // y and z transforms fused per y-z plane when every plane fits in LDS
+    d.pme_npl = maxyz <= 4096 ? 4096 : (maxyz <= PME_PLANE ? PME_PLANE : 0);
+    if (d.pme_npl) {
+      HIPCHK(s, upload(b, &d.pme_plw, plw.data(), plw.size()));
+      s->pme_planes = npl;
+    } else {
+      d.pme_plw = nullptr;
+      s->pme_planes = 0;
+    }
     double *tab = nullptr;
     HIPCHK(s, dalloc(b, &tab, 2 * toff));
     d.pme_tab = tab;

@@ -54,10 +54,11 @@ struct WalkerMeta {
 // Smooth PME of one walker.  The complex grid holds the environment's charge
 // density in the real part and the alchemical group's in the imaginary part,
 // so that one complex transform serves both; z is the fastest index.
-constexpr int PME_TILE = 2048;  // complex points per FFT block
+constexpr int PME_TILE = 4096;  // complex points per FFT block (1024 threads)
 constexpr int PME_KMAX = 256;   // largest grid edge
 constexpr int PME_PMAX = 8;     // largest B-spline order
 constexpr int PME_BR = 8;       // grid brick edge of the charge spread (>= PME_PMAX)
+constexpr int PME_PLANE = 8192; // largest K1 K2 transformed as one y-z plane in LDS
 struct PmeWalker {
   int32_t K[3];           // grid points per edge (powers of two, 16 .. PME_KMAX)
   int32_t lg[3];          // log2 K
@@ -67,7 +68,7 @@ struct PmeWalker {
   int32_t nbr[3];         // grid bricks per edge (K / PME_BR)
   int32_t br_begin;       // first brick of the walker
   int32_t br_cap;         // atom capacity of one brick's list
-  int32_t pad;
+  int32_t pl_begin;       // first y-z plane block of the walker (K0 planes)
   int64_t loff;           // first brick-list entry of the walker
   int64_t goff;           // first grid point
   int64_t toff;           // first entry of the per-axis tables (K0 + K1 + K2 entries)
@@ -173,6 +174,8 @@ struct Dev {
   const int32_t *pme_bw[3];     // walker of every FFT block along each axis
   double2 *pme_grid;            // [sum K0 K1 K2] complex grid
   const int32_t *pme_brw;       // [bricks] walker of every grid brick
+  const int32_t *pme_plw;       // [planes] walker of every y-z plane (NULL: per-axis passes)
+  int32_t pme_npl;              // LDS plane capacity of the y-z transform (4096 or 8192)
   int32_t *pme_bcnt;            // [bricks] atoms whose base grid point lies in the brick
   int32_t *pme_blist;           // [bricks][br_cap] their slots
   int64_t pme_nbr;              // bricks in all
@@ -196,6 +199,7 @@ struct Range {
   int32_t w0, wn;      // walkers
   int32_t pb0[3], pbn[3];  // PME FFT blocks along each axis
   int32_t bb0, bbn;        // PME grid bricks
+  int32_t pl0, pln;        // PME y-z planes
 };
 
 // Host-side launchers (defined in labf_kernels.hip).

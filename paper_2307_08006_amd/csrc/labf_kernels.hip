@@ -1947,7 +1947,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // along y and x are taken NL at a time from consecutive z so that every
 // load and store is a run of NL contiguous points.
 template <int AX, int MODE>
-__global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
+__global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
                                                  double2 *grid, const double *tab, int b0) {
   __shared__ double2 buf[PME_TILE];
   __shared__ double2 tw[PME_KMAX / 2];
@@ -1969,13 +1969,13 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
     sp = AX == 1 ? K2 : K1 * K2;
   }
   base += pw.goff;
-  for (int k = threadIdx.x; k < (K >> 1); k += 256) {
+  for (int k = threadIdx.x; k < (K >> 1); k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K, &sn, &cs);
     tw[k] = make_double2(cs, sn);
   }
   const int n = NL << lg;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int t, pos;
     int64_t gi;
     if (AX == 2) {
@@ -1994,7 +1994,7 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
   if (MODE <= 2) {
     for (int l = lg; l >= 1; --l) {  // span 2^l
       const int half = 1 << (l - 1), ts = 1 << (lg - l);
-      for (int b = threadIdx.x; b < nb; b += 256) {
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         const int t = b >> hl, j = b & ((1 << hl) - 1);
         const int k = j & (half - 1);
         const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
@@ -2013,7 +2013,7 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
     const int lg1 = pw.lg[1], lg2 = pw.lg[2];
     const double *tx = tab + 2 * pw.toff, *ty = tx + 2 * pw.K[0], *tz = ty + 2 * pw.K[1];
     const int fy = (int)(__brev((unsigned)iy) >> (32 - lg1));
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const int t = i >> lg, pos = i & (K - 1);
       const int fx = (int)(__brev((unsigned)pos) >> (32 - lg));
       const int fz = (int)(__brev((unsigned)(iz0 + t)) >> (32 - lg2));
@@ -2027,7 +2027,7 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
   if (MODE >= 2) {
     for (int l = 1; l <= lg; ++l) {
       const int half = 1 << (l - 1), ts = 1 << (lg - l);
-      for (int b = threadIdx.x; b < nb; b += 256) {
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         const int t = b >> hl, j = b & ((1 << hl) - 1);
         const int k = j & (half - 1);
         const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
@@ -2039,7 +2039,7 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int t, pos;
     int64_t gi;
     if (AX == 2) {
@@ -2053,6 +2053,75 @@ __global__ __launch_bounds__(256) void k_pme_fft(const PmeWalker *pme, const int
     }
     grid[gi] = buf[(t << lg) + pos];
   }
+}
+
+// Radix-2 transforms of nl lines of length 2^lg held in LDS, element p of
+// line t at buf[t * ls + p * es]; forward: decimation in frequency with
+// twiddles tw[k] = exp(-2 pi i k / 2^lg); inverse: decimation in time with
+// their conjugates.  Ends with a barrier.
+// Consecutive threads take consecutive butterflies of a line when its
+// elements are contiguous (es == 1) and consecutive lines otherwise (then
+// ls == 1), so that a wave's LDS accesses are contiguous either way.
+template <bool FWD>
+__device__ __forceinline__ void lds_fft(double2 *buf, const double2 *tw, int lg, int nl, int ls, int es) {
+  const int hl = lg - 1, nb = nl << hl;
+  for (int st = 0; st < lg; ++st) {
+    const int l = FWD ? lg - st : st + 1;  // span 2^l
+    const int half = 1 << (l - 1), ts = 1 << (lg - l);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int t = es == 1 ? b >> hl : b % nl, j = es == 1 ? b & ((1 << hl) - 1) : b / nl;
+      const int k = j & (half - 1);
+      const int p0 = ((j >> (l - 1)) << l) + k;
+      double2 *u0 = buf + t * ls + p0 * es, *u1 = u0 + half * es;
+      const double2 u = *u0, w = tw[k * ts];
+      if (FWD) {
+        const double2 v = *u1;
+        *u0 = make_double2(u.x + v.x, u.y + v.y);
+        *u1 = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+      } else {
+        const double2 v = cmul(*u1, make_double2(w.x, -w.y));
+        *u0 = make_double2(u.x + v.x, u.y + v.y);
+        *u1 = make_double2(u.x - v.x, u.y - v.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One block per y-z plane (fixed x) of K1 K2 <= NPL points: both transforms
+// of the plane in LDS, forward (z then y) or inverse (y then z).
+template <bool FWD, int NPL>
+__global__ __launch_bounds__(1024) void k_pme_fft_yz(const PmeWalker *pme, const int32_t *plw,
+                                                    double2 *grid, int p0) {
+  __shared__ double2 buf[NPL];
+  __shared__ double2 twb[PME_KMAX];
+  const int pid = p0 + (int)blockIdx.x;
+  const PmeWalker &pw = pme[plw[pid]];
+  const int ix = pid - pw.pl_begin;
+  const int K1 = pw.K[1], K2 = pw.K[2], lg1 = pw.lg[1], lg2 = pw.lg[2];
+  const int n = K1 * K2;
+  double2 *ty = twb, *tz = twb + (K1 >> 1);
+  for (int k = threadIdx.x; k < (K1 >> 1); k += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * (double)k / (double)K1, &sn, &cs);
+    ty[k] = make_double2(cs, sn);
+  }
+  for (int k = threadIdx.x; k < (K2 >> 1); k += blockDim.x) {
+    double sn, cs;
+    sincospi(-2.0 * (double)k / (double)K2, &sn, &cs);
+    tz[k] = make_double2(cs, sn);
+  }
+  double2 *g = grid + pw.goff + (int64_t)ix * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = g[i];
+  __syncthreads();
+  if (FWD) {
+    lds_fft<true>(buf, tz, lg2, K1, K2, 1);   // z lines: K1 lines, contiguous
+    lds_fft<true>(buf, ty, lg1, K2, 1, K2);   // y lines: K2 lines, stride K2
+  } else {
+    lds_fft<false>(buf, ty, lg1, K2, 1, K2);
+    lds_fft<false>(buf, tz, lg2, K1, K2, 1);
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = buf[i];
 }
 
 // One thread per slot: potentials of both groups and their gradients at the
@@ -2374,11 +2443,24 @@ static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hi
   k_pme_bin<T><<<ns, 256, 0, s>>>(d, r, xb);
   k_pme_spread<T, P><<<(unsigned)r.bbn, 256, 0, s>>>(d, r, xb);
   const double *tab = d.pme_tab;
-  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 256, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 256, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 256, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+  if (d.pme_plw) {
+    // y-z planes in LDS
+    if (d.pme_npl == 4096)
+      k_pme_fft_yz<true, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
+    else
+      k_pme_fft_yz<true, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
+    if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+    if (d.pme_npl == 4096)
+      k_pme_fft_yz<false, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
+    else
+      k_pme_fft_yz<false, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
+  } else {
+    if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+    if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+    if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+    if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+    if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+  }
   k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
 }
 

@@ -79,6 +79,13 @@ def _uneven_pme(precision):
     return synth.with_pme(spec, dims=[[32, 32, 32], [16, 32, 64], [64, 16, 16]], order=6), lam
 
 
+def _pme_axes(precision):
+    """A 16 x 128 x 128 grid: y-z planes too large for one LDS block, so the
+    transforms run axis by axis."""
+    spec, lam = _pme(precision)
+    return synth.with_pme(spec, dims=(16, 128, 128), order=4), lam
+
+
 SYSTEMS = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp32": lambda: _small_charged("fp32"),
@@ -91,6 +98,7 @@ SYSTEMS = {
     "charged3k_fp32_pme": lambda: _pme("fp32"),
     "charged3k_fp64_pme": lambda: _pme("fp64"),
     "uneven3_fp32_pme": lambda: _uneven_pme("fp32"),
+    "charged3k_fp64_pme_axes": lambda: _pme_axes("fp64"),
 }
 
 
