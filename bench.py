@@ -284,6 +284,8 @@ def main(argv=None):
     ap.add_argument("--variant-steps", type=int, default=200,
                     help="timed steps of the separation-shifted soft-core variant (0: skip)")
     ap.add_argument("--variant-equil-steps", type=int, default=200)
+    ap.add_argument("--pme-only", action="store_true",
+                    help="run only the smooth-PME section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -316,6 +318,9 @@ def main(argv=None):
     specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
     log(f"equilibrating the batch at its initial lambdas for {args.batch_equil_steps} steps")
     specb, lamb = equilibrate(specb, lamb, args.batch_equil_steps, lambda_dynamics=True)
+    if args.pme_only:
+        print(json.dumps({"pme": run_pme(args, specb, lamb)}), flush=True)
+        return 0
 
     out = {}
     with labf.System(specb, lamb) as s:

@@ -206,7 +206,11 @@ labf_status labf_write_atoms(labf_system *sys, const double *pos, const double *
 /* Evaluate, at the current positions and lambda, the forces [N][3], the
  * energy decomposition energy[W][5] = {environment-environment,
  * solute-solute, alchemical LJ, alchemical Coulomb, restraints} and
- * dV/dlambda [W] (synchronous; nullable outputs).  Rebuilds the list. */
+ * dV/dlambda [W] (synchronous; nullable outputs).  Rebuilds the list.
+ * With PME the reciprocal, self and background energies of the environment's
+ * own charges go to the first entry, those of the group's own charges to the
+ * second, and the cross part (ce times the reciprocal cross term and the
+ * background cross term) to the alchemical Coulomb entry. */
 labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy, double *dudl,
                                 void *stream);
 
