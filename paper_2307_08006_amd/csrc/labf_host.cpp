@@ -652,7 +652,11 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     HIPCHK(s, dalloc(b, &d.pme_frc, 3 * s->S));
     HIPCHK(s, dalloc(b, &d.pme_phi, 2 * s->S));
     HIPCHK(s, dalloc(b, &d.pme_qs, 4 * W));
-    HIPCHK(s, Launch<T>::pme_tables(d, st));
+    float4 *ewtab = nullptr;
+    HIPCHK(s, dalloc(b, &ewtab, 2 * EWTAB_N));
+    d.ewtab = ewtab;
+    d.ewtab_inv = (float)(EWTAB_N / (desc->r_cut * desc->r_cut));
+    HIPCHK(s, Launch<T>::pme_tables(d, ewtab, st));
     HIPCHK(s, Launch<T>::pme_charges(d, st));
   }
   d.a_pos0 = nullptr;

@@ -59,6 +59,7 @@ constexpr int PME_KMAX = 256;   // largest grid edge
 constexpr int PME_PMAX = 8;     // largest B-spline order
 constexpr int PME_BR = 8;       // grid brick edge of the charge spread (>= PME_PMAX)
 constexpr int PME_PLANE = 8192; // largest K1 K2 transformed as one y-z plane in LDS
+constexpr int EWTAB_N = 256;    // intervals of the FP32 real-space Ewald correction table
 struct PmeWalker {
   int32_t K[3];           // grid points per edge (powers of two, 16 .. PME_KMAX)
   int32_t lg[3];          // log2 K
@@ -170,6 +171,8 @@ struct Dev {
   int32_t pme_on, pme_order;
   double ewald_beta;
   T ewb, ewc;                   // beta, 2 beta / sqrt(pi) (storage precision)
+  const float4 *ewtab;          // [2][EWTAB_N] cubic pieces of the real-space correction in r^2
+  float ewtab_inv;              // EWTAB_N / r_cut^2
   const PmeWalker *pme;         // [W]
   const int32_t *pme_bw[3];     // walker of every FFT block along each axis
   double2 *pme_grid;            // [sum K0 K1 K2] complex grid
@@ -230,8 +233,8 @@ struct Launch {
   static hipError_t pme(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s);
   // per-walker charge sums of the two groups (after a charge change)
   static hipError_t pme_charges(const Dev<T> &d, hipStream_t s);
-  // influence-function tables (once, at creation)
-  static hipError_t pme_tables(const Dev<T> &d, hipStream_t s);
+  // influence-function and real-space correction tables (once, at creation)
+  static hipError_t pme_tables(const Dev<T> &d, float4 *ewtab, hipStream_t s);
   // total potential energy per walker after eval()
   static hipError_t energy_total(const Dev<T> &d, double *out, hipStream_t s);
   // upstream gradient g[W] times the derivatives of the last eval()

@@ -729,11 +729,14 @@ struct Ring {
     bj = LB ? b[k] : (T)0;
   }
 };
-// Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut): F/r and, with
-// ENERGY, the energy.  FP64: the library erfc.  FP32: erfc(x) =
-// t P(t) exp(-x^2), t = 1 / (1 + p x), with the five-term polynomial of
-// Abramowitz and Stegun 7.1.26 (Hastings), absolute error <= 1.5e-7, so that
-// exp(-x^2) is shared with the force term.
+// Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut): F/r and the
+// energy (unused outside the energy kernels).  FP64: the library erfc.
+// FP32: with erfc = 1 - erf, F/r = qq (1/r^3 - gF(r^2)) and
+// U = qq (1/r - gE(r^2)), where gE = erf(beta r)/r and
+// gF = erf(beta r)/r^3 - (2 beta/sqrt(pi)) exp(-beta^2 r^2)/r^2 are smooth,
+// even functions of r; they are read from cubic Hermite pieces on EWTAB_N
+// equal intervals of r^2 in [0, r_cut^2] (built in FP64, error < 2e-9 of
+// the bare Coulomb term), so a pair costs a table read and three FMAs.
 template <typename T>
 __device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
   const T br = d.ewb * (r2 * rinv);
@@ -745,15 +748,52 @@ __device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2i
 template <>
 __device__ __forceinline__ float ewald_fr<float>(const Dev<float> &d, float qq, float r2, float rinv,
                                                  float r2inv, float &ue) {
-  const float x = d.ewb * (r2 * rinv);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  const float poly =
-      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
-               0.254829592f);
-  const float e = __expf(-x * x);
-  const float ec = qq * rinv * (poly * e);
-  ue = ec;
-  return fmaf(qq * d.ewc, e, ec) * r2inv;
+  // the largest float below EWTAB_N: pairs just inside r_cut keep their
+  // offset in the last interval; lanes beyond r_cut (masked) stay in range
+  const float u = fminf(r2 * d.ewtab_inv, (float)EWTAB_N * 0.99999994f);
+  const int k = (int)u;
+  const float f = u - (float)k;
+  const float4 cf = d.ewtab[k], ce = d.ewtab[EWTAB_N + k];
+  const float gf = fmaf(f, fmaf(f, fmaf(f, cf.w, cf.z), cf.y), cf.x);
+  const float ge = fmaf(f, fmaf(f, fmaf(f, ce.w, ce.z), ce.y), ce.x);
+  ue = qq * (rinv - ge);
+  return qq * (r2inv * rinv - gf);
+}
+
+// gF, gE and dgF/ds at s = r^2 in FP64 (dgE/ds = -gF/2); a series in
+// x^2 = beta^2 s below x = 0.1, where the closed forms cancel.
+__device__ inline void ewald_g(double s, double beta, double &gf, double &ge, double &dgf) {
+  const double tsp = 1.1283791670955126;  // 2 / sqrt(pi)
+  const double x2 = beta * beta * s;
+  if (x2 < 0.01) {
+    const double b3 = beta * beta * beta;
+    gf = b3 * tsp * (2.0 / 3.0 + x2 * (-2.0 / 5.0 + x2 * (1.0 / 7.0 + x2 * (-1.0 / 27.0 + x2 / 132.0))));
+    ge = beta * tsp * (1.0 + x2 * (-1.0 / 3.0 + x2 * (1.0 / 10.0 + x2 * (-1.0 / 42.0 + x2 / 216.0))));
+    dgf = b3 * beta * beta * tsp * (-2.0 / 5.0 + x2 * (2.0 / 7.0 + x2 * (-3.0 / 27.0 + x2 * 4.0 / 132.0)));
+  } else {
+    const double r = sqrt(s), x = beta * r, e = exp(-x2), ef = erf(x);
+    gf = ef / (s * r) - beta * tsp * e / s;
+    ge = ef / r;
+    dgf = beta * tsp * e * (1.5 / (s * s) + beta * beta / s) - 1.5 * ef / (s * s * r);
+  }
+}
+
+// One thread per interval: cubic Hermite pieces a0 + f (a1 + f (a2 + f a3)),
+// f in [0, 1), from the values and slopes at both ends.
+__global__ void k_ewald_table(double beta, double smax, float4 *tab) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= EWTAB_N) return;
+  const double ds = smax / EWTAB_N;
+  double f0, e0, df0, f1, e1, df1;
+  ewald_g(k * ds, beta, f0, e0, df0);
+  ewald_g((k + 1) * ds, beta, f1, e1, df1);
+  const double g0[2] = {f0, e0}, g1[2] = {f1, e1};
+  const double d0[2] = {df0 * ds, -0.5 * f0 * ds}, d1[2] = {df1 * ds, -0.5 * f1 * ds};
+  for (int q = 0; q < 2; ++q) {
+    const double a2 = 3.0 * (g1[q] - g0[q]) - 2.0 * d0[q] - d1[q];
+    const double a3 = 2.0 * (g0[q] - g1[q]) + d0[q] + d1[q];
+    tab[q * EWTAB_N + k] = make_float4((float)g0[q], (float)d0[q], (float)a2, (float)a3);
+  }
 }
 
 template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
@@ -2481,8 +2521,9 @@ hipError_t Launch<T>::pme_charges(const Dev<T> &d, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t Launch<T>::pme_tables(const Dev<T> &d, hipStream_t s) {
+hipError_t Launch<T>::pme_tables(const Dev<T> &d, float4 *ewtab, hipStream_t s) {
   if (!d.pme_on) return hipSuccess;
+  k_ewald_table<<<1, EWTAB_N, 0, s>>>(d.ewald_beta, d.r_cut * d.r_cut, ewtab);
   double *tab = const_cast<double *>(d.pme_tab);
   if (d.pme_order == 4) k_pme_tables<T, 4><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, tab);
   else if (d.pme_order == 6) k_pme_tables<T, 6><<<(unsigned)d.n_walkers, 256, 0, s>>>(d, tab);

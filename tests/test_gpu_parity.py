@@ -213,6 +213,32 @@ def test_short_fp64_trajectory_matches_oracle(mode):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pme_pairs_up_to_the_cutoff_match_oracle(precision):
+    """Single charged pairs with Ewald electrostatics from 1 A out to just
+    inside r_cut (the last interval of the FP32 real-space table)."""
+    import dataclasses
+    base, lam = synth.charged_lj(n_atoms=3000, n_solute=0, precision=precision)
+    L = 32.0
+    for r in (1.0, 4.7, 9.3, 11.99, 11.9995):
+        pos = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+        pos, box = synth.quantize(pos, np.array([L, L, L]), precision)
+        spec = dataclasses.replace(base, atom_offset=np.array([0, 2]), box=box[None, :], pos=pos,
+                                   vel=np.zeros((2, 3)), mass=np.full(2, 20.0),
+                                   charge=np.array([0.4, -0.4]), sigma=np.full(2, 2.04),
+                                   epsilon=np.zeros(2), is_solute=np.zeros(2, np.uint8),
+                                   anchor=None, k0=None, k1=None)
+        spec = synth.with_pme(spec)
+        s = labf.System(spec, lam)
+        f, e, _ = s.compute_forces()
+        p, _ = s.read_atoms()
+        fo, uo, _ = oracle.Oracle(spec, lam).evaluate(0, p, 0.0)
+        s.close()
+        ftol = 1e-10 if precision == "fp64" else 1e-6
+        assert _rel(f, fo) <= ftol, (r, f, fo)
+        assert abs(e[0, 0] - uo[0]) <= ftol * abs(uo[0]), (r, e[0, 0], uo[0])
+
+
 @pytest.mark.parametrize("pme", [False, True])
 def test_batched_and_plain_are_bitwise_identical(pme):
     spec, lam = _uneven_pme("fp32") if pme else _uneven("fp32")
