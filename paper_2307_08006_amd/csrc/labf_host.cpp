@@ -85,7 +85,7 @@ struct labf_system {
   int32_t pme_planes = 0;
   std::vector<int32_t> n_acl_host;
   hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, pme_ev = nullptr;
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
   DevBufs bufs;
@@ -384,6 +384,7 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
       HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream2, hipStreamNonBlocking));
       HIPCHK(s, hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
       HIPCHK(s, hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+      HIPCHK(s, hipEventCreateWithFlags(&s->pme_ev, hipEventDisableTiming));
     }
     HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     int xb = s->xb, vb = s->vb, lb = s->lb;
@@ -393,12 +394,18 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
     // each step: the alchemical kernel (second stream) runs beside the
     // environment kernel; they read the same positions and write disjoint
     // slots, lambda and step counters are double-buffered
+    // with PME the reciprocal-space chain runs on the second stream beside
+    // the environment pair kernel, followed there by the alchemical kernel;
+    // the environment atoms are integrated once both forces are in
     for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
-      e = Launch<T>::pme(d, full_range(s), xb, lb, s->cap_stream);
-      if (e == hipSuccess) e = hipEventRecord(s->fork_ev, s->cap_stream);
+      e = hipEventRecord(s->fork_ev, s->cap_stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
+      if (e == hipSuccess && d.pme_on) e = Launch<T>::pme(d, full_range(s), xb, lb, s->cap_stream2);
+      if (e == hipSuccess && d.pme_on) e = hipEventRecord(s->pme_ev, s->cap_stream2);
       if (e == hipSuccess) e = Launch<T>::step_alch(d, full_range(s), xb, vb, lb, s->cap_stream2);
       if (e == hipSuccess) e = Launch<T>::step_env(d, full_range(s), xb, vb, lb, s->cap_stream);
+      if (e == hipSuccess && d.pme_on) e = hipStreamWaitEvent(s->cap_stream, s->pme_ev, 0);
+      if (e == hipSuccess && d.pme_on) e = Launch<T>::env_integrate(d, full_range(s), xb, vb, lb, s->cap_stream);
       if (e == hipSuccess) e = hipEventRecord(s->join_ev, s->cap_stream2);
       if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, s->join_ev, 0);
       xb ^= 1;
@@ -1066,6 +1073,7 @@ labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) 
     HIPCHK(s, Launch<T>::step_alch(d, full_range(s), s->xb, s->vb, s->lb, st));
     HIPCHK(s, hipEventRecord(ev[3 + 3 * i], st));
     HIPCHK(s, Launch<T>::step_env(d, full_range(s), s->xb, s->vb, s->lb, st));
+    HIPCHK(s, Launch<T>::env_integrate(d, full_range(s), s->xb, s->vb, s->lb, st));
     HIPCHK(s, hipEventRecord(ev[4 + 3 * i], st));
     s->xb ^= 1;
     s->lb ^= 1;
@@ -1413,6 +1421,7 @@ void labf_destroy_system(labf_system *sys) {
   if (sys->cap_stream2) (void)hipStreamDestroy(sys->cap_stream2);
   if (sys->fork_ev) (void)hipEventDestroy(sys->fork_ev);
   if (sys->join_ev) (void)hipEventDestroy(sys->join_ev);
+  if (sys->pme_ev) (void)hipEventDestroy(sys->pme_ev);
   sys->item_bufs.release();
   sys->bufs.release();
   delete sys;

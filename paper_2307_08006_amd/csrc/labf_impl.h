@@ -216,6 +216,10 @@ struct Launch {
                               hipStream_t s);
   static hipError_t step_env(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                              hipStream_t s);
+  // PME stepping: reciprocal force + BAOAB of the environment atoms after
+  // step_env (which then only writes forces) and pme()
+  static hipError_t env_integrate(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                                  hipStream_t s);
   static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, hipStream_t s);
   static hipError_t export_pairs(const Dev<T> &d, const Range &r, int xb, int mode,
                                  hipStream_t s);

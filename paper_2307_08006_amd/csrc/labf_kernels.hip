@@ -1153,9 +1153,10 @@ __global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, 
           for (int k = 0; k < 3; ++k) F[k] += d.dr_k * t.e * t.u[k];
       }
     }
-    if (EW && valid) {
-      // reciprocal-space force; energy: half the atom's own-group potential
-      // times its charge, minus the Ewald self term
+    if (EW && valid && (INTEG || ENERGY)) {
+      // reciprocal-space force (the plain force launch of the PME step
+      // leaves it to k_env_integrate); energy: half the atom's own-group
+      // potential times its charge, minus the Ewald self term
 #pragma unroll
       for (int k = 0; k < 3; ++k) F[k] += d.pme_frc[(int64_t)k * d.n_slots + s];
       if (ENERGY) {
@@ -2360,15 +2361,52 @@ static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, 
   }
 }
 
+// PME step, environment side: k_env writes the pair, restraint and
+// distance-restraint forces (so that it can run beside the reciprocal-space
+// chain); this kernel adds the reciprocal force and integrates, one thread
+// per slot of the environment clusters in use (the same arithmetic, in the
+// same order, as the fused epilogue of the other stepping launch).
+template <typename T>
+__global__ __launch_bounds__(256) void k_env_integrate(Dev<T> d, Range r, int xb, int vb, int lb) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= (r.c0 + r.cn) * CL) return;
+  const int64_t c = s / CL;
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  if (c - m.cl_begin >= d.n_env[w]) return;  // unused or alchemical cluster
+  const int64_t S = d.n_slots;
+  if (d.orig[s] >= 0) {
+    double F[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] = d.fout[k * S + s] + d.pme_frc[k * S + s];
+    const int64_t st = d.step[lb * d.n_walkers + w];
+    integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+  }
+}
+
 template <typename T>
 hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                            hipStream_t s) {
   if (d.pme_on) {
-    const hipError_t e = pme(d, r, xb, lb, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = pme(d, r, xb, lb, s);
+    if (e == hipSuccess) e = step_alch(d, r, xb, vb, lb, s);
+    if (e == hipSuccess) e = step_env(d, r, xb, vb, lb, s);
+    if (e == hipSuccess) e = env_integrate(d, r, xb, vb, lb, s);
+    return e;
   }
   if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   env_launch<T>(d, r, xb, vb, lb, false, true, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::env_integrate(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+                                    hipStream_t s) {
+  if (!d.pme_on || r.cn <= 0) return hipSuccess;
+  k_env_integrate<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r, xb, vb, lb);
   return hipGetLastError();
 }
 
@@ -2382,7 +2420,8 @@ hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb,
 template <typename T>
 hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                hipStream_t s) {
-  env_launch<T>(d, r, xb, vb, lb, false, true, s);
+  // with PME: forces only; env_integrate finishes the step
+  env_launch<T>(d, r, xb, vb, lb, false, !d.pme_on, s);
   return hipGetLastError();
 }
 
