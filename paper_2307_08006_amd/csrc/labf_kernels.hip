@@ -1927,20 +1927,38 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
   }
   __syncthreads();
   const int ntot = sbase[8];
-  {
-    for (int t = threadIdx.x; t < ntot; t += 256) {
+  // chunks of the listed atoms: first the atoms whose footprint k0 - P + 1 ..
+  // k0 reaches this brick (base point at most P - 2 points past its upper
+  // edge on every axis) are compacted into LDS, then every thread spreads
+  // whole atoms of that list, so that waves do not idle on atoms that miss
+  constexpr int CH = 1024;
+  __shared__ int32_t use[CH];
+  __shared__ int nuse;
+  for (int c0 = 0; c0 < ntot; c0 += CH) {
+    if (threadIdx.x == 0) nuse = 0;
+    __syncthreads();
+    for (int t = c0 + (int)threadIdx.x; t < ntot && t < c0 + CH; t += 256) {
       int sb = 0;
       while (t >= sbase[sb + 1]) ++sb;
-      const int64_t s = d.pme_blist[pw.loff + (int64_t)sidx[sb] * pw.br_cap + (t - sbase[sb])];
+      const int32_t s = d.pme_blist[pw.loff + (int64_t)sidx[sb] * pw.br_cap + (t - sbase[sb])];
+      double f;
+      bool hit = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int o = a == 0 ? ox : (a == 1 ? oy : oz);
+        const int k0 = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
+        hit = hit && ((k0 - o) & (pw.K[a] - 1)) <= PME_BR + P - 2;
+      }
+      if (hit) use[atomicAdd(&nuse, 1)] = s;
+    }
+    __syncthreads();
+    const int nu = nuse;
+    for (int u = threadIdx.x; u < nu; u += 256) {
+      const int64_t s = use[u];
       double f[3];
       int k0[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) k0[a] = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f[a]);
-      // the footprint k0 - P + 1 .. k0 misses this brick unless the base point
-      // is at most P - 2 points past its upper edge on every axis
-      if (((k0[0] - ox) & m0) > PME_BR + P - 2 || ((k0[1] - oy) & m1) > PME_BR + P - 2 ||
-          ((k0[2] - oz) & m2) > PME_BR + P - 2)
-        continue;
       double wt[3][P], dw[3][P];
 #pragma unroll
       for (int a = 0; a < 3; ++a) bspline_w<P>(f[a], wt[a], dw[a]);
@@ -1965,6 +1983,7 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
         }
       }
     }
+    __syncthreads();
   }
   __syncthreads();
   const int64_t K1 = pw.K[1], K2 = pw.K[2];
