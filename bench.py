@@ -42,19 +42,28 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_env_charged_lj_16x30k_pmc.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2307_08006_amd", "csrc", "labf_kernels.hip")
+# sources the environment pair kernel is compiled from (the PME kernels live apart)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2307_08006_amd", "csrc", f)
+                  for f in ("labf_kernels.hip", "labf_device.h", "labf_impl.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per batched k_env launch from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
     when the kernel source has changed since the counters were taken."""
-    import hashlib
     try:
         txt = open(PMC_SUMMARY).read()
         want = txt.split("kernel_source_sha256:")[1].split()[0]
         nbytes = int(txt.split("traffic_bytes_per_launch:")[1].split()[0])
-        have = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        have = kernel_source_hash()
     except (OSError, IndexError, ValueError):
         return None
     return nbytes if have == want else None
