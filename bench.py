@@ -39,6 +39,9 @@ METRIC = "walker-steps/s and pair-interactions/s at 30k atoms, batched vs plain,
 SLOTS_PER_PAIR = 31
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, non-packed FP32 VALU lane-operations/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# packed FP32 executes two lane-operations per slot: 78.6 T lane-ops/s, the
+# published 157.3 TFLOP/s with FMA = 2 flops (packed math is not used here)
+PACKED_VALU_PEAK_TOPS = 2 * VALU_PEAK_TOPS
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_env_charged_lj_16x30k_pmc.txt")
@@ -67,6 +70,19 @@ def measured_traffic():
     except (OSError, IndexError, ValueError):
         return None
     return nbytes if have == want else None
+
+
+def measured_valu_instructions():
+    """VALU wave-instructions per batched k_env launch from the same PMC
+    summary (SQ_INSTS_VALU), or None when the kernel source has changed."""
+    try:
+        txt = open(PMC_SUMMARY).read()
+        want = txt.split("kernel_source_sha256:")[1].split()[0]
+        import re
+        n = int(re.search(r"SQ_INSTS_VALU ([0-9,]+);", txt).group(1).replace(",", ""))
+    except (OSError, IndexError, ValueError, AttributeError):
+        return None
+    return n if kernel_source_hash() == want else None
 
 
 def log(msg):
@@ -247,6 +263,59 @@ def run_pme(args, specb, lamb):
             "walker_status": int(np.bitwise_or.reduce(st["status"]))}
 
 
+def run_backward(args, spec1, lam1):
+    """The differentiable energy on 8 walkers x the 30k-atom system: the
+    torch.autograd.Function forward (energies) and backward (forces,
+    dV/dlambda and dV/d(eps, sigma, q) of the solute atoms, pair terms
+    recomputed), timed with device synchronisation around each call."""
+    import torch
+    from paper_2307_08006_amd import labf, synth
+    from paper_2307_08006_amd.autograd import energy
+    spec, lam = synth.batch(spec1, lam1, 8, seed=synth.BASE_SEED + 4)
+    with labf.System(spec, lam) as s:
+        pos0, _ = s.read_atoms()
+        dev = torch.device("cuda")
+        pos = torch.tensor(pos0, device=dev, requires_grad=True)
+        lamt = torch.tensor(np.asarray(lam.lambda0), device=dev, dtype=torch.float64, requires_grad=True)
+        par = torch.tensor(s.solute_params(), device=dev, requires_grad=True)
+
+        def once():
+            e = energy(s, pos, lamt, par)
+            _sync()
+            t1 = time.perf_counter()
+            e.sum().backward()
+            _sync()
+            return t1
+
+        for _ in range(3):
+            once()
+        tf = tb = 0.0
+        for _ in range(args.backward_reps):
+            _sync()
+            t0 = time.perf_counter()
+            t1 = once()
+            t2 = time.perf_counter()
+            tf += t1 - t0
+            tb += t2 - t1
+    n = args.backward_reps
+    log(f"backward: {n} forward+backward evaluations of 8 x 30k in {tf + tb:.3f} s")
+    return {"walkers": 8, "atoms_per_walker": int(spec1.n_atoms), "reps": n,
+            "forward_ms": 1e3 * tf / n, "backward_ms": 1e3 * tb / n,
+            "walker_evaluations_per_s": 8 * n / (tf + tb),
+            "note": "forward includes the configuration upload and a list rebuild; backward "
+                    "recomputes the pair terms"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, lam, n_walkers, n_steps):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -293,6 +362,8 @@ def main(argv=None):
     ap.add_argument("--variant-steps", type=int, default=200,
                     help="timed steps of the separation-shifted soft-core variant (0: skip)")
     ap.add_argument("--variant-equil-steps", type=int, default=200)
+    ap.add_argument("--backward-reps", type=int, default=10,
+                    help="timed forward+backward evaluations of 8 walkers (0: skip)")
     ap.add_argument("--pme-only", action="store_true",
                     help="run only the smooth-PME section (for profiling) and print its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -361,6 +432,7 @@ def main(argv=None):
     W = args.walkers
     value = W * args.steps / dt_b
     env_ms = prof["env_ms"]
+    valu_instr = measured_valu_instructions()
     achieved = SLOTS_PER_PAIR * env_pairs_per_step / (env_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -408,6 +480,9 @@ def main(argv=None):
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "per_unit": f"{SLOTS_PER_PAIR} FP32 VALU lane-ops per in-cutoff environment pair",
             "units_per_launch": env_pairs_per_step,
+            "frac_of_packed_fp32_peak": achieved / PACKED_VALU_PEAK_TOPS,
+            "valu_lane_instructions_per_pair": None if valu_instr is None
+            else 64.0 * valu_instr / env_pairs_per_step,
         },
         "walker_status": {"batched": int(np.bitwise_or.reduce(st_b["status"])),
                           "plain": int(np.bitwise_or.reduce(st_p["status"])),
@@ -420,15 +495,21 @@ def main(argv=None):
         out["shifted_softcore"] = run_shifted(args, specb, lamb)
         out["distance_restraint"] = run_restrained(args, specb, lamb)
         out["pme"] = run_pme(args, specb, lamb)
+    if args.backward_reps > 0:
+        out["backward"] = run_backward(args, spec1, lam1)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle)")
         v, cores, secs = cpu_baseline(specb, lamb, W, args.cpu_steps)
+        v1, _, secs1 = cpu_baseline(specb, lamb, 1, args.cpu_steps)
         out["cpu_baseline"] = {
             "value": v, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, {W} walkers x {args.cpu_steps} step(s) of the same "
                       f"{args.atoms}-atom workload ({secs:.1f} s wall)",
+            "single_core": {"value": v1, "sample": f"1 walker x {args.cpu_steps} step(s), one "
+                                                   f"thread ({secs1:.1f} s wall)"},
+            "cpu_model": cpu_model(),
         }
     if rank == 0:
         print(json.dumps(out), flush=True)
