@@ -33,10 +33,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s and pair-interactions/s at 30k atoms, batched vs plain, 1 GPU"
 # minimal FP32 VALU issue slots per in-cutoff environment pair (half list):
-# dx,dy,dz 3; r^2 3; cutoff compare 1; rsqrt 4 (quarter-rate transcendental);
-# 1/r^2 1; 1/r^6 2; LJ coefficients 4; LJ scalar 3; Coulomb scalar 3; sum 1;
-# i and j force FMAs 6.
-SLOTS_PER_PAIR = 31
+# dx,dy,dz 3; r^2 3; cutoff compare 1; rsqrt 2 (a transcendental issues at half
+# the FMA rate on gfx950, measured by the rsqrt probe); 1/r^2 1; 1/r^6 2; LJ
+# coefficients 4; LJ scalar 3; Coulomb scalar 3; sum 1; i and j force FMAs 6.
+SLOTS_PER_PAIR = 29
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, non-packed FP32 VALU lane-operations/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # packed FP32 executes two lane-operations per slot: 78.6 T lane-ops/s, the
@@ -433,6 +433,11 @@ def main(argv=None):
     value = W * args.steps / dt_b
     env_ms = prof["env_ms"]
     valu_instr = measured_valu_instructions()
+    log("achievable-peak probes")
+    ach = {"fp32_fma_lane_tops": labf.probe("fp32_fma", 4096) / 1e12,
+           "fp64_fma_lane_tops": labf.probe("fp64_fma", 2048) / 1e12,
+           "fp32_rsqrt_lane_tops": labf.probe("fp32_rsq", 2048) / 1e12,
+           "hbm_triad_gbs": labf.probe("triad", 1 << 28) / 1e9}
     achieved = SLOTS_PER_PAIR * env_pairs_per_step / (env_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -483,6 +488,8 @@ def main(argv=None):
             "frac_of_packed_fp32_peak": achieved / PACKED_VALU_PEAK_TOPS,
             "valu_lane_instructions_per_pair": None if valu_instr is None
             else 64.0 * valu_instr / env_pairs_per_step,
+            "achievable": ach,
+            "frac_of_achievable": achieved / ach["fp32_fma_lane_tops"],
         },
         "walker_status": {"batched": int(np.bitwise_or.reduce(st_b["status"])),
                           "plain": int(np.bitwise_or.reduce(st_p["status"])),

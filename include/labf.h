@@ -295,6 +295,21 @@ labf_status labf_profile_steps(labf_system *sys, int64_t n_steps, double *ms, vo
 labf_status labf_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                         void *stream);
 
+/* Achievable-peak probe of the device (for roofline reporting): kind
+ * LABF_PROBE_FP32_FMA / LABF_PROBE_FP64_FMA / LABF_PROBE_FP32_RSQ run 8
+ * independent dependency chains per lane for n iterations (1 .. 1e6) on
+ * 4096 blocks of 256 lanes and return lane-operations per second in *rate;
+ * LABF_PROBE_TRIAD streams a[i] = b[i] + s c[i] over three device arrays of
+ * n floats (n a positive multiple of 4, at most 2^30; the arrays are
+ * allocated and freed by the call) and returns bytes moved (12 n per pass)
+ * per second.  Timed with HIP events over 5 launches after one warm-up, on
+ * `stream`; synchronous.  Errors: LABF_E_ARG for a bad kind or n. */
+#define LABF_PROBE_FP32_FMA 0
+#define LABF_PROBE_FP64_FMA 1
+#define LABF_PROBE_FP32_RSQ 2
+#define LABF_PROBE_TRIAD 3
+labf_status labf_probe(int32_t kind, int64_t n, double *rate, void *stream);
+
 /* Sizes of the device layout (for diagnostics): clusters in use, cluster
  * capacity, list entries in use, list capacity per cluster. */
 typedef struct labf_info {

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblabf.so")
-SOURCES = ["labf_kernels.hip", "labf_pme.hip", "labf_host.cpp"]
+SOURCES = ["labf_kernels.hip", "labf_pme.hip", "labf_probe.hip", "labf_host.cpp"]
 HEADERS = ["labf_impl.h", "labf_device.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -18,6 +18,14 @@
 #include "labf.h"
 #include "labf_impl.h"
 
+namespace labf {
+// Achievable-peak probes (labf_probe.hip): kind 0/1/2 = FP32 FMA, FP64 FMA,
+// FP32 rsqrt chains of n iterations into buf0 [blocks * 256]; kind 3 = triad
+// over n floats (buf0 = buf1 + s buf2, n a multiple of 4).
+hipError_t launch_probe(int kind, int64_t n, void *buf0, void *buf1, void *buf2, unsigned blocks,
+                        hipStream_t s);
+}  // namespace labf
+
 using namespace labf;
 
 namespace {
@@ -1374,6 +1382,47 @@ labf_status labf_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uin
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(nullptr, e, "labf_philox");
+  return LABF_OK;
+}
+
+labf_status labf_probe(int32_t kind, int64_t n, double *rate, void *stream) {
+  if (!rate || kind < LABF_PROBE_FP32_FMA || kind > LABF_PROBE_TRIAD) return fail(nullptr, LABF_E_ARG, "bad probe kind");
+  const bool triad = kind == LABF_PROBE_TRIAD;
+  if (triad ? (n < 4 || n % 4 != 0 || n > (1LL << 30)) : (n < 1 || n > 1000000))
+    return fail(nullptr, LABF_E_ARG, "bad probe size");
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned blocks = triad ? (unsigned)((n / 4 + 255) / 256) : 4096u;
+  DevBufs b;
+  void *p0 = nullptr, *p1 = nullptr, *p2 = nullptr;
+  hipError_t e = hipSuccess;
+  if (triad) {
+    float *a = nullptr, *x = nullptr, *y = nullptr;
+    e = dalloc(b, &a, (size_t)n);
+    if (e == hipSuccess) e = dalloc(b, &x, (size_t)n);
+    if (e == hipSuccess) e = dalloc(b, &y, (size_t)n);
+    p0 = a;
+    p1 = x;
+    p2 = y;
+  } else {
+    double *o = nullptr;
+    e = dalloc(b, &o, (size_t)blocks * 256);
+    p0 = o;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = launch_probe(kind, n, p0, p1, p2, blocks, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  for (int i = 0; i < 5 && e == hipSuccess; ++i) e = launch_probe(kind, n, p0, p1, p2, blocks, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "labf_probe");
+  const double work = triad ? 12.0 * (double)n : (double)blocks * 256.0 * (double)n * 8.0;
+  *rate = 5.0 * work / (1e-3 * (double)ms);
   return LABF_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTS = ["labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
            "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
            "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
            "labf_energy", "labf_energy_backward", "labf_set_distance_restraint",
-           "labf_destroy_system",
+           "labf_probe", "labf_destroy_system",
            "labf_last_error"]
 
 
@@ -109,6 +109,7 @@ def lib():
             "labf_count_pairs": ([P, P, P, P], I32),
             "labf_profile_steps": ([P, I64, P, P], I32),
             "labf_philox": ([I64, P, P, P, P], I32),
+            "labf_probe": ([I32, I64, P, P], I32),
             "labf_get_info": ([P, P, P], I32),
             "labf_energy": ([P, P, P, P, P, P], I32),
             "labf_energy_backward": ([P, P, P, P, P, P, P, P, P], I32),
@@ -352,6 +353,19 @@ class System:
         inf = Info()
         self._chk(lib().labf_get_info(self._h, C.byref(inf), self.stream))
         return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+
+PROBES = {"fp32_fma": 0, "fp64_fma": 1, "fp32_rsq": 2, "triad": 3}
+
+
+def probe(kind: str, n: int, stream=None) -> float:
+    """Achievable-peak probe of the device: lane-operations/s for the FMA and
+    rsqrt chains (n iterations), bytes/s for the triad (n floats per array)."""
+    rate = np.zeros(1)
+    rc = lib().labf_probe(PROBES[kind], int(n), _p(rate), _stream(stream))
+    if rc != 0:
+        raise LabfError(rc, lib().labf_last_error(None).decode())
+    return float(rate[0])
 
 
 def philox(ctr, key, stream=None) -> np.ndarray:
