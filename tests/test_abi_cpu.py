@@ -95,3 +95,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(labf, "_lib", None)
     with pytest.raises(labf.LabfError):
         labf.lib()
+
+
+def test_probe_rejects_bad_arguments_without_a_gpu():
+    _ensure_built()
+    L = labf.lib()
+    rate = np.zeros(1)
+    p = rate.ctypes.data
+    assert L.labf_probe(7, 16, p, None) == -1              # unknown kind
+    assert L.labf_probe(0, 0, p, None) == -1               # no iterations
+    assert L.labf_probe(3, 6, p, None) == -1               # triad size not a multiple of 4
+    assert L.labf_probe(3, (1 << 30) + 4, p, None) == -1   # triad too large
+    assert L.labf_probe(0, 16, None, None) == -1           # no output
