@@ -79,6 +79,17 @@ def _uneven_pme(precision):
     return synth.with_pme(spec, dims=[[32, 32, 32], [16, 32, 64], [64, 16, 16]], order=6), lam
 
 
+def _pme_everything(precision):
+    """PME with the separation-shifted soft-core, the staggered schedule and
+    the lambda-dependent distance restraint, all at once."""
+    spec, lam = _restrained(precision)
+    lam.sc_form, lam.sc_shift = "shifted", 5.0
+    lam.elec_start, lam.elec_end, lam.vdw_start, lam.vdw_end = 0.0, 0.5, 0.0, 1.0
+    spec = synth.with_pme(spec, order=6)
+    spec.charge[np.nonzero(spec.is_solute)[0][:2]] -= 0.25
+    return spec, lam
+
+
 def _pme_axes(precision):
     """A 16 x 128 x 128 grid: y-z planes too large for one LDS block, so the
     transforms run axis by axis."""
@@ -99,6 +110,7 @@ SYSTEMS = {
     "charged3k_fp64_pme": lambda: _pme("fp64"),
     "uneven3_fp32_pme": lambda: _uneven_pme("fp32"),
     "charged3k_fp64_pme_axes": lambda: _pme_axes("fp64"),
+    "charged3k_fp32_pme_shifted_restrained": lambda: _pme_everything("fp32"),
 }
 
 
