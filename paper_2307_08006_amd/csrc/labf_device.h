@@ -29,6 +29,9 @@ __device__ __forceinline__ V wave_sum(V v) {
 }
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// hardware reciprocal in FP32 (about 1 ulp), a true division in FP64
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, multipliers 0xD2511F53 and

@@ -615,25 +615,26 @@ struct Ring {
     bj = LB ? b[k] : (T)0;
   }
 };
-// Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut): F/r and the
-// energy (unused outside the energy kernels).  FP64: the library erfc.
-// FP32: with erfc = 1 - erf, F/r = qq (1/r^3 - gF(r^2)) and
-// U = qq (1/r - gE(r^2)), where gE = erf(beta r)/r and
-// gF = erf(beta r)/r^3 - (2 beta/sqrt(pi)) exp(-beta^2 r^2)/r^2 are smooth,
-// even functions of r; they are read from cubic Hermite pieces on EWTAB_N
-// equal intervals of r^2 in [0, r_cut^2] (built in FP64, error < 2e-9 of
-// the bare Coulomb term), so a pair costs a table read and three FMAs.
+// Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut) written as the
+// bare Coulomb pair minus a correction: F/r = qq r^-3 - c, where c is what
+// ewald_corr returns, and U = qq/r - qq gE (in ue; used by the energy
+// kernels only).  FP64: c = qq r^-2 (erf(beta r)/r - (2 beta/sqrt(pi))
+// exp(-beta^2 r^2)) from the library erf.  FP32: with
+// gE = erf(beta r)/r and gF = erf(beta r)/r^3 - (2 beta/sqrt(pi))
+// exp(-beta^2 r^2)/r^2, smooth even functions of r, c = qq gF; both are read
+// from cubic Hermite pieces on EWTAB_N equal intervals of r^2 in
+// [0, r_cut^2] (built in FP64, error < 2e-9 of the bare Coulomb term), so a
+// pair costs a table read and three FMAs.
 template <typename T>
-__device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
-  const T br = d.ewb * (r2 * rinv);
-  const T ec = qq * erfc(br) * rinv;
-  ue = ec;
-  return (ec + qq * d.ewc * exp(-br * br)) * r2inv;
+__device__ __forceinline__ T ewald_corr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
+  const T x = d.ewb * (r2 * rinv);
+  ue = qq * erfc(x) * rinv;
+  return qq * r2inv * (erf(x) * rinv - d.ewc * exp(-x * x));
 }
 
 template <>
-__device__ __forceinline__ float ewald_fr<float>(const Dev<float> &d, float qq, float r2, float rinv,
-                                                 float r2inv, float &ue) {
+__device__ __forceinline__ float ewald_corr<float>(const Dev<float> &d, float qq, float r2, float rinv,
+                                                   float r2inv, float &ue) {
   // the largest float below EWTAB_N: pairs just inside r_cut keep their
   // offset in the last interval; lanes beyond r_cut (masked) stay in range
   const float u = fminf(r2 * d.ewtab_inv, (float)EWTAB_N * 0.99999994f);
@@ -643,7 +644,14 @@ __device__ __forceinline__ float ewald_fr<float>(const Dev<float> &d, float qq, 
   const float gf = fmaf(f, fmaf(f, fmaf(f, cf.w, cf.z), cf.y), cf.x);
   const float ge = fmaf(f, fmaf(f, fmaf(f, ce.w, ce.z), ce.y), ce.x);
   ue = qq * (rinv - ge);
-  return qq * (r2inv * rinv - gf);
+  return qq * gf;
+}
+
+// Coulomb F/r of a real-space Ewald pair.
+template <typename T>
+__device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv) {
+  T ue;
+  return qq * rinv * r2inv - ewald_corr(d, qq, r2, rinv, r2inv, ue);
 }
 
 template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
@@ -661,21 +669,24 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
     if (DIAG) in = in && (js != (int)(s0 + ii));
     const T rinv = rsq(r2);
     const T r2inv = rinv * rinv;
-    T flj, t3 = 0, bij = 0, r6 = 0;
+    // F/r = r^-2 (L + e) - c: L the LJ part without its r^-2 factor, e = qq/r,
+    // c = e / r_c^2 (shifted force) or the Ewald correction; two FMAs
+    const T qq = qi[ii] * qj;
+    const T e = qq * rinv;
+    T g, t3 = 0, bij = 0, r6 = 0;
     if (!LB) {
       r6 = r2inv * r2inv * r2inv;
-      flj = r6 * (c12x12 * r6 - c6x6);
+      g = fma(r6, fma(c12x12, r6, -c6x6), e);
     } else {
       const T sg = ai[ii] + aj;
       const T t = sg * sg * r2inv;
       t3 = t * t * t;
       bij = bi[ii] * bj;
-      flj = bij * t3 * ((T)2 * t3 - (T)1);
+      g = fma(bij * t3, fma((T)2, t3, (T)-1), e);
     }
-    const T qq = qi[ii] * qj;
     T uew = (T)0;
-    const T fc = EW ? ewald_fr(d, qq, r2, rinv, r2inv, uew) : qq * rinv * (r2inv - d.irc2);
-    T fr = flj * r2inv + fc;
+    const T c = EW ? ewald_corr(d, qq, r2, rinv, r2inv, uew) : d.irc2 * e;
+    T fr = fma(r2inv, g, -c);
     fr = in ? fr : (T)0;
     fx[ii] -= fr * dx;
     fy[ii] -= fr * dy;
@@ -723,21 +734,20 @@ __device__ __forceinline__ void env_alch_pairs(const Dev<T> &d, const T (&xi)[CL
     const T sg = ai[ii] + aj;
     T y, g;
     if (SHIFTED) {
-      const T sinv = (T)1 / (r2 + D);
+      const T sinv = rcp(r2 + D);
       const T w = sg * sg * sinv;
       y = w * w * w;
       g = sinv;
     } else {
-      const T t = r2 / (sg * sg);
+      const T t = r2 * rcp(sg * sg);
       const T u = t * t * t;
-      y = (T)1 / (A + u);
+      y = rcp(A + u);
       g = y * u * r2inv;
     }
     const T bij = bi[ii] * bj;
     T flj = bij * c * ((T)2 * y - (T)1) * y * g;
     flj = bij != (T)0 ? flj : (T)0;
-    T uew;
-    const T fc = EW ? ewald_fr(d, e * qi[ii] * qj, r2, rinv, r2inv, uew)
+    const T fc = EW ? ewald_fr(d, e * qi[ii] * qj, r2, rinv, r2inv)
                     : e * qi[ii] * qj * rinv * (r2inv - d.irc2);
     const T fr = in ? flj + fc : (T)0;
     fx[ii] -= fr * dx;
