@@ -142,7 +142,7 @@ struct Dev {
   int32_t *orig;                // walker-local atom index or -1
   double *fout;                 // [3][S] forces of an evaluation
   // --- per cluster
-  double *bbox;                 // [C][6] lo xyz, hi xyz
+  T *bbox;                      // [C][6] lo xyz, hi xyz (storage precision: exact)
   int32_t *cl_col;              // column of an environment cluster
   int32_t *list_count;          // entries in use (environment, then alchemical)
   int32_t *list_nenv;           // environment-cluster entries of an environment list

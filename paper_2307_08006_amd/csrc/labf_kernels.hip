@@ -393,8 +393,8 @@ __global__ void k_bbox(Dev<T> d, Range r, int xb) {
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d.bbox[c * 6 + k] = lo[k];
-    d.bbox[c * 6 + 3 + k] = hi[k];
+    d.bbox[c * 6 + k] = (T)lo[k];  // min/max of stored coordinates: exact in T
+    d.bbox[c * 6 + 3 + k] = (T)hi[k];
   }
   d.cl_col[c] = col;
 }
@@ -516,15 +516,16 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
           const int code_xy = s_sxy[wv][a];
           sx = code_xy / 3 - 1;
           sy = code_xy % 3 - 1;
-          const double *bj = d.bbox + J * 6;
+          const T *bj = d.bbox + J * 6;
+          const double b0 = bj[0], b1 = bj[1], b2 = bj[2], b3 = bj[3], b4 = bj[4], b5 = bj[5];
           const double ox = sx * m.L[0], oy = sy * m.L[1];
-          const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
-          const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
+          const double ax = gap1(lo[0], hi[0], b0 + ox, b3 + ox);
+          const double ay = gap1(lo[1], hi[1], b1 + oy, b4 + oy);
           const double axy = ax * ax + ay * ay;
 #pragma unroll
           for (int sz = -1; sz <= 1; ++sz) {
             const double oz = sz * m.L[2];
-            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
+            const double az = gap1(lo[2], hi[2], b2 + oz, b5 + oz);
             bool pass = axy + az * az < rl2;
             if (!isA && J == c && sx == 0 && sy == 0 && sz == 0) pass = false;
             mask |= (pass ? 1u : 0u) << (sz + 1);
@@ -555,14 +556,15 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
       int64_t J = 0;
       if (t < m.n_acl) {
         J = A0 + t;
-        const double *bj = d.bbox + J * 6;
-        if (bj[0] <= bj[3]) {
+        const T *bj = d.bbox + J * 6;
+        const double b0 = bj[0], b1 = bj[1], b2 = bj[2], b3 = bj[3], b4 = bj[4], b5 = bj[5];
+        if (b0 <= b3) {
           for (int t27 = 0; t27 < 27; ++t27) {
             const double ox = (t27 / 9 - 1) * m.L[0], oy = ((t27 / 3) % 3 - 1) * m.L[1],
                          oz = (t27 % 3 - 1) * m.L[2];
-            const double ax = gap1(lo[0], hi[0], bj[0] + ox, bj[3] + ox);
-            const double ay = gap1(lo[1], hi[1], bj[1] + oy, bj[4] + oy);
-            const double az = gap1(lo[2], hi[2], bj[2] + oz, bj[5] + oz);
+            const double ax = gap1(lo[0], hi[0], b0 + ox, b3 + ox);
+            const double ay = gap1(lo[1], hi[1], b1 + oy, b4 + oy);
+            const double az = gap1(lo[2], hi[2], b2 + oz, b5 + oz);
             if (ax * ax + ay * ay + az * az < rla2) mask |= 1u << t27;
           }
         }
