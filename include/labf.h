@@ -8,7 +8,9 @@
  *   2. the lambda-scaled nonbonded forces and the alchemical force
  *      dV/dlambda ("Alchemical pathway": soft-core LJ for lambda_v and
  *      linear scaling of electrostatics by lambda_e, decoupling; cutoff
- *      shifted-force Coulomb stands in for PME);
+ *      shifted-force Coulomb, or smooth PME with the reciprocal term
+ *      interpolated linearly between the electrostatic end states when
+ *      labf_system_desc.pme_order > 0);
  *   3. a BAOAB Langevin step of the atoms and of the extended coordinate
  *      (lambda, p_lambda) of Eq. (lambdadyn-Langevin-process), with the ABF
  *      term of Eq. (lambda-abf) and reflecting boundaries;
@@ -34,8 +36,9 @@
  *     data synchronise that stream.  A handle is not thread-safe.
  *   - Errors: every call returns a labf_status.  Argument errors are found on
  *     the host before any device work.  Numerical faults of a walker
- *     (non-finite lambda force, neighbour skin exceeded, list capacity
- *     exceeded) are recorded in that walker's status word (LABF_WS_*) and
+ *     (non-finite lambda force, neighbour skin exceeded, list or PME brick
+ *     capacity exceeded) are recorded in that walker's status word
+ *     (LABF_WS_*) and
  *     surface in labf_read_walker_state.  labf_last_error() describes the
  *     last failure of a handle (or of labf_create_system when passed NULL).
  *   - Positions are stored internally at the precision of the system
