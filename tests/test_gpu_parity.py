@@ -348,6 +348,28 @@ def test_full_size_single_walker_forces():
     s.close()
 
 
+def test_full_size_single_walker_pme():
+    """The benchmark walker with smooth PME (64^3 grid, order 4): every
+    force, dV/dlambda and the energy parts against the oracle."""
+    spec, lam = synth.charged_lj(n_atoms=30000, precision="fp32")
+    spec = synth.with_pme(spec, spacing=1.1, order=4)
+    spec.charge[np.nonzero(spec.is_solute)[0][:3]] += 0.2
+    s = labf.System(spec, lam)
+    o = oracle.Oracle(spec, lam)
+    pos, _ = s.read_atoms()
+    for lv in (0.25, 0.75):
+        lam2 = type(lam)(**{**lam.__dict__, "lambda0": np.array([lv])})
+        s.set_lambda_params(lam2)
+        f, e, g = s.compute_forces()
+        fo, uo, go = o.evaluate(0, pos, lv)
+        assert _rel(f, fo) <= 1e-5, _rel(f, fo)
+        assert abs(g[0] - go) <= 1e-9 * max(abs(go), 1e-3), (g[0], go)
+        for k in (1, 2, 3, 4):
+            assert abs(e[0, k] - uo[k]) <= 1e-9 * max(abs(uo[k]), 1e-3), (k, e[0, k], uo[k])
+        assert abs(e[0, 0] - uo[0]) <= 2e-6 * abs(uo[0]), (e[0, 0], uo[0])
+    s.close()
+
+
 def _top2(v):
     v = np.sort(np.asarray(v, float))
     pad = np.concatenate([np.zeros(2), v])
