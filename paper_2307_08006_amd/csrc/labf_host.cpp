@@ -211,7 +211,8 @@ Range walker_range(const labf_system *s, int w) {
   r.bb0 = s->pme.empty() ? 0 : s->pme[w].br_begin;
   r.bbn = s->pme.empty() ? 0 : s->pme[w].nbr[0] * s->pme[w].nbr[1] * s->pme[w].nbr[2];
   r.pl0 = s->pme.empty() ? 0 : s->pme[w].pl_begin;
-  r.pln = s->pme.empty() || s->pme_planes == 0 ? 0 : s->pme[w].K[0];
+  // a walker with y and z line blocks transforms line by line, else by planes
+  r.pln = s->pme.empty() || s->pme[w].blk[1] > 0 ? 0 : s->pme[w].K[0];
   return r;
 }
 
@@ -612,11 +613,14 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
         p.K[a] = desc->pme_dims[3 * w + a];
         while ((1 << p.lg[a]) < p.K[a]) ++p.lg[a];
       }
+      // y and z transforms: fused per y-z plane in LDS when the plane fits
+      // (no y or z line blocks then), else line by line
+      const bool plane = p.K[1] * p.K[2] <= PME_PLANE;
       p.nl[2] = PME_TILE / p.K[2];
       p.nl[1] = std::min(PME_TILE / p.K[1], p.K[2]);
       p.nl[0] = std::min(PME_TILE / p.K[0], p.K[2]);
-      p.blk[2] = p.K[0] * p.K[1] / p.nl[2];
-      p.blk[1] = p.K[0] * (p.K[2] / p.nl[1]);
+      p.blk[2] = plane ? 0 : p.K[0] * p.K[1] / p.nl[2];
+      p.blk[1] = plane ? 0 : p.K[0] * (p.K[2] / p.nl[1]);
       p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
       for (int a = 0; a < 3; ++a) {
         p.blk_begin[a] = s->pme_nblk[a];
@@ -634,9 +638,11 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       p.loff = loff;
       loff += (int64_t)nb * p.br_cap;
       p.pl_begin = npl;
-      npl += p.K[0];
-      plw.insert(plw.end(), (size_t)p.K[0], w);
-      maxyz = std::max(maxyz, p.K[1] * p.K[2]);
+      if (plane) {
+        npl += p.K[0];
+        plw.insert(plw.end(), (size_t)p.K[0], w);
+        maxyz = std::max(maxyz, p.K[1] * p.K[2]);
+      }
       p.goff = goff;
       goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
       p.toff = toff;
@@ -652,15 +658,14 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     HIPCHK(s, dalloc(b, &d.pme_blist, loff));
     d.pme_nbr = nbr;
     s->pme_bricks = nbr;
-    // y and z transforms fused per y-z plane when every plane fits in LDS
-    d.pme_npl = maxyz <= 4096 ? 4096 : (maxyz <= PME_PLANE ? PME_PLANE : 0);
-    if (d.pme_npl) {
+    // LDS plane capacity of the fused y-z transform (walkers whose planes fit)
+    d.pme_npl = maxyz <= 4096 ? 4096 : PME_PLANE;
+    if (npl > 0) {
       HIPCHK(s, upload(b, &d.pme_plw, plw.data(), plw.size()));
-      s->pme_planes = npl;
     } else {
       d.pme_plw = nullptr;
-      s->pme_planes = 0;
     }
+    s->pme_planes = npl;
     double *tab = nullptr;
     HIPCHK(s, dalloc(b, &tab, 2 * toff));
     d.pme_tab = tab;

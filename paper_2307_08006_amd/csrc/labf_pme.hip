@@ -578,24 +578,26 @@ static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hi
   k_pme_bin<T><<<ns, 256, 0, s>>>(d, r, xb);
   k_pme_spread<T, P><<<(unsigned)r.bbn, 256, 0, s>>>(d, r, xb);
   const double *tab = d.pme_tab;
-  if (d.pme_plw) {
-    // y-z planes in LDS
+  // forward: y-z planes (walkers whose planes fit in LDS) or z then y lines
+  // (the others), then x lines with the influence function and the inverse
+  // along x, then the inverse along y and z the same two ways
+  if (r.pln > 0) {
     if (d.pme_npl == 4096)
       k_pme_fft_yz<true, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
     else
       k_pme_fft_yz<true, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-    if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+  }
+  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+  if (r.pln > 0) {
     if (d.pme_npl == 4096)
       k_pme_fft_yz<false, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
     else
       k_pme_fft_yz<false, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-  } else {
-    if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
-    if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-    if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
-    if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-    if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
   }
+  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
+  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
   k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
 }
 

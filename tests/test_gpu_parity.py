@@ -79,6 +79,13 @@ def _uneven_pme(precision):
     return synth.with_pme(spec, dims=[[32, 32, 32], [16, 32, 64], [64, 16, 16]], order=6), lam
 
 
+def _uneven_pme_mixed(precision):
+    """Uneven walkers where one grid's y-z planes exceed the LDS plane limit
+    (32 x 128 x 128: transformed line by line) and the others fit (planes)."""
+    spec, lam = _uneven(precision)
+    return synth.with_pme(spec, dims=[[32, 128, 128], [32, 32, 32], [64, 16, 16]], order=4), lam
+
+
 def _pme_everything(precision):
     """PME with the separation-shifted soft-core, the staggered schedule and
     the lambda-dependent distance restraint, all at once."""
@@ -111,6 +118,7 @@ SYSTEMS = {
     "uneven3_fp32_pme": lambda: _uneven_pme("fp32"),
     "charged3k_fp64_pme_axes": lambda: _pme_axes("fp64"),
     "charged3k_fp32_pme_shifted_restrained": lambda: _pme_everything("fp32"),
+    "uneven3_fp64_pme_mixed": lambda: _uneven_pme_mixed("fp64"),
 }
 
 
@@ -251,9 +259,10 @@ def test_pme_pairs_up_to_the_cutoff_match_oracle(precision):
         assert abs(e[0, 0] - uo[0]) <= ftol * abs(uo[0]), (r, e[0, 0], uo[0])
 
 
-@pytest.mark.parametrize("pme", [False, True])
+@pytest.mark.parametrize("pme", [False, True, "mixed"])
 def test_batched_and_plain_are_bitwise_identical(pme):
-    spec, lam = _uneven_pme("fp32") if pme else _uneven("fp32")
+    spec, lam = (_uneven_pme_mixed("fp32") if pme == "mixed" else _uneven_pme("fp32")) if pme \
+        else _uneven("fp32")
     a = labf.System(spec, lam)
     b = labf.System(spec, lam)
     a.step(25, "batched")
