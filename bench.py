@@ -173,6 +173,21 @@ def run_uneven(args):
                                 "steps": args.uneven_plain_steps}
         log(f"uneven {label}: {rec['ms_per_step']:.3f} ms/step")
         out[label] = rec
+    if args.variant_steps > 0:
+        # the same batch with smooth PME: per-walker grids at <= 1.1 A spacing
+        # (64^3 or 128^3 here), order 4, after a short re-equilibration
+        sp = synth.with_pme(dataclasses.replace(spec, column_width=widths), spacing=1.1, order=4)
+        sp, lmp = equilibrate(sp, lam, args.variant_equil_steps, lambda_dynamics=True)
+        with labf.System(sp, lmp) as s:
+            s.step(args.warmup)
+            dt = timed_steps(s, args.variant_steps, "batched")
+            st = s.read_walker_state()
+        dims = np.asarray(sp.pme_dims)
+        out["pme"] = {"walker_steps_per_s": sp.n_walkers * args.variant_steps / dt,
+                      "ms_per_step": 1e3 * dt / args.variant_steps, "steps": args.variant_steps,
+                      "grids": {f"{k}^3": int((dims == k).all(axis=1).sum()) for k in (32, 64, 128, 256)},
+                      "walker_status": int(np.bitwise_or.reduce(st["status"]))}
+        log(f"uneven pme: {out['pme']['ms_per_step']:.3f} ms/step")
     return out
 
 
