@@ -186,9 +186,37 @@ void orc_pair_terms_shifted(double r, double sig, double eps, double qq, double 
  * ------------------------------------------------------------------------- */
 static const double ORC_PI = 3.14159265358979323846;
 
-/* in-place radix-2 complex FFT of n points spaced by stride; sign -1: forward
- * (exp(-2 pi i j k / n)), +1: inverse without the 1/n factor */
+/* direct DFT of n points spaced by stride (any n): X_k = sum_j x_j exp(sign 2 pi i j k / n) */
+static void dft1(double *re, double *im, int n, int64_t stride, int sign) {
+  double *xr = (double *)malloc(sizeof(double) * n), *xi = (double *)malloc(sizeof(double) * n);
+  int j, k;
+  for (j = 0; j < n; ++j) {
+    xr[j] = re[j * stride];
+    xi[j] = im[j * stride];
+  }
+  for (k = 0; k < n; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (j = 0; j < n; ++j) {
+      /* (j k) mod n keeps the angle small and exact in the integer part */
+      const double a = sign * 2.0 * ORC_PI * (double)((int64_t)j * k % n) / n;
+      sr += xr[j] * cos(a) - xi[j] * sin(a);
+      si += xr[j] * sin(a) + xi[j] * cos(a);
+    }
+    re[k * stride] = sr;
+    im[k * stride] = si;
+  }
+  free(xr);
+  free(xi);
+}
+
+/* in-place complex DFT of n points spaced by stride; sign -1: forward
+ * (exp(-2 pi i j k / n)), +1: inverse without the 1/n factor.  Radix-2
+ * Cooley-Tukey when n is a power of two, the direct sum otherwise. */
 static void fft1(double *re, double *im, int n, int64_t stride, int sign) {
+  if (n & (n - 1)) {
+    dft1(re, im, n, stride, sign);
+    return;
+  }
   int i, j = 0, k, len;
   for (i = 1; i < n; ++i) {
     int bit = n >> 1;
@@ -767,7 +795,11 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
       return -1;
     for (k = 0; k < 3; ++k) {
       int32_t d = s->pme_dims[3 * w + k];
-      if (d < s->pme_order || (d & (d - 1)) != 0) return -1;
+      int32_t r = d;
+      while (r % 2 == 0) r /= 2;
+      while (r % 3 == 0) r /= 3;
+      while (r % 5 == 0) r /= 5;
+      if (d < s->pme_order || r != 1) return -1;
     }
   }
   memset(&c, 0, sizeof(c));

@@ -61,7 +61,7 @@ typedef struct orc_sys {
   double dr_delta, dr_k;
   int32_t dr_freq;              /* n (1: the text's form; 2: lambda doubled) */
   int32_t pme_on;               /* 1: Ewald electrostatics (smooth PME) instead of shifted force */
-  const int32_t *pme_dims;      /* [W][3] PME grid points per edge (powers of two) */
+  const int32_t *pme_dims;      /* [W][3] PME grid points per edge (2^a 3^b 5^c) */
   double ewald_beta;            /* Ewald splitting parameter (1/length)    */
   int32_t pme_order;            /* B-spline order (4, 6 or 8)              */
   int32_t pad3;
@@ -74,7 +74,7 @@ typedef struct orc_sys {
 double orc_ewald_exact(int64_t n, const double *x, const double *q, const double *L, double beta,
                        double r_real, int32_t kmax, double coulomb_k, double *f);
 /* Smooth PME reciprocal energy of one charge set (tests): order p,
- * grid K[3] (powers of two), forces added to f (may be NULL). */
+ * grid K[3] (any sizes), forces added to f (may be NULL). */
 double orc_spme_energy(int64_t n, const double *x, const double *q, const double *L, double beta,
                        const int32_t K[3], int32_t p, double coulomb_k, double *f);
 

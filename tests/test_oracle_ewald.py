@@ -95,6 +95,23 @@ def test_spme_converges_to_exact_reciprocal_sum():
     assert errs[2][0] < 1e-8 * abs(e_ex) and errs[2][1] < 1e-6 * np.abs(f_ex).max(), errs
 
 
+def test_spme_on_the_papers_grid_sizes_converges_to_exact_sum():
+    """Grids of 2^a 3^b 5^c points (24^3 and 48^3 as in the paper's Tinker
+    runs, and a mixed 40 x 48 x 24): SPME + self + background against the
+    exact k-space sum, the error shrinking with grid and order."""
+    x, q, L = _random_charges(n=30, net=0.4)
+    beta = 3.0
+    e_ex, f_ex = oracle.ewald_exact(x, q, L, beta, 1e-9, 14)
+    V = L.prod()
+    rest = -beta / np.sqrt(np.pi) * (q * q).sum() - np.pi * q.sum() ** 2 / (2 * V * beta * beta)
+    errs = []
+    for dims, p in (((24,) * 3, 6), ((40, 48, 24), 6), ((48,) * 3, 8)):
+        e, f = oracle.spme_energy(x, q, L, beta, dims, p)
+        errs.append((abs(e + rest - e_ex), np.abs(f - f_ex).max()))
+    assert errs[0][0] > errs[2][0] and errs[0][1] > errs[2][1]
+    assert errs[2][0] < 1e-7 * abs(e_ex) and errs[2][1] < 1e-5 * np.abs(f_ex).max(), errs
+
+
 def test_spme_forces_are_minus_gradient():
     x, q, L = _random_charges(n=12)
     args = (L, 2.0, (16, 16, 16), 4)
@@ -220,7 +237,7 @@ def test_pme_walker_charge_gradient_matches_finite_difference():
 
 def test_pme_rejects_bad_grids():
     spec, lam = _pme_small(dims=(16, 16, 16), order=4)
-    for dims, order in (((16, 24, 16), 4), ((16, 16, 16), 5), ((16, 16, 16), 10), ((2, 16, 16), 4)):
+    for dims, order in (((16, 28, 16), 4), ((16, 16, 16), 5), ((16, 16, 16), 10), ((2, 16, 16), 4)):
         sp = dataclasses.replace(spec, pme_dims=np.array([dims], np.int32), pme_order=order)
         with pytest.raises(ValueError):
             oracle.Oracle(sp, lam).evaluate(0, sp.pos, 0.1)
