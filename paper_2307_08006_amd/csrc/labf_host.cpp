@@ -236,8 +236,12 @@ labf_status validate_desc(const labf_system_desc *d) {
     for (int w = 0; w < d->n_walkers; ++w)
       for (int k = 0; k < 3; ++k) {
         const int32_t K = d->pme_dims[3 * w + k];
-        if (K < 16 || K > PME_KMAX || (K & (K - 1)) != 0)
-          return fail(nullptr, LABF_E_ARG, "pme_dims must be powers of two in [16, 256]");
+        int32_t rest = K;
+        while (rest % 2 == 0) rest /= 2;
+        while (rest % 3 == 0) rest /= 3;
+        while (rest % 5 == 0) rest /= 5;
+        if (K < 16 || K > PME_KMAX || K % PME_BR != 0 || rest != 1)
+          return fail(nullptr, LABF_E_ARG, "pme_dims must be multiples of 8 in [16, 256] with no prime factor above 5");
       }
   }
   if (!d->atom_offset || !d->box || !d->pos || !d->mass || !d->charge || !d->sigma || !d->epsilon || !d->is_solute)
@@ -611,14 +615,34 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       std::memset(&p, 0, sizeof(p));
       for (int a = 0; a < 3; ++a) {
         p.K[a] = desc->pme_dims[3 * w + a];
-        while ((1 << p.lg[a]) < p.K[a]) ++p.lg[a];
+        const int32_t K = p.K[a];
+        if ((K & (K - 1)) == 0) {
+          while ((1 << p.lg[a]) < K) ++p.lg[a];
+        } else {
+          // mixed-radix stage plan: fives, threes, fours, a last two
+          p.lg[a] = -1;
+          int32_t rest = K, ns = 0;
+          for (int r : {5, 3, 4, 2})
+            while (rest % r == 0) {
+              p.rad[a][ns++] = (int8_t)r;
+              rest /= r;
+            }
+          p.nst[a] = ns;
+        }
       }
       // y and z transforms: fused per y-z plane in LDS when the plane fits
       // (no y or z line blocks then), else line by line
       const bool plane = p.K[1] * p.K[2] <= PME_PLANE;
-      p.nl[2] = PME_TILE / p.K[2];
-      p.nl[1] = std::min(PME_TILE / p.K[1], p.K[2]);
-      p.nl[0] = std::min(PME_TILE / p.K[0], p.K[2]);
+      // lines per FFT block: the largest power of two that fills at most one
+      // tile and divides the number of lines taken together
+      auto pow2_div = [](int64_t cap, int64_t n) {
+        int32_t q = 1;
+        while (2 * q <= cap && n % (2 * q) == 0) q *= 2;
+        return q;
+      };
+      p.nl[2] = pow2_div(PME_TILE / p.K[2], (int64_t)p.K[0] * p.K[1]);
+      p.nl[1] = pow2_div(std::min(PME_TILE / p.K[1], p.K[2]), p.K[2]);
+      p.nl[0] = pow2_div(std::min(PME_TILE / p.K[0], p.K[2]), p.K[2]);
       p.blk[2] = plane ? 0 : p.K[0] * p.K[1] / p.nl[2];
       p.blk[1] = plane ? 0 : p.K[0] * (p.K[2] / p.nl[1]);
       p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
@@ -669,6 +693,36 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
     double *tab = nullptr;
     HIPCHK(s, dalloc(b, &tab, 2 * toff));
     d.pme_tab = tab;
+    {
+      // frequency index at each position of a forward transform: with the
+      // radices r_1 .. r_n of the decimation-in-frequency stages, position
+      // p = j_1 m_1 + p' (m_1 = K / r_1) holds frequency j_1 + r_1 f(p')
+      // (bit reversal for radix 2)
+      std::vector<int32_t> perm(toff);
+      for (int w = 0; w < W; ++w) {
+        const PmeWalker &p = s->pme[w];
+        int64_t o = p.toff;
+        for (int a = 0; a < 3; ++a) {
+          const int32_t K = p.K[a];
+          std::vector<int32_t> rads;
+          if (p.lg[a] >= 0) rads.assign((size_t)p.lg[a], 2);
+          else rads.assign(p.rad[a], p.rad[a] + p.nst[a]);
+          for (int32_t pos = 0; pos < K; ++pos) {
+            int32_t rem = pos, len = K, mult = 1, f = 0;
+            for (int32_t r : rads) {
+              const int32_t m = len / r, j = rem / m;
+              rem -= j * m;
+              f += j * mult;
+              mult *= r;
+              len = m;
+            }
+            perm[o + pos] = f;
+          }
+          o += K;
+        }
+      }
+      HIPCHK(s, upload(b, &d.pme_perm, perm.data(), perm.size()));
+    }
     HIPCHK(s, dalloc(b, &d.pme_frc, 3 * s->S));
     HIPCHK(s, dalloc(b, &d.pme_phi, 2 * s->S));
     HIPCHK(s, dalloc(b, &d.pme_qs, 4 * W));

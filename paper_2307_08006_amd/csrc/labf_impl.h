@@ -61,8 +61,10 @@ constexpr int PME_BR = 8;       // grid brick edge of the charge spread (>= PME_
 constexpr int PME_PLANE = 8192; // largest K1 K2 transformed as one y-z plane in LDS
 constexpr int EWTAB_N = 256;    // intervals of the FP32 real-space Ewald correction table
 struct PmeWalker {
-  int32_t K[3];           // grid points per edge (powers of two, 16 .. PME_KMAX)
-  int32_t lg[3];          // log2 K
+  int32_t K[3];           // grid points per edge (2^a 3^b 5^c, multiples of 8, 16 .. PME_KMAX)
+  int32_t lg[3];          // log2 K, or -1 when K is not a power of two
+  int8_t rad[3][8];       // radices of the mixed-radix stages (forward order), K not a power of two
+  int32_t nst[3];         // number of such stages
   int32_t nl[3];          // FFT lines per block along each axis
   int32_t blk[3];         // FFT blocks along each axis
   int32_t blk_begin[3];   // first FFT block of the walker along each axis
@@ -183,6 +185,7 @@ struct Dev {
   int32_t *pme_blist;           // [bricks][br_cap] their slots
   int64_t pme_nbr;              // bricks in all
   const double *pme_tab;        // [sum (K0+K1+K2)][2] exp(-pi^2 m~^2 / beta^2) |b(m)|^2, m~^2
+  const int32_t *pme_perm;      // [sum (K0+K1+K2)] frequency index at each position of a forward transform
   double *pme_frc;              // [3][S] reciprocal force per slot
   double *pme_phi;              // [2][S] reciprocal potential: own group, other group
   double *pme_qs;               // [W][4] Q_E, Q_S, sum_E q^2, sum_S q^2

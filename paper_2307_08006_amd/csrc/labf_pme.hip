@@ -59,6 +59,12 @@ __device__ __forceinline__ void bspline_w(double f, double (&w)[P], double (&dw)
   }
 }
 
+// v in (-K, 2K) wrapped into [0, K)
+__device__ __forceinline__ int wrapk(int v, int K) {
+  v += v < 0 ? K : 0;
+  return v >= K ? v - K : v;
+}
+
 // Grid base point k0 and offset f of one coordinate (positions are stored
 // relative to B and may lie up to a list buffer outside [0, L)).
 __device__ __forceinline__ int pme_axis(double x, double L, int K, double &f) {
@@ -120,7 +126,6 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
     acc[1][i] = 0ull;
   }
   __syncthreads();
-  const int m0 = pw.K[0] - 1, m1 = pw.K[1] - 1, m2 = pw.K[2] - 1;
   const int ox = bx * PME_BR, oy = by * PME_BR, oz = bz * PME_BR;
   // the eight source lists as one index range
   __shared__ int sbase[9], sidx[8];
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
       for (int a = 0; a < 3; ++a) {
         const int o = a == 0 ? ox : (a == 1 ? oy : oz);
         const int k0 = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
-        hit = hit && ((k0 - o) & (pw.K[a] - 1)) <= PME_BR + P - 2;
+        hit = hit && wrapk(k0 - o, pw.K[a]) <= PME_BR + P - 2;
       }
       if (hit) use[atomicAdd(&nuse, 1)] = s;
     }
@@ -177,16 +182,16 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
       unsigned long long *ah = acc[d.sol[s] ? 1 : 0];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const int lx = ((k0[0] - i) - ox) & m0;
+        const int lx = wrapk((k0[0] - i) - ox, pw.K[0]);
         if (lx >= PME_BR) continue;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          const int ly = ((k0[1] - j) - oy) & m1;
+          const int ly = wrapk((k0[1] - j) - oy, pw.K[1]);
           if (ly >= PME_BR) continue;
           const double qw = q * wt[0][i] * wt[1][j];
 #pragma unroll
           for (int k = 0; k < P; ++k) {
-            const int lz = ((k0[2] - k) - oz) & m2;
+            const int lz = wrapk((k0[2] - k) - oz, pw.K[2]);
             if (lz >= PME_BR) continue;
             const long long v = __double2ll_rn(qw * wt[2][k] * 0x1p40);
             atomicAdd(ah + (lx * PME_BR + ly) * PME_BR + lz, (unsigned long long)v);
@@ -209,22 +214,100 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// One mixed-radix stage butterfly (radix R, span len = R m, offset k < m of
+// its block; the R inputs R apart by m elements, i.e. mes in memory; tw[t] =
+// exp(-2 pi i t / K), tws = K / len).  Forward (decimation in frequency):
+// y_j = sum_l x_l w_R^{jl}, then y_j *= w_len^{jk}; inverse (decimation in
+// time, the stages in reverse order): x_l *= conj(w_len^{lk}), then
+// y_j = sum_l x_l conj(w_R^{jl}).  Radix 2 reduces to the usual butterfly.
+template <bool FWD, int R>
+__device__ __forceinline__ void mr_butterfly(double2 *base, int mes, const double2 *tw, int K, int k, int tws) {
+  double2 x[R], y[R];
+#pragma unroll
+  for (int l = 0; l < R; ++l) x[l] = base[l * mes];
+  if (!FWD) {
+#pragma unroll
+    for (int l = 1; l < R; ++l) x[l] = cmul(x[l], cconj(tw[l * k * tws]));
+  }
+  const int rs = K / R;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    double2 acc = x[0];
+#pragma unroll
+    for (int l = 1; l < R; ++l) {
+      const double2 w = tw[((j * l) % R) * rs];
+      const double2 v = cmul(x[l], FWD ? w : cconj(w));
+      acc = make_double2(acc.x + v.x, acc.y + v.y);
+    }
+    y[j] = acc;
+  }
+  if (FWD) {
+#pragma unroll
+    for (int j = 1; j < R; ++j) y[j] = cmul(y[j], tw[j * k * tws]);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) base[j * mes] = y[j];
+}
+
+// Transforms of nl lines of length K = pw.K[ax] (not a power of two) held in
+// LDS, element p of line t at buf[t * ls + p * es], by the stage plan
+// pw.rad[ax] (forward: stages in order, output in the plan's digit-reversed
+// order, which pme_perm maps to frequencies; inverse: stages in reverse
+// order, digit-reversed input, natural output).  Ends with a barrier.
+template <bool FWD>
+__device__ void lds_fft_mixed(double2 *buf, const double2 *tw, const PmeWalker &pw, int ax, int nl,
+                              int ls, int es) {
+  const int K = pw.K[ax], ns = pw.nst[ax];
+  for (int q = 0; q < ns; ++q) {
+    const int st = FWD ? q : ns - 1 - q;
+    int len = K;
+    for (int u = 0; u < st; ++u) len /= pw.rad[ax][u];
+    const int r = pw.rad[ax][st], m = len / r, tws = K / len, per = K / r;
+    const int nb = nl * per;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      int t, j;
+      if (es == 1) {
+        t = b / per;
+        j = b - t * per;
+      } else {
+        j = b / nl;
+        t = b - j * nl;
+      }
+      const int blk = j / m, k = j - blk * m;
+      double2 *base = buf + t * ls + (blk * len + k) * es;
+      const int mes = m * es;
+      if (r == 2) mr_butterfly<FWD, 2>(base, mes, tw, K, k, tws);
+      else if (r == 3) mr_butterfly<FWD, 3>(base, mes, tw, K, k, tws);
+      else if (r == 4) mr_butterfly<FWD, 4>(base, mes, tw, K, k, tws);
+      else mr_butterfly<FWD, 5>(base, mes, tw, K, k, tws);
+    }
+    __syncthreads();
+  }
+}
+
 // One block transforms NL grid lines of length K along axis AX in LDS.
 // MODE 1: forward; 2: forward, times the influence function, inverse
-// (x lines); 3: inverse.  The forward transform is decimation in frequency (natural in,
-// bit-reversed out), the inverse decimation in time (bit-reversed in, natural
-// out), so the grid holds bit-reversed frequency indices between the passes
-// and no permutation is ever done.  Lines along z are contiguous; lines
-// along y and x are taken NL at a time from consecutive z so that every
-// load and store is a run of NL contiguous points.
+// (x lines); 3: inverse.  The forward transform is decimation in frequency
+// (natural in, digit-reversed out: bit-reversed for the radix-2 stages of a
+// power of two, the stage plan's order otherwise), the inverse decimation in
+// time (digit-reversed in, natural out), so the grid holds permuted
+// frequency indices between the passes and no permutation is ever done;
+// pme_perm gives the frequency of each position.  Lines along z are
+// contiguous; lines along y and x are taken NL (a power of two) at a time
+// from consecutive z so that every load and store is a run of NL
+// contiguous points.
 template <int AX, int MODE>
 __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
-                                                 double2 *grid, const double *tab, int b0) {
+                                                 double2 *grid, const double *tab, const int32_t *perm,
+                                                 int b0) {
   __shared__ double2 buf[PME_TILE];
-  __shared__ double2 tw[PME_KMAX / 2];
+  __shared__ double2 tw[PME_KMAX];
   const int bid = b0 + (int)blockIdx.x;
   const PmeWalker &pw = pme[bw[bid]];
   const int K = pw.K[AX], lg = pw.lg[AX], NL = pw.nl[AX];
+  const bool p2 = lg >= 0;
   const int g = bid - pw.blk_begin[AX];
   const int64_t K1 = pw.K[1], K2 = pw.K[2];
   int64_t base, sp;
@@ -240,54 +323,66 @@ __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const in
     sp = AX == 1 ? K2 : K1 * K2;
   }
   base += pw.goff;
-  for (int k = threadIdx.x; k < (K >> 1); k += blockDim.x) {
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K, &sn, &cs);
     tw[k] = make_double2(cs, sn);
   }
-  const int n = NL << lg;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    int t, pos;
-    int64_t gi;
+  const int n = NL * K;
+  // tile element i in global order -> (line t, position pos); LDS t * K + pos
+  auto split = [&](int i, int &t, int &pos, int64_t &gi) {
     if (AX == 2) {
-      t = i >> lg;
-      pos = i & (K - 1);
+      if (p2) {
+        t = i >> lg;
+        pos = i & (K - 1);
+      } else {
+        t = i / K;
+        pos = i - t * K;
+      }
       gi = base + i;
     } else {
       t = i & (NL - 1);
       pos = i >> lgnl;
       gi = base + t + pos * sp;
     }
-    buf[(t << lg) + pos] = grid[gi];
+  };
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int t, pos;
+    int64_t gi;
+    split(i, t, pos, gi);
+    buf[t * K + pos] = grid[gi];
   }
   __syncthreads();
-  const int nb = n >> 1, hl = lg - 1;
   if (MODE <= 2) {
-    for (int l = lg; l >= 1; --l) {  // span 2^l
-      const int half = 1 << (l - 1), ts = 1 << (lg - l);
-      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int t = b >> hl, j = b & ((1 << hl) - 1);
-        const int k = j & (half - 1);
-        const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
-        const double2 u = buf[i0], v = buf[i1];
-        buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-        buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[k * ts]);
+    if (p2) {
+      const int nb = n >> 1, hl = lg - 1;
+      for (int l = lg; l >= 1; --l) {  // span 2^l
+        const int half = 1 << (l - 1), ts = 1 << (lg - l);
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+          const int t = b >> hl, j = b & ((1 << hl) - 1);
+          const int k = j & (half - 1);
+          const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+          const double2 u = buf[i0], v = buf[i1];
+          buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+          buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[k * ts]);
+        }
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+      lds_fft_mixed<true>(buf, tw, pw, AX, NL, K, 1);
     }
   }
   if (MODE == 2) {
-    // x lines (AX == 0): line t is grid column (iy, iz0 + t); every index
-    // is a bit-reversed frequency
+    // x lines (AX == 0): line t is grid column (iy, iz0 + t); each index
+    // is mapped to its frequency through pme_perm
     const int gz = (int)(K2 >> lgnl);
     const int iy = g / gz, iz0 = (g % gz) * NL;
-    const int lg1 = pw.lg[1], lg2 = pw.lg[2];
     const double *tx = tab + 2 * pw.toff, *ty = tx + 2 * pw.K[0], *tz = ty + 2 * pw.K[1];
-    const int fy = (int)(__brev((unsigned)iy) >> (32 - lg1));
+    const int32_t *px = perm + pw.toff, *py = px + pw.K[0], *pz = py + pw.K[1];
+    const int fy = py[iy];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int t = i >> lg, pos = i & (K - 1);
-      const int fx = (int)(__brev((unsigned)pos) >> (32 - lg));
-      const int fz = (int)(__brev((unsigned)(iz0 + t)) >> (32 - lg2));
+      const int t = i / K, pos = i - t * K;
+      const int fx = px[pos], fz = pz[iz0 + t];
       const double m2 = (tx[2 * fx + 1] + ty[2 * fy + 1]) + tz[2 * fz + 1];
       const double G = (fx | fy | fz) == 0 ? 0.0 : pw.pref * (tx[2 * fx] * ty[2 * fy] * tz[2 * fz]) / m2;
       const double2 v = buf[i];
@@ -296,33 +391,30 @@ __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const in
     __syncthreads();
   }
   if (MODE >= 2) {
-    for (int l = 1; l <= lg; ++l) {
-      const int half = 1 << (l - 1), ts = 1 << (lg - l);
-      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int t = b >> hl, j = b & ((1 << hl) - 1);
-        const int k = j & (half - 1);
-        const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
-        const double2 u = buf[i0], w0 = tw[k * ts];
-        const double2 v = cmul(buf[i1], make_double2(w0.x, -w0.y));
-        buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-        buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+    if (p2) {
+      const int nb = n >> 1, hl = lg - 1;
+      for (int l = 1; l <= lg; ++l) {
+        const int half = 1 << (l - 1), ts = 1 << (lg - l);
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+          const int t = b >> hl, j = b & ((1 << hl) - 1);
+          const int k = j & (half - 1);
+          const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+          const double2 u = buf[i0], w0 = tw[k * ts];
+          const double2 v = cmul(buf[i1], make_double2(w0.x, -w0.y));
+          buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+          buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+      lds_fft_mixed<false>(buf, tw, pw, AX, NL, K, 1);
     }
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int t, pos;
     int64_t gi;
-    if (AX == 2) {
-      t = i >> lg;
-      pos = i & (K - 1);
-      gi = base + i;
-    } else {
-      t = i & (NL - 1);
-      pos = i >> lgnl;
-      gi = base + t + pos * sp;
-    }
-    grid[gi] = buf[(t << lg) + pos];
+    split(i, t, pos, gi);
+    grid[gi] = buf[t * K + pos];
   }
 }
 
@@ -365,19 +457,19 @@ template <bool FWD, int NPL>
 __global__ __launch_bounds__(1024) void k_pme_fft_yz(const PmeWalker *pme, const int32_t *plw,
                                                     double2 *grid, int p0) {
   __shared__ double2 buf[NPL];
-  __shared__ double2 twb[PME_KMAX];
+  __shared__ double2 twb[2 * PME_KMAX];
   const int pid = p0 + (int)blockIdx.x;
   const PmeWalker &pw = pme[plw[pid]];
   const int ix = pid - pw.pl_begin;
   const int K1 = pw.K[1], K2 = pw.K[2], lg1 = pw.lg[1], lg2 = pw.lg[2];
   const int n = K1 * K2;
-  double2 *ty = twb, *tz = twb + (K1 >> 1);
-  for (int k = threadIdx.x; k < (K1 >> 1); k += blockDim.x) {
+  double2 *ty = twb, *tz = twb + K1;
+  for (int k = threadIdx.x; k < K1; k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K1, &sn, &cs);
     ty[k] = make_double2(cs, sn);
   }
-  for (int k = threadIdx.x; k < (K2 >> 1); k += blockDim.x) {
+  for (int k = threadIdx.x; k < K2; k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K2, &sn, &cs);
     tz[k] = make_double2(cs, sn);
@@ -385,12 +477,17 @@ __global__ __launch_bounds__(1024) void k_pme_fft_yz(const PmeWalker *pme, const
   double2 *g = grid + pw.goff + (int64_t)ix * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = g[i];
   __syncthreads();
+  // z lines: K1 lines, contiguous; y lines: K2 lines, stride K2
   if (FWD) {
-    lds_fft<true>(buf, tz, lg2, K1, K2, 1);   // z lines: K1 lines, contiguous
-    lds_fft<true>(buf, ty, lg1, K2, 1, K2);   // y lines: K2 lines, stride K2
+    if (lg2 >= 0) lds_fft<true>(buf, tz, lg2, K1, K2, 1);
+    else lds_fft_mixed<true>(buf, tz, pw, 2, K1, K2, 1);
+    if (lg1 >= 0) lds_fft<true>(buf, ty, lg1, K2, 1, K2);
+    else lds_fft_mixed<true>(buf, ty, pw, 1, K2, 1, K2);
   } else {
-    lds_fft<false>(buf, ty, lg1, K2, 1, K2);
-    lds_fft<false>(buf, tz, lg2, K1, K2, 1);
+    if (lg1 >= 0) lds_fft<false>(buf, ty, lg1, K2, 1, K2);
+    else lds_fft_mixed<false>(buf, ty, pw, 1, K2, 1, K2);
+    if (lg2 >= 0) lds_fft<false>(buf, tz, lg2, K1, K2, 1);
+    else lds_fft_mixed<false>(buf, tz, pw, 2, K1, K2, 1);
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = buf[i];
 }
@@ -421,14 +518,13 @@ __global__ __launch_bounds__(256) void k_pme_gather(Dev<T> d, Range r, int xb, i
     bspline_w<P>(f, wt[a], dw[a]);
   }
   const double2 *gr = d.pme_grid + pw.goff;
-  const int m0 = pw.K[0] - 1, m1 = pw.K[1] - 1, m2 = pw.K[2] - 1;
   double pe = 0.0, ps = 0.0, ge[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
   // one grid row (P points along z) per iteration keeps the loads in flight
   // few enough to avoid spilling; the x and y weights of the current row are
   // rotated into element 0 so that every array index is static
 #pragma unroll 1
   for (int i = 0; i < P; ++i) {
-    const int64_t ix = (int64_t)((k0[0] - i) & m0) * pw.K[1];
+    const int64_t ix = (int64_t)wrapk(k0[0] - i, pw.K[0]) * pw.K[1];
     double wy[P], dy[P];
 #pragma unroll
     for (int t = 0; t < P; ++t) {
@@ -437,11 +533,11 @@ __global__ __launch_bounds__(256) void k_pme_gather(Dev<T> d, Range r, int xb, i
     }
 #pragma unroll 1
     for (int j = 0; j < P; ++j) {
-      const int64_t ixy = (ix + ((k0[1] - j) & m1)) * pw.K[2];
+      const int64_t ixy = (ix + wrapk(k0[1] - j, pw.K[1])) * pw.K[2];
       const double wxy = wt[0][0] * wy[0], dxy = dw[0][0] * wy[0], xdy = wt[0][0] * dy[0];
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        const double2 v = gr[ixy + ((k0[2] - k) & m2)];
+        const double2 v = gr[ixy + wrapk(k0[2] - k, pw.K[2])];
         const double a = wxy * wt[2][k], bx = dxy * wt[2][k], by = xdy * wt[2][k], bz = wxy * dw[2][k];
         pe += a * v.x;
         ps += a * v.y;
@@ -587,17 +683,17 @@ static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hi
     else
       k_pme_fft_yz<true, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
   }
-  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, r.pb0[0]);
+  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, d.pme_perm, r.pb0[2]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, d.pme_perm, r.pb0[1]);
+  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, d.pme_perm, r.pb0[0]);
   if (r.pln > 0) {
     if (d.pme_npl == 4096)
       k_pme_fft_yz<false, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
     else
       k_pme_fft_yz<false, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
   }
-  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, r.pb0[1]);
-  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, r.pb0[2]);
+  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, d.pme_perm, r.pb0[1]);
+  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, d.pme_perm, r.pb0[2]);
   k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
 }
 

@@ -326,13 +326,15 @@ def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
 
 
 def with_pme(spec: SystemSpec, spacing: float = 1.1, tolerance: float = 1e-6, order: int = 4,
-             dims=None) -> SystemSpec:
-    """The same system with Ewald electrostatics: per walker the smallest
-    power-of-two PME grid with spacing <= `spacing` A on each edge (or the
-    given dims), the splitting parameter beta with erfc(beta r_cut) =
-    tolerance, and B-spline order `order`."""
+             dims=None, sizes: str = "pow2") -> SystemSpec:
+    """The same system with Ewald electrostatics: per walker the smallest PME
+    grid with spacing <= `spacing` A on each edge (sizes "pow2": powers of
+    two; "235": multiples of 8 with no prime factor above 5), or the given
+    dims; the splitting parameter beta with erfc(beta r_cut) = tolerance; and
+    B-spline order `order`."""
     if dims is None:
-        dims = np.array([[_grid_pow2(L / spacing, order) for L in b] for b in spec.box], np.int32)
+        pick = _grid_pow2 if sizes == "pow2" else _grid_235
+        dims = np.array([[pick(L / spacing, order) for L in b] for b in spec.box], np.int32)
     else:
         dims = np.broadcast_to(np.asarray(dims, np.int32), (spec.n_walkers, 3)).copy()
     lo, hi = 0.0, 10.0 / spec.r_cut
@@ -341,6 +343,18 @@ def with_pme(spec: SystemSpec, spacing: float = 1.1, tolerance: float = 1e-6, or
         lo, hi = (mid, hi) if math.erfc(mid * spec.r_cut) > tolerance else (lo, mid)
     return dataclasses.replace(spec, pme_dims=dims, ewald_beta=0.5 * (lo + hi), pme_order=order,
                                name=spec.name + "_pme")
+
+
+def _grid_235(x: float, floor: int) -> int:
+    k = 16
+    while True:
+        r = k
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if k >= x and k >= floor and r == 1:
+            return k
+        k += 8
 
 
 def _grid_pow2(x: float, floor: int) -> int:

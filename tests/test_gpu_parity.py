@@ -86,6 +86,14 @@ def _uneven_pme_mixed(precision):
     return synth.with_pme(spec, dims=[[32, 128, 128], [32, 32, 32], [64, 16, 16]], order=4), lam
 
 
+def _uneven_pme_235(precision, axes=False):
+    """Grids with factors 3 and 5 (24, 40, 48, 80, 96, 120 points): mixed-radix
+    transforms, by planes or (axes=True, 96 x 120 planes) line by line."""
+    spec, lam = _uneven(precision)
+    dims = [[24, 96, 120], [40, 40, 40], [16, 32, 48]] if axes else [[24, 48, 40], [48, 48, 48], [80, 24, 16]]
+    return synth.with_pme(spec, dims=dims, order=6), lam
+
+
 def _pme_everything(precision):
     """PME with the separation-shifted soft-core, the staggered schedule and
     the lambda-dependent distance restraint, all at once."""
@@ -119,6 +127,8 @@ SYSTEMS = {
     "charged3k_fp64_pme_axes": lambda: _pme_axes("fp64"),
     "charged3k_fp32_pme_shifted_restrained": lambda: _pme_everything("fp32"),
     "uneven3_fp64_pme_mixed": lambda: _uneven_pme_mixed("fp64"),
+    "uneven3_fp64_pme_235": lambda: _uneven_pme_235("fp64"),
+    "uneven3_fp32_pme_235_axes": lambda: _uneven_pme_235("fp32", axes=True),
 }
 
 
@@ -195,7 +205,8 @@ def _state(s):
     return st, c, s1, s2, pos, vel
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "fixed_lambda", "pme_batched", "pme_plain"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "fixed_lambda", "pme_batched", "pme_plain",
+                                  "pme235_batched"])
 def test_short_fp64_trajectory_matches_oracle(mode):
     if mode == "fixed_lambda":
         # fixed-lambda TI windows: lambda frozen at 4 window centres
@@ -203,10 +214,11 @@ def test_short_fp64_trajectory_matches_oracle(mode):
         spec, lam = synth.ti_windows(base, lam0, n_windows=4, replicas=1, seed=77)
         mode = "batched"
     elif mode.startswith("pme"):
-        # charged fluid with Ewald electrostatics on a 16 x 16 x 32 grid
+        # charged fluid with Ewald electrostatics on a 16 x 16 x 32 grid, or a
+        # 24 x 40 x 16 one (mixed-radix transforms)
         spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35, charges=0.5)
-        spec = synth.with_pme(spec, dims=(16, 16, 32))
-        mode = mode[4:]
+        spec = synth.with_pme(spec, dims=(24, 40, 16) if mode.startswith("pme235") else (16, 16, 32))
+        mode = mode.split("_", 1)[1]
     else:
         spec, lam = synth.lj_reduced(n_walkers=2, lambda0=0.35)
     lam.share_interval = 2
@@ -259,10 +271,14 @@ def test_pme_pairs_up_to_the_cutoff_match_oracle(precision):
         assert abs(e[0, 0] - uo[0]) <= ftol * abs(uo[0]), (r, e[0, 0], uo[0])
 
 
-@pytest.mark.parametrize("pme", [False, True, "mixed"])
+@pytest.mark.parametrize("pme", [False, True, "mixed", "235"])
 def test_batched_and_plain_are_bitwise_identical(pme):
-    spec, lam = (_uneven_pme_mixed("fp32") if pme == "mixed" else _uneven_pme("fp32")) if pme \
-        else _uneven("fp32")
+    if pme == "235":
+        spec, lam = _uneven_pme_235("fp32", axes=True)
+    elif pme:
+        spec, lam = _uneven_pme_mixed("fp32") if pme == "mixed" else _uneven_pme("fp32")
+    else:
+        spec, lam = _uneven("fp32")
     a = labf.System(spec, lam)
     b = labf.System(spec, lam)
     a.step(25, "batched")
