@@ -175,8 +175,10 @@ def run_uneven(args):
         out[label] = rec
     if args.variant_steps > 0:
         # the same batch with smooth PME: per-walker grids at <= 1.1 A spacing
-        # (64^3 or 128^3 here), order 4, after a short re-equilibration
-        sp = synth.with_pme(dataclasses.replace(spec, column_width=widths), spacing=1.1, order=4)
+        # with 2, 3 and 5 as the only prime factors, order 4, after a short
+        # re-equilibration
+        sp = synth.with_pme(dataclasses.replace(spec, column_width=widths), spacing=1.1, order=4,
+                            sizes="235")
         sp, lmp = equilibrate(sp, lam, args.variant_equil_steps, lambda_dynamics=True)
         with labf.System(sp, lmp) as s:
             s.step(args.warmup)
@@ -185,7 +187,8 @@ def run_uneven(args):
         dims = np.asarray(sp.pme_dims)
         out["pme"] = {"walker_steps_per_s": sp.n_walkers * args.variant_steps / dt,
                       "ms_per_step": 1e3 * dt / args.variant_steps, "steps": args.variant_steps,
-                      "grids": {f"{k}^3": int((dims == k).all(axis=1).sum()) for k in (32, 64, 128, 256)},
+                      "grids": {f"{k}^3": int((dims == k).all(axis=1).sum())
+                                for k in sorted(set(int(v) for v in dims[:, 0]))},
                       "walker_status": int(np.bitwise_or.reduce(st["status"]))}
         log(f"uneven pme: {out['pme']['ms_per_step']:.3f} ms/step")
     return out

@@ -91,6 +91,8 @@ struct labf_system {
   int32_t pme_nblk[3] = {0, 0, 0};
   int32_t pme_bricks = 0;
   int32_t pme_planes = 0;
+  int32_t pme_nblk2[3] = {0, 0, 0};  // leading blocks of walkers with power-of-two grids
+  int32_t pme_planes2 = 0;
   std::vector<int32_t> n_acl_host;
   hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, pme_ev = nullptr;
@@ -164,6 +166,9 @@ hipError_t upload(DevBufs &b, const P **p, const P *host, size_t count) {
   return e;
 }
 
+// all three grid lengths of the walker are powers of two
+static bool pme_pow2(const PmeWalker &p) { return p.lg[0] >= 0 && p.lg[1] >= 0 && p.lg[2] >= 0; }
+
 Range full_range(const labf_system *s) {
   Range r{};
   r.a0 = 0;
@@ -181,11 +186,13 @@ Range full_range(const labf_system *s) {
   for (int a = 0; a < 3; ++a) {
     r.pb0[a] = 0;
     r.pbn[a] = s->pme_nblk[a];
+    r.pbs[a] = s->pme_nblk2[a];
   }
   r.bb0 = 0;
   r.bbn = s->pme_bricks;
   r.pl0 = 0;
   r.pln = s->pme_planes;
+  r.pls = s->pme_planes2;
   return r;
 }
 
@@ -204,15 +211,18 @@ Range walker_range(const labf_system *s, int w) {
   r.kn = (int64_t)m.ncx * m.ncy + 1;
   r.w0 = w;
   r.wn = 1;
+  const bool p2 = !s->pme.empty() && pme_pow2(s->pme[w]);
   for (int a = 0; a < 3; ++a) {
     r.pb0[a] = s->pme.empty() ? 0 : s->pme[w].blk_begin[a];
     r.pbn[a] = s->pme.empty() ? 0 : s->pme[w].blk[a];
+    r.pbs[a] = p2 ? r.pbn[a] : 0;
   }
   r.bb0 = s->pme.empty() ? 0 : s->pme[w].br_begin;
   r.bbn = s->pme.empty() ? 0 : s->pme[w].nbr[0] * s->pme[w].nbr[1] * s->pme[w].nbr[2];
   r.pl0 = s->pme.empty() ? 0 : s->pme[w].pl_begin;
   // a walker with y and z line blocks transforms line by line, else by planes
   r.pln = s->pme.empty() || s->pme[w].blk[1] > 0 ? 0 : s->pme[w].K[0];
+  r.pls = p2 ? r.pln : 0;
   return r;
 }
 
@@ -604,7 +614,8 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.ewb = (T)d.ewald_beta;
   d.ewc = (T)(d.ewald_beta * 1.1283791670955126);  // 2 beta / sqrt(pi)
   s->pme.clear();
-  for (int a = 0; a < 3; ++a) s->pme_nblk[a] = 0;
+  for (int a = 0; a < 3; ++a) s->pme_nblk[a] = s->pme_nblk2[a] = 0;
+  s->pme_planes = s->pme_planes2 = 0;
   if (d.pme_on) {
     s->pme.resize(W);
     int64_t goff = 0, toff = 0, loff = 0;
@@ -633,24 +644,19 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       // y and z transforms: fused per y-z plane in LDS when the plane fits
       // (no y or z line blocks then), else line by line
       const bool plane = p.K[1] * p.K[2] <= PME_PLANE;
-      // lines per FFT block: the largest power of two that fills at most one
-      // tile and divides the number of lines taken together
-      auto pow2_div = [](int64_t cap, int64_t n) {
-        int32_t q = 1;
-        while (2 * q <= cap && n % (2 * q) == 0) q *= 2;
+      // lines per FFT block: the largest divisor of the number of lines
+      // taken together that fills at most one tile
+      auto max_div = [](int64_t cap, int64_t n) {
+        int32_t q = (int32_t)std::min(cap, n);
+        while (n % q) --q;
         return q;
       };
-      p.nl[2] = pow2_div(PME_TILE / p.K[2], (int64_t)p.K[0] * p.K[1]);
-      p.nl[1] = pow2_div(std::min(PME_TILE / p.K[1], p.K[2]), p.K[2]);
-      p.nl[0] = pow2_div(std::min(PME_TILE / p.K[0], p.K[2]), p.K[2]);
+      p.nl[2] = max_div(PME_TILE / p.K[2], (int64_t)p.K[0] * p.K[1]);
+      p.nl[1] = max_div(PME_TILE / p.K[1], p.K[2]);
+      p.nl[0] = max_div(PME_TILE / p.K[0], p.K[2]);
       p.blk[2] = plane ? 0 : p.K[0] * p.K[1] / p.nl[2];
       p.blk[1] = plane ? 0 : p.K[0] * (p.K[2] / p.nl[1]);
       p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
-      for (int a = 0; a < 3; ++a) {
-        p.blk_begin[a] = s->pme_nblk[a];
-        s->pme_nblk[a] += p.blk[a];
-        bw[a].insert(bw[a].end(), (size_t)p.blk[a], w);
-      }
       // spread bricks; list capacity: three times the mean atom count of a
       // brick plus 64 (overflow is flagged in the walker status)
       const int32_t nb = (p.K[0] / PME_BR) * (p.K[1] / PME_BR) * (p.K[2] / PME_BR);
@@ -661,18 +667,35 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
       p.br_cap = (int32_t)(((3 * (int64_t)s->meta[w].n_atoms) / nb + 64 + 31) / 32 * 32);
       p.loff = loff;
       loff += (int64_t)nb * p.br_cap;
-      p.pl_begin = npl;
-      if (plane) {
-        npl += p.K[0];
-        plw.insert(plw.end(), (size_t)p.K[0], w);
-        maxyz = std::max(maxyz, p.K[1] * p.K[2]);
-      }
+      if (plane) maxyz = std::max(maxyz, p.K[1] * p.K[2]);
       p.goff = goff;
       goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
       p.toff = toff;
       toff += p.K[0] + p.K[1] + p.K[2];
       const WalkerMeta &m = s->meta[w];
       p.pref = desc->coulomb_k / (3.14159265358979323846 * m.L[0] * m.L[1] * m.L[2]);
+    }
+    // FFT blocks and y-z planes: walkers whose three grid lengths are powers
+    // of two first (their own kernel instantiations), then the others
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int w = 0; w < W; ++w) {
+        PmeWalker &p = s->pme[w];
+        if (pme_pow2(p) != (pass == 0)) continue;
+        for (int a = 0; a < 3; ++a) {
+          p.blk_begin[a] = s->pme_nblk[a];
+          s->pme_nblk[a] += p.blk[a];
+          bw[a].insert(bw[a].end(), (size_t)p.blk[a], w);
+        }
+        p.pl_begin = npl;
+        if (p.blk[1] == 0) {
+          npl += p.K[0];
+          plw.insert(plw.end(), (size_t)p.K[0], w);
+        }
+      }
+      if (pass == 0) {
+        for (int a = 0; a < 3; ++a) s->pme_nblk2[a] = s->pme_nblk[a];
+        s->pme_planes2 = npl;
+      }
     }
     HIPCHK(s, upload(b, &d.pme, s->pme.data(), W));
     for (int a = 0; a < 3; ++a) HIPCHK(s, upload(b, &d.pme_bw[a], bw[a].data(), bw[a].size()));

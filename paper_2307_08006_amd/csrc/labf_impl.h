@@ -204,8 +204,10 @@ struct Range {
   int64_t k0, kn;      // per-column entries
   int32_t w0, wn;      // walkers
   int32_t pb0[3], pbn[3];  // PME FFT blocks along each axis
+  int32_t pbs[3];          // the first pbs of them: walkers whose grid lengths are powers of two
   int32_t bb0, bbn;        // PME grid bricks
   int32_t pl0, pln;        // PME y-z planes
+  int32_t pls;             // the first pls of them: walkers whose grid lengths are powers of two
 };
 
 // Host-side launchers (defined in labf_kernels.hip).

@@ -59,11 +59,8 @@ __device__ __forceinline__ void bspline_w(double f, double (&w)[P], double (&dw)
   }
 }
 
-// v in (-K, 2K) wrapped into [0, K)
-__device__ __forceinline__ int wrapk(int v, int K) {
-  v += v < 0 ? K : 0;
-  return v >= K ? v - K : v;
-}
+// v in (-K, K) wrapped into [0, K)
+__device__ __forceinline__ int wrapk(int v, int K) { return v < 0 ? v + K : v; }
 
 // Grid base point k0 and offset f of one coordinate (positions are stored
 // relative to B and may lie up to a list buffer outside [0, L)).
@@ -73,7 +70,9 @@ __device__ __forceinline__ int pme_axis(double x, double L, int K, double &f) {
   const double u = g * (double)K;
   const double k0 = floor(u);
   f = u - k0;
-  return (int)k0;
+  // g rounded up to 1 is the image of 0 (f = 0 there): k0 stays in [0, K)
+  const int ki = (int)k0;
+  return ki < K ? ki : ki - K;
 }
 
 // Charge spread, step 1 (one thread per slot): every charged atom joins the
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
       for (int a = 0; a < 3; ++a) {
         const int o = a == 0 ? ox : (a == 1 ? oy : oz);
         const int k0 = pme_axis((double)d.X[xb][a][s] - m.B[a], m.L[a], pw.K[a], f);
-        hit = hit && wrapk(k0 - o, pw.K[a]) <= PME_BR + P - 2;
+        hit = hit && wrapk(k0 - o, pw.K[a]) <= PME_BR + P - 2;  // k0, o in [0, K)
       }
       if (hit) use[atomicAdd(&nuse, 1)] = s;
     }
@@ -180,19 +179,24 @@ __global__ __launch_bounds__(256) void k_pme_spread(Dev<T> d, Range r, int xb) {
       for (int a = 0; a < 3; ++a) bspline_w<P>(f[a], wt[a], dw[a]);
       const double q = d.q64[s];
       unsigned long long *ah = acc[d.sol[s] ? 1 : 0];
+      // base point relative to the brick, in [0, K); point k0 - i lies in
+      // the brick iff 0 <= dx - i < PME_BR (the wrapped alternative
+      // dx - i + K is never below PME_BR, as K >= PME_BR + P - 1)
+      const int dx = wrapk(k0[0] - ox, pw.K[0]), dy = wrapk(k0[1] - oy, pw.K[1]),
+                dz = wrapk(k0[2] - oz, pw.K[2]);
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const int lx = wrapk((k0[0] - i) - ox, pw.K[0]);
-        if (lx >= PME_BR) continue;
+        const int lx = dx - i;
+        if ((unsigned)lx >= (unsigned)PME_BR) continue;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          const int ly = wrapk((k0[1] - j) - oy, pw.K[1]);
-          if (ly >= PME_BR) continue;
+          const int ly = dy - j;
+          if ((unsigned)ly >= (unsigned)PME_BR) continue;
           const double qw = q * wt[0][i] * wt[1][j];
 #pragma unroll
           for (int k = 0; k < P; ++k) {
-            const int lz = wrapk((k0[2] - k) - oz, pw.K[2]);
-            if (lz >= PME_BR) continue;
+            const int lz = dz - k;
+            if ((unsigned)lz >= (unsigned)PME_BR) continue;
             const long long v = __double2ll_rn(qw * wt[2][k] * 0x1p40);
             atomicAdd(ah + (lx * PME_BR + ly) * PME_BR + lz, (unsigned long long)v);
           }
@@ -216,39 +220,98 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
-// One mixed-radix stage butterfly (radix R, span len = R m, offset k < m of
-// its block; the R inputs R apart by m elements, i.e. mes in memory; tw[t] =
-// exp(-2 pi i t / K), tws = K / len).  Forward (decimation in frequency):
-// y_j = sum_l x_l w_R^{jl}, then y_j *= w_len^{jk}; inverse (decimation in
-// time, the stages in reverse order): x_l *= conj(w_len^{lk}), then
-// y_j = sum_l x_l conj(w_R^{jl}).  Radix 2 reduces to the usual butterfly.
+// DFT of R = 2, 3, 4, 5 points in place, y_j = sum_l x_l w^{jl} with
+// w = exp(-2 pi i / R) (forward) or its conjugate (inverse), written out so
+// that the roots are compile-time constants: cos and sin of 2 pi / 3,
+// 2 pi / 5 and 4 pi / 5.
 template <bool FWD, int R>
-__device__ __forceinline__ void mr_butterfly(double2 *base, int mes, const double2 *tw, int K, int k, int tws) {
-  double2 x[R], y[R];
+__device__ __forceinline__ void small_dft(double2 (&x)[R]) {
+  // i s v for the forward transform's -i and the inverse's +i
+  auto rot = [](double2 v, double s) {
+    return FWD ? make_double2(s * v.y, -s * v.x) : make_double2(-s * v.y, s * v.x);
+  };
+  auto add = [](double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); };
+  auto sub = [](double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); };
+  if constexpr (R == 2) {
+    const double2 a = x[0], b = x[1];
+    x[0] = add(a, b);
+    x[1] = sub(a, b);
+  } else if constexpr (R == 3) {
+    constexpr double S3 = 0.86602540378443865;  // sin(2 pi / 3)
+    const double2 t1 = add(x[1], x[2]), d = sub(x[1], x[2]);
+    const double2 t2 = make_double2(fma(-0.5, t1.x, x[0].x), fma(-0.5, t1.y, x[0].y));
+    const double2 r = rot(d, S3);
+    x[0] = add(x[0], t1);
+    x[1] = add(t2, r);
+    x[2] = sub(t2, r);
+  } else if constexpr (R == 4) {
+    const double2 a = add(x[0], x[2]), b = sub(x[0], x[2]);
+    const double2 c = add(x[1], x[3]), e = rot(sub(x[1], x[3]), 1.0);
+    x[0] = add(a, c);
+    x[2] = sub(a, c);
+    x[1] = add(b, e);
+    x[3] = sub(b, e);
+  } else {
+    static_assert(R == 5, "radix 2, 3, 4 or 5");
+    constexpr double C1 = 0.30901699437494742, C2 = -0.80901699437494742;  // cos(2 pi k / 5)
+    constexpr double S1 = 0.95105651629515357, S2 = 0.58778525229247313;   // sin(2 pi k / 5)
+    const double2 a1 = add(x[1], x[4]), b1 = sub(x[1], x[4]);
+    const double2 a2 = add(x[2], x[3]), b2 = sub(x[2], x[3]);
+    const double2 x0 = x[0];
+    const double2 p1 = make_double2(fma(C2, a2.x, fma(C1, a1.x, x0.x)), fma(C2, a2.y, fma(C1, a1.y, x0.y)));
+    const double2 p2 = make_double2(fma(C1, a2.x, fma(C2, a1.x, x0.x)), fma(C1, a2.y, fma(C2, a1.y, x0.y)));
+    const double2 q1 = make_double2(fma(S2, b2.x, S1 * b1.x), fma(S2, b2.y, S1 * b1.y));
+    const double2 q2 = make_double2(fma(-S1, b2.x, S2 * b1.x), fma(-S1, b2.y, S2 * b1.y));
+    const double2 r1 = rot(q1, 1.0), r2 = rot(q2, 1.0);
+    x[0] = add(x0, add(a1, a2));
+    x[1] = add(p1, r1);
+    x[4] = sub(p1, r1);
+    x[2] = add(p2, r2);
+    x[3] = sub(p2, r2);
+  }
+}
+
+// One mixed-radix butterfly of a stage of radix R (span len = R m, offset
+// k < m of its block; the R points m apart, mes apart in memory; tw[t] =
+// exp(-2 pi i t / K), tws = K / len).  Forward (decimation in frequency):
+// the R-point DFT, then output j times w_len^{jk}; inverse (decimation in
+// time, stages in reverse order): input l times conj(w_len^{lk}), then the
+// conjugate R-point DFT.
+template <bool FWD, int R>
+__device__ __forceinline__ void mr_butterfly(double2 *base, int mes, const double2 *tw, int k, int tws) {
+  double2 x[R];
 #pragma unroll
   for (int l = 0; l < R; ++l) x[l] = base[l * mes];
   if (!FWD) {
 #pragma unroll
     for (int l = 1; l < R; ++l) x[l] = cmul(x[l], cconj(tw[l * k * tws]));
   }
-  const int rs = K / R;
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    double2 acc = x[0];
-#pragma unroll
-    for (int l = 1; l < R; ++l) {
-      const double2 w = tw[((j * l) % R) * rs];
-      const double2 v = cmul(x[l], FWD ? w : cconj(w));
-      acc = make_double2(acc.x + v.x, acc.y + v.y);
-    }
-    y[j] = acc;
-  }
+  small_dft<FWD, R>(x);
   if (FWD) {
 #pragma unroll
-    for (int j = 1; j < R; ++j) y[j] = cmul(y[j], tw[j * k * tws]);
+    for (int j = 1; j < R; ++j) x[j] = cmul(x[j], tw[j * k * tws]);
   }
 #pragma unroll
-  for (int j = 0; j < R; ++j) base[j * mes] = y[j];
+  for (int j = 0; j < R; ++j) base[j * mes] = x[j];
+}
+
+// One stage of radix R over nl lines of length K (span len) in LDS.
+template <bool FWD, int R>
+__device__ __forceinline__ void mr_stage(double2 *buf, const double2 *tw, int K, int len, int nl, int ls,
+                                         int es) {
+  const int m = len / R, tws = K / len, per = K / R, nb = nl * per, mes = m * es;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    int t, j;
+    if (es == 1) {
+      t = b / per;
+      j = b - t * per;
+    } else {
+      j = b / nl;
+      t = b - j * nl;
+    }
+    const int blk = j / m, k = j - blk * m;
+    mr_butterfly<FWD, R>(buf + t * ls + (blk * len + k) * es, mes, tw, k, tws);
+  }
 }
 
 // Transforms of nl lines of length K = pw.K[ax] (not a power of two) held in
@@ -257,31 +320,18 @@ __device__ __forceinline__ void mr_butterfly(double2 *base, int mes, const doubl
 // order, which pme_perm maps to frequencies; inverse: stages in reverse
 // order, digit-reversed input, natural output).  Ends with a barrier.
 template <bool FWD>
-__device__ void lds_fft_mixed(double2 *buf, const double2 *tw, const PmeWalker &pw, int ax, int nl,
-                              int ls, int es) {
+__device__ __forceinline__ void lds_fft_mixed(double2 *buf, const double2 *tw, const PmeWalker &pw, int ax,
+                                              int nl, int ls, int es) {
   const int K = pw.K[ax], ns = pw.nst[ax];
   for (int q = 0; q < ns; ++q) {
     const int st = FWD ? q : ns - 1 - q;
     int len = K;
     for (int u = 0; u < st; ++u) len /= pw.rad[ax][u];
-    const int r = pw.rad[ax][st], m = len / r, tws = K / len, per = K / r;
-    const int nb = nl * per;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      int t, j;
-      if (es == 1) {
-        t = b / per;
-        j = b - t * per;
-      } else {
-        j = b / nl;
-        t = b - j * nl;
-      }
-      const int blk = j / m, k = j - blk * m;
-      double2 *base = buf + t * ls + (blk * len + k) * es;
-      const int mes = m * es;
-      if (r == 2) mr_butterfly<FWD, 2>(base, mes, tw, K, k, tws);
-      else if (r == 3) mr_butterfly<FWD, 3>(base, mes, tw, K, k, tws);
-      else if (r == 4) mr_butterfly<FWD, 4>(base, mes, tw, K, k, tws);
-      else mr_butterfly<FWD, 5>(base, mes, tw, K, k, tws);
+    switch (pw.rad[ax][st]) {
+      case 2: mr_stage<FWD, 2>(buf, tw, K, len, nl, ls, es); break;
+      case 3: mr_stage<FWD, 3>(buf, tw, K, len, nl, ls, es); break;
+      case 4: mr_stage<FWD, 4>(buf, tw, K, len, nl, ls, es); break;
+      default: mr_stage<FWD, 5>(buf, tw, K, len, nl, ls, es); break;
     }
     __syncthreads();
   }
@@ -295,35 +345,50 @@ __device__ void lds_fft_mixed(double2 *buf, const double2 *tw, const PmeWalker &
 // time (digit-reversed in, natural out), so the grid holds permuted
 // frequency indices between the passes and no permutation is ever done;
 // pme_perm gives the frequency of each position.  Lines along z are
-// contiguous; lines along y and x are taken NL (a power of two) at a time
+// contiguous; lines along y and x are taken NL (a divisor of K2) at a time
 // from consecutive z so that every load and store is a run of NL
-// contiguous points.
-template <int AX, int MODE>
-__global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
+// contiguous points.  MIX = false serves walkers whose three grid lengths
+// are powers of two (radix-2 stages, shifts and masks only, half the
+// twiddles), MIX = true the others.
+template <int AX, int MODE, bool MIX>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
                                                  double2 *grid, const double *tab, const int32_t *perm,
                                                  int b0) {
   __shared__ double2 buf[PME_TILE];
-  __shared__ double2 tw[PME_KMAX];
+  __shared__ double2 tw[MIX ? PME_KMAX : PME_KMAX / 2];
   const int bid = b0 + (int)blockIdx.x;
   const PmeWalker &pw = pme[bw[bid]];
   const int K = pw.K[AX], lg = pw.lg[AX], NL = pw.nl[AX];
-  const bool p2 = lg >= 0;
+  const bool p2 = !MIX || lg >= 0;
   const int g = bid - pw.blk_begin[AX];
   const int64_t K1 = pw.K[1], K2 = pw.K[2];
-  int64_t base, sp;
   int lgnl = 0;
-  while ((1 << lgnl) < NL) ++lgnl;
+  if (!MIX)
+    while ((1 << lgnl) < NL) ++lgnl;
+  // lines of a block and their first z index (y and x lines)
+  auto zsplit = [&](int &outer, int &iz0) {
+    if (MIX) {
+      const int gz = (int)K2 / NL;
+      outer = g / gz;
+      iz0 = (g - outer * gz) * NL;
+    } else {
+      const int lgz = pw.lg[2] - lgnl;
+      outer = g >> lgz;
+      iz0 = (g & ((1 << lgz) - 1)) << lgnl;
+    }
+  };
+  int64_t base, sp;
   if (AX == 2) {
     base = (int64_t)g * NL * K;
     sp = 1;
   } else {
-    const int gz = (int)(K2 >> lgnl);
-    const int64_t outer = g / gz, iz0 = (int64_t)(g % gz) * NL;
-    base = (AX == 1 ? outer * K1 * K2 : outer * K2) + iz0;
+    int outer, iz0;
+    zsplit(outer, iz0);
+    base = (AX == 1 ? (int64_t)outer * K1 * K2 : (int64_t)outer * K2) + iz0;
     sp = AX == 1 ? K2 : K1 * K2;
   }
   base += pw.goff;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+  for (int k = threadIdx.x; k < (MIX ? K : K >> 1); k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K, &sn, &cs);
     tw[k] = make_double2(cs, sn);
@@ -341,8 +406,13 @@ __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const in
       }
       gi = base + i;
     } else {
-      t = i & (NL - 1);
-      pos = i >> lgnl;
+      if (MIX) {
+        pos = i / NL;
+        t = i - pos * NL;
+      } else {
+        pos = i >> lgnl;
+        t = i & (NL - 1);
+      }
       gi = base + t + pos * sp;
     }
   };
@@ -368,20 +438,20 @@ __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const in
         }
         __syncthreads();
       }
-    } else {
+    } else if constexpr (MIX) {
       lds_fft_mixed<true>(buf, tw, pw, AX, NL, K, 1);
     }
   }
   if (MODE == 2) {
     // x lines (AX == 0): line t is grid column (iy, iz0 + t); each index
     // is mapped to its frequency through pme_perm
-    const int gz = (int)(K2 >> lgnl);
-    const int iy = g / gz, iz0 = (g % gz) * NL;
+    int iy, iz0;
+    zsplit(iy, iz0);
     const double *tx = tab + 2 * pw.toff, *ty = tx + 2 * pw.K[0], *tz = ty + 2 * pw.K[1];
     const int32_t *px = perm + pw.toff, *py = px + pw.K[0], *pz = py + pw.K[1];
     const int fy = py[iy];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int t = i / K, pos = i - t * K;
+      const int t = p2 ? i >> lg : i / K, pos = i - t * K;
       const int fx = px[pos], fz = pz[iz0 + t];
       const double m2 = (tx[2 * fx + 1] + ty[2 * fy + 1]) + tz[2 * fz + 1];
       const double G = (fx | fy | fz) == 0 ? 0.0 : pw.pref * (tx[2 * fx] * ty[2 * fy] * tz[2 * fz]) / m2;
@@ -406,7 +476,7 @@ __global__ __launch_bounds__(1024) void k_pme_fft(const PmeWalker *pme, const in
         }
         __syncthreads();
       }
-    } else {
+    } else if constexpr (MIX) {
       lds_fft_mixed<false>(buf, tw, pw, AX, NL, K, 1);
     }
   }
@@ -452,24 +522,27 @@ __device__ __forceinline__ void lds_fft(double2 *buf, const double2 *tw, int lg,
 }
 
 // One block per y-z plane (fixed x) of K1 K2 <= NPL points: both transforms
-// of the plane in LDS, forward (z then y) or inverse (y then z).
-template <bool FWD, int NPL>
-__global__ __launch_bounds__(1024) void k_pme_fft_yz(const PmeWalker *pme, const int32_t *plw,
+// of the plane in LDS, forward (z then y) or inverse (y then z).  MIX as
+// for k_pme_fft.
+template <bool FWD, int NPL, bool MIX>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_pme_fft_yz(const PmeWalker *pme, const int32_t *plw,
                                                     double2 *grid, int p0) {
   __shared__ double2 buf[NPL];
-  __shared__ double2 twb[2 * PME_KMAX];
+  __shared__ double2 twb[MIX ? 2 * PME_KMAX : PME_KMAX];
   const int pid = p0 + (int)blockIdx.x;
   const PmeWalker &pw = pme[plw[pid]];
   const int ix = pid - pw.pl_begin;
   const int K1 = pw.K[1], K2 = pw.K[2], lg1 = pw.lg[1], lg2 = pw.lg[2];
   const int n = K1 * K2;
-  double2 *ty = twb, *tz = twb + K1;
-  for (int k = threadIdx.x; k < K1; k += blockDim.x) {
+  // radix-2 stages use the first half of the twiddles only
+  const int n1 = MIX ? K1 : K1 >> 1, n2 = MIX ? K2 : K2 >> 1;
+  double2 *ty = twb, *tz = twb + n1;
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K1, &sn, &cs);
     ty[k] = make_double2(cs, sn);
   }
-  for (int k = threadIdx.x; k < K2; k += blockDim.x) {
+  for (int k = threadIdx.x; k < n2; k += blockDim.x) {
     double sn, cs;
     sincospi(-2.0 * (double)k / (double)K2, &sn, &cs);
     tz[k] = make_double2(cs, sn);
@@ -478,7 +551,15 @@ __global__ __launch_bounds__(1024) void k_pme_fft_yz(const PmeWalker *pme, const
   for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = g[i];
   __syncthreads();
   // z lines: K1 lines, contiguous; y lines: K2 lines, stride K2
-  if (FWD) {
+  if constexpr (!MIX) {
+    if (FWD) {
+      lds_fft<true>(buf, tz, lg2, K1, K2, 1);
+      lds_fft<true>(buf, ty, lg1, K2, 1, K2);
+    } else {
+      lds_fft<false>(buf, ty, lg1, K2, 1, K2);
+      lds_fft<false>(buf, tz, lg2, K1, K2, 1);
+    }
+  } else if (FWD) {
     if (lg2 >= 0) lds_fft<true>(buf, tz, lg2, K1, K2, 1);
     else lds_fft_mixed<true>(buf, tz, pw, 2, K1, K2, 1);
     if (lg1 >= 0) lds_fft<true>(buf, ty, lg1, K2, 1, K2);
@@ -674,26 +755,31 @@ static void pme_order_launch(const Dev<T> &d, const Range &r, int xb, int lb, hi
   k_pme_bin<T><<<ns, 256, 0, s>>>(d, r, xb);
   k_pme_spread<T, P><<<(unsigned)r.bbn, 256, 0, s>>>(d, r, xb);
   const double *tab = d.pme_tab;
+  // Blocks (and planes) of walkers whose grid lengths are all powers of two
+  // come first in every list: the first pbs (pls) of a range go to the
+  // radix-2 instantiations, the rest to the mixed-radix ones.
+  auto axis = [&](auto k2, auto km, int a) {
+    if (r.pbs[a] > 0) k2<<<(unsigned)r.pbs[a], 1024, 0, s>>>(d.pme, d.pme_bw[a], d.pme_grid, tab, d.pme_perm, r.pb0[a]);
+    if (r.pbn[a] > r.pbs[a])
+      km<<<(unsigned)(r.pbn[a] - r.pbs[a]), 1024, 0, s>>>(d.pme, d.pme_bw[a], d.pme_grid, tab, d.pme_perm,
+                                                         r.pb0[a] + r.pbs[a]);
+  };
+  auto planes = [&](auto k2, auto km) {
+    if (r.pls > 0) k2<<<(unsigned)r.pls, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
+    if (r.pln > r.pls) km<<<(unsigned)(r.pln - r.pls), 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0 + r.pls);
+  };
   // forward: y-z planes (walkers whose planes fit in LDS) or z then y lines
   // (the others), then x lines with the influence function and the inverse
   // along x, then the inverse along y and z the same two ways
-  if (r.pln > 0) {
-    if (d.pme_npl == 4096)
-      k_pme_fft_yz<true, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-    else
-      k_pme_fft_yz<true, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-  }
-  if (r.pbn[2] > 0) k_pme_fft<2, 1><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, d.pme_perm, r.pb0[2]);
-  if (r.pbn[1] > 0) k_pme_fft<1, 1><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, d.pme_perm, r.pb0[1]);
-  if (r.pbn[0] > 0) k_pme_fft<0, 2><<<(unsigned)r.pbn[0], 1024, 0, s>>>(d.pme, d.pme_bw[0], d.pme_grid, tab, d.pme_perm, r.pb0[0]);
-  if (r.pln > 0) {
-    if (d.pme_npl == 4096)
-      k_pme_fft_yz<false, 4096><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-    else
-      k_pme_fft_yz<false, 8192><<<(unsigned)r.pln, 1024, 0, s>>>(d.pme, d.pme_plw, d.pme_grid, r.pl0);
-  }
-  if (r.pbn[1] > 0) k_pme_fft<1, 3><<<(unsigned)r.pbn[1], 1024, 0, s>>>(d.pme, d.pme_bw[1], d.pme_grid, tab, d.pme_perm, r.pb0[1]);
-  if (r.pbn[2] > 0) k_pme_fft<2, 3><<<(unsigned)r.pbn[2], 1024, 0, s>>>(d.pme, d.pme_bw[2], d.pme_grid, tab, d.pme_perm, r.pb0[2]);
+  if (d.pme_npl == 4096) planes(k_pme_fft_yz<true, 4096, false>, k_pme_fft_yz<true, 4096, true>);
+  else planes(k_pme_fft_yz<true, 8192, false>, k_pme_fft_yz<true, 8192, true>);
+  axis(k_pme_fft<2, 1, false>, k_pme_fft<2, 1, true>, 2);
+  axis(k_pme_fft<1, 1, false>, k_pme_fft<1, 1, true>, 1);
+  axis(k_pme_fft<0, 2, false>, k_pme_fft<0, 2, true>, 0);
+  if (d.pme_npl == 4096) planes(k_pme_fft_yz<false, 4096, false>, k_pme_fft_yz<false, 4096, true>);
+  else planes(k_pme_fft_yz<false, 8192, false>, k_pme_fft_yz<false, 8192, true>);
+  axis(k_pme_fft<1, 3, false>, k_pme_fft<1, 3, true>, 1);
+  axis(k_pme_fft<2, 3, false>, k_pme_fft<2, 3, true>, 2);
   k_pme_gather<T, P><<<ns, 256, 0, s>>>(d, r, xb, lb);
 }
 

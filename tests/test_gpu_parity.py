@@ -88,9 +88,11 @@ def _uneven_pme_mixed(precision):
 
 def _uneven_pme_235(precision, axes=False):
     """Grids with factors 3 and 5 (24, 40, 48, 80, 96, 120 points): mixed-radix
-    transforms, by planes or (axes=True, 96 x 120 planes) line by line."""
+    transforms, by planes or (axes=True, 96 x 120 planes) line by line, beside
+    one walker whose grid lengths are all powers of two (its blocks are
+    ordered first and run the radix-2 kernels)."""
     spec, lam = _uneven(precision)
-    dims = [[24, 96, 120], [40, 40, 40], [16, 32, 48]] if axes else [[24, 48, 40], [48, 48, 48], [80, 24, 16]]
+    dims = [[24, 96, 120], [40, 40, 40], [32, 32, 64]] if axes else [[24, 48, 40], [32, 64, 32], [80, 24, 48]]
     return synth.with_pme(spec, dims=dims, order=6), lam
 
 
