@@ -819,8 +819,12 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
 
 // SHIFTED selects the soft-core form of the alchemical segment at compile time
 // (both forms in one instantiation double the register allocation).
+// The FP32 real-space Ewald forces kernel is held to 80 VGPRs (6 waves per
+// SIMD instead of 5, no spills); asking more of any variant spills SGPRs
+// and measured slower.
 template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED, bool EW>
-__global__ __launch_bounds__(256) void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!ENERGY && !INTEG && EW && sizeof(T) == 4 ? 6 : 1)))
+void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   const int nb = (int)((r.en + 3) >> 2);
   const int lblk = xcd_block(nb);
   if (lblk >= nb) return;
