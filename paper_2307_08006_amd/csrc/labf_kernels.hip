@@ -628,21 +628,21 @@ struct Ring {
 // [0, r_cut^2] (built in FP64, error < 2e-9 of the bare Coulomb term), so a
 // pair costs a table read and three FMAs.
 template <typename T>
-__device__ __forceinline__ T ewald_corr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv, T &ue) {
+__device__ __forceinline__ T ewald_corr(const Dev<T> &d, const float4 *, T qq, T r2, T rinv, T r2inv, T &ue) {
   const T x = d.ewb * (r2 * rinv);
   ue = qq * erfc(x) * rinv;
   return qq * r2inv * (erf(x) * rinv - d.ewc * exp(-x * x));
 }
 
 template <>
-__device__ __forceinline__ float ewald_corr<float>(const Dev<float> &d, float qq, float r2, float rinv,
-                                                   float r2inv, float &ue) {
+__device__ __forceinline__ float ewald_corr<float>(const Dev<float> &d, const float4 *ft, float qq, float r2,
+                                                   float rinv, float r2inv, float &ue) {
   // the largest float below EWTAB_N: pairs just inside r_cut keep their
   // offset in the last interval; lanes beyond r_cut (masked) stay in range
   const float u = fminf(r2 * d.ewtab_inv, (float)EWTAB_N * 0.99999994f);
   const int k = (int)u;
   const float f = u - (float)k;
-  const float4 cf = d.ewtab[k], ce = d.ewtab[EWTAB_N + k];
+  const float4 cf = ft[k], ce = d.ewtab[EWTAB_N + k];
   const float gf = fmaf(f, fmaf(f, fmaf(f, cf.w, cf.z), cf.y), cf.x);
   const float ge = fmaf(f, fmaf(f, fmaf(f, ce.w, ce.z), ce.y), ce.x);
   ue = qq * (rinv - ge);
@@ -653,7 +653,7 @@ __device__ __forceinline__ float ewald_corr<float>(const Dev<float> &d, float qq
 template <typename T>
 __device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2inv) {
   T ue;
-  return qq * rinv * r2inv - ewald_corr(d, qq, r2, rinv, r2inv, ue);
+  return qq * rinv * r2inv - ewald_corr(d, d.ewtab, qq, r2, rinv, r2inv, ue);
 }
 
 template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
@@ -661,7 +661,7 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
                                           const T (&zi)[CL], const T (&qi)[CL], const T (&ai)[CL],
                                           const T (&bi)[CL], int64_t s0, T xj, T yj, T zj, T qj,
                                           T aj, T bj, int js, int vmask, T (&fx)[CL],
-                                          T (&fy)[CL], T (&fz)[CL], double &eacc) {
+                                          T (&fy)[CL], T (&fz)[CL], double &eacc, const float4 *ewt) {
   const T c12x12 = (T)12 * d.c12, c6x6 = (T)6 * d.c6;
 #pragma unroll
   for (int ii = 0; ii < CL; ++ii) {
@@ -687,7 +687,7 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
       g = fma(bij * t3, fma((T)2, t3, (T)-1), e);
     }
     T uew = (T)0;
-    const T c = EW ? ewald_corr(d, qq, r2, rinv, r2inv, uew) : d.irc2 * e;
+    const T c = EW ? ewald_corr(d, ewt, qq, r2, rinv, r2inv, uew) : d.irc2 * e;
     T fr = fma(r2inv, g, -c);
     fr = in ? fr : (T)0;
     fx[ii] -= fr * dx;
@@ -819,12 +819,22 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
 
 // SHIFTED selects the soft-core form of the alchemical segment at compile time
 // (both forms in one instantiation double the register allocation).
-// The FP32 real-space Ewald forces kernel is held to 80 VGPRs (6 waves per
-// SIMD instead of 5, no spills); asking more of any variant spills SGPRs
-// and measured slower.
+// The FP32 real-space Ewald forces kernel asks for at least 6 waves per SIMD
+// (at most 80 VGPRs, no spills); asking 8 of any variant spills SGPRs and
+// measured slower.
 template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED, bool EW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!ENERGY && !INTEG && EW && sizeof(T) == 4 ? 6 : 1)))
 void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
+  // the force half of the FP32 real-space Ewald table (4 KiB), staged in LDS
+  // by the whole block before any wave leaves: one LDS read per pair
+  // instead of a cached global gather
+  constexpr bool EWL = EW && !ENERGY && sizeof(T) == 4;
+  __shared__ float4 ewl[EWL ? EWTAB_N : 1];
+  if constexpr (EWL) {
+    for (int k = threadIdx.x; k < EWTAB_N; k += blockDim.x) ewl[k] = d.ewtab[k];
+    __syncthreads();
+  }
+  const float4 *ewt = EWL ? ewl : d.ewtab;
   const int nb = (int)((r.en + 3) >> 2);
   const int lblk = xcd_block(nb);
   if (lblk >= nb) return;
@@ -897,7 +907,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     int js;
     load_j(0, xj, yj, zj, qj, aj, bj, js);
     env_pairs<T, LB, ENERGY, true, EW>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js, vmask,
-                                   fx, fy, fz, eacc);
+                                   fx, fy, fz, eacc, ewt);
   }
   if (nenv > CL) {
     // Remaining entries: a j atom farther than r_cut from the box of the 8
@@ -939,7 +949,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
         rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
         __builtin_amdgcn_wave_barrier();
         env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
-                                        vmask, fx, fy, fz, eacc);
+                                        vmask, fx, fy, fz, eacc, ewt);
         head = (head + WAVE) & (RING - 1);
         cnt -= WAVE;
       }
@@ -949,7 +959,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
       if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
       env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
-                                      vmask, fx, fy, fz, eacc);
+                                      vmask, fx, fy, fz, eacc, ewt);
     }
   }
   if (nenv < n) {
