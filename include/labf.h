@@ -132,8 +132,10 @@ typedef struct labf_system_desc {
                                   (rho: the walker's environment atom density; 1 gives cubic
                                   8-atom clusters), or NULL: 1 for every walker; 0.5 .. 2.
                                   The tile shape that an autotuner chooses per size class */
-  const int32_t *pme_dims;     /* [W][3] PME grid points per edge when pme_order > 0: powers of
-                                  two in [16, 256]; ignored (may be NULL) otherwise */
+  const int32_t *pme_dims;     /* [W][3] PME grid points per edge when pme_order > 0: multiples
+                                  of 8 in [16, 256] with no prime factor above 5 (16, 24, 32,
+                                  40, 48, 64, 72, 80, 96, 120, ...; else LABF_E_ARG); ignored
+                                  (may be NULL) otherwise */
   double ewald_beta;           /* Ewald splitting parameter (1/length) > 0 when pme_order > 0 */
 } labf_system_desc;
 

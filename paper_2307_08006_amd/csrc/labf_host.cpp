@@ -246,11 +246,16 @@ labf_status validate_desc(const labf_system_desc *d) {
     for (int w = 0; w < d->n_walkers; ++w)
       for (int k = 0; k < 3; ++k) {
         const int32_t K = d->pme_dims[3 * w + k];
-        int32_t rest = K;
-        while (rest % 2 == 0) rest /= 2;
-        while (rest % 3 == 0) rest /= 3;
-        while (rest % 5 == 0) rest /= 5;
-        if (K < 16 || K > PME_KMAX || K % PME_BR != 0 || rest != 1)
+        // range first: the factor loops below do not end for K = 0
+        bool ok = K >= 16 && K <= PME_KMAX && K % PME_BR == 0;
+        if (ok) {
+          int32_t rest = K;
+          while (rest % 2 == 0) rest /= 2;
+          while (rest % 3 == 0) rest /= 3;
+          while (rest % 5 == 0) rest /= 5;
+          ok = rest == 1;
+        }
+        if (!ok)
           return fail(nullptr, LABF_E_ARG, "pme_dims must be multiples of 8 in [16, 256] with no prime factor above 5");
       }
   }

@@ -36,6 +36,13 @@ def test_library_exports_every_declared_symbol():
     assert sorted(labf.EXPORTS) == names
 
 
+def _pme_dims(spec, dims, order=4, beta=0.3):
+    """Smooth PME on with the given grid (rejected before any device work
+    when the grid, the order or beta is out of range)."""
+    spec.pme_order, spec.ewald_beta = order, beta
+    spec.pme_dims = np.array([dims], np.int32)
+
+
 def _spec():
     spec, lam = synth.lj_reduced(n_atoms=125, density=0.5, r_cut=2.0, r_skin=0.2)
     return spec, lam
@@ -54,6 +61,13 @@ def _spec():
     (lambda s: setattr(s, "r_skin_alch", 1.5), "L/2"),
     (lambda s: setattr(s, "column_width", np.array([0.3])), "column_width"),
     (lambda s: setattr(s, "precision", "fp16"), None),
+    (lambda s: _pme_dims(s, [0, 16, 16]), "pme_dims"),
+    (lambda s: _pme_dims(s, [16, 28, 16]), "pme_dims"),
+    (lambda s: _pme_dims(s, [16, 16, 20]), "pme_dims"),
+    (lambda s: _pme_dims(s, [264, 16, 16]), "pme_dims"),
+    (lambda s: _pme_dims(s, [16, 16, 8]), "pme_dims"),
+    (lambda s: _pme_dims(s, [16, 16, 16], order=5), "pme_order"),
+    (lambda s: _pme_dims(s, [16, 16, 16], beta=0.0), "ewald_beta"),
 ])
 def test_invalid_descriptor_is_rejected_on_host(mutate, msg):
     _ensure_built()
