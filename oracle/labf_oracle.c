@@ -796,10 +796,11 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
     for (k = 0; k < 3; ++k) {
       int32_t d = s->pme_dims[3 * w + k];
       int32_t r = d;
+      if (d < s->pme_order) return -1; /* before factoring: d = 0 would not end */
       while (r % 2 == 0) r /= 2;
       while (r % 3 == 0) r /= 3;
       while (r % 5 == 0) r /= 5;
-      if (d < s->pme_order || r != 1) return -1;
+      if (r != 1) return -1;
     }
   }
   memset(&c, 0, sizeof(c));

@@ -237,7 +237,8 @@ def test_pme_walker_charge_gradient_matches_finite_difference():
 
 def test_pme_rejects_bad_grids():
     spec, lam = _pme_small(dims=(16, 16, 16), order=4)
-    for dims, order in (((16, 28, 16), 4), ((16, 16, 16), 5), ((16, 16, 16), 10), ((2, 16, 16), 4)):
+    for dims, order in (((16, 28, 16), 4), ((16, 16, 16), 5), ((16, 16, 16), 10), ((2, 16, 16), 4),
+                        ((0, 16, 16), 4), ((16, -8, 16), 4)):
         sp = dataclasses.replace(spec, pme_dims=np.array([dims], np.int32), pme_order=order)
         with pytest.raises(ValueError):
             oracle.Oracle(sp, lam).evaluate(0, sp.pos, 0.1)
