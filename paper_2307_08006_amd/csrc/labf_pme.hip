@@ -354,7 +354,8 @@ template <int AX, int MODE, bool MIX>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_pme_fft(const PmeWalker *pme, const int32_t *bw,
                                                  double2 *grid, const double *tab, const int32_t *perm,
                                                  int b0) {
-  __shared__ double2 buf[PME_TILE];
+  // up to PME_TILE points in lines padded by one point (NL <= PME_TILE / 16)
+  __shared__ double2 buf[PME_TILE + PME_TILE / 16];
   __shared__ double2 tw[MIX ? PME_KMAX : PME_KMAX / 2];
   const int bid = b0 + (int)blockIdx.x;
   const PmeWalker &pw = pme[bw[bid]];
@@ -394,7 +395,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     tw[k] = make_double2(cs, sn);
   }
   const int n = NL * K;
-  // tile element i in global order -> (line t, position pos); LDS t * K + pos
+  // LDS line stride: x and y lines are loaded and stored transposed (the
+  // lanes of a wave take one point of consecutive lines), so their lines are
+  // padded by one point; otherwise the lanes' addresses would be K * 16 bytes
+  // apart and share their LDS banks
+  const int LS = AX == 2 ? K : K + 1;
+  // tile element i in global order -> (line t, position pos); LDS t * LS + pos
   auto split = [&](int i, int &t, int &pos, int64_t &gi) {
     if (AX == 2) {
       if (p2) {
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     int t, pos;
     int64_t gi;
     split(i, t, pos, gi);
-    buf[t * K + pos] = grid[gi];
+    buf[t * LS + pos] = grid[gi];
   }
   __syncthreads();
   if (MODE <= 2) {
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
           const int t = b >> hl, j = b & ((1 << hl) - 1);
           const int k = j & (half - 1);
-          const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+          const int i0 = t * LS + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
           const double2 u = buf[i0], v = buf[i1];
           buf[i0] = make_double2(u.x + v.x, u.y + v.y);
           buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), tw[k * ts]);
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         __syncthreads();
       }
     } else if constexpr (MIX) {
-      lds_fft_mixed<true>(buf, tw, pw, AX, NL, K, 1);
+      lds_fft_mixed<true>(buf, tw, pw, AX, NL, LS, 1);
     }
   }
   if (MODE == 2) {
@@ -455,8 +461,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int fx = px[pos], fz = pz[iz0 + t];
       const double m2 = (tx[2 * fx + 1] + ty[2 * fy + 1]) + tz[2 * fz + 1];
       const double G = (fx | fy | fz) == 0 ? 0.0 : pw.pref * (tx[2 * fx] * ty[2 * fy] * tz[2 * fz]) / m2;
-      const double2 v = buf[i];
-      buf[i] = make_double2(v.x * G, v.y * G);
+      const double2 v = buf[t * LS + pos];
+      buf[t * LS + pos] = make_double2(v.x * G, v.y * G);
     }
     __syncthreads();
   }
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
           const int t = b >> hl, j = b & ((1 << hl) - 1);
           const int k = j & (half - 1);
-          const int i0 = (t << lg) + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
+          const int i0 = t * LS + ((j >> (l - 1)) << l) + k, i1 = i0 + half;
           const double2 u = buf[i0], w0 = tw[k * ts];
           const double2 v = cmul(buf[i1], make_double2(w0.x, -w0.y));
           buf[i0] = make_double2(u.x + v.x, u.y + v.y);
@@ -477,14 +483,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         __syncthreads();
       }
     } else if constexpr (MIX) {
-      lds_fft_mixed<false>(buf, tw, pw, AX, NL, K, 1);
+      lds_fft_mixed<false>(buf, tw, pw, AX, NL, LS, 1);
     }
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int t, pos;
     int64_t gi;
     split(i, t, pos, gi);
-    grid[gi] = buf[t * K + pos];
+    grid[gi] = buf[t * LS + pos];
   }
 }
 
