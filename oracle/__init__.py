@@ -93,6 +93,10 @@ def lib():
             L.orc_evaluate.restype = I32
             L.orc_param_grad.argtypes = [P, I32, P, D, P]
             L.orc_param_grad.restype = I32
+            L.orc_force_scale.argtypes = [P, I32, P, D, P]
+            L.orc_force_scale.restype = I32
+            L.orc_abf_bias.argtypes = [P, P, I32, D]
+            L.orc_abf_bias.restype = D
             L.orc_philox4x32_10.argtypes = [P, P, P]
             L.orc_philox4x32_10.restype = None
             L.orc_normals.argtypes = [U64, U32, U32, U32, U32, P]
@@ -204,6 +208,43 @@ class Oracle:
         if rc != 0:
             raise ValueError("invalid evaluation request")
         return g
+
+    def force_scale(self, w: int, x, lam: float) -> np.ndarray:
+        """Per atom of walker w, the sum of the magnitudes of its force terms
+        (|f_ij| over pairs within r_cut, the reciprocal-space and restraint
+        forces): the scale against which per-atom force errors are judged."""
+        x = _f64(x, (-1, 3))
+        fs = np.zeros(x.shape[0])
+        rc = lib().orc_force_scale(C.byref(self.sys), w, _p(x), float(lam), _p(fs))
+        if rc != 0:
+            raise ValueError("invalid evaluation request")
+        return fs
+
+    def abf_bias(self, w: int, lam: float) -> float:
+        """ABF bias force on lambda that walker w sees at lambda in the
+        current state (shared bins plus its own unshared samples)."""
+        if self.st is None:
+            raise RuntimeError("init_state first")
+        return float(lib().orc_abf_bias(C.byref(self.sys), C.byref(self.st), int(w), float(lam)))
+
+    def load_state(self, x=None, v=None, lam=None, p_lambda=None, bin_count=None, bin_sum=None,
+                   bin_sum2=None, loc_count=None, loc_sum=None, loc_sum2=None, step=None,
+                   pending=None):
+        """Overwrite parts of the dynamic state (after init_state), e.g. to
+        continue from a state read back from elsewhere."""
+        if self.st is None:
+            self.init_state()
+        a = self.arr
+        for k, val in (("x", x), ("v", v), ("lam", lam), ("p_lambda", p_lambda),
+                       ("bin_count", bin_count), ("bin_sum", bin_sum), ("bin_sum2", bin_sum2),
+                       ("loc_count", loc_count), ("loc_sum", loc_sum), ("loc_sum2", loc_sum2)):
+            if val is not None:
+                a[k][...] = np.asarray(val).reshape(a[k].shape)
+        if step is not None:
+            self.st.step = int(step)
+        if pending is not None:
+            self.st.pending = int(pending)
+        return a
 
     def dmin(self, lam: float):
         """(d_min(lambda), d d_min / d lambda) of the distance restraint."""

@@ -633,6 +633,9 @@ typedef struct {
   double dudl;
   /* optional parameter gradient: [n][3] = dU/d(eps, sigma, q) */
   double *g;
+  /* optional per-atom force scale: [n] = sum over the atom's force terms of
+   * their magnitudes (pairs: |f_ij|; reciprocal, restraint: |F|) */
+  double *fs;
 } eval_ctx;
 
 static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], double r2) {
@@ -671,6 +674,10 @@ static void eval_pair(void *vctx, int64_t i, int64_t j, const double d[3], doubl
       c->f[3 * i + k] -= fr * d[k];
       c->f[3 * j + k] += fr * d[k];
     }
+  }
+  if (c->fs) {
+    c->fs[i] += fabs(fr) * r;
+    c->fs[j] += fabs(fr) * r;
   }
   if (alch) {
     c->u[ORC_U_ALCH_LJ] += t[0];
@@ -755,8 +762,13 @@ static void ewald_walker(const orc_sys *s, int32_t w, const double *x, int64_t n
     }
     pown = solute ? pS : pE;
     poth = solute ? pE : pS;
-    if (c->f)
-      for (k = 0; k < 3; ++k) c->f[3 * i + k] -= q[i] * ((solute ? gS[k] : gE[k]) + ce * (solute ? gE[k] : gS[k]));
+    if (c->f || c->fs) {
+      double fr[3];
+      for (k = 0; k < 3; ++k) fr[k] = -q[i] * ((solute ? gS[k] : gE[k]) + ce * (solute ? gE[k] : gS[k]));
+      if (c->f)
+        for (k = 0; k < 3; ++k) c->f[3 * i + k] += fr[k];
+      if (c->fs) c->fs[i] += sqrt((fr[0] * fr[0] + fr[1] * fr[1]) + fr[2] * fr[2]);
+    }
     if (c->g) c->g[3 * i + 2] += pown + ce * poth - 2.0 * kC * beta / sqrt(ORC_PI) * q[i];
   }
   bgE = -ORC_PI * kC * QE * QE / (2.0 * V * beta * beta);
@@ -777,7 +789,7 @@ static void ewald_walker(const orc_sys *s, int32_t w, const double *x, int64_t n
 }
 
 static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam, int brute,
-                       double *f, double *u_parts, double *dudl, double *g) {
+                       double *f, double *u_parts, double *dudl, double *g, double *fs) {
   eval_ctx c;
   int64_t n, i;
   const double *L;
@@ -813,8 +825,10 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
   c.dcv = sch[3];
   c.f = f;
   c.g = g;
+  c.fs = fs;
   if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
   if (g) memset(g, 0, sizeof(double) * 3 * (size_t)n);
+  if (fs) memset(fs, 0, sizeof(double) * (size_t)n);
   for_each_pair(x, n, L, s->r_cut, brute, eval_pair, &c);
   if (s->pme_on) ewald_walker(s, w, x, n, c.ce, c.dce, &c);
   if (s->anchor && s->k0 && s->k1) {
@@ -829,6 +843,7 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
       c.dudl += 0.5 * (k1 - k0) * r2;
       if (f)
         for (k = 0; k < 3; ++k) f[3 * i + k] -= kl * d[k];
+      if (fs) fs[i] += kl * sqrt(r2);
     }
   }
   if (s->dr_pairs) {
@@ -849,6 +864,10 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
           f[3 * ib + k] -= s->dr_k * e * d[k] / r;
           f[3 * ia + k] += s->dr_k * e * d[k] / r;
         }
+      if (fs) {
+        fs[ia] += fabs(s->dr_k * e);
+        fs[ib] += fabs(s->dr_k * e);
+      }
     }
   }
   if (u_parts)
@@ -866,11 +885,20 @@ void orc_dmin(const orc_sys *s, double lam, double out[2]) {
 
 int32_t orc_evaluate(const orc_sys *s, int32_t w, const double *x, double lam, int32_t brute,
                      double *f, double *u_parts, double *dudl) {
-  return eval_walker(s, w, x, lam, brute, f, u_parts, dudl, NULL);
+  return eval_walker(s, w, x, lam, brute, f, u_parts, dudl, NULL, NULL);
 }
 
 int32_t orc_param_grad(const orc_sys *s, int32_t w, const double *x, double lam, double *g) {
-  return eval_walker(s, w, x, lam, 0, NULL, NULL, NULL, g);
+  return eval_walker(s, w, x, lam, 0, NULL, NULL, NULL, g, NULL);
+}
+
+/* Per-atom force scale of walker w: the sum of the magnitudes of every
+ * force term acting on the atom (|f_ij| of each pair within r_cut, the
+ * magnitude of the reciprocal-space force, of each restraint force).  The
+ * net force can cancel to almost nothing; an error bound relative to this
+ * scale does not. */
+int32_t orc_force_scale(const orc_sys *s, int32_t w, const double *x, double lam, double *fs) {
+  return eval_walker(s, w, x, lam, 0, NULL, NULL, NULL, NULL, fs);
 }
 
 /* ---------------------------------------------------------------------------
@@ -979,6 +1007,11 @@ static double abf_bias(const orc_sys *s, const orc_state *st, int32_t w, int32_t
   return ramp * (sum / (double)n);
 }
 
+double orc_abf_bias(const orc_sys *s, const orc_state *st, int32_t w, double lam) {
+  if (w < 0 || w >= s->n_walkers) return NAN;
+  return abf_bias(s, st, w, orc_bin_of(s, lam));
+}
+
 int32_t orc_abf_readout(int32_t n_bins, double lo, double hi, const int64_t *count,
                         const double *sum, double *grad, double *profile, double *delta_a) {
   double w = (hi - lo) / (double)n_bins;
@@ -1060,7 +1093,7 @@ int32_t orc_run(const orc_sys *s, orc_state *st, int64_t n_steps, int32_t brute)
       int64_t a0 = s->atom_offset[w];
       double u[5];
       if (eval_walker(s, w, st->x + 3 * a0, st->lambda[w], brute, st->f + 3 * a0, u, &st->dudl[w],
-                      NULL) != 0)
+                      NULL, NULL) != 0)
         bad = 1;
       else if (!isfinite(st->dudl[w]))
         st->status[w] |= ORC_ST_NONFINITE;
@@ -1148,7 +1181,7 @@ int32_t orc_full_step(const orc_sys *s, const orc_state *st, double *v_full, dou
     double *f = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     double g = 0.0, bias = 0.0;
     int k;
-    if (eval_walker(s, w, st->x + 3 * a0, st->lambda[w], 0, f, NULL, &g, NULL) != 0) {
+    if (eval_walker(s, w, st->x + 3 * a0, st->lambda[w], 0, f, NULL, &g, NULL, NULL) != 0) {
       free(f);
       return -1;
     }

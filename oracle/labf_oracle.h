@@ -110,6 +110,13 @@ int64_t orc_neighbor_pairs(const orc_sys *s, int32_t w, const double *x, double 
 int32_t orc_evaluate(const orc_sys *s, int32_t w, const double *x, double lam,
                      int32_t brute, double *f, double *u_parts, double *dudl);
 int32_t orc_param_grad(const orc_sys *s, int32_t w, const double *x, double lam, double *g);
+/* fs[n]: per atom, the sum of the magnitudes of its force terms (pairs,
+ * reciprocal space, restraints): the scale of per-atom force errors. */
+int32_t orc_force_scale(const orc_sys *s, int32_t w, const double *x, double lam, double *fs);
+/* ABF bias force on lambda of walker w at lambda (bin of lambda): the ramp
+ * min(1, n/fullSamples) times the bin mean, over the shared accumulator plus
+ * the walker's own unshared samples; 0 for an empty bin. */
+double orc_abf_bias(const orc_sys *s, const orc_state *st, int32_t w, double lam);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_normals(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker,
                  uint32_t purpose, double out[4]);

@@ -258,7 +258,7 @@ def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
                seed: int = BASE_SEED + 1, precision: str = "fp32", r_cut: float = 12.0,
                r_skin: float = 1.0, temperature: float = 300.0, dt: float = 2.0,
                gamma_ps: float = 1.0, jitter: float = 0.05, sigma: float = FLUID_SIGMA,
-               solute_k: float = SOLUTE_K, r_skin_alch: float = 0.0):
+               solute_k: float = SOLUTE_K, r_skin_alch: float = 0.0, lj_spread: float = 0.0):
     """One walker: n_atoms (solvent + solute) of a charged LJ fluid at 0.1
     atoms/A^3 on a seeded FCC lattice (+-jitter A).  Solvent charges are
     +-0.4 e on alternating (001) planes of the FCC basis (8 unlike and 4 like
@@ -276,7 +276,10 @@ def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
     flies apart (~3000 K).
     Lambda: electrostatics removed over [0, 0.5], soft-core vdW over
     [0.5, 1] (decoupling), m_lambda = 150000 kcal/mol fs^2,
-    gamma_lambda = 1000 /ps, 100 bins, fullSamples 100."""
+    gamma_lambda = 1000 /ps, 100 bins, fullSamples 100.
+    lj_spread > 0 gives every solvent atom its own sigma and epsilon, each
+    uniform within +-lj_spread (relative) of the defaults (a mixture, so that
+    pairs take Lorentz-Berthelot mixed parameters)."""
     rng = np.random.default_rng(seed)
     L = (n_atoms / density) ** (1.0 / 3.0)
     n_cell = int(math.ceil((n_atoms / 4.0) ** (1.0 / 3.0) - 1e-9))
@@ -307,6 +310,10 @@ def charged_lj(n_atoms: int = 30000, n_solute: int = 30, density: float = 0.1,
     mass = np.full(n_atoms, SOLVENT_MASS)
     s_sig, s_eps, s_q = _solute_params(rng, n_solute)
     idx = np.nonzero(solute)[0]
+    if lj_spread > 0.0:
+        env = np.nonzero(solute == 0)[0]
+        sig[env] *= 1.0 + rng.uniform(-lj_spread, lj_spread, env.size)
+        eps[env] *= 1.0 + rng.uniform(-lj_spread, lj_spread, env.size)
     sig[idx], eps[idx], charge[idx], mass[idx] = s_sig, s_eps, s_q, SOLUTE_MASS
     k = np.zeros(n_atoms)
     k[idx] = solute_k

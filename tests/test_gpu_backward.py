@@ -5,7 +5,8 @@ FP64 oracle and against central finite differences.
 Tolerances:
   * energies: FP64 systems 1e-10 relative; FP32 systems 2e-6 relative
     (FP32 environment pair terms; alchemical parts are FP64);
-  * grad_pos = -g F: FP64 1e-10, FP32 1e-5 (norm-wise, as the forces);
+  * grad_pos = -g F: FP64 1e-10, FP32 1e-5 (norm-wise, as the forces, and
+    atom by atom relative to |g| times the oracle's per-atom force scale);
   * grad_lambda and grad_params: 1e-9 relative (FP64 on the stored
     positions, in FP32 systems too);
   * central differences (h = 1e-4): 1e-6 relative for lambda and the solute
@@ -19,6 +20,7 @@ import pytest
 
 import oracle
 from paper_2307_08006_amd import labf, synth
+from conftest import per_atom_ok
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -56,6 +58,10 @@ CASES = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp64": lambda: _charged("fp64"),
     "charged3k_fp32": lambda: _charged("fp32"),
+    "charged3k_fp32_mixedlj": lambda: synth.charged_lj(n_atoms=3000, precision="fp32",
+                                                       seed=synth.BASE_SEED + 11, lj_spread=0.15),
+    "charged3k_fp64_mixedlj": lambda: synth.charged_lj(n_atoms=3000, precision="fp64",
+                                                       seed=synth.BASE_SEED + 11, lj_spread=0.15),
     "charged3k_fp64_shifted": lambda: _shifted(*_charged("fp64")),
     "charged3k_fp64_restrained": lambda: _restrained(*_charged("fp64")),
     "charged3k_fp64_pme": lambda: _pme(*_charged("fp64")),
@@ -93,7 +99,8 @@ def _oracle(spec, lamb, s, t):
         lw = float(t["lam"][w])
         f, u, g = o.evaluate(w, pos[sl], lw)
         pg = o.param_grad(w, pos[sl], lw)
-        out.append((f, float(np.sum(u)), float(g), pg[np.asarray(spec.is_solute[sl]).astype(bool)]))
+        out.append((f, float(np.sum(u)), float(g), pg[np.asarray(spec.is_solute[sl]).astype(bool)],
+                    o.force_scale(w, pos[sl], lw)))
     return out
 
 
@@ -119,9 +126,11 @@ def test_backward_matches_oracle(case):
     nsol = 0
     for w in range(spec.n_walkers):
         gw = float(g[w])
-        f, _, dudl, pg = ref[w]
+        f, _, dudl, pg, fs = ref[w]
         sl = spec.walker_slice(w)
         assert _rel(gp[sl], -gw * f) <= ftol, (name, w, _rel(gp[sl], -gw * f))
+        ok, worst, i = per_atom_ok(gp[sl], -gw * f, abs(gw) * fs, ftol)
+        assert ok, (name, w, "per-atom", worst, i)
         assert abs(gl[w] - gw * dudl) <= 1e-9 * abs(gw * dudl), (name, w, gl[w], gw * dudl)
         k = pg.shape[0]
         assert _rel(gq[nsol:nsol + k], gw * pg) <= 1e-9, (name, w, gq[nsol:nsol + k], gw * pg)
@@ -249,6 +258,8 @@ def test_full_size_backward_8x30k():
         if w == 0:
             f, _, dudl = o.evaluate(w, pos[sl], lw)
             assert _rel(gp[sl], -gw * f) <= 1e-5
+            ok, worst, i = per_atom_ok(gp[sl], -gw * f, abs(gw) * o.force_scale(w, pos[sl], lw), 1e-5)
+            assert ok, ("per-atom", worst, i)
         else:
             _, _, dudl = o.evaluate(w, pos[sl], lw)
         assert abs(gl[w] - gw * dudl) <= 1e-9 * max(abs(gw * dudl), 1e-12), (w, gl[w], gw * dudl)

@@ -6,8 +6,11 @@ Tolerances (from the arithmetic of each path):
   * FP64 systems: forces, energies, dV/dlambda within 1e-10 relative
     (differences only in summation order);
   * FP32 systems: forces ||dF|| / ||F|| <= 1e-5 per walker (FP32 pair terms
-    on exact FP32 separations); dV/dlambda and every alchemical quantity
-    within 1e-9 relative (computed in FP64 on the FP32 positions);
+    on exact FP32 separations) and, atom by atom, |dF_i| <= 1e-5 s_i with
+    s_i the sum of the magnitudes of atom i's force terms (the oracle's force
+    scale; robust to cancellation in the net force; 1e-10 in FP64 systems);
+    dV/dlambda and every alchemical quantity within 1e-9 relative (computed
+    in FP64 on the FP32 positions);
   * short FP64 trajectories with the same noise: lambda, p_lambda, ABF sums
     and positions within 1e-9 relative.
 """
@@ -17,6 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import per_atom_ok
 from paper_2307_08006_amd import labf, synth
 
 pytestmark = pytest.mark.gpu
@@ -27,8 +31,15 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _small_charged(precision, n=3000, seed=synth.BASE_SEED + 11, n_solute=30):
-    return synth.charged_lj(n_atoms=n, n_solute=n_solute, precision=precision, seed=seed)
+def _small_charged(precision, n=3000, seed=synth.BASE_SEED + 11, n_solute=30, lj_spread=0.0):
+    return synth.charged_lj(n_atoms=n, n_solute=n_solute, precision=precision, seed=seed,
+                            lj_spread=lj_spread)
+
+
+def _mixed(precision):
+    """Every solvent atom with its own sigma and epsilon (+-15 %): pairs use
+    Lorentz-Berthelot mixing instead of one uniform LJ pair."""
+    return _small_charged(precision, lj_spread=0.15)
 
 
 def _uneven(precision):
@@ -118,6 +129,8 @@ SYSTEMS = {
     "lj512_fp64": lambda: synth.lj_reduced(),
     "charged3k_fp32": lambda: _small_charged("fp32"),
     "charged3k_fp64": lambda: _small_charged("fp64"),
+    "charged3k_fp32_mixedlj": lambda: _mixed("fp32"),
+    "charged3k_fp64_mixedlj": lambda: _mixed("fp64"),
     "uneven3_fp32": lambda: _uneven("fp32"),
     "charged3k_fp32_shifted": lambda: _shifted("fp32"),
     "charged3k_fp64_shifted": lambda: _shifted("fp64"),
@@ -187,11 +200,15 @@ def test_forces_energy_dudl_match_oracle(case, lam_value):
     o = oracle.Oracle(spec, lam2)
     pos, _ = s.read_atoms()
     fp64 = spec.precision == "fp64"
+    if name.endswith("mixedlj"):
+        assert s.info()["uniform_lj"] == 0, name
     for w in range(spec.n_walkers):
         sl = spec.walker_slice(w)
         fo, uo, go = o.evaluate(w, pos[sl], lam_value)
         ftol = 1e-10 if fp64 else 1e-5
         assert _rel(f[sl], fo) <= ftol, (name, w, _rel(f[sl], fo))
+        ok, worst, i = per_atom_ok(f[sl], fo, o.force_scale(w, pos[sl], lam_value), ftol)
+        assert ok, (name, w, "per-atom", worst, i)
         assert abs(g[w] - go) <= 1e-9 * max(abs(go), 1e-3), (name, w, g[w], go)
         # alchemical and restraint energies: FP64 on both sides
         for k in (1, 2, 3, 4):
@@ -266,10 +283,12 @@ def test_pme_pairs_up_to_the_cutoff_match_oracle(precision):
         s = labf.System(spec, lam)
         f, e, _ = s.compute_forces()
         p, _ = s.read_atoms()
-        fo, uo, _ = oracle.Oracle(spec, lam).evaluate(0, p, 0.0)
+        o = oracle.Oracle(spec, lam)
+        fo, uo, _ = o.evaluate(0, p, 0.0)
         s.close()
         ftol = 1e-10 if precision == "fp64" else 1e-6
         assert _rel(f, fo) <= ftol, (r, f, fo)
+        assert per_atom_ok(f, fo, o.force_scale(0, p, 0.0), ftol)[0], (r, f, fo)
         assert abs(e[0, 0] - uo[0]) <= ftol * abs(uo[0]), (r, e[0, 0], uo[0])
 
 
@@ -336,8 +355,10 @@ def test_distance_restraint_energy_at_half_lambda():
     assert r < 10.0
     assert e[0, 4] == pytest.approx(0.5 * 5.0 * (r - 10.0) ** 2, rel=1e-12)
     # forces on the pair include -dV/dx = k (d - delta) (x_b - x_a)/d on a
-    fo, _, _ = oracle.Oracle(spec, lam).evaluate(0, pos, 0.5)
+    o = oracle.Oracle(spec, lam)
+    fo, _, _ = o.evaluate(0, pos, 0.5)
     assert _rel(f, fo) <= 1e-10
+    assert per_atom_ok(f, fo, o.force_scale(0, pos, 0.5), 1e-10)[0]
 
 
 def test_fixed_lambda_ti_harmonic_closed_form():
@@ -369,6 +390,8 @@ def test_full_size_single_walker_forces():
         f, e, g = s.compute_forces()
         fo, uo, go = o.evaluate(0, pos, lv)
         assert _rel(f, fo) <= 1e-5, _rel(f, fo)
+        ok, worst, i = per_atom_ok(f, fo, o.force_scale(0, pos, lv), 1e-5)
+        assert ok, ("per-atom", worst, i)
         assert abs(g[0] - go) <= 1e-9 * abs(go)
     cnt = s.count_pairs()
     assert cnt[0] == o.neighbor_pairs(0, pos, spec.r_cut).shape[0]
@@ -390,6 +413,8 @@ def test_full_size_single_walker_pme():
         f, e, g = s.compute_forces()
         fo, uo, go = o.evaluate(0, pos, lv)
         assert _rel(f, fo) <= 1e-5, _rel(f, fo)
+        ok, worst, i = per_atom_ok(f, fo, o.force_scale(0, pos, lv), 1e-5)
+        assert ok, ("per-atom", worst, i)
         assert abs(g[0] - go) <= 1e-9 * max(abs(go), 1e-3), (g[0], go)
         for k in (1, 2, 3, 4):
             assert abs(e[0, k] - uo[k]) <= 1e-9 * max(abs(uo[k]), 1e-3), (k, e[0, k], uo[k])
@@ -475,6 +500,8 @@ def test_uneven_64_walkers_full_size_sampled():
         sl = spec.walker_slice(w)
         fo, uo, go = o.evaluate(w, pos[sl], float(lam.lambda0[w]))
         assert _rel(f[sl], fo) <= 1e-5, (w, _rel(f[sl], fo))
+        ok, worst, i = per_atom_ok(f[sl], fo, o.force_scale(w, pos[sl], float(lam.lambda0[w])), 1e-5)
+        assert ok, (w, "per-atom", worst, i)
         assert abs(g[w] - go) <= 1e-9 * max(abs(go), 1e-12), (w, g[w], go)
     w = int(np.argmin(n))
     sl = spec.walker_slice(w)

@@ -1,0 +1,197 @@
+"""GPU stepping parity: the integrator path the benchmark times (FP32 pair
+terms, FP64 lambda and ABF), and lambda reflection, against the FP64 oracle
+continued from the state the GPU holds.
+
+Bounds (derived from the arithmetic):
+  * one step from an identical state.  Positions are stored as B + x in
+    FP32 (B = 2^k >= 2L), so each of the two half-drifts rounds a coordinate
+    to the storage grid u = B 2^-23: |dx| <= u (plus h |dv|).  Velocities are
+    FP32: a few roundings of each term plus the force error,
+    |dv| <= 4e-7 (|v0| + |v1| + 2h a/m |F|) + 2h a/m 1e-5 s_i (s_i the
+    oracle's per-atom force scale).  lambda and p_lambda depend on dV/dlambda
+    at the starting positions only, computed in FP64 on identical FP32
+    positions: 1e-9 relative (p_lambda: of max(|p|, its thermal scale)); the
+    ABF samples likewise.
+  * ten steps (one graph block with its neighbour rebuild) from an
+    identical state.  Every half-drift adds a rounding of at most u/2; an
+    oracle experiment (the same system with one u/2 perturbation of every
+    coordinate) shows it growing at most 2.2 times over ten steps, so
+    |dx| <= 20 u and |dv| <= 2e-5 A/fs (0.5 % of the thermal velocity);
+    dV/dlambda of the charged solute moves by up to ~3e-3 kcal/mol per u/2 of
+    position change, so each ABF sample may differ by 1e-2, lambda by 2e-6
+    and p_lambda by 5e-3 (of |p| ~ 1e2).  A wrong force on one atom by 1 %,
+    a wrong noise term, or a lost neighbour would exceed these.
+  * reflection trajectories (FP64 system): lambda, p_lambda and the ABF
+    sums within 1e-9 over 20 steps, batched and plain.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_08006_amd import labf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _grid_u(spec, w):
+    L = float(spec.box[w].max())
+    B = 2.0 ** np.ceil(np.log2(2.0 * L))
+    return B * 2.0 ** -23
+
+
+def _gpu_state(s):
+    st = s.read_walker_state()
+    c, s1, s2 = s.read_abf_bins(True)
+    pos, vel = s.read_atoms()
+    return st, c, s1, s2, pos, vel
+
+
+def _oracle_from(spec, lam, s):
+    """An oracle whose dynamic state is the GPU's (share interval 1: every
+    sample is merged at the end of its step, so the unshared deltas are
+    empty between steps)."""
+    st, c, s1, s2, pos, vel = _gpu_state(s)
+    o = oracle.Oracle(spec, lam)
+    o.init_state()
+    o.load_state(x=pos, v=vel, lam=st["lam"], p_lambda=st["p_lambda"], bin_count=c, bin_sum=s1,
+                 bin_sum2=s2, step=st["step"], pending=1 if st["step"] > 0 else 0)
+    return o
+
+
+def _start_forces(spec, o):
+    """Oracle forces and per-atom force scales of every walker at the
+    current oracle state (walkers in parallel threads; the oracle calls
+    release the interpreter lock)."""
+    a = o.arr
+
+    def one(w):
+        sl = spec.walker_slice(w)
+        x, lw = a["x"][sl].copy(), float(a["lam"][w])
+        f, _, _ = o.evaluate(w, x, lw)
+        return f, o.force_scale(w, x, lw)
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        res = list(ex.map(one, range(spec.n_walkers)))
+    return np.concatenate([r[0] for r in res]), np.concatenate([r[1] for r in res])
+
+
+def _compare(spec, lam, s, o, n_steps, tag, f0=None, fs0=None):
+    st, c, s1, s2, pos, vel = _gpu_state(s)
+    a = o.arr
+    assert (st["status"] == 0).all(), (tag, st["status"])
+    assert st["step"] == o.step, (tag, st["step"], o.step)
+    assert np.array_equal(c, a["bin_count"] + a["loc_count"].sum(0)), tag
+    ref_s = a["bin_sum"] + a["loc_sum"].sum(0)
+    h = 0.5 * spec.dt
+    worst = {}
+    for w in range(spec.n_walkers):
+        sl = spec.walker_slice(w)
+        u = _grid_u(spec, w)
+        L = spec.box[w]
+        d = pos[sl] - a["x"][sl]
+        d -= L * np.rint(d / L)
+        dv = np.abs(vel[sl] - a["v"][sl])
+        if n_steps == 1:
+            # the step's kicks use the forces at its starting positions
+            fo, fs = f0[sl], fs0[sl]
+            im = spec.accel_unit / np.asarray(spec.mass)[sl]
+            xb = 1.02 * u + 1e-9
+            vb = (4e-7 * (np.abs(vel[sl]) + np.abs(a["v"][sl]) + 2 * h * im[:, None] * np.abs(fo))
+                  + (2 * h * im * 1e-5 * fs)[:, None] + 1e-12)
+        else:
+            xb = 20.0 * u
+            vb = np.full(dv.shape, 2e-5)
+        worst[w] = (float(np.abs(d).max() / u), float((dv / vb).max()))
+        assert np.abs(d).max() <= xb, (tag, w, "x", np.abs(d).max() / u)
+        assert (dv <= vb).all(), (tag, w, "v", (dv / vb).max())
+    pscale = np.sqrt(lam.m_lambda * lam.kT_lambda)
+    if n_steps == 1:
+        assert np.abs(st["lam"] - a["lam"]).max() <= 1e-9 * np.abs(a["lam"]).max(), tag
+        assert (np.abs(st["p_lambda"] - a["p_lambda"]) <= 1e-9 * np.maximum(np.abs(a["p_lambda"]), pscale)).all(), tag
+        assert _rel(st["dudl"], a["dudl"]) <= 1e-9, tag
+        assert _rel(s1, ref_s) <= 1e-9, tag
+    else:
+        assert np.abs(st["lam"] - a["lam"]).max() <= 2e-6, (tag, np.abs(st["lam"] - a["lam"]).max())
+        assert np.abs(st["p_lambda"] - a["p_lambda"]).max() <= 5e-3, (tag, np.abs(st["p_lambda"] - a["p_lambda"]).max())
+        assert (np.abs(s1 - ref_s) <= 1e-2 * c + 1e-12).all(), (tag, np.abs(s1 - ref_s).max())
+    print(tag, "worst |dx|/u and |dv|/bound per walker:", worst,
+          "max |dlambda|", float(np.abs(st["lam"] - a["lam"]).max()))
+
+
+def _charged3k(lj_spread=0.0):
+    spec, lam = synth.charged_lj(n_atoms=3000, precision="fp32", seed=synth.BASE_SEED + 11,
+                                 lj_spread=lj_spread)
+    lam.lambda0 = np.array([0.4])
+    return spec, lam
+
+
+def _batch16x30k():
+    base, lam = synth.charged_lj(n_atoms=30000, precision="fp32")
+    return synth.batch(base, lam, 16, seed=synth.BASE_SEED + 2)
+
+
+STEP_CASES = {
+    "charged3k_fp32": lambda: _charged3k(),
+    "charged3k_fp32_mixedlj": lambda: _charged3k(0.15),
+    "batch16x30k_fp32": _batch16x30k,
+}
+
+
+@pytest.mark.parametrize("name", sorted(STEP_CASES))
+def test_fp32_stepping_matches_oracle(name):
+    """One eager step, then nine more, then one captured graph block (its
+    rebuild included) of the batched FP32 path, each compared with the
+    oracle continued from the GPU's state."""
+    spec, lam = STEP_CASES[name]()
+    assert spec.precision == "fp32"
+    with labf.System(spec, lam) as s:
+        if name.endswith("mixedlj"):
+            assert s.info()["uniform_lj"] == 0
+        o = _oracle_from(spec, lam, s)
+        f0, fs0 = _start_forces(spec, o)
+        s.step(1)
+        o.run(1)
+        _compare(spec, lam, s, o, 1, name + " step 1", f0, fs0)
+        s.step(spec.rebuild_interval - 1)
+        o = _oracle_from(spec, lam, s)
+        s.step(spec.rebuild_interval)     # a graph block: rebuild + interval steps
+        o.run(spec.rebuild_interval)
+        _compare(spec, lam, s, o, spec.rebuild_interval, name + " graph block")
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_reflection_trajectories_match_oracle(mode):
+    """lambda started next to both walls with momenta pointing outwards, on a
+    bin edge, and exactly at hi: each walker reflects in its first steps
+    (lambda -> 2 hi - lambda or 2 lo - lambda, p -> -p); the GPU follows the
+    oracle within 1e-9 over 20 steps."""
+    spec, lam = synth.lj_reduced(n_walkers=4, lambda0=0.5)
+    lam.lambda0 = np.array([0.999, 0.001, 0.5, 1.0])
+    lam.p_lambda0 = np.array([6.0, -6.0, 0.3, 2.0])
+    lam.share_interval = 2
+    s = labf.System(spec, lam)
+    o = oracle.Oracle(spec, lam)
+    ost = o.init_state()
+    seen = np.zeros(4, bool)
+    for n in (1, 1, 3, 5, 10):
+        s.step(n, mode)
+        o.run(n)
+        st = s.read_walker_state()
+        c, s1, _ = s.read_abf_bins(True)
+        assert np.array_equal(c, ost["bin_count"] + ost["loc_count"].sum(0))
+        assert _rel(s1, ost["bin_sum"] + ost["loc_sum"].sum(0)) <= 1e-9
+        assert np.abs(st["lam"] - ost["lam"]).max() <= 1e-9, (st["lam"], ost["lam"])
+        assert _rel(st["p_lambda"], ost["p_lambda"]) <= 1e-9, (st["p_lambda"], ost["p_lambda"])
+        assert ((st["lam"] >= 0.0) & (st["lam"] <= 1.0)).all()
+        assert (st["status"] == 0).all(), st["status"]
+        seen |= np.sign(st["p_lambda"]) != np.sign(lam.p_lambda0)
+    # the two walls and lambda = hi reflected (the momentum turned inwards)
+    assert seen[0] and seen[1] and seen[3], seen
+    s.close()

@@ -307,6 +307,58 @@ def test_normals_have_unit_moments():
     assert abs((z ** 4).mean() - 3.0) < 0.1
 
 
+def test_normals_invert_to_their_philox_uniforms():
+    """Box-Muller maps the uniforms u1 = (a + 1) 2^-32 in (0, 1] and
+    u2 = b 2^-32 of the Philox output words (a, b) to a pair whose squared
+    radius is -2 ln u1 and whose angle is 2 pi u2: checked by inverting the
+    oracle's normals against the known-answer-pinned Philox words, so a
+    swapped pair, a dropped +1 or a wrong scale of either uniform fails."""
+    seed, w, step = 0x0123456789ABCDEF, 5, 17
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for atom in (0, 1, 2, 77, 4095, 0xFFFFFFFF):
+        words = oracle.philox4x32_10([atom, step, w, 0], key)
+        z = oracle.normals(seed, atom, step, w, 0)
+        for k in range(2):
+            a, b = int(words[2 * k]), int(words[2 * k + 1])
+            u1 = (a + 1) * 2.0 ** -32
+            u2 = b * 2.0 ** -32
+            z0, z1 = z[2 * k], z[2 * k + 1]
+            assert abs((z0 * z0 + z1 * z1) - (-2.0 * math.log(u1))) <= 1e-12 * max(1.0, -2.0 * math.log(u1))
+            ang = math.atan2(z1, z0) % (2.0 * math.pi)
+            d = abs(ang - 2.0 * math.pi * u2)
+            assert min(d, 2.0 * math.pi - d) <= 1e-9, (atom, k, ang, u2)
+
+
+def test_initial_velocities_are_maxwell_boltzmann():
+    """Initial atom velocities sample exp(-m v^2 / 2kT) per component (in
+    units where a force/mass factor a converts kcal/mol/A/amu: variance
+    kT a / m), and lambda momenta exp(-p^2 / 2 m_lambda kT): per-walker draws
+    differ, and the sample variances of 3 x 30,000 components (two masses)
+    and of 4,000 lambda momenta agree with those within 4 standard errors."""
+    spec, lam = synth.charged_lj(n_atoms=30000, precision="fp64")
+    spec, lamb = synth.batch(spec, lam, 2, seed=3)
+    o = oracle.Oracle(spec, lamb)
+    st = o.init_state()
+    v = st["v"]
+    m = np.asarray(spec.mass)
+    for mass in np.unique(m):
+        sel = v[m == mass]
+        want = spec.kT * spec.accel_unit / mass
+        got = float((sel * sel).mean())
+        se = want * math.sqrt(2.0 / sel.size)
+        assert abs(got - want) <= 4 * se + 1e-300, (mass, got, want)
+    n0 = spec.walker_slice(0).stop
+    assert not np.array_equal(v[:n0], v[n0:])
+    # lambda momenta: 4000 walkers of the 3-particle system
+    hs, hl = synth.harmonic(n_walkers=4000, seed=5)
+    oh = oracle.Oracle(hs, hl)
+    sh = oh.init_state()
+    p = sh["p_lambda"]
+    want = hl.m_lambda * hl.kT_lambda
+    assert abs(float((p * p).mean()) - want) <= 4 * want * math.sqrt(2.0 / p.size)
+    assert abs(float(p.mean())) <= 4 * math.sqrt(want / p.size)
+
+
 def test_units_standard_state_correction():
     (t, ratio, val, digits), = read_golden("units_standard_state.txt")
     corr = synth.KB_KCAL * float(t) * math.log(float(ratio))
@@ -326,6 +378,70 @@ def test_abf_readout_is_riemann_sum_of_bin_means():
     assert np.allclose(prof, np.concatenate([[0], np.cumsum(grad)[:-1]]) / n)
     count[3] = 0
     assert oracle.abf_readout(count, grad * count, 0.0, 1.0)[3] == -7
+
+
+def _bias_state(n_bins=10, full=100, W=2):
+    spec, lam = synth.harmonic(n_walkers=W)
+    lam.n_bins, lam.full_samples = n_bins, full
+    o = oracle.Oracle(spec, lam)
+    o.init_state()
+    z = dict(bin_count=np.zeros(n_bins, np.int64), bin_sum=np.zeros(n_bins),
+             loc_count=np.zeros((W, n_bins), np.int64), loc_sum=np.zeros((W, n_bins)))
+    return o, z
+
+
+def test_abf_bias_hand_computed_states():
+    """The bias force on lambda (the blue term of Eq. lambda-abf) for
+    constructed accumulator states, computed by hand: ramp(n) = min(1,
+    n / fullSamples) on the bin's combined count (shared + the walker's own
+    unshared samples), times that bin's mean; 0 for an empty bin.  A ramp
+    fixed at 1, an uncapped n / N_full, a mean over the shared samples only
+    or over another walker's deltas each fail one of these values."""
+    o, z = _bias_state()
+    # bin 3 (lambda in [0.3, 0.4)): 30 shared samples summing to 60
+    z["bin_count"][3], z["bin_sum"][3] = 30, 60.0
+    # walker 0 holds 20 unshared samples of bin 3 summing to 10; walker 1 none
+    z["loc_count"][0, 3], z["loc_sum"][0, 3] = 20, 10.0
+    # bin 7: 150 shared samples summing to -300 (beyond full_samples)
+    z["bin_count"][7], z["bin_sum"][7] = 150, -300.0
+    # bin 8: only walker 1's unshared samples, 250 of them summing to 500
+    z["loc_count"][1, 8], z["loc_sum"][1, 8] = 250, 500.0
+    o.load_state(**z)
+    # walker 1, bin 3: n = 30, ramp 0.3, mean 2        -> 0.6
+    assert o.abf_bias(1, 0.35) == pytest.approx(0.6, abs=1e-15)
+    # walker 0, bin 3: n = 50, ramp 0.5, mean 70/50    -> 0.7
+    assert o.abf_bias(0, 0.35) == pytest.approx(0.7, abs=1e-15)
+    # bin 7: n = 150 >= 100, ramp 1, mean -2           -> -2
+    assert o.abf_bias(0, 0.75) == pytest.approx(-2.0, abs=1e-15)
+    # bin 8: walker 1 sees its own 250 samples (mean 2) -> 2; walker 0 sees nothing -> 0
+    assert o.abf_bias(1, 0.85) == pytest.approx(2.0, abs=1e-15)
+    assert o.abf_bias(0, 0.85) == 0.0
+    # an empty bin, and lambda = hi falling into the last bin (empty)
+    assert o.abf_bias(0, 0.05) == 0.0 and o.abf_bias(1, 1.0) == 0.0
+    # exactly full_samples: ramp 1
+    z["bin_count"][5], z["bin_sum"][5] = 100, 25.0
+    o.load_state(**z)
+    assert o.abf_bias(0, 0.5) == pytest.approx(0.25, abs=1e-15)
+
+
+def test_abf_bias_drives_the_first_steps_as_constructed():
+    """One oracle step from a constructed accumulator: the lambda momentum
+    of a walker with dV/dlambda = 0 (no atoms interact, k0 = k1) and no
+    friction changes by exactly dt/2 times the hand-computed bias over the
+    opening half-kick, so the step uses the frozen state as constructed."""
+    spec, lam = synth.harmonic(n_walkers=1, k0=1.0, k1=1.0)
+    lam.n_bins, lam.full_samples, lam.gamma_lambda = 10, 100, 0.0
+    lam.lambda0, lam.p_lambda0 = np.array([0.35]), np.array([0.0])
+    o = oracle.Oracle(spec, lam)
+    o.init_state()
+    o.load_state(bin_count=np.array([0, 0, 0, 40, 0, 0, 0, 0, 0, 0], np.int64),
+                 bin_sum=np.array([0, 0, 0, 100.0, 0, 0, 0, 0, 0, 0]))
+    st = o.run(1)
+    bias = 0.4 * (100.0 / 40.0)          # ramp 40/100 times mean 2.5
+    assert st["bias"][0] == pytest.approx(bias, abs=1e-15)
+    assert st["dudl"][0] == 0.0
+    # p after B (h bias) and O with gamma_lambda = 0 (c1 = 1, no noise)
+    assert st["p_lambda"][0] == pytest.approx(0.5 * spec.dt * bias, rel=1e-14)
 
 
 def test_bin_edges():
