@@ -30,9 +30,16 @@
  *     otherwise; they are copied during the call and may be freed after it.
  *     Atom arrays are in the caller's original atom order, walker w owning
  *     atoms [atom_offset[w], atom_offset[w+1]).  Vectors are AoS [N][3].
- *   - The library owns its device memory (allocated in labf_create_system,
- *     released in labf_destroy_system).  Device work is asynchronous on the
- *     HIP stream passed in (NULL = default stream); calls that return host
+ *   - Device memory is the caller's: labf_workspace_size gives the bytes a
+ *     system needs, and labf_create_system lays out every device array of
+ *     the system inside the workspace the caller passes (a torch uint8
+ *     tensor, say).  The library allocates no device memory for a system
+ *     (only the test hooks labf_export_pairs, labf_philox and labf_probe
+ *     allocate their own staging, released before they return or with the
+ *     handle).  The workspace must stay allocated, and must not be touched by
+ *     the caller, until labf_destroy_system returns.  Device work is
+ *     asynchronous on the HIP stream passed in (NULL = default stream; the
+ *     Python binding passes torch's current stream); calls that return host
  *     data synchronise that stream.  A handle is not thread-safe.
  *   - Errors: every call returns a labf_status.  Argument errors are found on
  *     the host before any device work.  Numerical faults of a walker
@@ -137,6 +144,15 @@ typedef struct labf_system_desc {
                                   40, 48, 64, 72, 80, 96, 120, ...; else LABF_E_ARG); ignored
                                   (may be NULL) otherwise */
   double ewald_beta;           /* Ewald splitting parameter (1/length) > 0 when pme_order > 0 */
+  int32_t max_bins;            /* ABF bin capacity: labf_set_lambda_params accepts n_bins up to
+                                  this; 0: 1024; at most 4096 */
+  int32_t list_capacity;       /* neighbour-list entries per cluster, or 0: twice the longest list
+                                  estimated on the host from the initial positions plus headroom
+                                  (overflow later sets LABF_WS_CAPACITY); 16 .. 2^20 */
+  void *workspace;             /* DEVICE memory owned by the caller, 256-byte aligned, at least
+                                  labf_workspace_size bytes (labf_create_system only; ignored by
+                                  labf_workspace_size) */
+  size_t workspace_bytes;      /* its size in bytes */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF
@@ -163,15 +179,27 @@ typedef struct labf_lambda_params {
   double sc_shift;             /* delta of LABF_SC_SHIFTED (length^2, >= 0)       */
 } labf_lambda_params;
 
-/* Create a system: validates the descriptor on the host, allocates device
- * memory, uploads the atoms and builds the first neighbour list on `stream`.
- * On success *out receives the handle.  On failure *out is NULL and
- * labf_last_error(NULL) describes the error. */
+/* Bytes of device workspace a system of this descriptor needs (host
+ * arithmetic only, no device call: the walker layout, the PME tables, the
+ * neighbour-list capacity estimated from the initial positions, the ABF
+ * accumulators for max_bins bins).  Validates the descriptor like
+ * labf_create_system (the workspace fields are not read).  Errors:
+ * LABF_E_ARG. */
+labf_status labf_workspace_size(const labf_system_desc *desc, size_t *bytes);
+
+/* Create a system: validates the descriptor on the host, lays out the
+ * device arrays in desc->workspace (LABF_E_ARG if it is NULL, misaligned or
+ * smaller than labf_workspace_size), uploads the atoms and builds the first
+ * neighbour list on `stream`; allocates no device memory.  LABF_E_CAPACITY
+ * if the initial lists exceed the list capacity.  On success *out receives
+ * the handle.  On failure *out is NULL and labf_last_error(NULL) describes
+ * the error. */
 labf_status labf_create_system(const labf_system_desc *desc, void *stream, labf_system **out);
 
 /* Set lambda/ABF parameters and reset lambda state: lambda = lambda0,
  * p_lambda = p_lambda0 (or Maxwell-Boltzmann draws), ABF bins emptied, the
- * next step starts a fresh BAOAB sequence.  Required before stepping. */
+ * next step starts a fresh BAOAB sequence.  Required before stepping.
+ * n_bins must not exceed the system's max_bins (LABF_E_ARG). */
 labf_status labf_set_lambda_params(labf_system *sys, const labf_lambda_params *lp, void *stream);
 
 /* Advance every walker by n_steps >= 0 steps (asynchronous).  mode:
@@ -238,8 +266,9 @@ labf_status labf_set_distance_restraint(labf_system *sys, const int32_t *pairs, 
  * V(q; lambda) whose derivatives drive the dynamics and the ABF estimator;
  * "Alchemical pathway": the lambda-scaled soft-core LJ and shifted-force
  * Coulomb terms).  For automatic differentiation (a torch.autograd.Function
- * sits on top); nothing computed by labf_energy is kept for the backward
- * call, which recomputes every pair term.
+ * sits on top): the forward call evaluates energies only (no forces, no
+ * parameter gradient), and nothing it computes is kept for the backward
+ * call, whose own kernels recompute every pair term.
  *
  * Every array argument of these two calls is a DEVICE pointer on the
  * system's GPU, read and written in the order of `stream`; the caller owns
@@ -253,11 +282,14 @@ labf_status labf_set_distance_restraint(labf_system *sys, const int32_t *pairs, 
  *           validated (finite, epsilon >= 0, sigma > 0 where epsilon > 0;
  *           LABF_E_ARG otherwise, nothing changed)
  * The given values replace the system's (velocities, lambda momenta and the
- * ABF accumulators are kept) and the neighbour structure is rebuilt
- * (positions given: without the list-validity check).
+ * ABF accumulators are kept).  The neighbour structure is rebuilt when pos
+ * or params are given or the atoms have moved since the last rebuild
+ * (positions given: without the list-validity check); a backward call
+ * with NULL pos and params after a forward call reuses the forward's lists.
  *
- * labf_energy: energy[W] = total potential energy of each walker (FP64
- *   sums; environment pair terms in the storage precision).
+ * labf_energy_forward: energy[W] = total potential energy of each walker
+ *   (FP64 sums; environment pair terms in the storage precision); dudl[W]
+ *   = dV/dlambda of each walker (or NULL).
  * labf_energy_backward: for the upstream gradient grad_energy[W] = dL/dV_w,
  *   grad_pos[N][3]    = g_w dV_w/dx_a = -g_w F_a      (or NULL)
  *   grad_lambda[W]    = g_w dV_w/dlambda_w             (or NULL)
@@ -266,8 +298,8 @@ labf_status labf_set_distance_restraint(labf_system *sys, const int32_t *pairs, 
  * A non-finite position gives non-finite outputs and walker status bit 1.
  * Errors: LABF_E_STATE before labf_set_lambda_params; LABF_E_ARG for NULL
  * energy / grad_energy or invalid params. */
-labf_status labf_energy(labf_system *sys, const double *pos, const double *lambda,
-                        const double *params, double *energy, void *stream);
+labf_status labf_energy_forward(labf_system *sys, const double *pos, const double *lambda,
+                                const double *params, double *energy, double *dudl, void *stream);
 labf_status labf_energy_backward(labf_system *sys, const double *pos, const double *lambda,
                                  const double *params, const double *grad_energy,
                                  double *grad_pos, double *grad_lambda, double *grad_params,

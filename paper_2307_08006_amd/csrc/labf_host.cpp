@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -82,6 +84,7 @@ struct labf_system {
   int interval = 10;
   bool lam_set = false;
   bool xref_valid = false;
+  bool list_current = false;      // the list was built at the current positions
   int xb = 0, vb = 0, lb = 0;
   int since_rebuild = 0;
   int64_t host_steps = 0;
@@ -98,8 +101,10 @@ struct labf_system {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, pme_ev = nullptr;
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
-  DevBufs bufs;
-  DevBufs item_bufs;
+  int max_bins = 0;
+  void *workspace = nullptr;      // caller-owned device memory holding every array
+  size_t workspace_bytes = 0;
+  DevBufs hook_bufs;              // staging of the pair-export test hook (allocated by that call)
   Dev<float> df{};
   Dev<double> dd{};
   std::string err;
@@ -109,7 +114,7 @@ struct labf_system {
   double *lam_stage = nullptr;   // [2W]
   int64_t *pairs_dev = nullptr;
   int64_t pairs_cap = 0;
-  int32_t *dr_partner_dev = nullptr;  // distance-restraint tables (allocated on first use)
+  int32_t *dr_partner_dev = nullptr;  // distance-restraint tables (in the workspace)
   int32_t *dr_pair_dev = nullptr;
 
   template <typename T>
@@ -278,6 +283,9 @@ labf_status validate_desc(const labf_system_desc *d) {
       !(d->accel_unit > 0))
     return fail(nullptr, LABF_E_ARG, "scalar parameter out of range");
   if (d->rebuild_interval < 1 || d->rebuild_interval > 1000) return fail(nullptr, LABF_E_ARG, "rebuild_interval out of range");
+  if (d->max_bins < 0 || d->max_bins > 4096) return fail(nullptr, LABF_E_ARG, "max_bins must be 0 (1024) or 1..4096");
+  if (d->list_capacity != 0 && (d->list_capacity < 16 || d->list_capacity > (1 << 20)))
+    return fail(nullptr, LABF_E_ARG, "list_capacity must be 0 (estimated) or 16..2^20");
   if (d->column_width)
     for (int w = 0; w < d->n_walkers; ++w)
       if (!(d->column_width[w] >= 0.5 && d->column_width[w] <= 2.0))
@@ -337,34 +345,546 @@ labf_status validate_lambda(const labf_system *s, const labf_lambda_params *p) {
 }
 
 // --- layout -------------------------------------------------------------------
+// Creating a system has three parts:
+//   plan  (host only): walker metadata, static tables, PME tables, the list
+//         capacity (estimated from the initial positions) and every array size;
+//   carve: pointers into the caller's workspace, 256-byte aligned, in a fixed
+//         order (with no workspace: only the total is summed, which is what
+//         labf_workspace_size returns);
+//   init  (device, on the caller's stream): clear, upload, first rebuild.
+// No device memory is allocated by the library for a system.
+
+// Bump allocator over the workspace; base == nullptr only sums the sizes.
+struct Carver {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename P>
+  void take(P **p, size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    if (p) *p = base ? (P *)(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(P);
+  }
+};
+
+// Everything about a system that the host computes before any device work.
+struct HostLayout {
+  int W = 0;
+  int64_t N = 0, C = 0, S = 0, K = 0, E = 0, I = 0;
+  int list_cap = 0, max_bins = 0;
+  bool uniform = true;
+  double u_sig = 1.0, u_eps = 0.0;
+  std::vector<WalkerMeta> meta;
+  std::vector<uint8_t> alch, sol;
+  std::vector<double> pos_grid, anc_grid;
+  std::vector<int32_t> atom_walker, cl_walker, env_table, col_walker, solute_atom;
+  std::vector<int32_t> item_walker, alch_cluster, slot0, orig0;
+  // smooth PME
+  std::vector<PmeWalker> pme;
+  int64_t pme_goff = 0, pme_toff = 0, pme_loff = 0;
+  int32_t pme_nbr = 0, pme_npl = 0, pme_maxyz = 0;
+  int32_t pme_nblk[3] = {0, 0, 0}, pme_nblk2[3] = {0, 0, 0}, pme_planes2 = 0;
+  std::vector<int32_t> pme_bw[3], pme_brw, pme_plw, pme_perm;
+};
+
+double gap1h(double lo_i, double hi_i, double lo_j, double hi_j) {
+  return std::max(0.0, std::max(lo_j - hi_i, lo_i - hi_j));
+}
+
+// Upper estimate of the longest neighbour lists of the initial positions,
+// from the cluster layout the rebuild produces (x-y columns of width cw,
+// each sorted by z and cut into clusters of CL atoms; one cluster per
+// alchemical atom): for a cluster box, every cluster of the columns and
+// periodic images in reach whose z range comes within the list radius,
+// with the column rectangle standing in for the other cluster's x-y extent
+// (never below what the device list holds for the same positions).
+// Returns {longest environment list, longest alchemical list}.
+std::pair<int, int> estimate_lists(const HostLayout &h, double rl, double rla) {
+  int mx_env = 0, mx_a = 0;
+  for (int w = 0; w < h.W; ++w) {
+    const WalkerMeta &m = h.meta[w];
+    const int ncol = m.ncx * m.ncy;
+    std::vector<std::vector<std::pair<double, int64_t>>> cols(ncol);
+    std::vector<std::array<double, 3>> apos;
+    for (int64_t i = m.atom_begin; i < m.atom_begin + m.n_atoms; ++i) {
+      const double x = h.pos_grid[3 * i] - m.B[0], y = h.pos_grid[3 * i + 1] - m.B[1],
+                   z = h.pos_grid[3 * i + 2] - m.B[2];
+      if (h.alch[i]) {
+        apos.push_back({x, y, z});
+        continue;
+      }
+      const int cx = (int)std::min(std::max(std::floor(x / m.cw[0]), 0.0), (double)(m.ncx - 1));
+      const int cy = (int)std::min(std::max(std::floor(y / m.cw[1]), 0.0), (double)(m.ncy - 1));
+      cols[cx * m.ncy + cy].push_back({z, i});
+    }
+    // cluster boxes per column (z ranges sorted)
+    std::vector<std::vector<std::array<double, 6>>> box(ncol);
+    std::vector<std::vector<double>> zlo(ncol), zhi(ncol);
+    for (int c = 0; c < ncol; ++c) {
+      auto &v = cols[c];
+      std::sort(v.begin(), v.end());
+      for (size_t k = 0; k < v.size(); k += CL) {
+        std::array<double, 6> b = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+        for (size_t t = k; t < std::min(v.size(), k + CL); ++t) {
+          const int64_t i = v[t].second;
+          for (int q = 0; q < 3; ++q) {
+            const double p = h.pos_grid[3 * i + q] - m.B[q];
+            b[q] = std::min(b[q], p);
+            b[3 + q] = std::max(b[3 + q], p);
+          }
+        }
+        box[c].push_back(b);
+        zlo[c].push_back(b[2]);
+        zhi[c].push_back(b[5]);
+      }
+    }
+    const int nx = (int)std::ceil(rla / m.cw[0]) + 1, ny = (int)std::ceil(rla / m.cw[1]) + 1;
+    // clusters of the columns in reach of box b within radius r
+    auto count = [&](const std::array<double, 6> &b, double r) {
+      int64_t n = 0;
+      const double r2 = r * r;
+      for (int dx = -nx; dx <= nx; ++dx)
+        for (int dy = -ny; dy <= ny; ++dy) {
+          const int cx0 = (int)std::floor(b[0] / m.cw[0]), cy0 = (int)std::floor(b[1] / m.cw[1]);
+          const int rx = cx0 + dx, ry = cy0 + dy;
+          const int cx = ((rx % m.ncx) + m.ncx) % m.ncx, cy = ((ry % m.ncy) + m.ncy) % m.ncy;
+          const int sx = (rx - cx) / m.ncx, sy = (ry - cy) / m.ncy;
+          if (sx < -1 || sx > 1 || sy < -1 || sy > 1) continue;
+          const double xl = rx * m.cw[0], xh = (rx + 1) * m.cw[0];
+          const double yl = ry * m.cw[1], yh = (ry + 1) * m.cw[1];
+          const double gx = gap1h(b[0], b[3], xl, xh), gy = gap1h(b[1], b[4], yl, yh);
+          const double gxy = gx * gx + gy * gy;
+          if (gxy >= r2) continue;
+          const double dz = std::sqrt(r2 - gxy);
+          const int c = cx * m.ncy + cy;
+          for (int sz = -1; sz <= 1; ++sz) {
+            const double lo = b[2] - dz - sz * m.L[2], hi = b[5] + dz - sz * m.L[2];
+            // clusters with zhi >= lo and zlo <= hi
+            const auto a0 = std::lower_bound(zhi[c].begin(), zhi[c].end(), lo) - zhi[c].begin();
+            const auto a1 = std::upper_bound(zlo[c].begin(), zlo[c].end(), hi) - zlo[c].begin();
+            if (a1 > a0) n += a1 - a0;
+          }
+        }
+      return n;
+    };
+    auto count_alch = [&](const std::array<double, 6> &b, double r) {
+      int64_t n = 0;
+      for (const auto &p : apos)
+        for (int t = 0; t < 27; ++t) {
+          const double ox = (t / 9 - 1) * m.L[0], oy = ((t / 3) % 3 - 1) * m.L[1], oz = (t % 3 - 1) * m.L[2];
+          const double gx = gap1h(b[0], b[3], p[0] + ox, p[0] + ox), gy = gap1h(b[1], b[4], p[1] + oy, p[1] + oy),
+                       gz = gap1h(b[2], b[5], p[2] + oz, p[2] + oz);
+          if (gx * gx + gy * gy + gz * gz < r * r) ++n;
+        }
+      return n;
+    };
+    for (int c = 0; c < ncol; ++c)
+      for (const auto &b : box[c])
+        mx_env = (int)std::max<int64_t>(mx_env, count(b, rl) + count_alch(b, rla));
+    for (const auto &p : apos) {
+      const std::array<double, 6> b = {p[0], p[1], p[2], p[0], p[1], p[2]};
+      mx_a = (int)std::max<int64_t>(mx_a, count(b, rla) + count_alch(b, rla));
+    }
+  }
+  return {mx_env, mx_a};
+}
+
+// The host part of creating a system (no device work).
 template <typename T>
-labf_status alloc_items(labf_system *s) {
-  Dev<T> &d = s->dev<T>();
-  s->item_bufs.release();
-  std::vector<int32_t> item_walker, alch_cluster;
+labf_status plan_system(const labf_system_desc *desc, HostLayout &h) {
+  const int W = desc->n_walkers;
+  const int64_t N = desc->atom_offset[W];
+  h.W = W;
+  h.N = N;
+  h.max_bins = desc->max_bins > 0 ? desc->max_bins : 1024;
+  // alchemical set: solute atoms and atoms with a lambda-dependent restraint
+  h.alch.resize(N);
+  h.sol.resize(N);
+  for (int64_t i = 0; i < N; ++i) {
+    h.sol[i] = desc->is_solute[i];
+    h.alch[i] = desc->is_solute[i] || (desc->anchor && desc->k0[i] != desc->k1[i]);
+  }
+  // uniform environment LJ parameters?
+  bool first = true;
+  for (int64_t i = 0; i < N && h.uniform; ++i) {
+    if (h.alch[i]) continue;
+    if (first) {
+      h.u_sig = desc->sigma[i];
+      h.u_eps = desc->epsilon[i];
+      first = false;
+    } else if (desc->sigma[i] != h.u_sig || desc->epsilon[i] != h.u_eps) {
+      h.uniform = false;
+    }
+  }
+  if (h.u_eps == 0.0) h.u_sig = 1.0;
+  // per-walker metadata
+  h.meta.resize(W);
+  h.pos_grid.resize(3 * N);
+  if (desc->anchor) h.anc_grid.resize(3 * N);
+  int64_t cl = 0, col = 0, env = 0;
+  const double rla = desc->r_cut + std::max(desc->r_skin, desc->r_skin_alch);
+  for (int w = 0; w < W; ++w) {
+    WalkerMeta &m = h.meta[w];
+    std::memset(&m, 0, sizeof(m));
+    m.atom_begin = desc->atom_offset[w];
+    m.n_atoms = (int32_t)(desc->atom_offset[w + 1] - desc->atom_offset[w]);
+    int64_t na = 0;
+    for (int64_t i = m.atom_begin; i < m.atom_begin + m.n_atoms; ++i) na += h.alch[i];
+    m.n_a = (int32_t)na;
+    const int64_t nenv = m.n_atoms - na;
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      const double L0 = desc->box[3 * w + k];
+      m.B[k] = pow2_at_least(2.0 * L0);
+      m.L[k] = grid_edge<T>(L0, m.B[k]);
+      if (!(rla < 0.5 * m.L[k])) return fail(nullptr, LABF_E_ARG, "r_list >= L/2 after rounding the box");
+      vol *= m.L[k];
+    }
+    const double rho = (double)std::max<int64_t>(nenv, 1) / vol;
+    const double target = std::cbrt((double)CL / rho) * (desc->column_width ? desc->column_width[w] : 1.0);
+    m.ncx = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[0] / target)));
+    m.ncy = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[1] / target)));
+    m.cw[0] = m.L[0] / m.ncx;
+    m.cw[1] = m.L[1] / m.ncy;
+    m.cap_env = (int32_t)((nenv + CL - 1) / CL + (int64_t)m.ncx * m.ncy);
+    m.n_acl = (int32_t)na;  // one alchemical atom per cluster
+    m.cl_begin = cl;
+    m.col_begin = (int32_t)col;
+    m.env_item_begin = (int32_t)env;
+    cl += (int64_t)m.cap_env + m.n_acl;
+    col += (int64_t)m.ncx * m.ncy + 1;
+    env += m.cap_env;
+    for (int64_t i = m.atom_begin; i < m.atom_begin + m.n_atoms; ++i)
+      for (int k = 0; k < 3; ++k) {
+        h.pos_grid[3 * i + k] = grid_pos<T>(desc->pos[3 * i + k], m.L[k], m.B[k]);
+        if (desc->anchor) h.anc_grid[3 * i + k] = grid_pos<T>(desc->anchor[3 * i + k], m.L[k], m.B[k]);
+      }
+  }
+  if (cl >= (int64_t)CL_MASK) return fail(nullptr, LABF_E_UNSUPPORTED, "too many clusters");
+  h.C = cl;
+  h.S = cl * CL;
+  h.K = col;
+  h.E = env;
+  // static tables
+  h.atom_walker.resize(N);
+  h.cl_walker.resize(h.C);
+  h.env_table.resize(h.E);
+  h.col_walker.resize(h.K);
+  for (int w = 0; w < W; ++w) {
+    const WalkerMeta &m = h.meta[w];
+    for (int64_t i = 0; i < m.n_atoms; ++i) h.atom_walker[m.atom_begin + i] = w;
+    for (int64_t c = 0; c < (int64_t)m.cap_env + m.n_acl; ++c) h.cl_walker[m.cl_begin + c] = w;
+    for (int64_t c = 0; c < m.cap_env; ++c) h.env_table[m.env_item_begin + c] = (int32_t)(m.cl_begin + c);
+    for (int64_t k = m.col_begin; k < (int64_t)m.col_begin + (int64_t)m.ncx * m.ncy + 1; ++k) h.col_walker[k] = w;
+  }
+  for (int64_t i = 0; i < N; ++i)
+    if (h.sol[i]) h.solute_atom.push_back((int32_t)i);
+  // alchemical blocks: one per alchemical atom (a walker without any still
+  // gets one block, which runs its lambda tail)
   int64_t ib = 0;
-  for (int w = 0; w < s->W; ++w) {
-    WalkerMeta &m = s->meta[w];
+  for (int w = 0; w < W; ++w) {
+    WalkerMeta &m = h.meta[w];
     m.item_begin = (int32_t)ib;
     m.item_cap = std::max(1, m.n_acl);
     for (int t = 0; t < m.item_cap; ++t) {
-      item_walker.push_back(w);
-      alch_cluster.push_back(t < m.n_acl ? (int32_t)(m.cl_begin + m.cap_env + t) : -1);
+      h.item_walker.push_back(w);
+      h.alch_cluster.push_back(t < m.n_acl ? (int32_t)(m.cl_begin + m.cap_env + t) : -1);
     }
     ib += m.item_cap;
   }
-  if (ib > 0x7FFFFFF0LL) return fail(s, LABF_E_UNSUPPORTED, "too many alchemical atoms");
-  s->I = ib;
-  HIPCHK(s, upload(s->item_bufs, &d.item_walker, item_walker.data(), item_walker.size()));
-  HIPCHK(s, upload(s->item_bufs, &d.alch_cluster, alch_cluster.data(), alch_cluster.size()));
-  HIPCHK(s, dalloc(s->item_bufs, &d.item_force, (size_t)ib * 3));
-  HIPCHK(s, dalloc(s->item_bufs, &d.item_dudl, (size_t)ib));
-  HIPCHK(s, dalloc(s->item_bufs, &d.item_energy, (size_t)ib * 5));
-  HIPCHK(s, dalloc(s->item_bufs, &d.item_pgrad, (size_t)ib * 3));
-  HIPCHK(s, dalloc(s->item_bufs, &d.list, (size_t)s->C * s->list_cap));
-  // metadata changed (item ranges)
-  HIPCHK(s, hipMemcpy((void *)d.meta, s->meta.data(), sizeof(WalkerMeta) * s->W, hipMemcpyHostToDevice));
-  d.list_cap = s->list_cap;
+  if (ib > 0x7FFFFFF0LL) return fail(nullptr, LABF_E_UNSUPPORTED, "too many alchemical atoms");
+  h.I = ib;
+  // initial layout: atom i of walker w in slot cl_begin*8 + i; slot -> walker-local atom
+  h.slot0.resize(N);
+  h.orig0.assign(h.S, -1);
+  for (int w = 0; w < W; ++w)
+    for (int64_t i = 0; i < h.meta[w].n_atoms; ++i) {
+      const int32_t sl = (int32_t)(h.meta[w].cl_begin * CL + i);
+      h.slot0[h.meta[w].atom_begin + i] = sl;
+      h.orig0[sl] = (int32_t)i;
+    }
+  // smooth PME: per-walker grids, FFT block tables, influence-function tables
+  if (desc->pme_order) {
+    h.pme.resize(W);
+    int64_t goff = 0, toff = 0, loff = 0;
+    int32_t nbr = 0, npl = 0, maxyz = 0;
+    for (int w = 0; w < W; ++w) {
+      PmeWalker &p = h.pme[w];
+      std::memset(&p, 0, sizeof(p));
+      for (int a = 0; a < 3; ++a) {
+        p.K[a] = desc->pme_dims[3 * w + a];
+        const int32_t K = p.K[a];
+        if ((K & (K - 1)) == 0) {
+          while ((1 << p.lg[a]) < K) ++p.lg[a];
+        } else {
+          // mixed-radix stage plan: fives, threes, fours, a last two
+          p.lg[a] = -1;
+          int32_t rest = K, ns = 0;
+          for (int r : {5, 3, 4, 2})
+            while (rest % r == 0) {
+              p.rad[a][ns++] = (int8_t)r;
+              rest /= r;
+            }
+          p.nst[a] = ns;
+        }
+      }
+      // y and z transforms: fused per y-z plane in LDS when the plane fits
+      // (no y or z line blocks then), else line by line
+      const bool plane = p.K[1] * p.K[2] <= PME_PLANE;
+      // lines per FFT block: the largest divisor of the number of lines
+      // taken together that fills at most one tile
+      auto max_div = [](int64_t cap, int64_t n) {
+        int32_t q = (int32_t)std::min(cap, n);
+        while (n % q) --q;
+        return q;
+      };
+      p.nl[2] = max_div(PME_TILE / p.K[2], (int64_t)p.K[0] * p.K[1]);
+      p.nl[1] = max_div(PME_TILE / p.K[1], p.K[2]);
+      p.nl[0] = max_div(PME_TILE / p.K[0], p.K[2]);
+      p.blk[2] = plane ? 0 : p.K[0] * p.K[1] / p.nl[2];
+      p.blk[1] = plane ? 0 : p.K[0] * (p.K[2] / p.nl[1]);
+      p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
+      // spread bricks; list capacity: three times the mean atom count of a
+      // brick plus 64 (overflow is flagged in the walker status)
+      const int32_t nb = (p.K[0] / PME_BR) * (p.K[1] / PME_BR) * (p.K[2] / PME_BR);
+      for (int a = 0; a < 3; ++a) p.nbr[a] = p.K[a] / PME_BR;
+      p.br_begin = nbr;
+      nbr += nb;
+      h.pme_brw.insert(h.pme_brw.end(), (size_t)nb, w);
+      p.br_cap = (int32_t)(((3 * (int64_t)h.meta[w].n_atoms) / nb + 64 + 31) / 32 * 32);
+      p.loff = loff;
+      loff += (int64_t)nb * p.br_cap;
+      if (plane) maxyz = std::max(maxyz, p.K[1] * p.K[2]);
+      p.goff = goff;
+      goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
+      p.toff = toff;
+      toff += p.K[0] + p.K[1] + p.K[2];
+      const WalkerMeta &m = h.meta[w];
+      p.pref = desc->coulomb_k / (3.14159265358979323846 * m.L[0] * m.L[1] * m.L[2]);
+    }
+    // FFT blocks and y-z planes: walkers whose three grid lengths are powers
+    // of two first (their own kernel instantiations), then the others
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int w = 0; w < W; ++w) {
+        PmeWalker &p = h.pme[w];
+        if (pme_pow2(p) != (pass == 0)) continue;
+        for (int a = 0; a < 3; ++a) {
+          p.blk_begin[a] = h.pme_nblk[a];
+          h.pme_nblk[a] += p.blk[a];
+          h.pme_bw[a].insert(h.pme_bw[a].end(), (size_t)p.blk[a], w);
+        }
+        p.pl_begin = npl;
+        if (p.blk[1] == 0) {
+          npl += p.K[0];
+          h.pme_plw.insert(h.pme_plw.end(), (size_t)p.K[0], w);
+        }
+      }
+      if (pass == 0) {
+        for (int a = 0; a < 3; ++a) h.pme_nblk2[a] = h.pme_nblk[a];
+        h.pme_planes2 = npl;
+      }
+    }
+    // frequency index at each position of a forward transform: with the
+    // radices r_1 .. r_n of the decimation-in-frequency stages, position
+    // p = j_1 m_1 + p' (m_1 = K / r_1) holds frequency j_1 + r_1 f(p')
+    // (bit reversal for radix 2)
+    h.pme_perm.resize(toff);
+    for (int w = 0; w < W; ++w) {
+      const PmeWalker &p = h.pme[w];
+      int64_t o = p.toff;
+      for (int a = 0; a < 3; ++a) {
+        const int32_t K = p.K[a];
+        std::vector<int32_t> rads;
+        if (p.lg[a] >= 0) rads.assign((size_t)p.lg[a], 2);
+        else rads.assign(p.rad[a], p.rad[a] + p.nst[a]);
+        for (int32_t pos = 0; pos < K; ++pos) {
+          int32_t rem = pos, len = K, mult = 1, f = 0;
+          for (int32_t r : rads) {
+            const int32_t mm = len / r, j = rem / mm;
+            rem -= j * mm;
+            f += j * mult;
+            mult *= r;
+            len = mm;
+          }
+          h.pme_perm[o + pos] = f;
+        }
+        o += K;
+      }
+    }
+    h.pme_goff = goff;
+    h.pme_toff = toff;
+    h.pme_loff = loff;
+    h.pme_nbr = nbr;
+    h.pme_npl = npl;
+    h.pme_maxyz = maxyz;
+  }
+  // neighbour-list capacity: the given one, or twice the estimated longest
+  // environment list plus 64 and three times the longest alchemical one plus
+  // 128 (headroom for denser regions and larger cluster boxes once the
+  // configuration relaxes; overflow is flagged in the walker status)
+  if (desc->list_capacity > 0) {
+    h.list_cap = desc->list_capacity;
+  } else {
+    const auto mx = estimate_lists(h, desc->r_cut + desc->r_skin, rla);
+    h.list_cap = std::max({128, (2 * mx.first + 64 + 31) / 32 * 32, (3 * mx.second + 128 + 31) / 32 * 32});
+  }
+  return LABF_OK;
+}
+
+// Device arrays of a system, in a fixed order (count or assign).
+template <typename T>
+void carve(const HostLayout &h, labf_system *s, Dev<T> &d, Carver &cv) {
+  const int64_t N = h.N, S = h.S, C = h.C, W = h.W, K = h.K;
+  const WalkerMeta *meta = nullptr;
+  cv.take(&meta, W);
+  d.meta = meta;
+  int32_t *p32 = nullptr;
+  cv.take(&p32, N);
+  d.atom_walker = p32;
+  cv.take(&p32, C);
+  d.cl_walker = p32;
+  cv.take(&p32, h.E);
+  d.env_table = p32;
+  cv.take(&p32, K);
+  d.col_walker = p32;
+  cv.take(&p32, h.I);
+  d.item_walker = p32;
+  cv.take(&p32, h.I);
+  d.alch_cluster = p32;
+  cv.take(&p32, h.solute_atom.size());
+  d.solute_atom = p32;
+  cv.take(&d.a_q, N);
+  cv.take(&d.a_sig, N);
+  cv.take(&d.a_eps, N);
+  double *p64 = nullptr;
+  cv.take(&p64, N);
+  d.a_mass = p64;
+  uint8_t *p8 = nullptr;
+  cv.take(&p8, N);
+  d.a_sol = p8;
+  cv.take(&p8, N);
+  d.a_alch = p8;
+  if (!h.anc_grid.empty()) {
+    cv.take(&p64, N);
+    d.a_k0 = p64;
+    cv.take(&p64, N);
+    d.a_k1 = p64;
+    cv.take(&p64, 3 * N);
+    d.a_anchor = p64;
+  } else {
+    d.a_k0 = d.a_k1 = d.a_anchor = nullptr;
+  }
+  if (!h.pme.empty()) {
+    const PmeWalker *pw = nullptr;
+    cv.take(&pw, W);
+    d.pme = pw;
+    for (int a = 0; a < 3; ++a) {
+      cv.take(&p32, h.pme_bw[a].size());
+      d.pme_bw[a] = p32;
+    }
+    cv.take(&d.pme_grid, h.pme_goff);
+    cv.take(&p32, h.pme_brw.size());
+    d.pme_brw = p32;
+    cv.take(&d.pme_bcnt, h.pme_nbr);
+    cv.take(&d.pme_blist, h.pme_loff);
+    if (h.pme_npl > 0) {
+      cv.take(&p32, h.pme_plw.size());
+      d.pme_plw = p32;
+    } else {
+      d.pme_plw = nullptr;
+    }
+    cv.take(&p64, 2 * h.pme_toff);
+    d.pme_tab = p64;
+    cv.take(&p32, h.pme_perm.size());
+    d.pme_perm = p32;
+    cv.take(&d.pme_frc, 3 * S);
+    cv.take(&d.pme_phi, 2 * S);
+    cv.take(&d.pme_qs, 4 * W);
+    float4 *ew = nullptr;
+    cv.take(&ew, 2 * EWTAB_N);
+    d.ewtab = ew;
+  }
+  cv.take(&d.slot_of, N);
+  cv.take(&d.new_slot, N);
+  cv.take(&d.col_of, N);
+  cv.take(&d.key_col, N);
+  cv.take(&d.members, N);
+  cv.take(&d.xref, 3 * N);
+  cv.take(&d.disp, N);
+  cv.take(&d.skin_part, (size_t)W * SKIN_PARTS * 4);
+  cv.take(&d.col_count, K);
+  cv.take(&d.col_fill, K);
+  cv.take(&d.col_atom0, K);
+  cv.take(&d.col_cl0, K);
+  for (int u = 0; u < 2; ++u)
+    for (int k = 0; k < 3; ++k) {
+      cv.take(&d.X[u][k], S);
+      cv.take(&d.V[u][k], S);
+    }
+  cv.take(&d.q, S);
+  cv.take(&d.lja, S);
+  cv.take(&d.ljb, S);
+  cv.take(&d.aim, S);
+  cv.take(&d.nsd, S);
+  cv.take(&d.rk, S);
+  for (int k = 0; k < 3; ++k) cv.take(&d.anc[k], S);
+  cv.take(&d.q64, S);
+  cv.take(&d.sig64, S);
+  cv.take(&d.eps64, S);
+  cv.take(&d.k0_64, S);
+  cv.take(&d.k1_64, S);
+  cv.take(&d.sol, S);
+  cv.take(&d.orig, S);
+  cv.take(&d.fout, 3 * S);
+  cv.take(&d.bbox, 6 * C);
+  cv.take(&d.cl_col, C);
+  cv.take(&d.list_count, C);
+  cv.take(&d.list_nenv, C);
+  cv.take(&d.cl_energy, 2 * C);
+  cv.take(&d.list, (size_t)C * h.list_cap);
+  cv.take(&d.item_force, (size_t)h.I * 3);
+  cv.take(&d.item_dudl, (size_t)h.I);
+  cv.take(&d.item_energy, (size_t)h.I * 5);
+  cv.take(&d.item_pgrad, (size_t)h.I * 3);
+  cv.take(&d.n_env, W);
+  cv.take(&d.ticket, W);
+  cv.take(&d.gticket, 1);
+  cv.take(&d.status, W);
+  cv.take(&d.lambda, 2 * W);
+  cv.take(&d.p_lambda, W);
+  cv.take(&d.dudl, W);
+  cv.take(&d.bias, W);
+  cv.take(&d.step, 2 * W);
+  cv.take(&d.start_step, 1);
+  cv.take(&d.energy, 5 * W);
+  cv.take(&d.pair_n, 2 * W);
+  // ABF accumulators, sized for max_bins
+  cv.take(&d.bin_count, h.max_bins);
+  cv.take(&d.bin_sum, h.max_bins);
+  cv.take(&d.bin_sum2, h.max_bins);
+  cv.take(&d.loc_count, (size_t)h.max_bins * W);
+  cv.take(&d.loc_sum, (size_t)h.max_bins * W);
+  cv.take(&d.loc_sum2, (size_t)h.max_bins * W);
+  // distance-restraint tables (used once a restraint is set)
+  cv.take(&s->dr_partner_dev, N);
+  cv.take(&s->dr_pair_dev, 2 * W);
+  // host <-> device staging
+  cv.take(&s->stage, 3 * N);
+  cv.take(&s->stage2, 3 * N);
+  cv.take(&s->lam_stage, 2 * W);
+}
+
+// Bytes of workspace a system needs (host computation only).
+template <typename T>
+labf_status workspace_bytes(const labf_system_desc *desc, size_t *bytes, HostLayout *keep) {
+  HostLayout local;
+  HostLayout &h = keep ? *keep : local;
+  labf_status rc = plan_system<T>(desc, h);
+  if (rc != LABF_OK) return rc;
+  labf_system tmp;
+  Dev<T> d{};
+  Carver cv;
+  carve<T>(h, &tmp, d, cv);
+  *bytes = (cv.off + 255) & ~(size_t)255;
   return LABF_OK;
 }
 
@@ -381,6 +901,7 @@ labf_status do_rebuild(labf_system *s, int mode, hipStream_t st) {
   s->vb ^= 1;
   s->xref_valid = true;
   s->since_rebuild = 0;
+  s->list_current = true;
   return LABF_OK;
 }
 
@@ -465,91 +986,54 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
 template <typename T>
 labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_system *s) {
   Dev<T> &d = s->dev<T>();
-  const int W = desc->n_walkers;
-  const int64_t N = desc->atom_offset[W];
+  HostLayout h;
+  size_t need = 0;
+  labf_status rc = workspace_bytes<T>(desc, &need, &h);
+  if (rc != LABF_OK) return rc;
+  if (!desc->workspace) return fail(nullptr, LABF_E_ARG, "workspace is NULL (labf_workspace_size gives its size)");
+  if ((uintptr_t)desc->workspace % 256 != 0) return fail(nullptr, LABF_E_ARG, "workspace must be 256-byte aligned");
+  if (desc->workspace_bytes < need)
+    return fail(nullptr, LABF_E_ARG,
+                "workspace too small: " + std::to_string(desc->workspace_bytes) + " bytes given, " +
+                    std::to_string(need) + " needed");
+  const int W = h.W;
+  const int64_t N = h.N;
   s->W = W;
   s->N = N;
+  s->C = h.C;
+  s->S = h.S;
+  s->K = h.K;
+  s->E = h.E;
+  s->I = h.I;
   s->interval = desc->rebuild_interval;
   s->atom_offset.assign(desc->atom_offset, desc->atom_offset + W + 1);
-  // alchemical set: solute atoms and atoms with a lambda-dependent restraint
-  std::vector<uint8_t> alch(N), sol(N);
-  for (int64_t i = 0; i < N; ++i) {
-    sol[i] = desc->is_solute[i];
-    alch[i] = desc->is_solute[i] || (desc->anchor && desc->k0[i] != desc->k1[i]);
+  s->meta = h.meta;
+  s->pme = h.pme;
+  for (int a = 0; a < 3; ++a) {
+    s->pme_nblk[a] = h.pme_nblk[a];
+    s->pme_nblk2[a] = h.pme_nblk2[a];
   }
-  // uniform environment LJ parameters?
-  bool uniform = true;
-  double u_sig = 1.0, u_eps = 0.0;
-  bool first = true;
-  for (int64_t i = 0; i < N && uniform; ++i) {
-    if (alch[i]) continue;
-    if (first) {
-      u_sig = desc->sigma[i];
-      u_eps = desc->epsilon[i];
-      first = false;
-    } else if (desc->sigma[i] != u_sig || desc->epsilon[i] != u_eps) {
-      uniform = false;
-    }
-  }
-  if (u_eps == 0.0) u_sig = 1.0;
-  // per-walker metadata
-  s->meta.resize(W);
-  std::vector<double> pos_grid(3 * N), anc_grid;
-  if (desc->anchor) anc_grid.resize(3 * N);
-  int64_t cl = 0, col = 0, env = 0;
-  const double rl = desc->r_cut + desc->r_skin;
-  const double rla = desc->r_cut + std::max(desc->r_skin, desc->r_skin_alch);
-  for (int w = 0; w < W; ++w) {
-    WalkerMeta &m = s->meta[w];
-    std::memset(&m, 0, sizeof(m));
-    m.atom_begin = desc->atom_offset[w];
-    m.n_atoms = (int32_t)(desc->atom_offset[w + 1] - desc->atom_offset[w]);
-    int64_t na = 0;
-    for (int64_t i = m.atom_begin; i < m.atom_begin + m.n_atoms; ++i) na += alch[i];
-    m.n_a = (int32_t)na;
-    const int64_t nenv = m.n_atoms - na;
-    double vol = 1.0;
-    for (int k = 0; k < 3; ++k) {
-      const double L0 = desc->box[3 * w + k];
-      m.B[k] = pow2_at_least(2.0 * L0);
-      m.L[k] = grid_edge<T>(L0, m.B[k]);
-      if (!(rla < 0.5 * m.L[k])) return fail(nullptr, LABF_E_ARG, "r_list >= L/2 after rounding the box");
-      vol *= m.L[k];
-    }
-    const double rho = (double)std::max<int64_t>(nenv, 1) / vol;
-    const double target = std::cbrt((double)CL / rho) * (desc->column_width ? desc->column_width[w] : 1.0);
-    m.ncx = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[0] / target)));
-    m.ncy = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[1] / target)));
-    m.cw[0] = m.L[0] / m.ncx;
-    m.cw[1] = m.L[1] / m.ncy;
-    m.cap_env = (int32_t)((nenv + CL - 1) / CL + (int64_t)m.ncx * m.ncy);
-    m.n_acl = (int32_t)na;  // one alchemical atom per cluster
-    m.cl_begin = cl;
-    m.col_begin = (int32_t)col;
-    m.env_item_begin = (int32_t)env;
-    cl += (int64_t)m.cap_env + m.n_acl;
-    col += (int64_t)m.ncx * m.ncy + 1;
-    env += m.cap_env;
-    for (int64_t i = m.atom_begin; i < m.atom_begin + m.n_atoms; ++i)
-      for (int k = 0; k < 3; ++k) {
-        pos_grid[3 * i + k] = grid_pos<T>(desc->pos[3 * i + k], m.L[k], m.B[k]);
-        if (desc->anchor) anc_grid[3 * i + k] = grid_pos<T>(desc->anchor[3 * i + k], m.L[k], m.B[k]);
-      }
-  }
-  if (cl >= (int64_t)CL_MASK) return fail(nullptr, LABF_E_UNSUPPORTED, "too many clusters");
-  s->C = cl;
-  s->S = cl * CL;
-  s->K = col;
-  s->E = env;
+  s->pme_bricks = h.pme_nbr;
+  s->pme_planes = h.pme_npl;
+  s->pme_planes2 = h.pme_planes2;
+  s->list_cap = h.list_cap;
+  s->max_bins = h.max_bins;
+  s->n_solute = (int64_t)h.solute_atom.size();
+  s->workspace = desc->workspace;
+  s->workspace_bytes = need;
+  Carver cv;
+  cv.base = (char *)desc->workspace;
+  carve<T>(h, s, d, cv);
   // scalars
   d.n_walkers = W;
   d.n_atoms = N;
   d.n_slots = s->S;
   d.n_clusters = s->C;
-  d.uniform_lj = uniform ? 1 : 0;
+  d.list_cap = h.list_cap;
+  d.uniform_lj = h.uniform ? 1 : 0;
   d.r_cut = desc->r_cut;
-  d.r_list = rl;
-  d.r_list_a = rla;
+  d.r_list = desc->r_cut + desc->r_skin;
+  d.r_list_a = desc->r_cut + std::max(desc->r_skin, desc->r_skin_alch);
   d.dt = desc->dt;
   d.kT = desc->kT;
   d.gamma = desc->gamma;
@@ -561,318 +1045,83 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.irc = (T)(1.0 / desc->r_cut);
   d.irc2 = (T)(1.0 / (desc->r_cut * desc->r_cut));
   {
-    const double s6 = std::pow(u_sig, 6.0);
-    const double c6 = 4.0 * u_eps * s6, c12 = 4.0 * u_eps * s6 * s6;
+    const double s6 = std::pow(h.u_sig, 6.0);
+    const double c6 = 4.0 * h.u_eps * s6, c12 = 4.0 * h.u_eps * s6 * s6;
     const double ir6 = 1.0 / std::pow(desc->r_cut, 6.0);
     d.c6 = (T)c6;
     d.c12 = (T)c12;
     d.ushift = (T)((c12 * ir6 - c6) * ir6);
   }
-  // static tables
-  std::vector<int32_t> atom_walker(N), cl_walker(s->C), env_table(s->E);
-  for (int w = 0; w < W; ++w) {
-    const WalkerMeta &m = s->meta[w];
-    for (int64_t i = 0; i < m.n_atoms; ++i) atom_walker[m.atom_begin + i] = w;
-    for (int64_t c = 0; c < (int64_t)m.cap_env + m.n_acl; ++c) cl_walker[m.cl_begin + c] = w;
-    for (int64_t c = 0; c < m.cap_env; ++c) env_table[m.env_item_begin + c] = (int32_t)(m.cl_begin + c);
-  }
-  DevBufs &b = s->bufs;
-  HIPCHK(s, upload(b, &d.meta, s->meta.data(), W));
-  HIPCHK(s, upload(b, &d.atom_walker, atom_walker.data(), N));
-  HIPCHK(s, upload(b, &d.cl_walker, cl_walker.data(), s->C));
-  HIPCHK(s, upload(b, &d.env_table, env_table.data(), s->E));
-  {
-    std::vector<int32_t> col_walker(s->K);
-    for (int w = 0; w < W; ++w) {
-      const WalkerMeta &m = s->meta[w];
-      for (int64_t k = m.col_begin; k < (int64_t)m.col_begin + (int64_t)m.ncx * m.ncy + 1; ++k) col_walker[k] = w;
-    }
-    HIPCHK(s, upload(b, &d.col_walker, col_walker.data(), col_walker.size()));
-  }
-  for (auto pr : {std::make_pair(&d.a_q, desc->charge), std::make_pair(&d.a_sig, desc->sigma),
-                  std::make_pair(&d.a_eps, desc->epsilon)}) {
-    HIPCHK(s, dalloc(b, pr.first, N));
-    HIPCHK(s, hipMemcpy(*pr.first, pr.second, sizeof(double) * N, hipMemcpyHostToDevice));
-  }
-  {
-    std::vector<int32_t> solute_atom;
-    for (int64_t i = 0; i < N; ++i)
-      if (sol[i]) solute_atom.push_back((int32_t)i);
-    s->n_solute = (int64_t)solute_atom.size();
-    d.n_solute = s->n_solute;
-    HIPCHK(s, upload(b, &d.solute_atom, solute_atom.data(), solute_atom.size()));
-  }
-  HIPCHK(s, upload(b, &d.a_mass, desc->mass, N));
-  HIPCHK(s, upload(b, &d.a_sol, sol.data(), N));
-  HIPCHK(s, upload(b, &d.a_alch, alch.data(), N));
-  if (desc->anchor) {
-    HIPCHK(s, upload(b, &d.a_k0, desc->k0, N));
-    HIPCHK(s, upload(b, &d.a_k1, desc->k1, N));
-    HIPCHK(s, upload(b, &d.a_anchor, anc_grid.data(), 3 * N));
-  } else {
-    d.a_k0 = d.a_k1 = d.a_anchor = nullptr;
-  }
-  // smooth PME: per-walker grids, FFT block tables, influence-function tables
+  d.n_solute = s->n_solute;
+  d.a_pos0 = nullptr;
+  d.dr_partner = nullptr;
+  d.dr_pair = nullptr;
   d.pme_on = desc->pme_order ? 1 : 0;
   d.pme_order = desc->pme_order;
   d.ewald_beta = desc->pme_order ? desc->ewald_beta : 0.0;
   d.ewb = (T)d.ewald_beta;
   d.ewc = (T)(d.ewald_beta * 1.1283791670955126);  // 2 beta / sqrt(pi)
-  s->pme.clear();
-  for (int a = 0; a < 3; ++a) s->pme_nblk[a] = s->pme_nblk2[a] = 0;
-  s->pme_planes = s->pme_planes2 = 0;
+  d.pme_nbr = h.pme_nbr;
+  d.pme_npl = h.pme_maxyz <= 4096 ? 4096 : PME_PLANE;
+  d.ewtab_inv = (float)(EWTAB_N / (desc->r_cut * desc->r_cut));
+  // clear everything, then upload the static tables (the host vectors live
+  // until the stream is synchronised below)
+  HIPCHK(s, hipMemsetAsync(desc->workspace, 0, need, st));
+  auto put = [&](const void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (!bytes || !dst) return hipSuccess;
+    return hipMemcpyAsync((void *)dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  auto vput = [&](const void *dst, const auto &v) { return put(dst, v.data(), v.size() * sizeof(v[0])); };
+  HIPCHK(s, put(d.meta, h.meta.data(), sizeof(WalkerMeta) * W));
+  HIPCHK(s, vput(d.atom_walker, h.atom_walker));
+  HIPCHK(s, vput(d.cl_walker, h.cl_walker));
+  HIPCHK(s, vput(d.env_table, h.env_table));
+  HIPCHK(s, vput(d.col_walker, h.col_walker));
+  HIPCHK(s, vput(d.item_walker, h.item_walker));
+  HIPCHK(s, vput(d.alch_cluster, h.alch_cluster));
+  HIPCHK(s, vput(d.solute_atom, h.solute_atom));
+  HIPCHK(s, put(d.a_q, desc->charge, sizeof(double) * N));
+  HIPCHK(s, put(d.a_sig, desc->sigma, sizeof(double) * N));
+  HIPCHK(s, put(d.a_eps, desc->epsilon, sizeof(double) * N));
+  HIPCHK(s, put(d.a_mass, desc->mass, sizeof(double) * N));
+  HIPCHK(s, vput(d.a_sol, h.sol));
+  HIPCHK(s, vput(d.a_alch, h.alch));
+  if (desc->anchor) {
+    HIPCHK(s, put(d.a_k0, desc->k0, sizeof(double) * N));
+    HIPCHK(s, put(d.a_k1, desc->k1, sizeof(double) * N));
+    HIPCHK(s, vput(d.a_anchor, h.anc_grid));
+  }
+  HIPCHK(s, vput(d.slot_of, h.slot0));
+  HIPCHK(s, vput(d.orig, h.orig0));
   if (d.pme_on) {
-    s->pme.resize(W);
-    int64_t goff = 0, toff = 0, loff = 0;
-    int32_t nbr = 0, npl = 0, maxyz = 0;
-    std::vector<int32_t> bw[3], brw, plw;
-    for (int w = 0; w < W; ++w) {
-      PmeWalker &p = s->pme[w];
-      std::memset(&p, 0, sizeof(p));
-      for (int a = 0; a < 3; ++a) {
-        p.K[a] = desc->pme_dims[3 * w + a];
-        const int32_t K = p.K[a];
-        if ((K & (K - 1)) == 0) {
-          while ((1 << p.lg[a]) < K) ++p.lg[a];
-        } else {
-          // mixed-radix stage plan: fives, threes, fours, a last two
-          p.lg[a] = -1;
-          int32_t rest = K, ns = 0;
-          for (int r : {5, 3, 4, 2})
-            while (rest % r == 0) {
-              p.rad[a][ns++] = (int8_t)r;
-              rest /= r;
-            }
-          p.nst[a] = ns;
-        }
-      }
-      // y and z transforms: fused per y-z plane in LDS when the plane fits
-      // (no y or z line blocks then), else line by line
-      const bool plane = p.K[1] * p.K[2] <= PME_PLANE;
-      // lines per FFT block: the largest divisor of the number of lines
-      // taken together that fills at most one tile
-      auto max_div = [](int64_t cap, int64_t n) {
-        int32_t q = (int32_t)std::min(cap, n);
-        while (n % q) --q;
-        return q;
-      };
-      p.nl[2] = max_div(PME_TILE / p.K[2], (int64_t)p.K[0] * p.K[1]);
-      p.nl[1] = max_div(PME_TILE / p.K[1], p.K[2]);
-      p.nl[0] = max_div(PME_TILE / p.K[0], p.K[2]);
-      p.blk[2] = plane ? 0 : p.K[0] * p.K[1] / p.nl[2];
-      p.blk[1] = plane ? 0 : p.K[0] * (p.K[2] / p.nl[1]);
-      p.blk[0] = p.K[1] * (p.K[2] / p.nl[0]);
-      // spread bricks; list capacity: three times the mean atom count of a
-      // brick plus 64 (overflow is flagged in the walker status)
-      const int32_t nb = (p.K[0] / PME_BR) * (p.K[1] / PME_BR) * (p.K[2] / PME_BR);
-      for (int a = 0; a < 3; ++a) p.nbr[a] = p.K[a] / PME_BR;
-      p.br_begin = nbr;
-      nbr += nb;
-      brw.insert(brw.end(), (size_t)nb, w);
-      p.br_cap = (int32_t)(((3 * (int64_t)s->meta[w].n_atoms) / nb + 64 + 31) / 32 * 32);
-      p.loff = loff;
-      loff += (int64_t)nb * p.br_cap;
-      if (plane) maxyz = std::max(maxyz, p.K[1] * p.K[2]);
-      p.goff = goff;
-      goff += (int64_t)p.K[0] * p.K[1] * p.K[2];
-      p.toff = toff;
-      toff += p.K[0] + p.K[1] + p.K[2];
-      const WalkerMeta &m = s->meta[w];
-      p.pref = desc->coulomb_k / (3.14159265358979323846 * m.L[0] * m.L[1] * m.L[2]);
-    }
-    // FFT blocks and y-z planes: walkers whose three grid lengths are powers
-    // of two first (their own kernel instantiations), then the others
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int w = 0; w < W; ++w) {
-        PmeWalker &p = s->pme[w];
-        if (pme_pow2(p) != (pass == 0)) continue;
-        for (int a = 0; a < 3; ++a) {
-          p.blk_begin[a] = s->pme_nblk[a];
-          s->pme_nblk[a] += p.blk[a];
-          bw[a].insert(bw[a].end(), (size_t)p.blk[a], w);
-        }
-        p.pl_begin = npl;
-        if (p.blk[1] == 0) {
-          npl += p.K[0];
-          plw.insert(plw.end(), (size_t)p.K[0], w);
-        }
-      }
-      if (pass == 0) {
-        for (int a = 0; a < 3; ++a) s->pme_nblk2[a] = s->pme_nblk[a];
-        s->pme_planes2 = npl;
-      }
-    }
-    HIPCHK(s, upload(b, &d.pme, s->pme.data(), W));
-    for (int a = 0; a < 3; ++a) HIPCHK(s, upload(b, &d.pme_bw[a], bw[a].data(), bw[a].size()));
-    HIPCHK(s, dalloc(b, &d.pme_grid, goff));
-    HIPCHK(s, upload(b, &d.pme_brw, brw.data(), brw.size()));
-    HIPCHK(s, dalloc(b, &d.pme_bcnt, nbr));
-    HIPCHK(s, dalloc(b, &d.pme_blist, loff));
-    d.pme_nbr = nbr;
-    s->pme_bricks = nbr;
-    // LDS plane capacity of the fused y-z transform (walkers whose planes fit)
-    d.pme_npl = maxyz <= 4096 ? 4096 : PME_PLANE;
-    if (npl > 0) {
-      HIPCHK(s, upload(b, &d.pme_plw, plw.data(), plw.size()));
-    } else {
-      d.pme_plw = nullptr;
-    }
-    s->pme_planes = npl;
-    double *tab = nullptr;
-    HIPCHK(s, dalloc(b, &tab, 2 * toff));
-    d.pme_tab = tab;
-    {
-      // frequency index at each position of a forward transform: with the
-      // radices r_1 .. r_n of the decimation-in-frequency stages, position
-      // p = j_1 m_1 + p' (m_1 = K / r_1) holds frequency j_1 + r_1 f(p')
-      // (bit reversal for radix 2)
-      std::vector<int32_t> perm(toff);
-      for (int w = 0; w < W; ++w) {
-        const PmeWalker &p = s->pme[w];
-        int64_t o = p.toff;
-        for (int a = 0; a < 3; ++a) {
-          const int32_t K = p.K[a];
-          std::vector<int32_t> rads;
-          if (p.lg[a] >= 0) rads.assign((size_t)p.lg[a], 2);
-          else rads.assign(p.rad[a], p.rad[a] + p.nst[a]);
-          for (int32_t pos = 0; pos < K; ++pos) {
-            int32_t rem = pos, len = K, mult = 1, f = 0;
-            for (int32_t r : rads) {
-              const int32_t m = len / r, j = rem / m;
-              rem -= j * m;
-              f += j * mult;
-              mult *= r;
-              len = m;
-            }
-            perm[o + pos] = f;
-          }
-          o += K;
-        }
-      }
-      HIPCHK(s, upload(b, &d.pme_perm, perm.data(), perm.size()));
-    }
-    HIPCHK(s, dalloc(b, &d.pme_frc, 3 * s->S));
-    HIPCHK(s, dalloc(b, &d.pme_phi, 2 * s->S));
-    HIPCHK(s, dalloc(b, &d.pme_qs, 4 * W));
-    float4 *ewtab = nullptr;
-    HIPCHK(s, dalloc(b, &ewtab, 2 * EWTAB_N));
-    d.ewtab = ewtab;
-    d.ewtab_inv = (float)(EWTAB_N / (desc->r_cut * desc->r_cut));
-    HIPCHK(s, Launch<T>::pme_tables(d, ewtab, st));
+    HIPCHK(s, put(d.pme, h.pme.data(), sizeof(PmeWalker) * W));
+    for (int a = 0; a < 3; ++a) HIPCHK(s, vput(d.pme_bw[a], h.pme_bw[a]));
+    HIPCHK(s, vput(d.pme_brw, h.pme_brw));
+    if (h.pme_npl > 0) HIPCHK(s, vput(d.pme_plw, h.pme_plw));
+    HIPCHK(s, vput(d.pme_perm, h.pme_perm));
+    HIPCHK(s, Launch<T>::pme_tables(d, (float4 *)d.ewtab, st));
     HIPCHK(s, Launch<T>::pme_charges(d, st));
   }
-  d.a_pos0 = nullptr;
-  HIPCHK(s, dalloc(b, &d.slot_of, N));
-  HIPCHK(s, dalloc(b, &d.new_slot, N));
-  HIPCHK(s, dalloc(b, &d.col_of, N));
-  HIPCHK(s, dalloc(b, &d.key_col, N));
-  HIPCHK(s, dalloc(b, &d.members, N));
-  HIPCHK(s, dalloc(b, &d.xref, 3 * N));
-  HIPCHK(s, dalloc(b, &d.disp, N));
-  HIPCHK(s, dalloc(b, &d.skin_part, (size_t)W * SKIN_PARTS * 4));
-  HIPCHK(s, dalloc(b, &d.col_count, s->K));
-  HIPCHK(s, dalloc(b, &d.col_fill, s->K));
-  HIPCHK(s, dalloc(b, &d.col_atom0, s->K));
-  HIPCHK(s, dalloc(b, &d.col_cl0, s->K));
-  for (int u = 0; u < 2; ++u)
-    for (int k = 0; k < 3; ++k) {
-      HIPCHK(s, dalloc(b, &d.X[u][k], s->S));
-      HIPCHK(s, dalloc(b, &d.V[u][k], s->S));
-    }
-  HIPCHK(s, dalloc(b, &d.q, s->S));
-  HIPCHK(s, dalloc(b, &d.lja, s->S));
-  HIPCHK(s, dalloc(b, &d.ljb, s->S));
-  HIPCHK(s, dalloc(b, &d.aim, s->S));
-  HIPCHK(s, dalloc(b, &d.nsd, s->S));
-  HIPCHK(s, dalloc(b, &d.rk, s->S));
-  for (int k = 0; k < 3; ++k) HIPCHK(s, dalloc(b, &d.anc[k], s->S));
-  HIPCHK(s, dalloc(b, &d.q64, s->S));
-  HIPCHK(s, dalloc(b, &d.sig64, s->S));
-  HIPCHK(s, dalloc(b, &d.eps64, s->S));
-  HIPCHK(s, dalloc(b, &d.k0_64, s->S));
-  HIPCHK(s, dalloc(b, &d.k1_64, s->S));
-  HIPCHK(s, dalloc(b, &d.sol, s->S));
-  HIPCHK(s, dalloc(b, &d.orig, s->S));
-  HIPCHK(s, dalloc(b, &d.fout, 3 * s->S));
-  HIPCHK(s, dalloc(b, &d.bbox, 6 * s->C));
-  HIPCHK(s, dalloc(b, &d.cl_col, s->C));
-  HIPCHK(s, dalloc(b, &d.list_count, s->C));
-  HIPCHK(s, dalloc(b, &d.list_nenv, s->C));
-  HIPCHK(s, dalloc(b, &d.cl_energy, 2 * s->C));
-  HIPCHK(s, dalloc(b, &d.n_env, W));
-  HIPCHK(s, dalloc(b, &d.ticket, W));
-  HIPCHK(s, dalloc(b, &d.gticket, 1));
-  HIPCHK(s, dalloc(b, &d.status, W));
-  HIPCHK(s, dalloc(b, &d.lambda, 2 * W));
-  HIPCHK(s, dalloc(b, &d.p_lambda, W));
-  HIPCHK(s, dalloc(b, &d.dudl, W));
-  HIPCHK(s, dalloc(b, &d.bias, W));
-  HIPCHK(s, dalloc(b, &d.step, 2 * W));
-  HIPCHK(s, dalloc(b, &d.start_step, 1));
-  HIPCHK(s, dalloc(b, &d.energy, 5 * W));
-  HIPCHK(s, dalloc(b, &d.pair_n, 2 * W));
-  HIPCHK(s, dalloc(b, &s->stage, 3 * N));
-  HIPCHK(s, dalloc(b, &s->stage2, 3 * N));
-  HIPCHK(s, dalloc(b, &s->lam_stage, 2 * W));
-  // ABF arrays are (re)allocated by labf_set_lambda_params
-  d.bin_count = d.loc_count = nullptr;
-  d.bin_sum = d.bin_sum2 = d.loc_sum = d.loc_sum2 = nullptr;
-  // initial layout: atom i of walker w in slot cl_begin*8 + i
-  std::vector<int32_t> slot0(N);
-  for (int w = 0; w < W; ++w)
-    for (int64_t i = 0; i < s->meta[w].n_atoms; ++i)
-      slot0[s->meta[w].atom_begin + i] = (int32_t)(s->meta[w].cl_begin * CL + i);
-  HIPCHK(s, hipMemcpy(d.slot_of, slot0.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
-  {
-    // slot -> walker-local atom (-1: empty); the rebuilds keep it current
-    std::vector<int32_t> orig0(s->S, -1);
-    for (int w = 0; w < W; ++w)
-      for (int64_t i = 0; i < s->meta[w].n_atoms; ++i) orig0[slot0[s->meta[w].atom_begin + i]] = (int32_t)i;
-    HIPCHK(s, hipMemcpy(d.orig, orig0.data(), sizeof(int32_t) * s->S, hipMemcpyHostToDevice));
-  }
-  HIPCHK(s, hipMemcpy(s->stage, pos_grid.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice));
-  if (desc->vel) HIPCHK(s, hipMemcpy(s->stage2, desc->vel, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
+  HIPCHK(s, vput(s->stage, h.pos_grid));
+  if (desc->vel) HIPCHK(s, put(s->stage2, desc->vel, sizeof(double) * 3 * N));
   s->xb = 0;
   s->vb = 0;
   HIPCHK(s, Launch<T>::scatter_atoms(d, 0, 0, s->stage, desc->vel ? s->stage2 : nullptr, st));
   if (!desc->vel) HIPCHK(s, Launch<T>::init_velocities(d, 0, st));
-  // first rebuild with a generous list capacity, then size the capacity
-  s->list_cap = 1024;
-  labf_status rc = alloc_items<T>(s);
-  if (rc != LABF_OK) return rc;
   s->xref_valid = false;
   rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
   if (rc != LABF_OK) return rc;
-  for (int attempt = 0; attempt < 4; ++attempt) {
-    std::vector<int32_t> cnt(s->C);
-    HIPCHK(s, hipStreamSynchronize(st));
-    HIPCHK(s, hipMemcpy(cnt.data(), d.list_count, sizeof(int32_t) * s->C, hipMemcpyDeviceToHost));
-    int mx_env = 0, mx_a = 0;
-    for (int w = 0; w < W; ++w) {
-      const WalkerMeta &m = s->meta[w];
-      for (int64_t c = m.cl_begin; c < m.cl_begin + m.cap_env; ++c) mx_env = std::max(mx_env, (int)cnt[c]);
-      for (int64_t c = m.cl_begin + m.cap_env; c < m.cl_begin + m.cap_env + m.n_acl; ++c)
-        mx_a = std::max(mx_a, (int)cnt[c]);
-    }
-    const int mx = std::max(mx_env, mx_a);
-    if (mx >= s->list_cap) {
-      s->list_cap *= 2;  // overflowed: grow and rebuild from the same positions
-    } else {
-      // headroom for denser regions and larger cluster boxes once the
-      // configuration relaxes; alchemical clusters (a spread-out solute) get
-      // more (overflow is flagged in the walker status)
-      const int want = std::max({128, ((int)(2.0 * mx_env) + 64 + 31) / 32 * 32,
-                                 ((int)(3.0 * mx_a) + 128 + 31) / 32 * 32});
-      if (want >= s->list_cap) break;
-      s->list_cap = want;
-    }
-    rc = alloc_items<T>(s);
-    if (rc != LABF_OK) return rc;
-    s->xref_valid = false;
-    rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
-    if (rc != LABF_OK) return rc;
-  }
+  // the capacity must hold the lists of the initial configuration
+  std::vector<int32_t> cnt(s->C);
+  HIPCHK(s, hipMemcpyAsync(cnt.data(), d.list_count, sizeof(int32_t) * s->C, hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> status(W);
+  HIPCHK(s, hipMemcpyAsync(status.data(), d.status, sizeof(uint32_t) * W, hipMemcpyDeviceToHost, st));
   HIPCHK(s, hipStreamSynchronize(st));
+  for (int w = 0; w < W; ++w)
+    if (status[w] & LABF_WS_CAPACITY)
+      return fail(nullptr, LABF_E_CAPACITY,
+                  "the neighbour lists of walker " + std::to_string(w) + " exceed the list capacity " +
+                      std::to_string(h.list_cap) + " (raise labf_system_desc.list_capacity)");
   s->since_rebuild = 0;
   return LABF_OK;
 }
@@ -880,6 +1129,10 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
 template <typename T>
 labf_status set_lambda_impl(labf_system *s, const labf_lambda_params *p, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
+  if (p->n_bins > s->max_bins)
+    return fail(s, LABF_E_ARG,
+                "n_bins exceeds the bin capacity of the system (labf_system_desc.max_bins = " +
+                    std::to_string(s->max_bins) + ")");
   LamParams &lp = d.lp;
   lp.m_lambda = p->m_lambda;
   lp.gamma_lambda = p->gamma_lambda;
@@ -903,22 +1156,14 @@ labf_status set_lambda_impl(labf_system *s, const labf_lambda_params *p, hipStre
   lp.share_interval = p->share_interval;
   lp.fixed_lambda = p->fixed_lambda;
   lp.abf_on = p->abf_on;
-  if (d.bin_count) {
-    for (void *q : {(void *)d.bin_count, (void *)d.bin_sum, (void *)d.bin_sum2, (void *)d.loc_count,
-                    (void *)d.loc_sum, (void *)d.loc_sum2}) {
-      auto it = std::find(s->bufs.ptrs.begin(), s->bufs.ptrs.end(), q);
-      if (it != s->bufs.ptrs.end()) {
-        (void)hipFree(*it);
-        s->bufs.ptrs.erase(it);
-      }
-    }
-  }
-  HIPCHK(s, dalloc(s->bufs, &d.bin_count, p->n_bins));
-  HIPCHK(s, dalloc(s->bufs, &d.bin_sum, p->n_bins));
-  HIPCHK(s, dalloc(s->bufs, &d.bin_sum2, p->n_bins));
-  HIPCHK(s, dalloc(s->bufs, &d.loc_count, (size_t)p->n_bins * s->W));
-  HIPCHK(s, dalloc(s->bufs, &d.loc_sum, (size_t)p->n_bins * s->W));
-  HIPCHK(s, dalloc(s->bufs, &d.loc_sum2, (size_t)p->n_bins * s->W));
+  // empty the accumulators (their capacity was carved at creation)
+  const size_t nb = (size_t)s->max_bins, nl = nb * (size_t)s->W;
+  HIPCHK(s, hipMemsetAsync(d.bin_count, 0, sizeof(int64_t) * nb, st));
+  HIPCHK(s, hipMemsetAsync(d.bin_sum, 0, sizeof(double) * nb, st));
+  HIPCHK(s, hipMemsetAsync(d.bin_sum2, 0, sizeof(double) * nb, st));
+  HIPCHK(s, hipMemsetAsync(d.loc_count, 0, sizeof(int64_t) * nl, st));
+  HIPCHK(s, hipMemsetAsync(d.loc_sum, 0, sizeof(double) * nl, st));
+  HIPCHK(s, hipMemsetAsync(d.loc_sum2, 0, sizeof(double) * nl, st));
   HIPCHK(s, hipMemcpyAsync(s->lam_stage, p->lambda0, sizeof(double) * s->W, hipMemcpyHostToDevice, st));
   if (p->p_lambda0)
     HIPCHK(s, hipMemcpyAsync(s->lam_stage + s->W, p->p_lambda0, sizeof(double) * s->W, hipMemcpyHostToDevice, st));
@@ -964,7 +1209,7 @@ labf_status eval_impl(labf_system *s, double *forces, double *energy, double *du
   Dev<T> &d = s->dev<T>();
   labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
   if (rc != LABF_OK) return rc;
-  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, st));
+  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, EVAL_ALL, st));
   if (forces) {
     HIPCHK(s, Launch<T>::gather_forces(d, s->stage, st));
     HIPCHK(s, hipMemcpyAsync(forces, s->stage, sizeof(double) * 3 * s->N, hipMemcpyDeviceToHost, st));
@@ -992,9 +1237,11 @@ labf_status eval_impl(labf_system *s, double *forces, double *energy, double *du
 }
 
 // Differentiable energy: install the configuration (device arrays, each may
-// be NULL), rebuild, evaluate every pair term once.
+// be NULL), rebuild the neighbour structure when positions or solute
+// parameters were given or the atoms have moved since the last rebuild, then
+// evaluate every pair term once in the given mode.
 template <typename T>
-labf_status energy_eval(labf_system *s, const double *pos, const double *lam, const double *params,
+labf_status energy_eval(labf_system *s, const double *pos, const double *lam, const double *params, int mode,
                         hipStream_t st) {
   Dev<T> &d = s->dev<T>();
   if (params && s->n_solute > 0) {
@@ -1009,25 +1256,29 @@ labf_status energy_eval(labf_system *s, const double *pos, const double *lam, co
   }
   HIPCHK(s, Launch<T>::set_config(d, s->xb, s->lb, pos, lam, params, st));
   if (pos) s->xref_valid = false;  // positions replaced: nothing to check at this rebuild
-  labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
-  if (rc != LABF_OK) return rc;
-  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, st));
+  // the slot copies of the parameters are refreshed by the rebuild
+  if (pos || (params && s->n_solute > 0) || s->since_rebuild > 0 || !s->list_current) {
+    labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
+    if (rc != LABF_OK) return rc;
+  }
+  HIPCHK(s, Launch<T>::eval(d, full_range(s), s->xb, s->vb, s->lb, mode, st));
   return LABF_OK;
 }
 
 template <typename T>
 labf_status energy_impl(labf_system *s, const double *pos, const double *lam, const double *params,
-                        double *energy, hipStream_t st) {
-  labf_status rc = energy_eval<T>(s, pos, lam, params, st);
+                        double *energy, double *dudl, hipStream_t st) {
+  labf_status rc = energy_eval<T>(s, pos, lam, params, EVAL_ENERGY, st);
   if (rc != LABF_OK) return rc;
   HIPCHK(s, Launch<T>::energy_total(s->dev<T>(), energy, st));
+  if (dudl) HIPCHK(s, hipMemcpyAsync(dudl, s->dev<T>().dudl, sizeof(double) * s->W, hipMemcpyDeviceToDevice, st));
   return LABF_OK;
 }
 
 template <typename T>
 labf_status energy_backward_impl(labf_system *s, const double *pos, const double *lam, const double *params,
                                  const double *g, double *gpos, double *glam, double *gpar, hipStream_t st) {
-  labf_status rc = energy_eval<T>(s, pos, lam, params, st);
+  labf_status rc = energy_eval<T>(s, pos, lam, params, EVAL_GRAD, st);
   if (rc != LABF_OK) return rc;
   HIPCHK(s, Launch<T>::energy_grads(s->dev<T>(), g, gpos, glam, gpar, st));
   return LABF_OK;
@@ -1061,10 +1312,6 @@ labf_status dr_impl(labf_system *s, const int32_t *pairs, double delta, double k
     pair[2 * w] = (int32_t)ga;
     pair[2 * w + 1] = (int32_t)gb;
   }
-  if (!s->dr_partner_dev) {
-    HIPCHK(s, dalloc(s->bufs, &s->dr_partner_dev, s->N));
-    HIPCHK(s, dalloc(s->bufs, &s->dr_pair_dev, 2 * s->W));
-  }
   HIPCHK(s, hipMemcpyAsync(s->dr_partner_dev, partner.data(), sizeof(int32_t) * s->N, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync(s->dr_pair_dev, pair.data(), sizeof(int32_t) * 2 * s->W, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipStreamSynchronize(st));
@@ -1082,13 +1329,13 @@ labf_status ensure_pairs_buf(labf_system *s, int64_t n) {
   Dev<T> &d = s->dev<T>();
   if (n <= s->pairs_cap) return LABF_OK;
   if (s->pairs_dev) {
-    auto it = std::find(s->bufs.ptrs.begin(), s->bufs.ptrs.end(), (void *)s->pairs_dev);
-    if (it != s->bufs.ptrs.end()) {
+    auto it = std::find(s->hook_bufs.ptrs.begin(), s->hook_bufs.ptrs.end(), (void *)s->pairs_dev);
+    if (it != s->hook_bufs.ptrs.end()) {
       (void)hipFree(*it);
-      s->bufs.ptrs.erase(it);
+      s->hook_bufs.ptrs.erase(it);
     }
   }
-  HIPCHK(s, dalloc(s->bufs, &s->pairs_dev, (size_t)(2 * n)));
+  HIPCHK(s, dalloc(s->hook_bufs, &s->pairs_dev, (size_t)(2 * n)));
   s->pairs_cap = n;
   d.pair_out = s->pairs_dev;
   d.pair_max = n;
@@ -1239,6 +1486,15 @@ labf_status dispatch(labf_system *s, F &&f) {
 // C ABI
 // =============================================================================
 extern "C" {
+
+labf_status labf_workspace_size(const labf_system_desc *desc, size_t *bytes) {
+  if (!bytes) return fail(nullptr, LABF_E_ARG, "bytes is NULL");
+  *bytes = 0;
+  labf_status rc = validate_desc(desc);
+  if (rc != LABF_OK) return rc;
+  return desc->precision == LABF_FP64 ? workspace_bytes<double>(desc, bytes, nullptr)
+                                      : workspace_bytes<float>(desc, bytes, nullptr);
+}
 
 labf_status labf_create_system(const labf_system_desc *desc, void *stream, labf_system **out) {
   if (!out) return fail(nullptr, LABF_E_ARG, "out is NULL");
@@ -1392,14 +1648,14 @@ labf_status labf_compute_forces(labf_system *sys, double *forces, double *energy
   });
 }
 
-labf_status labf_energy(labf_system *sys, const double *pos, const double *lambda, const double *params,
-                        double *energy, void *stream) {
+labf_status labf_energy_forward(labf_system *sys, const double *pos, const double *lambda, const double *params,
+                                double *energy, double *dudl, void *stream) {
   if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
   if (!energy) return fail(sys, LABF_E_ARG, "energy is NULL");
   if (!sys->lam_set) return fail(sys, LABF_E_STATE, "labf_set_lambda_params must be called first");
   return dispatch(sys, [&](auto *tag) {
     using T = std::remove_pointer_t<decltype(tag)>;
-    return energy_impl<T>(sys, pos, lambda, params, energy, (hipStream_t)stream);
+    return energy_impl<T>(sys, pos, lambda, params, energy, dudl, (hipStream_t)stream);
   });
 }
 
@@ -1558,8 +1814,7 @@ void labf_destroy_system(labf_system *sys) {
   if (sys->fork_ev) (void)hipEventDestroy(sys->fork_ev);
   if (sys->join_ev) (void)hipEventDestroy(sys->join_ev);
   if (sys->pme_ev) (void)hipEventDestroy(sys->pme_ev);
-  sys->item_bufs.release();
-  sys->bufs.release();
+  sys->hook_bufs.release();
   delete sys;
 }
 

@@ -32,6 +32,10 @@ constexpr int image_code(int sx, int sy, int sz) { return (sx + 1) | ((sy + 1) <
 constexpr int SHIFT_ZERO = image_code(0, 0, 0);  // code of the (0,0,0) image
 constexpr int IMG_CODES = 64;                    // table size indexed by code
 constexpr uint32_t LAMBDA_ATOM = 0xFFFFFFFFu;  // noise stream of lambda
+// what an evaluation (no integration) computes
+constexpr int EVAL_ALL = 0;     // forces, energy parts, dV/dlambda, solute parameter gradient
+constexpr int EVAL_ENERGY = 1;  // energy parts and dV/dlambda only
+constexpr int EVAL_GRAD = 2;    // forces, dV/dlambda and the solute parameter gradient
 
 struct WalkerMeta {
   int64_t atom_begin;     // first atom (caller order)
@@ -225,7 +229,9 @@ struct Launch {
   // step_env (which then only writes forces) and pme()
   static hipError_t env_integrate(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                   hipStream_t s);
-  static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, hipStream_t s);
+  // mode: EVAL_ALL, EVAL_ENERGY or EVAL_GRAD (what an evaluation computes)
+  static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, int mode,
+                         hipStream_t s);
   static hipError_t export_pairs(const Dev<T> &d, const Range &r, int xb, int mode,
                                  hipStream_t s);
   static hipError_t init_velocities(const Dev<T> &d, int vb, hipStream_t s);

@@ -656,7 +656,7 @@ __device__ __forceinline__ T ewald_fr(const Dev<T> &d, T qq, T r2, T rinv, T r2i
   return qq * rinv * r2inv - ewald_corr(d, d.ewtab, qq, r2, rinv, r2inv, ue);
 }
 
-template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW>
+template <typename T, bool LB, bool ENERGY, bool DIAG, bool EW, bool EONLY = false>
 __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], const T (&yi)[CL],
                                           const T (&zi)[CL], const T (&qi)[CL], const T (&ai)[CL],
                                           const T (&bi)[CL], int64_t s0, T xj, T yj, T zj, T qj,
@@ -688,11 +688,13 @@ __device__ __forceinline__ void env_pairs(const Dev<T> &d, const T (&xi)[CL], co
     }
     T uew = (T)0;
     const T c = EW ? ewald_corr(d, ewt, qq, r2, rinv, r2inv, uew) : d.irc2 * e;
-    T fr = fma(r2inv, g, -c);
-    fr = in ? fr : (T)0;
-    fx[ii] -= fr * dx;
-    fy[ii] -= fr * dy;
-    fz[ii] -= fr * dz;
+    if (!EONLY) {
+      T fr = fma(r2inv, g, -c);
+      fr = in ? fr : (T)0;
+      fx[ii] -= fr * dx;
+      fy[ii] -= fr * dy;
+      fz[ii] -= fr * dz;
+    }
     if (ENERGY) {
       T el;
       if (!LB) {
@@ -822,9 +824,12 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
 // The FP32 real-space Ewald forces kernel asks for at least 6 waves per SIMD
 // (at most 80 VGPRs, no spills); asking 8 of any variant spills SGPRs and
 // measured slower.
-template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED, bool EW>
+// EONLY (with ENERGY): energies only, no forces (the forward pass of the
+// differentiable energy).
+template <typename T, bool LB, bool ENERGY, bool INTEG, bool SHIFTED, bool EW, bool EONLY = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!ENERGY && !INTEG && EW && sizeof(T) == 4 ? 6 : 1)))
 void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
+  static_assert(!EONLY || (ENERGY && !INTEG), "the energy-only variant evaluates energies");
   // the force half of the FP32 real-space Ewald table (4 KiB), staged in LDS
   // by the whole block before any wave leaves: one LDS read per pair
   // instead of a cached global gather
@@ -849,7 +854,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
   const int n = d.list_count[c];
   const int nenv = d.list_nenv[c];
-  const bool need_lj = LB || nenv < n;
+  const bool need_lj = LB || (!EONLY && nenv < n);
   T xi[CL], yi[CL], zi[CL], qi[CL], ai[CL], bi[CL];
   int vmask = 0;
 #pragma unroll
@@ -906,8 +911,8 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     T xj, yj, zj, qj, aj, bj;
     int js;
     load_j(0, xj, yj, zj, qj, aj, bj, js);
-    env_pairs<T, LB, ENERGY, true, EW>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js, vmask,
-                                   fx, fy, fz, eacc, ewt);
+    env_pairs<T, LB, ENERGY, true, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
+                                              vmask, fx, fy, fz, eacc, ewt);
   }
   if (nenv > CL) {
     // Remaining entries: a j atom farther than r_cut from the box of the 8
@@ -948,7 +953,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
         T x2, y2, z2, q2, a2, b2;
         rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
         __builtin_amdgcn_wave_barrier();
-        env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+        env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
                                         vmask, fx, fy, fz, eacc, ewt);
         head = (head + WAVE) & (RING - 1);
         cnt -= WAVE;
@@ -958,11 +963,11 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       __builtin_amdgcn_wave_barrier();
       T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
       if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
-      env_pairs<T, LB, ENERGY, false, EW>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+      env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
                                       vmask, fx, fy, fz, eacc, ewt);
     }
   }
-  if (nenv < n) {
+  if (!EONLY && nenv < n) {
     // alchemical partners: one atom per alchemical cluster (slot 0), 64 per pass
     const LamParams &lp = d.lp;
     double ce, dce, cv, dcv;
@@ -993,13 +998,15 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     }
   }
   T Fx = (T)0, Fy = (T)0, Fz = (T)0;
+  if constexpr (!EONLY) {
 #pragma unroll
-  for (int ii = 0; ii < CL; ++ii) {
-    const T sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
-    if (lane == ii) {
-      Fx = sx;
-      Fy = sy;
-      Fz = sz;
+    for (int ii = 0; ii < CL; ++ii) {
+      const T sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+      if (lane == ii) {
+        Fx = sx;
+        Fy = sy;
+        Fz = sz;
+      }
     }
   }
   double eres = 0.0;
@@ -1019,7 +1026,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       }
       eres = 0.5 * (double)kr * r2;
     }
-    if (valid && d.dr_partner) {
+    if (!EONLY && valid && d.dr_partner) {
       const int64_t a = m.atom_begin + d.orig[s];
       const int64_t b = d.dr_partner[a];
       if (b >= 0) {
@@ -1048,7 +1055,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
       }
-    } else {
+    } else if (!EONLY) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
     }
@@ -1317,9 +1324,11 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
 // neighbour list, each lane one partner per pass (FP64), and the block
 // reduces force, dV/dlambda and energies in a fixed order (no atomics).  The
 // block that completes a walker's set runs the walker's lambda/ABF tail.
-template <typename T, bool ENERGY, bool INTEG>
+// ENERGY: the walker's energy parts (alchemical side); PGRAD: dV/d(eps,
+// sigma, q) of the block's atom; INTEG: the stepping tail.
+template <typename T, bool ENERGY, bool INTEG, bool PGRAD>
 __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
-  constexpr int NACC = ENERGY ? 12 : 9;
+  constexpr int NACC = PGRAD ? 12 : (ENERGY ? 9 : 4);
   __shared__ double red[4][NACC];
   __shared__ int is_last;
   const int64_t k = r.i0 + blockIdx.x;
@@ -1373,11 +1382,13 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
         if (dcv != 0.0) acc[3] += dcv * o.dulj;
         if (dce != 0.0) acc[3] += dce * o.duc;
       }
-      if (ENERGY) {
+      if (PGRAD) {
         // eps_ij = sqrt(eps_i eps_j), sig_ij = (sig_i + sig_j)/2, q_i q_j
         if (epi != 0.0) acc[9] += o.ulj / (2.0 * epi);
         acc[10] += 0.5 * o.dsig;
         acc[11] += (alch ? ce : 1.0) * d.coulomb_k * d.q64[js] * o.g;
+      }
+      if (ENERGY) {
         const bool isAj = (J - m.cl_begin) >= m.cap_env;
         if (!isAj || si < js) {
           if (alch) {
@@ -1411,10 +1422,12 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
 #pragma unroll
       for (int a = 0; a < 3; ++a) tot[a] += d.pme_frc[(int64_t)a * d.n_slots + si];
       if (so) tot[3] += dce * q * pt;
+      const double kb = d.coulomb_k * d.ewald_beta * 0.56418958354775628;  // k beta / sqrt(pi)
       if (ENERGY) {
-        const double kb = d.coulomb_k * d.ewald_beta * 0.56418958354775628;  // k beta / sqrt(pi)
         tot[so ? 5 : 4] += 0.5 * q * po - kb * q * q;
         if (so) tot[7] += ce * q * pt;
+      }
+      if (PGRAD) {
         const double *qs = d.pme_qs + 4 * w;
         const double V = m.L[0] * m.L[1] * m.L[2];
         const double qo = so ? qs[1] : qs[0], qt = so ? qs[0] : qs[1];
@@ -1426,10 +1439,10 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     d.item_force[k * 3 + 1] = tot[1];
     d.item_force[k * 3 + 2] = tot[2];
     d.item_dudl[k] = tot[3];
-    if (ENERGY) {
+    if (ENERGY)
       for (int q = 0; q < 5; ++q) d.item_energy[k * 5 + q] = tot[4 + q];
+    if (PGRAD)
       for (int q = 0; q < 3; ++q) d.item_pgrad[k * 3 + q] = tot[9 + q];
-    }
     __threadfence();
     const unsigned old = atomicAdd(&d.ticket[w], 1u);
     is_last = old == (unsigned)(m.item_cap - 1);
@@ -1709,22 +1722,25 @@ hipError_t Launch<T>::rebuild(const Dev<T> &d, const Range &r, int xb, int vb, i
   return hipGetLastError();
 }
 
+// energy: 0 forces only, 1 forces and energies, 2 energies only
 template <typename T, bool SH, bool EW>
-static void env_launch_form(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
+static void env_launch_form(const Dev<T> &d, const Range &r, int xb, int vb, int lb, int energy,
                             bool integ, unsigned grid, hipStream_t s) {
   if (d.uniform_lj) {
     if (integ) k_env<T, false, false, true, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, false, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy == 2) k_env<T, false, true, false, SH, EW, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy == 1) k_env<T, false, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
     else k_env<T, false, false, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   } else {
     if (integ) k_env<T, true, false, true, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
-    else if (energy) k_env<T, true, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy == 2) k_env<T, true, true, false, SH, EW, true><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
+    else if (energy == 1) k_env<T, true, true, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
     else k_env<T, true, false, false, SH, EW><<<grid, 256, 0, s>>>(d, r, xb, vb, lb);
   }
 }
 
 template <typename T>
-static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, bool energy,
+static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, int energy,
                        bool integ, hipStream_t s) {
   const int nb = (int)((r.en + 3) / 4);
   const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
@@ -1764,6 +1780,22 @@ __global__ __launch_bounds__(256) void k_env_integrate(Dev<T> d, Range r, int xb
   }
 }
 
+// Reciprocal-space force added to the forces-only output of k_env (which
+// leaves it to k_env_integrate on the stepping path): the gradient
+// evaluation with PME.
+template <typename T>
+__global__ __launch_bounds__(256) void k_env_recip(Dev<T> d, Range r) {
+  const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= (r.c0 + r.cn) * CL) return;
+  const int64_t c = s / CL;
+  const int w = d.cl_walker[c];
+  const WalkerMeta &m = d.meta[w];
+  if (c - m.cl_begin >= d.n_env[w] || d.orig[s] < 0) return;
+  const int64_t S = d.n_slots;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d.fout[k * S + s] += d.pme_frc[k * S + s];
+}
+
 template <typename T>
 hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                            hipStream_t s) {
@@ -1774,8 +1806,8 @@ hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int 
     if (e == hipSuccess) e = env_integrate(d, r, xb, vb, lb, s);
     return e;
   }
-  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
-  env_launch<T>(d, r, xb, vb, lb, false, true, s);
+  if (r.in_ > 0) k_alch<T, false, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  env_launch<T>(d, r, xb, vb, lb, 0, true, s);
   return hipGetLastError();
 }
 
@@ -1790,7 +1822,7 @@ hipError_t Launch<T>::env_integrate(const Dev<T> &d, const Range &r, int xb, int
 template <typename T>
 hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                 hipStream_t s) {
-  if (r.in_ > 0) k_alch<T, false, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  if (r.in_ > 0) k_alch<T, false, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   return hipGetLastError();
 }
 
@@ -1798,19 +1830,33 @@ template <typename T>
 hipError_t Launch<T>::step_env(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                hipStream_t s) {
   // with PME: forces only; env_integrate finishes the step
-  env_launch<T>(d, r, xb, vb, lb, false, !d.pme_on, s);
+  env_launch<T>(d, r, xb, vb, lb, 0, !d.pme_on, s);
   return hipGetLastError();
 }
 
+// mode EVAL_ALL: forces, energies, dV/dlambda and the solute parameter
+// gradient; EVAL_ENERGY: energies and dV/dlambda only (no forces, no
+// parameter gradient); EVAL_GRAD: forces, dV/dlambda and the parameter
+// gradient (no energies).
 template <typename T>
-hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
+hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, int mode,
                            hipStream_t s) {
   if (d.pme_on) {
     const hipError_t e = pme(d, r, xb, lb, s);
     if (e != hipSuccess) return e;
   }
-  if (r.in_ > 0) k_alch<T, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
-  env_launch<T>(d, r, xb, vb, lb, true, false, s);
+  const unsigned ni = (unsigned)r.in_;
+  if (mode == EVAL_ENERGY) {
+    if (ni) k_alch<T, true, false, false><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    env_launch<T>(d, r, xb, vb, lb, 2, false, s);
+  } else if (mode == EVAL_GRAD) {
+    if (ni) k_alch<T, false, false, true><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    env_launch<T>(d, r, xb, vb, lb, 0, false, s);
+    if (d.pme_on && r.cn > 0) k_env_recip<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r);
+  } else {
+    if (ni) k_alch<T, true, false, true><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    env_launch<T>(d, r, xb, vb, lb, 1, false, s);
+  }
   return hipGetLastError();
 }
 

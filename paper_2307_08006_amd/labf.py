@@ -25,11 +25,11 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NONFINI
                 -5: "E_SKIN", -6: "E_UNSUPPORTED", -7: "E_EMPTY_BIN", -8: "E_CAPACITY"}
 
 # every symbol include/labf.h declares
-EXPORTS = ["labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
+EXPORTS = ["labf_workspace_size", "labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
            "labf_read_abf_bins", "labf_free_energy", "labf_read_walker_state",
            "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
            "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
-           "labf_energy", "labf_energy_backward", "labf_set_distance_restraint",
+           "labf_energy_forward", "labf_energy_backward", "labf_set_distance_restraint",
            "labf_probe", "labf_destroy_system",
            "labf_last_error"]
 
@@ -53,6 +53,8 @@ class SystemDesc(C.Structure):
         ("rebuild_interval", C.c_int32), ("pme_order", C.c_int32),
         ("r_skin_alch", C.c_double), ("column_width", C.c_void_p),
         ("pme_dims", C.c_void_p), ("ewald_beta", C.c_double),
+        ("max_bins", C.c_int32), ("list_capacity", C.c_int32),
+        ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
     ]
 
 
@@ -96,6 +98,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
+            "labf_workspace_size": ([P, P], I32),
             "labf_create_system": ([P, P, P], I32),
             "labf_set_lambda_params": ([P, P, P], I32),
             "labf_step_walkers": ([P, I64, I32, P], I32),
@@ -111,7 +114,7 @@ def lib():
             "labf_philox": ([I64, P, P, P, P], I32),
             "labf_probe": ([I32, I64, P, P], I32),
             "labf_get_info": ([P, P, P], I32),
-            "labf_energy": ([P, P, P, P, P, P], I32),
+            "labf_energy_forward": ([P, P, P, P, P, P, P], I32),
             "labf_energy_backward": ([P, P, P, P, P, P, P, P, P], I32),
             "labf_set_distance_restraint": ([P, P, C.c_double, C.c_double, I32, P], I32),
             "labf_destroy_system": ([P], None),
@@ -137,9 +140,17 @@ def _f64(a, shape=None):
 
 
 def _stream(stream):
-    if stream is None:
-        return None
-    return int(stream)
+    """The HIP stream handle of a call: the given one, else torch's current
+    stream (the default stream without a GPU build of torch)."""
+    if stream is not None:
+        return int(stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream) or None
+    except ImportError:
+        pass
+    return None
 
 
 def _dev(t, shape, name):
@@ -159,35 +170,72 @@ def _torch_stream(stream):
     return int(stream) if stream is not None else torch.cuda.current_stream().cuda_stream
 
 
-class System:
-    """A batch of walkers living on the GPU (one labf_system handle)."""
+def _desc(spec: SystemSpec, max_bins: int = 0, list_capacity: int = 0):
+    """(labf_system_desc, the host arrays it points to) of a SystemSpec."""
+    keep = dict(
+        atom_offset=np.ascontiguousarray(spec.atom_offset, np.int64), box=_f64(spec.box, (-1, 3)),
+        pos=_f64(spec.pos, (-1, 3)), vel=_f64(spec.vel, (-1, 3)), mass=_f64(spec.mass),
+        charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
+        is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
+        k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width),
+        pme_dims=None if spec.pme_dims is None else np.ascontiguousarray(spec.pme_dims, np.int32))
+    d = SystemDesc()
+    d.n_walkers = spec.n_walkers
+    d.precision = LABF_FP64 if spec.precision == "fp64" else LABF_FP32
+    for k, v in keep.items():
+        setattr(d, k, _p(v))
+    for k in ("r_cut", "r_skin", "kT", "gamma", "dt", "coulomb_k", "accel_unit"):
+        setattr(d, k, float(getattr(spec, k)))
+    d.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
+    d.rebuild_interval = int(spec.rebuild_interval)
+    d.pme_order = 0 if spec.pme_dims is None else int(spec.pme_order)
+    d.ewald_beta = float(spec.ewald_beta) if spec.pme_dims is not None else 0.0
+    d.r_skin_alch = float(spec.r_skin_alch)
+    d.max_bins = int(max_bins)
+    d.list_capacity = int(list_capacity)
+    return d, keep
 
-    def __init__(self, spec: SystemSpec, lam: Optional[LambdaSpec] = None, stream=None):
+
+def workspace_size(spec: SystemSpec, max_bins: int = 0, list_capacity: int = 0) -> int:
+    """Bytes of device workspace a system of this spec needs (host arithmetic
+    in the library, no GPU call)."""
+    d, keep = _desc(spec, max_bins, list_capacity)
+    n = C.c_size_t(0)
+    rc = lib().labf_workspace_size(C.byref(d), C.byref(n))
+    if rc != 0:
+        raise LabfError(rc, lib().labf_last_error(None).decode())
+    return int(n.value)
+
+
+class System:
+    """A batch of walkers living on the GPU (one labf_system handle).  Its
+    device memory is a torch uint8 tensor (the workspace) that this object
+    owns; every call runs on torch's current stream unless a stream is
+    given."""
+
+    def __init__(self, spec: SystemSpec, lam: Optional[LambdaSpec] = None, stream=None,
+                 max_bins: Optional[int] = None, list_capacity: int = 0):
         self.spec = spec
-        self.stream = _stream(stream)
+        self._stream_arg = stream
         self._h = None
-        keep = dict(
-            atom_offset=np.ascontiguousarray(spec.atom_offset, np.int64), box=_f64(spec.box, (-1, 3)),
-            pos=_f64(spec.pos, (-1, 3)), vel=_f64(spec.vel, (-1, 3)), mass=_f64(spec.mass),
-            charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
-            is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
-            k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width),
-            pme_dims=None if spec.pme_dims is None else np.ascontiguousarray(spec.pme_dims, np.int32))
-        d = SystemDesc()
-        d.n_walkers = spec.n_walkers
-        d.precision = LABF_FP64 if spec.precision == "fp64" else LABF_FP32
-        for k, v in keep.items():
-            setattr(d, k, _p(v))
-        for k in ("r_cut", "r_skin", "kT", "gamma", "dt", "coulomb_k", "accel_unit"):
-            setattr(d, k, float(getattr(spec, k)))
-        d.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
-        d.rebuild_interval = int(spec.rebuild_interval)
-        d.pme_order = 0 if spec.pme_dims is None else int(spec.pme_order)
-        d.ewald_beta = float(spec.ewald_beta) if spec.pme_dims is not None else 0.0
-        d.r_skin_alch = float(spec.r_skin_alch)
+        self._ws = None
+        self._last_cfg = {}
+        if max_bins is None:
+            max_bins = max(1024, int(lam.n_bins) if lam is not None else 0)
+        d, keep = _desc(spec, max_bins, list_capacity)
+        n = C.c_size_t(0)
+        rc = lib().labf_workspace_size(C.byref(d), C.byref(n))
+        if rc != 0:
+            raise LabfError(rc, lib().labf_last_error(None).decode())
+        import torch
+        # torch owns the device memory (its caching allocator hands out
+        # blocks aligned to at least 512 bytes)
+        self._ws = torch.empty(int(n.value), dtype=torch.uint8, device="cuda")
+        d.workspace, d.workspace_bytes = self._ws.data_ptr(), int(n.value)
         h = C.c_void_p()
         rc = lib().labf_create_system(C.byref(d), self.stream, C.byref(h))
         if rc != 0:
+            self._ws = None
             raise LabfError(rc, lib().labf_last_error(None).decode())
         self._h = h
         self.W, self.N = spec.n_walkers, spec.n_atoms
@@ -200,10 +248,28 @@ class System:
         if rc != 0:
             raise LabfError(rc, lib().labf_last_error(self._h).decode())
 
+    def _chk_cfg(self, rc):
+        """_chk for the calls that install a configuration: after a failure
+        the system's configuration is unknown to the binding."""
+        if rc != 0:
+            self._last_cfg.clear()
+        self._chk(rc)
+
+    @property
+    def stream(self):
+        """Stream handle of the calls: the one given at creation, else torch's
+        current stream."""
+        return _stream(self._stream_arg)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return 0 if self._ws is None else int(self._ws.numel())
+
     def close(self):
         if self._h is not None:
             lib().labf_destroy_system(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -240,6 +306,7 @@ class System:
 
     def step(self, n_steps: int, mode: str = "batched"):
         m = MODE_PLAIN if mode == "plain" else MODE_BATCHED
+        self._last_cfg.clear()
         self._chk(lib().labf_step_walkers(self._h, int(n_steps), m, self.stream))
 
     def set_distance_restraint(self, pairs, delta: float, k: float, freq: int = 1):
@@ -284,28 +351,49 @@ class System:
         return np.stack([np.asarray(self.spec.epsilon)[m], np.asarray(self.spec.sigma)[m],
                          np.asarray(self.spec.charge)[m]], axis=1)
 
-    def energy(self, pos=None, lam=None, params=None, out=None, stream=None):
+    def _changed(self, name, t):
+        """Device pointer of t, or None when t is the tensor (same storage,
+        same version) the system was given last time under this name: the
+        library then keeps its configuration and the lists built for it."""
+        if t is None:
+            return None
+        key = (t.data_ptr(), t._version, tuple(t.shape))
+        last = self._last_cfg.get(name)
+        if last is not None and last[1] == key:
+            return None
+        # the reference keeps that memory from being reused by another
+        # tensor, which could otherwise present the same pointer and version
+        self._last_cfg[name] = (t, key)
+        return t.data_ptr()
+
+    def energy(self, pos=None, lam=None, params=None, out=None, dudl=None, stream=None):
         """Total potential energy per walker [W] at the given configuration
-        (float64 GPU tensors, each optional); the configuration replaces the
-        system's."""
+        (float64 GPU tensors, each optional; the configuration replaces the
+        system's); dV/dlambda per walker into dudl if given.  Energies only:
+        no forces or parameter gradients are computed."""
         import torch
         W, N, S = self.W, self.N, self.n_solute
         if out is None:
             out = torch.empty(W, dtype=torch.float64, device="cuda")
-        self._chk(lib().labf_energy(self._h, _dev(pos, (N, 3), "pos"), _dev(lam, (W,), "lambda"),
-                                    _dev(params, (S, 3), "params"), _dev(out, (W,), "energy"),
-                                    _torch_stream(stream)))
+        _dev(pos, (N, 3), "pos"), _dev(params, (S, 3), "params")
+        self._chk_cfg(lib().labf_energy_forward(
+            self._h, self._changed("pos", pos), _dev(lam, (W,), "lambda"),
+            self._changed("params", params), _dev(out, (W,), "energy"), _dev(dudl, (W,), "dudl"),
+            _torch_stream(stream)))
         return out
 
     def energy_backward(self, grad_energy, pos=None, lam=None, params=None, grad_pos=None,
                         grad_lam=None, grad_params=None, stream=None):
         """Recompute the pair terms at the given configuration and write
         g_w dV/dx, g_w dV/dlambda and g_w dV/d(eps, sigma, q) of the solute
-        into the given output tensors (each optional)."""
+        into the given output tensors (each optional).  Positions and
+        parameters identical to the last call's (same tensors, unmodified)
+        are not installed again, so the neighbour lists are reused."""
         W, N, S = self.W, self.N, self.n_solute
-        self._chk(lib().labf_energy_backward(
-            self._h, _dev(pos, (N, 3), "pos"), _dev(lam, (W,), "lambda"),
-            _dev(params, (S, 3), "params"), _dev(grad_energy, (W,), "grad_energy"),
+        _dev(pos, (N, 3), "pos"), _dev(params, (S, 3), "params")
+        self._chk_cfg(lib().labf_energy_backward(
+            self._h, self._changed("pos", pos), _dev(lam, (W,), "lambda"),
+            self._changed("params", params), _dev(grad_energy, (W,), "grad_energy"),
             _dev(grad_pos, (N, 3), "grad_pos"), _dev(grad_lam, (W,), "grad_lambda"),
             _dev(grad_params, (S, 3), "grad_params"), _torch_stream(stream)))
 
@@ -318,6 +406,7 @@ class System:
     def write_atoms(self, pos=None, vel=None):
         pos = _f64(pos, (-1, 3))
         vel = _f64(vel, (-1, 3))
+        self._last_cfg.clear()
         self._chk(lib().labf_write_atoms(self._h, _p(pos), _p(vel), self.stream))
 
     def compute_forces(self):

@@ -95,7 +95,8 @@ def test_null_arguments_are_rejected():
     h = C.c_void_p()
     assert L.labf_create_system(None, None, C.byref(h)) == -1
     assert L.labf_step_walkers(None, 1, 0, None) == -1
-    assert L.labf_energy(None, None, None, None, None, None) == -1
+    assert L.labf_energy_forward(None, None, None, None, None, None, None) == -1
+    assert L.labf_workspace_size(None, None) == -1
     assert L.labf_energy_backward(None, None, None, None, None, None, None, None, None) == -1
     assert L.labf_read_atoms(None, None, None, None) == -1
     assert L.labf_philox(-1, None, None, None, None) == -1
@@ -121,3 +122,58 @@ def test_probe_rejects_bad_arguments_without_a_gpu():
     assert L.labf_probe(3, 6, p, None) == -1               # triad size not a multiple of 4
     assert L.labf_probe(3, (1 << 30) + 4, p, None) == -1   # triad too large
     assert L.labf_probe(0, 16, None, None) == -1           # no output
+
+
+def _raw_desc(spec, **over):
+    d, keep = labf._desc(spec)
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, keep
+
+
+def test_workspace_size_is_host_arithmetic():
+    """labf_workspace_size runs without a GPU: it plans the layout on the
+    host; the size grows with the walkers, the ABF bin capacity and the list
+    capacity, and is a multiple of 256 bytes."""
+    _ensure_built()
+    spec, lam = _spec()
+    n1 = labf.workspace_size(spec)
+    assert n1 > 0 and n1 % 256 == 0
+    b2, _ = synth.batch(spec, lam, 3, seed=5)
+    assert labf.workspace_size(b2) > 2 * n1
+    assert labf.workspace_size(spec, max_bins=4096) > labf.workspace_size(spec, max_bins=64)
+    assert labf.workspace_size(spec, list_capacity=4096) > labf.workspace_size(spec, list_capacity=256)
+    # PME grids live in the workspace too
+    sp = synth.with_pme(dataclasses.replace(spec), dims=(16, 16, 32))
+    assert labf.workspace_size(sp) >= n1 + 16 * 16 * 32 * 16
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("max_bins", -1, "max_bins"), ("max_bins", 5000, "max_bins"),
+    ("list_capacity", 3, "list_capacity"), ("list_capacity", (1 << 20) + 1, "list_capacity"),
+])
+def test_workspace_size_validates_the_descriptor(field, value, msg):
+    _ensure_built()
+    spec, _ = _spec()
+    d, keep = _raw_desc(spec, **{field: value})
+    n = C.c_size_t(7)
+    assert labf.lib().labf_workspace_size(C.byref(d), C.byref(n)) == -1
+    assert n.value == 0
+    assert msg in labf.lib().labf_last_error(None).decode()
+
+
+@pytest.mark.parametrize("ws,nbytes,msg", [
+    (None, 0, "workspace is NULL"),
+    (256, 1024, "too small"),
+    (0x1000 + 8, 1 << 40, "aligned"),
+])
+def test_create_rejects_a_missing_or_short_workspace_before_device_work(ws, nbytes, msg):
+    """The workspace checks come before any device call (the pointer is
+    never touched), so they run without a GPU."""
+    _ensure_built()
+    spec, _ = _spec()
+    d, keep = _raw_desc(spec, workspace=ws, workspace_bytes=nbytes)
+    h = C.c_void_p()
+    assert labf.lib().labf_create_system(C.byref(d), None, C.byref(h)) == -1
+    assert h.value is None
+    assert msg in labf.lib().labf_last_error(None).decode()

@@ -1,6 +1,6 @@
-"""GPU: the differentiable energy and its backward kernel (labf_energy,
-labf_energy_backward and the torch.autograd.Function over them) against the
-FP64 oracle and against central finite differences.
+"""GPU: the differentiable energy and its backward kernels
+(labf_energy_forward, labf_energy_backward and the torch.autograd.Function
+over them) against the FP64 oracle and against central finite differences.
 
 Tolerances:
   * energies: FP64 systems 1e-10 relative; FP32 systems 2e-6 relative
@@ -106,11 +106,14 @@ def _oracle(spec, lamb, s, t):
 
 def test_energy_matches_oracle(case):
     name, spec, lamb, s, t = case
-    e = s.energy(t["pos"], t["lam"], t["par"]).cpu().numpy()
+    g = torch.empty_like(t["lam"])
+    e = s.energy(t["pos"], t["lam"], t["par"], dudl=g).cpu().numpy()
+    g = g.cpu().numpy()
     ref = _oracle(spec, lamb, s, t)
     tol = 1e-10 if spec.precision == "fp64" else 2e-6
     for w in range(spec.n_walkers):
         assert abs(e[w] - ref[w][1]) <= tol * abs(ref[w][1]), (name, w, e[w], ref[w][1])
+        assert abs(g[w] - ref[w][2]) <= 1e-9 * max(abs(ref[w][2]), 1e-3), (name, w, g[w], ref[w][2])
 
 
 def test_backward_matches_oracle(case):
@@ -247,6 +250,13 @@ def test_full_size_backward_8x30k():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / 5 * 1e3
         print(f"forward + backward, 8 x 30k atoms: {ms:.2f} ms")
+        # a forward at new positions, then a backward on the same tensors
+        # (which reuses the forward's lists) give the same gradients
+        tp2 = tp.clone()
+        s.energy(tp2, tl, tq)
+        gp2 = torch.empty_like(tp)
+        s.energy_backward(g, tp2, tl, tq, gp2, None, None)
+        assert torch.equal(gp2, gp)
         pos, _ = s.read_atoms()
     gp, gl, gq = gp.cpu().numpy(), gl.cpu().numpy(), gq.cpu().numpy()
     o = oracle.Oracle(spec, lamb)
