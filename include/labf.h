@@ -312,6 +312,21 @@ labf_status labf_energy_backward(labf_system *sys, const double *pos, const doub
 labf_status labf_export_pairs(labf_system *sys, int32_t walker, int64_t max_pairs, int64_t *pairs,
                               int64_t *n_pairs, void *stream);
 
+/* labf_export_pairs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same output, with the device staging in a static array
+ * of LABF_EXPORT_NOALLOC_MAX_PAIRS pairs (16 MiB per GPU, held until the
+ * process ends) instead of a buffer the call allocates; the host output is
+ * sorted in place.  It calls no hipMalloc, hipFree or allocating routine.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other threads, other handles) race.  Errors: LABF_E_ARG as
+ * labf_export_pairs; LABF_E_CAPACITY, with *n_pairs set and nothing
+ * written, if the walker has more than LABF_EXPORT_NOALLOC_MAX_PAIRS
+ * pairs. */
+#define LABF_EXPORT_NOALLOC_MAX_PAIRS (1 << 20)
+labf_status labf_export_pairs_noalloc(labf_system *sys, int32_t walker, int64_t max_pairs,
+                                      int64_t *pairs, int64_t *n_pairs, void *stream);
+
 /* Number of unordered pairs with r < r_cut in each walker (FP64 decision),
  * counted by a separate pass over the device list (rebuilt first):
  * pairs_all[W] every pair, pairs_env[W] pairs of two environment atoms

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1378,6 +1379,67 @@ labf_status export_impl(labf_system *s, int w, int64_t max_pairs, int64_t *pairs
   return LABF_OK;
 }
 
+// Device staging of labf_export_pairs_noalloc: LABF_EXPORT_NOALLOC_MAX_PAIRS
+// pairs (16 MiB), one array per GPU for the life of the process.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) int64_t scratch[2 * (int64_t)LABF_EXPORT_NOALLOC_MAX_PAIRS];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int64_t *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Address of the current device's staging array (looked up once per device).
+hipError_t scratch_ptr(int64_t **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (int64_t *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// labf_export_pairs without any allocation: the device staging is the
+// static array above, the host output is sorted in place.
+template <typename T>
+labf_status export_noalloc_impl(labf_system *s, int w, int64_t max_pairs, int64_t *pairs, int64_t *n_pairs,
+                                hipStream_t st) {
+  int64_t *stage = nullptr;
+  HIPCHK(s, scratch_ptr(&stage));
+  labf_status rc = do_rebuild<T>(s, LABF_MODE_BATCHED, st);
+  if (rc != LABF_OK) return rc;
+  Dev<T> d = s->dev<T>();  // launch copy pointing at the static staging
+  d.pair_out = stage;
+  d.pair_max = LABF_EXPORT_NOALLOC_MAX_PAIRS;
+  HIPCHK(s, Launch<T>::export_pairs(d, walker_range(s, w), s->xb, 0, st));
+  unsigned long long cnt = 0;
+  HIPCHK(s, hipMemcpyAsync(&cnt, d.pair_n + w, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  if (n_pairs) *n_pairs = (int64_t)cnt;
+  if ((int64_t)cnt > LABF_EXPORT_NOALLOC_MAX_PAIRS)
+    return fail(s, LABF_E_CAPACITY,
+                "walker " + std::to_string(w) + " has " + std::to_string(cnt) +
+                    " pairs, more than the static staging holds (" +
+                    std::to_string((int64_t)LABF_EXPORT_NOALLOC_MAX_PAIRS) + "); use labf_export_pairs");
+  const int64_t got = std::min<int64_t>((int64_t)cnt, max_pairs);
+  if (got > 0 && pairs) {
+    HIPCHK(s, hipMemcpyAsync(pairs, stage, sizeof(int64_t) * 2 * got, hipMemcpyDeviceToHost, st));
+    HIPCHK(s, hipStreamSynchronize(st));
+    struct P2 {
+      int64_t a, b;
+    };
+    P2 *pv = reinterpret_cast<P2 *>(pairs);
+    std::sort(pv, pv + got, [](const P2 &x, const P2 &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; });
+  }
+  return LABF_OK;
+}
+
 template <typename T>
 labf_status count_impl(labf_system *s, int64_t *pairs, int64_t *pairs_env, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
@@ -1689,6 +1751,17 @@ labf_status labf_export_pairs(labf_system *sys, int32_t walker, int64_t max_pair
   return dispatch(sys, [&](auto *tag) {
     using T = std::remove_pointer_t<decltype(tag)>;
     return export_impl<T>(sys, walker, max_pairs, pairs, n_pairs, (hipStream_t)stream);
+  });
+}
+
+labf_status labf_export_pairs_noalloc(labf_system *sys, int32_t walker, int64_t max_pairs, int64_t *pairs,
+                                      int64_t *n_pairs, void *stream) {
+  if (!sys) return fail(nullptr, LABF_E_ARG, "sys is NULL");
+  if (walker < 0 || walker >= sys->W) return fail(sys, LABF_E_ARG, "walker out of range");
+  if (max_pairs < 0 || (max_pairs > 0 && !pairs)) return fail(sys, LABF_E_ARG, "bad output buffer");
+  return dispatch(sys, [&](auto *tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return export_noalloc_impl<T>(sys, walker, max_pairs, pairs, n_pairs, (hipStream_t)stream);
   });
 }
 

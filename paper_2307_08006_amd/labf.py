@@ -28,6 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_NONFINI
 EXPORTS = ["labf_workspace_size", "labf_create_system", "labf_set_lambda_params", "labf_step_walkers",
            "labf_read_abf_bins", "labf_free_energy", "labf_read_walker_state",
            "labf_read_atoms", "labf_write_atoms", "labf_compute_forces", "labf_export_pairs",
+           "labf_export_pairs_noalloc",
            "labf_count_pairs", "labf_profile_steps", "labf_philox", "labf_get_info",
            "labf_energy_forward", "labf_energy_backward", "labf_set_distance_restraint",
            "labf_probe", "labf_destroy_system",
@@ -109,6 +110,7 @@ def lib():
             "labf_write_atoms": ([P, P, P, P], I32),
             "labf_compute_forces": ([P, P, P, P, P], I32),
             "labf_export_pairs": ([P, I32, I64, P, P, P], I32),
+            "labf_export_pairs_noalloc": ([P, I32, I64, P, P, P], I32),
             "labf_count_pairs": ([P, P, P, P], I32),
             "labf_profile_steps": ([P, I64, P, P], I32),
             "labf_philox": ([I64, P, P, P, P], I32),
