@@ -320,22 +320,40 @@ def run_backward(args, spec1, lam1):
     return {"walkers": 8, "atoms_per_walker": int(spec1.n_atoms), "reps": n,
             "forward_ms": 1e3 * tf / n, "backward_ms": 1e3 * tb / n,
             "walker_evaluations_per_s": 8 * n / (tf + tb),
-            "note": "forward includes the configuration upload and a list rebuild; backward "
-                    "recomputes the pair terms"}
+            "note": "forward: configuration upload, list rebuild and the energy-only kernels; "
+                    "backward: the force and parameter-gradient kernels (pair terms recomputed) "
+                    "on the forward's lists"}
 
 
 def cpu_model():
+    """Full model name, logical CPUs of the machine and of this process."""
+    model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+                model = line.split(":", 1)[1].strip()
+                break
     except OSError:
         pass
-    return "unknown"
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, avail
+
+
+def omp_threads():
+    """Threads the oracle's OpenMP regions use."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return n if n > 0 else cpu_model()[2]
 
 
 def cpu_baseline(spec, lam, n_walkers, n_steps):
-    """The FP64 oracle on a bounded sample of the same workload."""
+    """The FP64 oracle on a bounded sample of the same workload: OpenMP over
+    walkers, and for one walker over the cell columns of its pair loop."""
     import oracle
     sp, lm = spec, lam
     if spec.n_walkers > n_walkers:
@@ -353,7 +371,7 @@ def cpu_baseline(spec, lam, n_walkers, n_steps):
     t0 = time.perf_counter()
     o.run(n_steps)
     dt = time.perf_counter() - t0
-    cores = min(n_walkers, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    cores = omp_threads() if n_walkers == 1 else min(n_walkers, omp_threads())
     return n_walkers * n_steps / dt, cores, dt
 
 
@@ -471,9 +489,14 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{W} walkers x {args.atoms}-atom charged LJ fluid (0.1 atoms/A^3, 12 A "
-                        "cutoff, 2 fs, 30-atom decoupled solute held by k=100 restraints), batched: "
-                        "10-step HIP-graph blocks",
+            "workload": f"{W} walkers x {args.atoms}-atom charged LJ fluid (0.1 atoms/A^3 on a "
+                        "seeded FCC lattice +-0.05 A, solvent sigma 2.04 A instead of 3.15 A "
+                        "(rho sigma^3 0.85: the literal value is a compressed solid that heats to "
+                        "1e4 K), eps 0.15 kcal/mol, charges +-0.4 e on alternating (001) planes, "
+                        "12 A cutoff with shifted-force Coulomb, 2 fs, 30-atom decoupled solute "
+                        "held by k=100 restraints, lambda_elec removed over [0,0.5], soft-core vdW "
+                        "over [0.5,1]), batched: 10-step HIP-graph blocks",
+            "solvent_sigma_A": 2.04, "lattice": "fcc, charge species on alternating (001) planes",
             "walkers": W, "atoms_per_walker": args.atoms, "cutoff_A": 12.0, "skin_A": 1.0,
             "rebuild_interval": 10, "abf_bins": 100, "pair_precision": "f32",
             "lambda_precision": "f64", "equilibration_steps_untimed": args.equil_steps,
@@ -527,14 +550,18 @@ def main(argv=None):
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle)")
         v, cores, secs = cpu_baseline(specb, lamb, W, args.cpu_steps)
-        v1, _, secs1 = cpu_baseline(specb, lamb, 1, args.cpu_steps)
+        v1, cores1, secs1 = cpu_baseline(specb, lamb, 1, 2 * args.cpu_steps)
+        model, nproc, avail = cpu_model()
         out["cpu_baseline"] = {
             "value": v, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, {W} walkers x {args.cpu_steps} step(s) of the same "
-                      f"{args.atoms}-atom workload ({secs:.1f} s wall)",
-            "single_core": {"value": v1, "sample": f"1 walker x {args.cpu_steps} step(s), one "
-                                                   f"thread ({secs1:.1f} s wall)"},
-            "cpu_model": cpu_model(),
+                      f"{args.atoms}-atom workload, one thread per walker ({secs:.1f} s wall, "
+                      f"about {secs * cores:.0f} thread-s)",
+            "pair_interactions_per_s": v * pairs_per_step / W,
+            "single_walker": {"value": v1, "cores": cores1,
+                              "sample": f"1 walker x {2 * args.cpu_steps} step(s), its pair loop "
+                                        f"over cell columns in parallel ({secs1:.1f} s wall)"},
+            "cpu_model": model, "nproc": nproc, "cpus_available": avail,
         }
     if rank == 0:
         print(json.dumps(out), flush=True)

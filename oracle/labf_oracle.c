@@ -581,6 +581,60 @@ static void for_each_pair(const double *x, int64_t n, const double *L, double rm
   }
 }
 
+/* The same pairs as for_each_pair with a cell list, with the cell columns
+ * (a, b) as independent chunks: visit(ctxs[a * nc[1] + b], ...) for every
+ * pair whose first atom's cell lies in column (a, b), columns in parallel
+ * (OpenMP).  Returns 0 without visiting anything if the box has fewer than
+ * 3 cells per edge.  With one context per column, merged afterwards in
+ * column order, the sums do not depend on the number of threads. */
+static int cell_dims(const double *L, double r, int nc[3]) {
+  int k;
+  for (k = 0; k < 3; ++k) {
+    int m = (int)floor(L[k] / r);
+    while (m > 0 && L[k] / (double)m < r * (1.0 + 1e-12)) --m;
+    nc[k] = m;
+    if (m < 3) return 0;
+  }
+  return 1;
+}
+
+static int for_each_pair_columns(const double *x, int64_t n, const double *L, double rmax,
+                                 visit_fn visit, void **ctxs) {
+  double invL[3];
+  double r2max = rmax * rmax;
+  int k, col, ncol;
+  cells_t c;
+  for (k = 0; k < 3; ++k) invL[k] = 1.0 / L[k];
+  if (!cells_build(&c, x, n, L, rmax)) return 0;
+  ncol = c.nc[0] * c.nc[1];
+#pragma omp parallel for schedule(dynamic, 1)
+  for (col = 0; col < ncol; ++col) {
+    int a = col / c.nc[1], b = col % c.nc[1], e;
+    for (e = 0; e < c.nc[2]; ++e) {
+      int64_t id = ((int64_t)a * c.nc[1] + b) * c.nc[2] + e;
+      int da, db, de;
+      for (da = -1; da <= 1; ++da)
+        for (db = -1; db <= 1; ++db)
+          for (de = -1; de <= 1; ++de) {
+            int a2 = (a + da + c.nc[0]) % c.nc[0];
+            int b2 = (b + db + c.nc[1]) % c.nc[1];
+            int e2 = (e + de + c.nc[2]) % c.nc[2];
+            int64_t id2 = ((int64_t)a2 * c.nc[1] + b2) * c.nc[2] + e2;
+            int64_t i, j;
+            for (i = c.head[id]; i >= 0; i = c.next[i])
+              for (j = c.head[id2]; j >= 0; j = c.next[j]) {
+                double d[3], r2;
+                if (j <= i) continue;
+                r2 = min_image(x + 3 * i, x + 3 * j, L, invL, d);
+                if (r2 < r2max) visit(ctxs[col], i, j, d, r2);
+              }
+          }
+    }
+  }
+  cells_free(&c);
+  return 1;
+}
+
 typedef struct {
   int64_t count, max;
   int64_t *pairs;
@@ -829,7 +883,44 @@ static int eval_walker(const orc_sys *s, int32_t w, const double *x, double lam,
   if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
   if (g) memset(g, 0, sizeof(double) * 3 * (size_t)n);
   if (fs) memset(fs, 0, sizeof(double) * (size_t)n);
-  for_each_pair(x, n, L, s->r_cut, brute, eval_pair, &c);
+  {
+    /* walkers of 2048 atoms or more: the cell columns in parallel, each with
+     * its own sums, added in column order (the same result whatever the
+     * thread count); smaller ones in one sweep */
+    int nc[3], done = 0;
+    if (!brute && n >= 2048 && cell_dims(L, s->r_cut, nc)) {
+      int ncol = nc[0] * nc[1], col, q;
+      int64_t i;
+      eval_ctx *cs = (eval_ctx *)calloc((size_t)ncol, sizeof(eval_ctx));
+      void **ptrs = (void **)malloc(sizeof(void *) * (size_t)ncol);
+      for (col = 0; col < ncol; ++col) {
+        cs[col] = c;
+        memset(cs[col].u, 0, sizeof(cs[col].u));
+        cs[col].dudl = 0.0;
+        cs[col].f = f ? (double *)calloc(3 * (size_t)n, sizeof(double)) : NULL;
+        cs[col].g = g ? (double *)calloc(3 * (size_t)n, sizeof(double)) : NULL;
+        cs[col].fs = fs ? (double *)calloc((size_t)n, sizeof(double)) : NULL;
+        ptrs[col] = &cs[col];
+      }
+      done = for_each_pair_columns(x, n, L, s->r_cut, eval_pair, ptrs);
+      for (col = 0; col < ncol; ++col) {
+        for (q = 0; q < 5; ++q) c.u[q] += cs[col].u[q];
+        c.dudl += cs[col].dudl;
+        for (i = 0; i < 3 * n; ++i) {
+          if (f) f[i] += cs[col].f[i];
+          if (g) g[i] += cs[col].g[i];
+        }
+        if (fs)
+          for (i = 0; i < n; ++i) fs[i] += cs[col].fs[i];
+        free(cs[col].f);
+        free(cs[col].g);
+        free(cs[col].fs);
+      }
+      free(cs);
+      free(ptrs);
+    }
+    if (!done) for_each_pair(x, n, L, s->r_cut, brute, eval_pair, &c);
+  }
   if (s->pme_on) ewald_walker(s, w, x, n, c.ce, c.dce, &c);
   if (s->anchor && s->k0 && s->k1) {
     for (i = 0; i < n; ++i) {
@@ -1088,7 +1179,9 @@ int32_t orc_run(const orc_sys *s, orc_state *st, int64_t n_steps, int32_t brute)
     uint32_t step = (uint32_t)st->step;
     int32_t bad = 0;
     /* 1. forces and dV/dlambda (walkers are independent: one thread each) */
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad) if (s->atom_offset[W] >= 1024)
+    /* one walker: its pair loop runs over the cell columns in parallel
+     * instead (a nested region would run on one thread) */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad) if (W > 1 && s->atom_offset[W] >= 1024)
     for (w = 0; w < W; ++w) {
       int64_t a0 = s->atom_offset[w];
       double u[5];

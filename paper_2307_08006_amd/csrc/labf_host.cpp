@@ -906,6 +906,39 @@ labf_status do_rebuild(labf_system *s, int mode, hipStream_t st) {
   return LABF_OK;
 }
 
+// The two internal streams (default priority) and events of the batched
+// steps: the alchemical kernel runs on the second stream beside the
+// environment kernel.
+labf_status ensure_streams(labf_system *s) {
+  if (s->cap_stream) return LABF_OK;
+  HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream2, hipStreamNonBlocking));
+  HIPCHK(s, hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+  HIPCHK(s, hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
+  HIPCHK(s, hipEventCreateWithFlags(&s->pme_ev, hipEventDisableTiming));
+  return LABF_OK;
+}
+
+// One batched step on `st`, forked: with PME the reciprocal-space chain and
+// then the alchemical kernel on the second stream, the environment kernel on
+// `st`, and (with PME) the environment atoms integrated once both are done.
+template <typename T>
+hipError_t batched_step(labf_system *s, int xb, int vb, int lb, hipStream_t st) {
+  Dev<T> &d = s->dev<T>();
+  const Range r = full_range(s);
+  hipError_t e = hipEventRecord(s->fork_ev, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
+  if (e == hipSuccess && d.pme_on) e = Launch<T>::pme(d, r, xb, lb, s->cap_stream2);
+  if (e == hipSuccess && d.pme_on) e = hipEventRecord(s->pme_ev, s->cap_stream2);
+  if (e == hipSuccess) e = Launch<T>::step_alch(d, r, xb, vb, lb, s->cap_stream2);
+  if (e == hipSuccess) e = Launch<T>::step_env(d, r, xb, vb, lb, st);
+  if (e == hipSuccess && d.pme_on) e = hipStreamWaitEvent(st, s->pme_ev, 0);
+  if (e == hipSuccess && d.pme_on) e = Launch<T>::env_integrate(d, r, xb, vb, lb, st);
+  if (e == hipSuccess) e = hipEventRecord(s->join_ev, s->cap_stream2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, s->join_ev, 0);
+  return e;
+}
+
 template <typename T>
 labf_status do_step(labf_system *s, int mode, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
@@ -913,7 +946,9 @@ labf_status do_step(labf_system *s, int mode, hipStream_t st) {
     for (int w = 0; w < s->W; ++w)
       HIPCHK(s, Launch<T>::step(d, walker_range(s, w), s->xb, s->vb, s->lb, st));
   } else {
-    HIPCHK(s, Launch<T>::step(d, full_range(s), s->xb, s->vb, s->lb, st));
+    labf_status rc = ensure_streams(s);
+    if (rc != LABF_OK) return rc;
+    HIPCHK(s, batched_step<T>(s, s->xb, s->vb, s->lb, st));
   }
   s->xb ^= 1;
   s->lb ^= 1;
@@ -929,13 +964,8 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
   const int key = s->xb * 2 + s->vb + (s->xref_valid ? 4 : 0) + s->lb * 8;
   auto it = s->graphs.find(key);
   if (it == s->graphs.end()) {
-    if (!s->cap_stream) {
-      HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-      HIPCHK(s, hipStreamCreateWithFlags(&s->cap_stream2, hipStreamNonBlocking));
-      HIPCHK(s, hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
-      HIPCHK(s, hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming));
-      HIPCHK(s, hipEventCreateWithFlags(&s->pme_ev, hipEventDisableTiming));
-    }
+    labf_status rc = ensure_streams(s);
+    if (rc != LABF_OK) return rc;
     HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     int xb = s->xb, vb = s->vb, lb = s->lb;
     hipError_t e = Launch<T>::rebuild(d, full_range(s), xb, vb, s->xref_valid ? 1 : 0, s->cap_stream);
@@ -948,16 +978,7 @@ labf_status graph_block(labf_system *s, hipStream_t st) {
     // the environment pair kernel, followed there by the alchemical kernel;
     // the environment atoms are integrated once both forces are in
     for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
-      e = hipEventRecord(s->fork_ev, s->cap_stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
-      if (e == hipSuccess && d.pme_on) e = Launch<T>::pme(d, full_range(s), xb, lb, s->cap_stream2);
-      if (e == hipSuccess && d.pme_on) e = hipEventRecord(s->pme_ev, s->cap_stream2);
-      if (e == hipSuccess) e = Launch<T>::step_alch(d, full_range(s), xb, vb, lb, s->cap_stream2);
-      if (e == hipSuccess) e = Launch<T>::step_env(d, full_range(s), xb, vb, lb, s->cap_stream);
-      if (e == hipSuccess && d.pme_on) e = hipStreamWaitEvent(s->cap_stream, s->pme_ev, 0);
-      if (e == hipSuccess && d.pme_on) e = Launch<T>::env_integrate(d, full_range(s), xb, vb, lb, s->cap_stream);
-      if (e == hipSuccess) e = hipEventRecord(s->join_ev, s->cap_stream2);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, s->join_ev, 0);
+      e = batched_step<T>(s, xb, vb, lb, s->cap_stream);
       xb ^= 1;
       lb ^= 1;
     }

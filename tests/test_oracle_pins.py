@@ -6,6 +6,7 @@ special case that reduces to a textbook expression, a finite difference, a
 brute-force enumeration or a conservation law.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -759,3 +760,26 @@ def test_distance_restraint_derivatives_match_fd(n):
         hl = 1e-5
         fd = (_energy(o, x, l + hl) - _energy(o, x, l - hl)) / (2 * hl)
         assert abs(g - fd) < 1e-6 * max(1.0, abs(g)), (l, g, fd)
+
+
+def test_parallel_evaluation_does_not_depend_on_the_thread_count():
+    """Walkers of 2048 atoms or more are evaluated cell column by cell column
+    in parallel, each column with its own sums added in column order: one
+    thread and eight give bitwise the same forces, energies and dV/dlambda
+    (and the per-atom force scale)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r); import oracle; "
+        "from paper_2307_08006_amd import synth; "
+        "spec, lam = synth.charged_lj(n_atoms=3000, precision='fp64', seed=5, r_cut=8.0); "
+        "o = oracle.Oracle(spec, lam); f, u, g = o.evaluate(0, spec.pos, 0.3); "
+        "fs = o.force_scale(0, spec.pos, 0.3); "
+        "sys.stdout.buffer.write(np.concatenate([f.ravel(), u, [g], fs]).tobytes())"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),)
+    out = []
+    for nt in ("1", "8"):
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        out.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
+                                  capture_output=True).stdout)
+    assert len(out[0]) > 0 and out[0] == out[1]
