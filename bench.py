@@ -325,6 +325,36 @@ def run_backward(args, spec1, lam1):
                     "on the forward's lists"}
 
 
+def run_precision(spec1, lam1):
+    """Error of the FP32 path against the FP64 path (itself within 1e-10 of
+    the FP64 oracle in the parity tests) on the 30k walker at the benchmark's
+    equilibrated positions (read back from the FP32 path, so exact in both),
+    lambda 0.25 and 0.75: forces, the environment energy, the energy parts
+    computed in FP64 and dV/dlambda."""
+    import dataclasses
+    from paper_2307_08006_amd import labf
+    rows = []
+    for lv in (0.25, 0.75):
+        lam = dataclasses.replace(lam1, lambda0=np.array([lv]))
+        res = {}
+        for prec in ("fp32", "fp64"):
+            with labf.System(dataclasses.replace(spec1, precision=prec), lam) as s:
+                res[prec] = s.compute_forces()
+        f32, e32, g32 = res["fp32"]
+        f64, e64, g64 = res["fp64"]
+        d = np.linalg.norm(f32 - f64, axis=1)
+        rms = float(np.sqrt((f64 * f64).sum(1).mean()))
+        rows.append({"lambda": lv,
+                     "force_norm_rel": float(np.linalg.norm(f32 - f64) / np.linalg.norm(f64)),
+                     "force_max_abs_over_rms": float(d.max() / rms),
+                     "energy_env_rel": float(abs(e32[0, 0] - e64[0, 0]) / abs(e64[0, 0])),
+                     "energy_fp64_parts_rel": float(max(abs(e32[0, k] - e64[0, k]) / max(abs(e64[0, k]), 1e-3)
+                                                        for k in range(1, 5))),
+                     "dudl_rel": float(abs(g32[0] - g64[0]) / max(abs(g64[0]), 1e-3))})
+    return {"reference": "FP64 path (within 1e-10 of the FP64 oracle in the parity tests)",
+            "workload": "30k-atom walker at the benchmark's equilibrated positions", "rows": rows}
+
+
 def cpu_model():
     """Full model name, logical CPUs of the machine and of this process."""
     model = "unknown"
@@ -545,6 +575,7 @@ def main(argv=None):
         out["pme"] = run_pme(args, specb, lamb)
     if args.backward_reps > 0:
         out["backward"] = run_backward(args, spec1, lam1)
+    out["precision"] = run_precision(spec1, lam1)
     if args.uneven_steps > 0:
         out["uneven"] = run_uneven(args)
     if not args.no_cpu_baseline and rank == 0:

@@ -819,6 +819,61 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
   }
 }
 
+// Cross-lane sums on gfx950 without LDS: the halves of the wave swap data
+// with v_permlane32_swap, the 16-lane rows with v_permlane16_swap, and lanes
+// within a row exchange through DPP (row_ror:8, half-row mirror, quad
+// permutations).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float halves_sum(float a, float b) {
+  // lanes 0-31 get a[l] + a[l + 32], lanes 32-63 get b[l - 32] + b[l]
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float rows_sum(float a, float b) {
+  // even rows (lanes 0-15, 32-47) get a summed over the row pair, odd rows b
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Transposed sum of the per-lane forces fx/fy/fz[ii] of the 8 i atoms over
+// the 64 lanes: each stage halves the values a lane keeps (lanes 0-31 keep
+// atoms 0-3 and lanes 32-63 atoms 4-7, then by 16-lane row, then by 8-lane
+// half row), the last sums within 8 lanes; atom ii ends in lanes 8 ii ..
+// 8 ii + 7.  About 50 VALU operations instead of 24 full-wave reductions.
+__device__ __forceinline__ void reduce_transposed(const float (&fx)[CL], const float (&fy)[CL],
+                                                  const float (&fz)[CL], float &Fx, float &Fy,
+                                                  float &Fz) {
+  float u[4][3];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    u[j][0] = halves_sum(fx[j], fx[j + 4]);
+    u[j][1] = halves_sum(fy[j], fy[j + 4]);
+    u[j][2] = halves_sum(fz[j], fz[j + 4]);
+  }
+  // lane in row r holds atom j + 2 r in w[j]
+  float w[2][3];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[j][k] = rows_sum(u[j][k], u[j + 2][k]);
+  const bool hi = (lane_id() & 8) != 0;
+  float z[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float keep = hi ? w[1][k] : w[0][k], send = hi ? w[0][k] : w[1][k];
+    z[k] = keep + dpp_f<0x128>(send);  // row_ror:8 (lane l ^ 8)
+    z[k] += dpp_f<0x141>(z[k]);        // row_half_mirror (lane 7 - l within 8)
+    z[k] += dpp_f<0x4E>(z[k]);         // quad_perm 2,3,0,1 (lane l ^ 2)
+    z[k] += dpp_f<0xB1>(z[k]);         // quad_perm 1,0,3,2 (lane l ^ 1)
+  }
+  Fx = z[0];
+  Fy = z[1];
+  Fz = z[2];
+}
+
 // SHIFTED selects the soft-core form of the alchemical segment at compile time
 // (both forms in one instantiation double the register allocation).
 // The FP32 real-space Ewald forces kernel asks for at least 6 waves per SIMD
@@ -997,21 +1052,27 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
                                  (T)cv, (T)ce, Asc, Dsc, fx, fy, fz);
     }
   }
+  // the forces of the 8 i atoms summed over the wave: atom ii ends in
+  // lanes 8 ii .. 8 ii + 7, whose first lane finishes the atom
   T Fx = (T)0, Fy = (T)0, Fz = (T)0;
   if constexpr (!EONLY) {
+    if constexpr (sizeof(T) == 4) {
+      reduce_transposed(fx, fy, fz, Fx, Fy, Fz);
+    } else {
 #pragma unroll
-    for (int ii = 0; ii < CL; ++ii) {
-      const T sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
-      if (lane == ii) {
-        Fx = sx;
-        Fy = sy;
-        Fz = sz;
+      for (int ii = 0; ii < CL; ++ii) {
+        const T sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+        if ((lane >> 3) == ii) {
+          Fx = sx;
+          Fy = sy;
+          Fz = sz;
+        }
       }
     }
   }
   double eres = 0.0;
-  if (lane < CL) {
-    const int64_t s = s0 + lane;
+  if ((lane & 7) == 0) {
+    const int64_t s = s0 + (lane >> 3);
     const bool valid = d.orig[s] >= 0;
     double F[3] = {(double)Fx, (double)Fy, (double)Fz};
     const T kr = d.rk[s];
