@@ -336,10 +336,13 @@ labf_status labf_count_pairs(labf_system *sys, int64_t *pairs_all, int64_t *pair
 
 /* Timing pass (for roofline reporting): rebuilds the list, then runs
  * n_steps >= 1 batched steps launched one kernel at a time with HIP events
- * around each launch on `stream`.  ms[4]: ms[0] = rebuild, ms[1] = alchemical
+ * around each launch on `stream`.  ms[5]: ms[0] = rebuild, ms[1] = alchemical
  * kernel (average per step), ms[2] = environment kernel (average per step),
  * ms[3] = PME reciprocal space (spread, transforms, gather; average per step,
- * 0 without PME).  Advances the dynamics by n_steps like labf_step_walkers. */
+ * 0 without PME), ms[4] = pruning of the environment pair lists (average per
+ * step: a full prune after the rebuild and whenever the atoms have moved far
+ * enough, a test otherwise).  Advances the dynamics by n_steps like
+ * labf_step_walkers. */
 labf_status labf_profile_steps(labf_system *sys, int64_t n_steps, double *ms, void *stream);
 
 /* Philox4x32-10 on the device (test hook): out[n][4] for counters ctr[n][4]

@@ -28,6 +28,12 @@ __device__ __forceinline__ V wave_sum(V v) {
   return v;
 }
 
+// load at a 32-bit byte offset from a base pointer
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, uint32_t bo) {
+  return *(const T *)((const char *)base + bo);
+}
+
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 // hardware reciprocal in FP32 (about 1 ulp), a true division in FP64
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

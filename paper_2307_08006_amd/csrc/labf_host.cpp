@@ -372,6 +372,7 @@ struct HostLayout {
   int W = 0;
   int64_t N = 0, C = 0, S = 0, K = 0, E = 0, I = 0;
   int list_cap = 0, max_bins = 0;
+  int plist_cap = 0;  // pruned-list entries per environment cluster
   bool uniform = true;
   double u_sig = 1.0, u_eps = 0.0;
   std::vector<WalkerMeta> meta;
@@ -728,6 +729,12 @@ labf_status plan_system(const labf_system_desc *desc, HostLayout &h) {
     const auto mx = estimate_lists(h, desc->r_cut + desc->r_skin, rla);
     h.list_cap = std::max({128, (2 * mx.first + 64 + 31) / 32 * 32, (3 * mx.second + 128 + 31) / 32 * 32});
   }
+  // a pruned list keeps at most every atom of the cluster list's entries;
+  // its entries address walker-relative slots in SHIFT_BITS bits
+  h.plist_cap = (CL * h.list_cap + WAVE - 1) / WAVE * WAVE;
+  for (int w = 0; w < W; ++w)
+    if (((int64_t)h.meta[w].cap_env + h.meta[w].n_acl) * CL > (int64_t)CL_MASK)
+      return fail(nullptr, LABF_E_UNSUPPORTED, "too many atoms in one walker");
   return LABF_OK;
 }
 
@@ -842,6 +849,10 @@ void carve(const HostLayout &h, labf_system *s, Dev<T> &d, Carver &cv) {
   cv.take(&d.list_nenv, C);
   cv.take(&d.cl_energy, 2 * C);
   cv.take(&d.list, (size_t)C * h.list_cap);
+  cv.take(&d.plist, (size_t)h.E * h.plist_cap);
+  cv.take(&d.plist_n, h.E);
+  for (int k = 0; k < 3; ++k) cv.take(&d.xprune[k], S);
+  cv.take(&d.pdisp, (size_t)2 * W * PDISP_SLOTS);
   cv.take(&d.item_force, (size_t)h.I * 3);
   cv.take(&d.item_dudl, (size_t)h.I);
   cv.take(&d.item_energy, (size_t)h.I * 5);
@@ -926,7 +937,11 @@ template <typename T>
 hipError_t batched_step(labf_system *s, int xb, int vb, int lb, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
   const Range r = full_range(s);
-  hipError_t e = hipEventRecord(s->fork_ev, st);
+  // the prune test (and the occasional prune) first, alone on the device:
+  // beside the alchemical kernel it takes several times longer, and the
+  // environment kernel waits for it either way
+  hipError_t e = Launch<T>::prune(d, r, xb, lb, st);
+  if (e == hipSuccess) e = hipEventRecord(s->fork_ev, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
   if (e == hipSuccess && d.pme_on) e = Launch<T>::pme(d, r, xb, lb, s->cap_stream2);
   if (e == hipSuccess && d.pme_on) e = hipEventRecord(s->pme_ev, s->cap_stream2);
@@ -1052,6 +1067,14 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.n_slots = s->S;
   d.n_clusters = s->C;
   d.list_cap = h.list_cap;
+  d.plist_cap = h.plist_cap;
+  {
+    // prune buffer: half the skin, at most 0.5 A; the re-prune threshold
+    // keeps 1e-4 A for the rounding of the box distances
+    const double b = std::min(0.5, 0.5 * desc->r_skin);
+    d.prune_r2 = (T)((desc->r_cut + b) * (desc->r_cut + b));
+    d.prune_half = (float)(0.5 * b - 1e-4);
+  }
   d.uniform_lj = h.uniform ? 1 : 0;
   d.r_cut = desc->r_cut;
   d.r_list = desc->r_cut + desc->r_skin;
@@ -1190,6 +1213,8 @@ labf_status set_lambda_impl(labf_system *s, const labf_lambda_params *p, hipStre
   if (p->p_lambda0)
     HIPCHK(s, hipMemcpyAsync(s->lam_stage + s->W, p->p_lambda0, sizeof(double) * s->W, hipMemcpyHostToDevice, st));
   HIPCHK(s, launch_init_lambda<T>(d, s->lam_stage, p->p_lambda0 ? s->lam_stage + s->W : nullptr, s->lb, st));
+  // the step numbers restart: prune before the next evaluation
+  HIPCHK(s, hipMemsetAsync(d.plist_n, 0xFF, sizeof(int32_t) * s->E, st));
   HIPCHK(s, hipStreamSynchronize(st));
   drop_graphs(s);
   s->host_steps = 0;
@@ -1480,7 +1505,9 @@ labf_status count_impl(labf_system *s, int64_t *pairs, int64_t *pairs_env, hipSt
 template <typename T>
 labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) {
   Dev<T> &d = s->dev<T>();
-  std::vector<hipEvent_t> ev(2 + 3 * n + 1);
+  // ev[0] start, ev[1] rebuilt; step i: ev[4i+2] PME, ev[4i+3] alchemical,
+  // ev[4i+4] prune, ev[4i+5] environment done
+  std::vector<hipEvent_t> ev(2 + 4 * n);
   for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
   auto cleanup = [&]() {
     for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1492,35 +1519,36 @@ labf_status profile_impl(labf_system *s, int64_t n, double *ms, hipStream_t st) 
     return rc;
   }
   HIPCHK(s, hipEventRecord(ev[1], st));
+  const Range r = full_range(s);
   for (int64_t i = 0; i < n; ++i) {
-    HIPCHK(s, Launch<T>::pme(d, full_range(s), s->xb, s->lb, st));
-    HIPCHK(s, hipEventRecord(ev[2 + 3 * i], st));
-    HIPCHK(s, Launch<T>::step_alch(d, full_range(s), s->xb, s->vb, s->lb, st));
-    HIPCHK(s, hipEventRecord(ev[3 + 3 * i], st));
-    HIPCHK(s, Launch<T>::step_env(d, full_range(s), s->xb, s->vb, s->lb, st));
-    HIPCHK(s, Launch<T>::env_integrate(d, full_range(s), s->xb, s->vb, s->lb, st));
-    HIPCHK(s, hipEventRecord(ev[4 + 3 * i], st));
+    HIPCHK(s, Launch<T>::pme(d, r, s->xb, s->lb, st));
+    HIPCHK(s, hipEventRecord(ev[4 * i + 2], st));
+    HIPCHK(s, Launch<T>::step_alch(d, r, s->xb, s->vb, s->lb, st));
+    HIPCHK(s, hipEventRecord(ev[4 * i + 3], st));
+    HIPCHK(s, Launch<T>::prune(d, r, s->xb, s->lb, st));
+    HIPCHK(s, hipEventRecord(ev[4 * i + 4], st));
+    HIPCHK(s, Launch<T>::step_env(d, r, s->xb, s->vb, s->lb, st));
+    HIPCHK(s, Launch<T>::env_integrate(d, r, s->xb, s->vb, s->lb, st));
+    HIPCHK(s, hipEventRecord(ev[4 * i + 5], st));
     s->xb ^= 1;
     s->lb ^= 1;
     s->since_rebuild += 1;
     s->host_steps += 1;
   }
-  HIPCHK(s, hipEventSynchronize(ev[1 + 3 * n]));
+  HIPCHK(s, hipEventSynchronize(ev[1 + 4 * n]));
   float t = 0.f;
   HIPCHK(s, hipEventElapsedTime(&t, ev[0], ev[1]));
   ms[0] = t;
-  double a = 0.0, e = 0.0, p = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 1], ev[3 * i + 2]));
-    p += t;
-    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 2], ev[3 * i + 3]));
-    a += t;
-    HIPCHK(s, hipEventElapsedTime(&t, ev[3 * i + 3], ev[3 * i + 4]));
-    e += t;
-  }
-  ms[1] = a / n;
-  ms[2] = e / n;
-  ms[3] = d.pme_on ? p / n : 0.0;
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};  // PME, alchemical, prune, environment
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 4; ++k) {
+      HIPCHK(s, hipEventElapsedTime(&t, ev[4 * i + 1 + k], ev[4 * i + 2 + k]));
+      sum[k] += t;
+    }
+  ms[1] = sum[1] / n;
+  ms[2] = sum[3] / n;
+  ms[3] = d.pme_on ? sum[0] / n : 0.0;
+  ms[4] = sum[2] / n;
   cleanup();
   return LABF_OK;
 }

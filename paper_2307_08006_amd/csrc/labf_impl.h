@@ -31,6 +31,10 @@ constexpr uint32_t CL_MASK = (1u << SHIFT_BITS) - 1u;
 constexpr int image_code(int sx, int sy, int sz) { return (sx + 1) | ((sy + 1) << 2) | ((sz + 1) << 4); }
 constexpr int SHIFT_ZERO = image_code(0, 0, 0);  // code of the (0,0,0) image
 constexpr int IMG_CODES = 64;                    // table size indexed by code
+// Filler entry of a pruned list: the walker's first slot shifted by two box
+// edges along every axis, farther than r_cut from any atom of the box.
+constexpr uint32_t PRUNE_PAD = (uint32_t)image_code(2, 2, 2) << SHIFT_BITS;
+constexpr int PDISP_SLOTS = 64;  // displacement maxima per walker (one wave reads them)
 constexpr uint32_t LAMBDA_ATOM = 0xFFFFFFFFu;  // noise stream of lambda
 // what an evaluation (no integration) computes
 constexpr int EVAL_ALL = 0;     // forces, energy parts, dV/dlambda, solute parameter gradient
@@ -154,6 +158,19 @@ struct Dev {
   int32_t *list_nenv;           // environment-cluster entries of an environment list
   uint32_t *list;               // [C * list_cap]
   double *cl_energy;            // [C][2] env-env, restraint (evaluation)
+  // --- pruned pair lists (per environment work-table entry): the j atoms of
+  // the list's environment entries within r_cut + prune buffer of the
+  // cluster box when last pruned, as (walker-relative slot | image code <<
+  // SHIFT_BITS), padded with PRUNE_PAD to whole chunks of 64
+  int32_t plist_cap;            // entries per cluster (a multiple of 64)
+  uint32_t *plist;              // [E][plist_cap]
+  int32_t *plist_n;             // [E] chunks of 64 in use; -1: stale (rebuilt list)
+  T *xprune[3];                 // [3][S] positions at the last prune
+  uint32_t *pdisp;              // [2][W][PDISP_SLOTS] bits of the largest displacement since
+                                // the last prune (non-negative float), spread over slots
+                                // (fewer atomics per address), double-buffered like lambda
+  T prune_r2;                   // (r_cut + prune buffer)^2
+  float prune_half;             // re-prune once the largest displacement exceeds this
   // --- alchemical blocks (one per alchemical atom)
   double *item_force;           // [I][3] force on the block's atom
   double *item_dudl;            // [I]
@@ -229,6 +246,9 @@ struct Launch {
   // step_env (which then only writes forces) and pme()
   static hipError_t env_integrate(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                   hipStream_t s);
+  // pruned pair lists of the environment clusters, refreshed where stale
+  // (before every environment launch)
+  static hipError_t prune(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s);
   // mode: EVAL_ALL, EVAL_ENERGY or EVAL_GRAD (what an evaluation computes)
   static hipError_t eval(const Dev<T> &d, const Range &r, int xb, int vb, int lb, int mode,
                          hipStream_t s);

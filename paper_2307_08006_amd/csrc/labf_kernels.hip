@@ -585,38 +585,138 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
     d.list_count[c] = cnt < cap ? cnt : cap;
     d.list_nenv[c] = nenv < cap ? nenv : cap;
     if (cnt > cap) atomicOr(&d.status[w], 8u);
+    if (!isA) d.plist_n[m.env_item_begin + loc] = -1;  // prune again before use
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dynamic pruning of the environment pair lists
+// ---------------------------------------------------------------------------
+// A cluster list holds whole neighbour clusters within r_list of the cluster
+// box; most of their atoms lie beyond r_cut of every atom of the box.  Every
+// few steps k_prune keeps, per environment cluster, the j atoms within
+// r_cut + b of the box (b, the prune buffer, below the skin) in a compact
+// list; k_env evaluates that list 64 atoms at a time.  Between prunes an atom
+// moves at most D (the largest displacement in the walker since the prune,
+// measured by the integrating kernels), so a pair inside r_cut now was
+// inside r_cut + 2D then: the list stays complete while 2D <= b.  The test is
+// walker-wide so that all clusters of a walker share one prune step (and one
+// reference configuration); the cluster list itself stays valid while the
+// displacements since the rebuild stay within the skin (the k_skin test).
+// A stale list (after a rebuild) is always pruned.
+constexpr int PRUNE_CPW = 4;  // clusters per wave of k_prune
+template <typename T>
+__global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb) {
+  const int64_t nw = (r.en + PRUNE_CPW - 1) / PRUNE_CPW;  // waves in all
+  const int nb = (int)((nw + 3) >> 2);
+  // plain block order: the walkers that prune at a step spread over all
+  // XCDs (with the XCD-aware order of k_env, a step on which a few walkers
+  // prune would load only their XCDs)
+  const int lblk = (int)blockIdx.x;
+  if (lblk >= nb) return;
+  const int64_t e_first = r.e0 + ((int64_t)lblk * 4 + uni(threadIdx.x >> 6)) * PRUNE_CPW;
+  const int lane = lane_id();
+  const int W = d.n_walkers;
+  const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
+  __shared__ T shtab[4][3][IMG_CODES];
+  T *shx = shtab[threadIdx.x >> 6][0], *shy = shtab[threadIdx.x >> 6][1], *shz = shtab[threadIdx.x >> 6][2];
+  int wtab = -1;  // walker of the image-shift table and of D
+  float D = 0.f;
+  for (int64_t e = e_first; e < e_first + PRUNE_CPW && e < r.e0 + r.en; ++e) {
+    const int64_t c = d.env_table[e];
+    const int w = d.cl_walker[c];
+    const WalkerMeta &m = d.meta[w];
+    const int64_t loc = c - m.cl_begin;
+    if (loc >= d.n_env[w]) continue;
+    if (w != wtab) {
+      // the largest displacement since the prune, as the last step measured
+      // it (maximum over the walker's slots)
+      uint32_t Db = d.pdisp[((int64_t)lb * W + w) * PDISP_SLOTS + lane];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) Db = max(Db, (uint32_t)__shfl_xor((int)Db, o, WAVE));
+      D = __uint_as_float(Db);
+      __builtin_amdgcn_wave_barrier();
+      shx[lane] = (T)img_x(lane) * (T)m.L[0];
+      shy[lane] = (T)img_y(lane) * (T)m.L[1];
+      shz[lane] = (T)img_z(lane) * (T)m.L[2];
+      __builtin_amdgcn_wave_barrier();
+      wtab = w;
+    }
+    // the next step's integration measures into the other buffer
+    if (loc == 0) d.pdisp[((int64_t)(lb ^ 1) * W + w) * PDISP_SLOTS + lane] = 0u;
+    if (d.plist_n[e] >= 0 && D <= d.prune_half) continue;
+    const int64_t s0 = c * CL;
+    if (lane < CL) {
+      d.xprune[0][s0 + lane] = X0[s0 + lane];
+      d.xprune[1][s0 + lane] = X1[s0 + lane];
+      d.xprune[2][s0 + lane] = X2[s0 + lane];
+    }
+    const T far = (T)(8.0 * m.B[0]);
+    T lox = far, loy = far, loz = far, hix = -far, hiy = -far, hiz = -far;
+#pragma unroll
+    for (int ii = 0; ii < CL; ++ii) {
+      if (d.orig[s0 + ii] >= 0) {
+        lox = fmin(lox, X0[s0 + ii]);
+        loy = fmin(loy, X1[s0 + ii]);
+        loz = fmin(loz, X2[s0 + ii]);
+        hix = fmax(hix, X0[s0 + ii]);
+        hiy = fmax(hiy, X1[s0 + ii]);
+        hiz = fmax(hiz, X2[s0 + ii]);
+      }
+    }
+    const uint32_t *lst = d.list + c * (int64_t)d.list_cap;
+    uint32_t *out = d.plist + e * (int64_t)d.plist_cap;
+    const int cap = d.plist_cap;
+    const int nenv = d.list_nenv[c];
+    const int64_t ws0 = m.cl_begin * CL;
+    int cnt = 0;
+    // Batches of 64 entries: one coalesced load of the entries, then the
+    // candidates of all eight passes gathered at once (lane -> entry
+    // b0 + 8 t + lane / 8, atom lane % 8 in pass t), then tested and
+    // compacted pass by pass.  The cluster's own entry comes first, so its
+    // atoms open the pruned list (chunk 0).  Unused slots hold positions
+    // B + 3L, farther than L from every atom image: they never pass.
+    for (int b0 = 0; b0 < nenv; b0 += WAVE) {
+      const uint32_t eb = lst[min(b0 + lane, nenv - 1)];
+      T xj[CL], yj[CL], zj[CL];
+      uint32_t val[CL];
+#pragma unroll
+      for (int t = 0; t < CL; ++t) {
+        const uint32_t ent = (uint32_t)__shfl((int)eb, t * CL + (lane >> 3), WAVE);
+        const int code = (int)(ent >> SHIFT_BITS);
+        const int64_t js = (int64_t)(ent & CL_MASK) * CL + (lane & 7);
+        xj[t] = X0[js] + shx[code];
+        yj[t] = X1[js] + shy[code];
+        zj[t] = X2[js] + shz[code];
+        val[t] = (uint32_t)(js - ws0) | ((uint32_t)code << SHIFT_BITS);
+      }
+#pragma unroll
+      for (int t = 0; t < CL; ++t) {
+        const T gx = fmax(fmax(lox - xj[t], xj[t] - hix), (T)0);
+        const T gy = fmax(fmax(loy - yj[t], yj[t] - hiy), (T)0);
+        const T gz = fmax(fmax(loz - zj[t], zj[t] - hiz), (T)0);
+        const bool keep = b0 + t * CL + (lane >> 3) < nenv && fma(gz, gz, fma(gy, gy, gx * gx)) < d.prune_r2;
+        const unsigned long long bal = __ballot(keep);
+        const int pos = cnt + lanes_below(bal);
+        if (keep && pos < cap) out[pos] = val[t];
+        cnt += __popcll(bal);
+      }
+    }
+    if (cnt > cap) {
+      if (lane == 0) atomicOr(&d.status[w], 8u);
+      cnt = cap;
+    }
+    // fill the last chunk
+    const int nch = (cnt + WAVE - 1) / WAVE;
+    const int pad = (nch - 1) * WAVE + lane;
+    if (nch > 0 && pad >= cnt) out[pad] = PRUNE_PAD;
+    if (lane == 0) d.plist_n[e] = nch;
   }
 }
 
 // ---------------------------------------------------------------------------
 // environment pair kernel
 // ---------------------------------------------------------------------------
-// Per-wave LDS ring of pruned j atoms (position, scaled charge; sigma/2 and
-// sqrt(24 eps) for per-atom mixing).  At most 63 + 64 entries are pending.
-constexpr int RING = 128;
-template <typename T, bool LB>
-struct Ring {
-  T x[RING], y[RING], z[RING], q[RING];
-  T a[LB ? RING : 1], b[LB ? RING : 1];
-  __device__ __forceinline__ void put(int k, T xj, T yj, T zj, T qj, T aj, T bj) {
-    x[k] = xj;
-    y[k] = yj;
-    z[k] = zj;
-    q[k] = qj;
-    if (LB) {
-      a[k] = aj;
-      b[k] = bj;
-    }
-  }
-  __device__ __forceinline__ void get(int k, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj) const {
-    xj = x[k];
-    yj = y[k];
-    zj = z[k];
-    qj = q[k];
-    aj = LB ? a[k] : (T)0;
-    bj = LB ? b[k] : (T)0;
-  }
-};
 // Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut) written as the
 // bare Coulomb pair minus a correction: F/r = qq r^-3 - c, where c is what
 // ewald_corr returns, and U = qq/r - qq gE (in ue; used by the energy
@@ -794,13 +894,16 @@ __device__ __forceinline__ DrTerm dr_term(const Dev<T> &d, const WalkerMeta &m, 
   return t;
 }
 
+// Returns the squared displacement of the new position from the position at
+// the last prune (used by the environment atoms' integration only).
 template <typename T>
-__device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int xb, int vb, int w,
-                                               int64_t step, bool pending, const double F[3]) {
+__device__ __forceinline__ double integrate_atom(const Dev<T> &d, int64_t s, int xb, int vb, int w,
+                                                 int64_t step, bool pending, const double F[3]) {
   const T h = (T)(0.5 * d.dt);
   const T c1 = (T)d.c1;
   const T im = d.aim[s], sd = d.nsd[s];
   double z[4];
+  T xo[3];
   gauss4(d.seed, (uint32_t)d.orig[s], (uint32_t)step, (uint32_t)w, 0u, z);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -816,6 +919,36 @@ __device__ __forceinline__ void integrate_atom(const Dev<T> &d, int64_t s, int x
     // no wrap here: the cluster-pair list fixes the periodic image of every
     // cluster pair until the next rebuild, which wraps positions back.
     d.X[xb ^ 1][k][s] = x;
+    xo[k] = x;
+  }
+  double r2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = (double)(xo[k] - d.xprune[k][s]);  // exact: one storage grid
+    r2 += u * u;
+  }
+  return r2;
+}
+
+// Largest displacement since the prune over the lanes of one walker, rounded
+// up, into the buffer the next step's prune test reads (slot `slot` of the
+// walker's PDISP_SLOTS: atomics on one address per walker would serialise).
+// Every lane of the wave takes part; w < 0: nothing to record.
+template <typename T>
+__device__ __forceinline__ void record_disp(const Dev<T> &d, int lb, int w, int slot, double r2) {
+  bool pend = w >= 0 && r2 > 0.0;
+  unsigned long long bal = __ballot(pend);
+  while (bal) {
+    const int lead = __ffsll((long long)bal) - 1;
+    const int wl = __shfl(w, lead, WAVE);
+    double v = (pend && w == wl) ? r2 : 0.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    if (lane_id() == lead)
+      atomicMax(&d.pdisp[((int64_t)(lb ^ 1) * d.n_walkers + wl) * PDISP_SLOTS + (slot & (PDISP_SLOTS - 1))],
+                __float_as_uint(__double2float_ru(sqrt(v))));
+    if (w == wl) pend = false;
+    bal = __ballot(pend);
   }
 }
 
@@ -935,92 +1068,65 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   shy[lane] = (T)img_y(lane) * (T)m.L[1];
   shz[lane] = (T)img_z(lane) * (T)m.L[2];
   __builtin_amdgcn_wave_barrier();
-  // Candidate j atoms of list entries [e0, e0 + 8): lane -> (entry, atom).
-  auto load_j = [&](int e0, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj, int &js) {
-    const int ee = e0 + (lane >> 3);
-    xj = far;
-    yj = far;
-    zj = far;
-    qj = (T)0;
-    aj = (T)0;
-    bj = (T)0;
-    js = -1;
-    if (ee < nenv) {
-      const uint32_t ent = lst[ee];
-      const int64_t J = ent & CL_MASK;
-      const int code = (int)(ent >> SHIFT_BITS);
-      js = (int)(J * CL + (lane & 7));
-      xj = X0[js] + shx[code];
-      yj = X1[js] + shy[code];
-      zj = X2[js] + shz[code];
-      qj = d.q[js];
-      if (LB) {
-        aj = d.lja[js];
-        bj = d.ljb[js];
-      }
-    }
+  // The pruned list, 64 j atoms per chunk (chunk 0 opens with the cluster's
+  // own atoms: the self pairs are masked there).  The list streams from HBM
+  // while the atoms it names are in L2: a chunk's entries are loaded two
+  // chunks ahead, its atoms one chunk ahead, the gathers issued before the
+  // entry loads (loads complete in order, so waiting for a gather does not
+  // wait for HBM).  Two register sets take turns (no copies, which would
+  // wait for loads in flight).  Slot offsets are 32-bit byte offsets (fewer
+  // than 2^29 slots) so that the loads take a scalar base and a lane offset.
+  const int nch = d.plist_n[e];
+  typedef __attribute__((address_space(1))) const uint32_t gu32;
+  gu32 *pl = (gu32 *)(d.plist + e * (int64_t)d.plist_cap);
+  const uint32_t wsb = (uint32_t)(m.cl_begin * CL) * (uint32_t)sizeof(T);
+  struct Jset {
+    T x, y, z, q, a, b;
   };
-  {
-    // first 8 entries (the cluster's own entry among them) unpruned, with
-    // the self pairs masked
-    T xj, yj, zj, qj, aj, bj;
-    int js;
-    load_j(0, xj, yj, zj, qj, aj, bj, js);
-    env_pairs<T, LB, ENERGY, true, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
-                                              vmask, fx, fy, fz, eacc, ewt);
-  }
-  if (nenv > CL) {
-    // Remaining entries: a j atom farther than r_cut from the box of the 8
-    // i atoms cannot interact with any of them, so it is dropped before the
-    // pair arithmetic; survivors are compacted through a per-wave LDS ring
-    // and evaluated 64 at a time.  Coordinates are exact multiples of the
-    // storage grid, so the box gaps are exact and, with the same fma order as
-    // r^2, the box distance never exceeds any member pair's r^2: no pair
-    // inside the cutoff is dropped.
-    __shared__ Ring<T, LB> ring[4];
-    Ring<T, LB> &rg = ring[threadIdx.x >> 6];
-    T lox = far, loy = far, loz = far, hix = -far, hiy = -far, hiz = -far;
-#pragma unroll
-    for (int ii = 0; ii < CL; ++ii) {
-      if (d.orig[s0 + ii] >= 0) {
-        lox = fmin(lox, xi[ii]);
-        loy = fmin(loy, yi[ii]);
-        loz = fmin(loz, zi[ii]);
-        hix = fmax(hix, xi[ii]);
-        hiy = fmax(hiy, yi[ii]);
-        hiz = fmax(hiz, zi[ii]);
-      }
+  const int last = nch - 1;
+  // each chunk's address passes an empty asm statement, so that the
+  // compiler cannot match it with a later iteration's and sink the load
+  auto entry = [&](int k) {
+    gu32 *pk = pl + min(k, last) * WAVE;
+    asm volatile("" : "+s"(pk));
+    return __builtin_nontemporal_load(pk + lane);
+  };
+  auto gather = [&](uint32_t ent, Jset &j) {
+    const int code = (int)(ent >> SHIFT_BITS);
+    const uint32_t bo = wsb + (ent & CL_MASK) * (uint32_t)sizeof(T);
+    j.x = ld_off(X0, bo) + shx[code];
+    j.y = ld_off(X1, bo) + shy[code];
+    j.z = ld_off(X2, bo) + shz[code];
+    j.q = ld_off(d.q, bo);
+    j.a = LB ? ld_off(d.lja, bo) : (T)0;
+    j.b = LB ? ld_off(d.ljb, bo) : (T)0;
+  };
+  auto pairs = [&](const Jset &j) {
+    env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, j.x, j.y, j.z, j.q, j.a,
+                                               j.b, -1, vmask, fx, fy, fz, eacc, ewt);
+  };
+  if (nch > 0) {
+    // chunk k sits in ja (k even) or jb (k odd); at step k the entries of
+    // chunk k + 1 are in ua (k even) or ub (k odd)
+    const uint32_t u0 = entry(0);
+    uint32_t ua = entry(1), ub = entry(2);
+    Jset ja, jb;
+    gather(u0, ja);
+    gather(ua, jb);
+    ua = entry(3);
+    const int js0 = (int)(m.cl_begin * CL + (u0 & CL_MASK));
+    env_pairs<T, LB, ENERGY, true, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, ja.x, ja.y, ja.z, ja.q,
+                                              ja.a, ja.b, js0, vmask, fx, fy, fz, eacc, ewt);
+    int k = 1;
+    for (; k + 1 < nch; k += 2) {
+      gather(ub, ja);
+      ub = entry(k + 3);
+      pairs(jb);
+      gather(ua, jb);
+      ua = entry(k + 4);
+      pairs(ja);
     }
-    int head = 0, cnt = 0;
-    for (int e0 = CL; e0 < nenv; e0 += CL) {
-      T xj, yj, zj, qj, aj, bj;
-      int js;
-      load_j(e0, xj, yj, zj, qj, aj, bj, js);
-      const T gx = fmax(fmax(lox - xj, xj - hix), (T)0);
-      const T gy = fmax(fmax(loy - yj, yj - hiy), (T)0);
-      const T gz = fmax(fmax(loz - zj, zj - hiz), (T)0);
-      const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < d.rc2;
-      const unsigned long long bal = __ballot(keep);
-      if (keep) rg.put((head + cnt + lanes_below(bal)) & (RING - 1), xj, yj, zj, qj, aj, bj);
-      cnt += __popcll(bal);
-      if (cnt >= WAVE) {
-        __builtin_amdgcn_wave_barrier();
-        T x2, y2, z2, q2, a2, b2;
-        rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
-        __builtin_amdgcn_wave_barrier();
-        env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
-                                        vmask, fx, fy, fz, eacc, ewt);
-        head = (head + WAVE) & (RING - 1);
-        cnt -= WAVE;
-      }
-    }
-    if (cnt > 0) {
-      __builtin_amdgcn_wave_barrier();
-      T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
-      if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
-      env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
-                                      vmask, fx, fy, fz, eacc, ewt);
-    }
+    if (k < nch) pairs(jb);
   }
   if (!EONLY && nenv < n) {
     // alchemical partners: one atom per alchemical cluster (slot 0), 64 per pass
@@ -1070,7 +1176,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       }
     }
   }
-  double eres = 0.0;
+  double eres = 0.0, dq = 0.0;
   if ((lane & 7) == 0) {
     const int64_t s = s0 + (lane >> 3);
     const bool valid = d.orig[s] >= 0;
@@ -1111,7 +1217,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     if (INTEG) {
       if (valid) {
         const int64_t st = d.step[lb * d.n_walkers + w];
-        integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
+        dq = integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
       } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
@@ -1121,6 +1227,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
     }
   }
+  if (INTEG) record_disp(d, lb, w, (int)e, dq);
   if (ENERGY) {
     const double et = wave_sum(eacc), er = wave_sum(eres);
     if (lane == 0) {
@@ -1241,7 +1348,7 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
       }
     }
     if (INTEG) {
-      integrate_atom<T>(d, s, xb, vb, w, step, pending, F);
+      (void)integrate_atom<T>(d, s, xb, vb, w, step, pending, F);
     } else {
 #pragma unroll
       for (int q = 0; q < 3; ++q) d.fout[(int64_t)q * d.n_slots + s] = F[q];
@@ -1823,22 +1930,28 @@ static void env_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_env_integrate(Dev<T> d, Range r, int xb, int vb, int lb) {
   const int64_t s = r.c0 * CL + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s >= (r.c0 + r.cn) * CL) return;
-  const int64_t c = s / CL;
-  const int w = d.cl_walker[c];
-  const WalkerMeta &m = d.meta[w];
-  if (c - m.cl_begin >= d.n_env[w]) return;  // unused or alchemical cluster
-  const int64_t S = d.n_slots;
-  if (d.orig[s] >= 0) {
-    double F[3];
+  int wd = -1;  // walker of a displacement to record
+  double dq = 0.0;
+  if (s < (r.c0 + r.cn) * CL) {
+    const int64_t c = s / CL;
+    const int w = d.cl_walker[c];
+    const WalkerMeta &m = d.meta[w];
+    if (c - m.cl_begin < d.n_env[w]) {  // not an unused or alchemical cluster
+      const int64_t S = d.n_slots;
+      if (d.orig[s] >= 0) {
+        double F[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) F[k] = d.fout[k * S + s] + d.pme_frc[k * S + s];
-    const int64_t st = d.step[lb * d.n_walkers + w];
-    integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
-  } else {
+        for (int k = 0; k < 3; ++k) F[k] = d.fout[k * S + s] + d.pme_frc[k * S + s];
+        const int64_t st = d.step[lb * d.n_walkers + w];
+        dq = integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
+        wd = w;
+      } else {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+        for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+      }
+    }
   }
+  record_disp(d, lb, wd, (int)blockIdx.x, dq);
 }
 
 // Reciprocal-space force added to the forces-only output of k_env (which
@@ -1858,15 +1971,27 @@ __global__ __launch_bounds__(256) void k_env_recip(Dev<T> d, Range r) {
 }
 
 template <typename T>
+hipError_t Launch<T>::prune(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
+  const int64_t nw = (r.en + PRUNE_CPW - 1) / PRUNE_CPW;
+  const int nb = (int)((nw + 3) / 4);
+  const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
+  if (grid > 0) k_prune<T><<<grid, 256, 0, s>>>(d, r, xb, lb);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                            hipStream_t s) {
   if (d.pme_on) {
     hipError_t e = pme(d, r, xb, lb, s);
     if (e == hipSuccess) e = step_alch(d, r, xb, vb, lb, s);
+    if (e == hipSuccess) e = prune(d, r, xb, lb, s);
     if (e == hipSuccess) e = step_env(d, r, xb, vb, lb, s);
     if (e == hipSuccess) e = env_integrate(d, r, xb, vb, lb, s);
     return e;
   }
+  const hipError_t e = prune(d, r, xb, lb, s);
+  if (e != hipSuccess) return e;
   if (r.in_ > 0) k_alch<T, false, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
   env_launch<T>(d, r, xb, vb, lb, 0, true, s);
   return hipGetLastError();
@@ -1907,6 +2032,8 @@ hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int 
     if (e != hipSuccess) return e;
   }
   const unsigned ni = (unsigned)r.in_;
+  const hipError_t ep = prune(d, r, xb, lb, s);
+  if (ep != hipSuccess) return ep;
   if (mode == EVAL_ENERGY) {
     if (ni) k_alch<T, true, false, false><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
     env_launch<T>(d, r, xb, vb, lb, 2, false, s);

@@ -435,10 +435,10 @@ class System:
 
     def profile_steps(self, n_steps: int) -> dict:
         """Per-kernel times (ms) from HIP events around single launches."""
-        ms = np.zeros(4)
+        ms = np.zeros(5)
         self._chk(lib().labf_profile_steps(self._h, int(n_steps), _p(ms), self.stream))
         return dict(rebuild_ms=float(ms[0]), alch_ms=float(ms[1]), env_ms=float(ms[2]),
-                    pme_ms=float(ms[3]))
+                    pme_ms=float(ms[3]), prune_ms=float(ms[4]))
 
     def info(self) -> dict:
         inf = Info()
