@@ -432,6 +432,8 @@ def main(argv=None):
                     help="timed forward+backward evaluations of 8 walkers (0: skip)")
     ap.add_argument("--pme-only", action="store_true",
                     help="run only the smooth-PME section (for profiling) and print its JSON")
+    ap.add_argument("--prune-buffer", type=float, default=0.0,
+                    help="pair-list prune buffer b in A (0: the library default, min(0.5, skin/2))")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -464,6 +466,7 @@ def main(argv=None):
     specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
     log(f"equilibrating the batch at its initial lambdas for {args.batch_equil_steps} steps")
     specb, lamb = equilibrate(specb, lamb, args.batch_equil_steps, lambda_dynamics=True)
+    specb.prune_buffer = args.prune_buffer
     if args.pme_only:
         print(json.dumps({"pme": run_pme(args, specb, lamb)}), flush=True)
         return 0

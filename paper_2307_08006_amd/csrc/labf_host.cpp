@@ -287,6 +287,8 @@ labf_status validate_desc(const labf_system_desc *d) {
   if (d->max_bins < 0 || d->max_bins > 4096) return fail(nullptr, LABF_E_ARG, "max_bins must be 0 (1024) or 1..4096");
   if (d->list_capacity != 0 && (d->list_capacity < 16 || d->list_capacity > (1 << 20)))
     return fail(nullptr, LABF_E_ARG, "list_capacity must be 0 (estimated) or 16..2^20");
+  if (!(d->prune_buffer >= 0.0 && d->prune_buffer <= d->r_skin))
+    return fail(nullptr, LABF_E_ARG, "prune_buffer must be 0 (default) or in (0, r_skin]");
   if (d->column_width)
     for (int w = 0; w < d->n_walkers; ++w)
       if (!(d->column_width[w] >= 0.5 && d->column_width[w] <= 2.0))
@@ -1069,9 +1071,9 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.list_cap = h.list_cap;
   d.plist_cap = h.plist_cap;
   {
-    // prune buffer: half the skin, at most 0.5 A; the re-prune threshold
-    // keeps 1e-4 A for the rounding of the box distances
-    const double b = std::min(0.5, 0.5 * desc->r_skin);
+    // prune buffer: the given one, else half the skin, at most 0.5; the
+    // re-prune threshold keeps 1e-4 for the rounding of the box distances
+    const double b = desc->prune_buffer > 0.0 ? desc->prune_buffer : std::min(0.5, 0.5 * desc->r_skin);
     d.prune_r2 = (T)((desc->r_cut + b) * (desc->r_cut + b));
     d.prune_half = (float)(0.5 * b - 1e-4);
   }

@@ -65,6 +65,7 @@ class SystemSpec:
     rebuild_interval: int = 10
     r_skin_alch: float = 0.0             # list buffer of alchemical pairs; 0 -> r_skin
     column_width: Optional[np.ndarray] = None  # float64 [W] cluster column width factor; None -> 1
+    prune_buffer: float = 0.0            # pair-list prune buffer b (A); 0 -> min(0.5, r_skin / 2)
     pme_dims: Optional[np.ndarray] = None  # int32 [W,3] PME grid (2^a 3^b 5^c, multiples of 8); None -> no PME
     ewald_beta: float = 0.0              # Ewald splitting parameter (1/A) when pme_dims is set
     pme_order: int = 4                   # B-spline order of the PME charge assignment

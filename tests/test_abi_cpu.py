@@ -143,6 +143,9 @@ def test_workspace_size_is_host_arithmetic():
     assert labf.workspace_size(b2) > 2 * n1
     assert labf.workspace_size(spec, max_bins=4096) > labf.workspace_size(spec, max_bins=64)
     assert labf.workspace_size(spec, list_capacity=4096) > labf.workspace_size(spec, list_capacity=256)
+    # the pruned lists hold up to every atom of a cluster list's entries
+    assert (labf.workspace_size(spec, list_capacity=512) - labf.workspace_size(spec, list_capacity=256)
+            >= 256 * 4 * (1 + 8) * int(np.ceil(spec.n_atoms / 8)))
     # PME grids live in the workspace too
     sp = synth.with_pme(dataclasses.replace(spec), dims=(16, 16, 32))
     assert labf.workspace_size(sp) >= n1 + 16 * 16 * 32 * 16
@@ -151,6 +154,8 @@ def test_workspace_size_is_host_arithmetic():
 @pytest.mark.parametrize("field,value,msg", [
     ("max_bins", -1, "max_bins"), ("max_bins", 5000, "max_bins"),
     ("list_capacity", 3, "list_capacity"), ("list_capacity", (1 << 20) + 1, "list_capacity"),
+    ("prune_buffer", -0.1, "prune_buffer"), ("prune_buffer", 5.0, "prune_buffer"),
+    ("prune_buffer", float("nan"), "prune_buffer"),
 ])
 def test_workspace_size_validates_the_descriptor(field, value, msg):
     _ensure_built()

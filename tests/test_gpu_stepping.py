@@ -147,9 +147,19 @@ def _batch16x30k():
     return synth.batch(base, lam, 16, seed=synth.BASE_SEED + 2)
 
 
+def _pruned(b):
+    """The 3,000-atom system with prune buffer b: 0.02 A re-prunes the pair
+    lists at almost every step, 1.5 A (the list buffer) only at rebuilds."""
+    spec, lam = _charged3k()
+    spec.prune_buffer = b
+    return spec, lam
+
+
 STEP_CASES = {
     "charged3k_fp32": lambda: _charged3k(),
     "charged3k_fp32_mixedlj": lambda: _charged3k(0.15),
+    "charged3k_fp32_prune_every_step": lambda: _pruned(0.02),
+    "charged3k_fp32_prune_at_rebuilds": lambda: _pruned(1.5),
     "batch16x30k_fp32": _batch16x30k,
 }
 
