@@ -33,6 +33,11 @@ template <typename T>
 __device__ __forceinline__ T ld_off(const T *base, uint32_t bo) {
   return *(const T *)((const char *)base + bo);
 }
+// store at a 32-bit byte offset from a base pointer
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, uint32_t bo, T v) {
+  *(T *)((char *)base + bo) = v;
+}
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 // hardware reciprocal in FP32 (about 1 ulp), a true division in FP64

@@ -604,7 +604,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
 // reference configuration); the cluster list itself stays valid while the
 // displacements since the rebuild stay within the skin (the k_skin test).
 // A stale list (after a rebuild) is always pruned.
-constexpr int PRUNE_CPW = 4;  // clusters per wave of k_prune
+constexpr int PRUNE_CPW = 2;  // clusters per wave of k_prune
 template <typename T>
 __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb) {
   const int64_t nw = (r.en + PRUNE_CPW - 1) / PRUNE_CPW;  // waves in all
@@ -670,35 +670,39 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
     const int nenv = d.list_nenv[c];
     const int64_t ws0 = m.cl_begin * CL;
     int cnt = 0;
-    // Batches of 64 entries: one coalesced load of the entries, then the
-    // candidates of all eight passes gathered at once (lane -> entry
+    // Batches of 32 entries: one coalesced load of the entries, then the
+    // candidates of all four passes gathered at once (lane -> entry
     // b0 + 8 t + lane / 8, atom lane % 8 in pass t), then tested and
     // compacted pass by pass.  The cluster's own entry comes first, so its
     // atoms open the pruned list (chunk 0).  Unused slots hold positions
     // B + 3L, farther than L from every atom image: they never pass.
-    for (int b0 = 0; b0 < nenv; b0 += WAVE) {
-      const uint32_t eb = lst[min(b0 + lane, nenv - 1)];
-      T xj[CL], yj[CL], zj[CL];
-      uint32_t val[CL];
+    // Slot offsets are 32-bit byte offsets (fewer than 2^29 slots).
+    const uint32_t wsl = (uint32_t)ws0;
+    for (int b0 = 0; b0 < nenv; b0 += 4 * CL) {
+      const uint32_t eb = lst[min(b0 + (lane & 31), nenv - 1)];
+      T xj[4], yj[4], zj[4];
+      uint32_t val[4];
 #pragma unroll
-      for (int t = 0; t < CL; ++t) {
+      for (int t = 0; t < 4; ++t) {
         const uint32_t ent = (uint32_t)__shfl((int)eb, t * CL + (lane >> 3), WAVE);
-        const int code = (int)(ent >> SHIFT_BITS);
-        const int64_t js = (int64_t)(ent & CL_MASK) * CL + (lane & 7);
-        xj[t] = X0[js] + shx[code];
-        yj[t] = X1[js] + shy[code];
-        zj[t] = X2[js] + shz[code];
-        val[t] = (uint32_t)(js - ws0) | ((uint32_t)code << SHIFT_BITS);
+        const uint32_t code = ent >> SHIFT_BITS;
+        const uint32_t js = (ent & CL_MASK) * CL + (uint32_t)(lane & 7);
+        const uint32_t bo = js * (uint32_t)sizeof(T);
+        xj[t] = ld_off(X0, bo) + shx[code];
+        yj[t] = ld_off(X1, bo) + shy[code];
+        zj[t] = ld_off(X2, bo) + shz[code];
+        val[t] = (js - wsl) | (code << SHIFT_BITS);
       }
+      const bool room = cnt + 4 * WAVE <= cap;
 #pragma unroll
-      for (int t = 0; t < CL; ++t) {
+      for (int t = 0; t < 4; ++t) {
         const T gx = fmax(fmax(lox - xj[t], xj[t] - hix), (T)0);
         const T gy = fmax(fmax(loy - yj[t], yj[t] - hiy), (T)0);
         const T gz = fmax(fmax(loz - zj[t], zj[t] - hiz), (T)0);
         const bool keep = b0 + t * CL + (lane >> 3) < nenv && fma(gz, gz, fma(gy, gy, gx * gx)) < d.prune_r2;
         const unsigned long long bal = __ballot(keep);
         const int pos = cnt + lanes_below(bal);
-        if (keep && pos < cap) out[pos] = val[t];
+        if (keep && (room || pos < cap)) st_off(out, (uint32_t)pos * 4u, val[t]);
         cnt += __popcll(bal);
       }
     }
