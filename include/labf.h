@@ -158,7 +158,9 @@ typedef struct labf_system_desc {
                                   box, pruned after each rebuild and again whenever an atom of the
                                   walker has moved more than b/2 since (a larger b prunes less
                                   often and evaluates more pairs); 0: min(0.5, r_skin/2) in
-                                  length units; else 0 < b <= r_skin */
+                                  length units; else 0 < b <= r_skin.  Unused with pme_order > 0
+                                  (the real-space Ewald kernels prune the cluster lists as they
+                                  evaluate them) */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF

@@ -733,7 +733,8 @@ labf_status plan_system(const labf_system_desc *desc, HostLayout &h) {
   }
   // a pruned list keeps at most every atom of the cluster list's entries;
   // its entries address walker-relative slots in SHIFT_BITS bits
-  h.plist_cap = (CL * h.list_cap + WAVE - 1) / WAVE * WAVE;
+  // (none with Ewald electrostatics: those kernels prune on the fly)
+  h.plist_cap = desc->pme_order ? 0 : (CL * h.list_cap + WAVE - 1) / WAVE * WAVE;
   for (int w = 0; w < W; ++w)
     if (((int64_t)h.meta[w].cap_env + h.meta[w].n_acl) * CL > (int64_t)CL_MASK)
       return fail(nullptr, LABF_E_UNSUPPORTED, "too many atoms in one walker");

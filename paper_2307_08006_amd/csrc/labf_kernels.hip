@@ -721,6 +721,33 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
 // ---------------------------------------------------------------------------
 // environment pair kernel
 // ---------------------------------------------------------------------------
+// Per-wave LDS ring of pruned j atoms (position, scaled charge; sigma/2 and
+// sqrt(24 eps) for per-atom mixing) of the real-space Ewald kernels, which
+// prune their cluster lists as they go.  At most 63 + 64 entries are pending.
+constexpr int RING = 128;
+template <typename T, bool LB>
+struct Ring {
+  T x[RING], y[RING], z[RING], q[RING];
+  T a[LB ? RING : 1], b[LB ? RING : 1];
+  __device__ __forceinline__ void put(int k, T xj, T yj, T zj, T qj, T aj, T bj) {
+    x[k] = xj;
+    y[k] = yj;
+    z[k] = zj;
+    q[k] = qj;
+    if (LB) {
+      a[k] = aj;
+      b[k] = bj;
+    }
+  }
+  __device__ __forceinline__ void get(int k, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj) const {
+    xj = x[k];
+    yj = y[k];
+    zj = z[k];
+    qj = q[k];
+    aj = LB ? a[k] : (T)0;
+    bj = LB ? b[k] : (T)0;
+  }
+};
 // Real-space Ewald pair (qq erfc(beta r)/r, cut at r_cut) written as the
 // bare Coulomb pair minus a correction: F/r = qq r^-3 - c, where c is what
 // ewald_corr returns, and U = qq/r - qq gE (in ue; used by the energy
@@ -1072,6 +1099,7 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
   shy[lane] = (T)img_y(lane) * (T)m.L[1];
   shz[lane] = (T)img_z(lane) * (T)m.L[2];
   __builtin_amdgcn_wave_barrier();
+  if constexpr (!EW) {
   // The pruned list, 64 j atoms per chunk (chunk 0 opens with the cluster's
   // own atoms: the self pairs are masked there).  The list streams from HBM
   // while the atoms it names are in L2: a chunk's entries are loaded two
@@ -1131,6 +1159,98 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       pairs(ja);
     }
     if (k < nch) pairs(jb);
+  }
+  } else {
+    // Real-space Ewald: the table lookups leave the kernel latency-bound,
+    // and the compact lists measured no faster than pruning the cluster
+    // list on the fly, which costs no separate prune: cluster list here.
+  // Candidate j atoms of list entries [e0, e0 + 8): lane -> (entry, atom).
+  auto load_j = [&](int e0, T &xj, T &yj, T &zj, T &qj, T &aj, T &bj, int &js) {
+    const int ee = e0 + (lane >> 3);
+    xj = far;
+    yj = far;
+    zj = far;
+    qj = (T)0;
+    aj = (T)0;
+    bj = (T)0;
+    js = -1;
+    if (ee < nenv) {
+      const uint32_t ent = lst[ee];
+      const int64_t J = ent & CL_MASK;
+      const int code = (int)(ent >> SHIFT_BITS);
+      js = (int)(J * CL + (lane & 7));
+      xj = X0[js] + shx[code];
+      yj = X1[js] + shy[code];
+      zj = X2[js] + shz[code];
+      qj = d.q[js];
+      if (LB) {
+        aj = d.lja[js];
+        bj = d.ljb[js];
+      }
+    }
+  };
+  {
+    // first 8 entries (the cluster's own entry among them) unpruned, with
+    // the self pairs masked
+    T xj, yj, zj, qj, aj, bj;
+    int js;
+    load_j(0, xj, yj, zj, qj, aj, bj, js);
+    env_pairs<T, LB, ENERGY, true, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, xj, yj, zj, qj, aj, bj, js,
+                                              vmask, fx, fy, fz, eacc, ewt);
+  }
+  if (nenv > CL) {
+    // Remaining entries: a j atom farther than r_cut from the box of the 8
+    // i atoms cannot interact with any of them, so it is dropped before the
+    // pair arithmetic; survivors are compacted through a per-wave LDS ring
+    // and evaluated 64 at a time.  Coordinates are exact multiples of the
+    // storage grid, so the box gaps are exact and, with the same fma order as
+    // r^2, the box distance never exceeds any member pair's r^2: no pair
+    // inside the cutoff is dropped.
+    __shared__ Ring<T, LB> ring[4];
+    Ring<T, LB> &rg = ring[threadIdx.x >> 6];
+    T lox = far, loy = far, loz = far, hix = -far, hiy = -far, hiz = -far;
+#pragma unroll
+    for (int ii = 0; ii < CL; ++ii) {
+      if (d.orig[s0 + ii] >= 0) {
+        lox = fmin(lox, xi[ii]);
+        loy = fmin(loy, yi[ii]);
+        loz = fmin(loz, zi[ii]);
+        hix = fmax(hix, xi[ii]);
+        hiy = fmax(hiy, yi[ii]);
+        hiz = fmax(hiz, zi[ii]);
+      }
+    }
+    int head = 0, cnt = 0;
+    for (int e0 = CL; e0 < nenv; e0 += CL) {
+      T xj, yj, zj, qj, aj, bj;
+      int js;
+      load_j(e0, xj, yj, zj, qj, aj, bj, js);
+      const T gx = fmax(fmax(lox - xj, xj - hix), (T)0);
+      const T gy = fmax(fmax(loy - yj, yj - hiy), (T)0);
+      const T gz = fmax(fmax(loz - zj, zj - hiz), (T)0);
+      const bool keep = fma(gz, gz, fma(gy, gy, gx * gx)) < d.rc2;
+      const unsigned long long bal = __ballot(keep);
+      if (keep) rg.put((head + cnt + lanes_below(bal)) & (RING - 1), xj, yj, zj, qj, aj, bj);
+      cnt += __popcll(bal);
+      if (cnt >= WAVE) {
+        __builtin_amdgcn_wave_barrier();
+        T x2, y2, z2, q2, a2, b2;
+        rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
+        __builtin_amdgcn_wave_barrier();
+        env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+                                        vmask, fx, fy, fz, eacc, ewt);
+        head = (head + WAVE) & (RING - 1);
+        cnt -= WAVE;
+      }
+    }
+    if (cnt > 0) {
+      __builtin_amdgcn_wave_barrier();
+      T x2 = far, y2 = far, z2 = far, q2 = (T)0, a2 = (T)0, b2 = (T)0;
+      if (lane < cnt) rg.get((head + lane) & (RING - 1), x2, y2, z2, q2, a2, b2);
+      env_pairs<T, LB, ENERGY, false, EW, EONLY>(d, xi, yi, zi, qi, ai, bi, s0, x2, y2, z2, q2, a2, b2, -1,
+                                      vmask, fx, fy, fz, eacc, ewt);
+    }
+  }
   }
   if (!EONLY && nenv < n) {
     // alchemical partners: one atom per alchemical cluster (slot 0), 64 per pass
@@ -1976,6 +2096,7 @@ __global__ __launch_bounds__(256) void k_env_recip(Dev<T> d, Range r) {
 
 template <typename T>
 hipError_t Launch<T>::prune(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
+  if (d.pme_on) return hipSuccess;  // the Ewald kernels prune on the fly
   const int64_t nw = (r.en + PRUNE_CPW - 1) / PRUNE_CPW;
   const int nb = (int)((nw + 3) / 4);
   const unsigned grid = (unsigned)(8 * ((nb + 7) / 8));
