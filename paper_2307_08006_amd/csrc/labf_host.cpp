@@ -976,40 +976,54 @@ labf_status do_step(labf_system *s, int mode, hipStream_t st) {
 }
 
 // Batched block: [rebuild + interval steps] captured once per buffer parity.
+// A block flips the position and velocity buffers and keeps the lambda
+// buffer (interval + 1 and 1 flips, interval flips: the alternating keys
+// below), so the graph of the block after this one is captured together
+// with this one: no capture falls between two blocks later on.
+template <typename T>
+labf_status capture_block(labf_system *s, int xb, int vb, int xref, int lb) {
+  Dev<T> &d = s->dev<T>();
+  const int key = xb * 2 + vb + (xref ? 4 : 0) + lb * 8;
+  if (s->graphs.count(key)) return LABF_OK;
+  labf_status rc = ensure_streams(s);
+  if (rc != LABF_OK) return rc;
+  HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = Launch<T>::rebuild(d, full_range(s), xb, vb, xref, s->cap_stream);
+  xb ^= 1;
+  vb ^= 1;
+  // each step: the alchemical kernel (second stream) runs beside the
+  // environment kernel; they read the same positions and write disjoint
+  // slots, lambda and step counters are double-buffered
+  // with PME the reciprocal-space chain runs on the second stream beside
+  // the environment pair kernel, followed there by the alchemical kernel;
+  // the environment atoms are integrated once both forces are in
+  for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
+    e = batched_step<T>(s, xb, vb, lb, s->cap_stream);
+    xb ^= 1;
+    lb ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+  if (e != hipSuccess) return hip_fail(s, e, "graph capture");
+  if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  HIPCHK(s, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  s->graphs[key] = ex;
+  s->graph_defs[key] = g;
+  // move the graph to the device now rather than at its first launch
+  HIPCHK(s, hipGraphUpload(ex, s->cap_stream));
+  HIPCHK(s, hipStreamSynchronize(s->cap_stream));
+  return LABF_OK;
+}
+
 template <typename T>
 labf_status graph_block(labf_system *s, hipStream_t st) {
-  Dev<T> &d = s->dev<T>();
   const int key = s->xb * 2 + s->vb + (s->xref_valid ? 4 : 0) + s->lb * 8;
+  labf_status rc = capture_block<T>(s, s->xb, s->vb, s->xref_valid ? 1 : 0, s->lb);
+  if (rc == LABF_OK)
+    rc = capture_block<T>(s, s->xb ^ ((s->interval + 1) & 1), s->vb ^ 1, 1, s->lb ^ (s->interval & 1));
+  if (rc != LABF_OK) return rc;
   auto it = s->graphs.find(key);
-  if (it == s->graphs.end()) {
-    labf_status rc = ensure_streams(s);
-    if (rc != LABF_OK) return rc;
-    HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    int xb = s->xb, vb = s->vb, lb = s->lb;
-    hipError_t e = Launch<T>::rebuild(d, full_range(s), xb, vb, s->xref_valid ? 1 : 0, s->cap_stream);
-    xb ^= 1;
-    vb ^= 1;
-    // each step: the alchemical kernel (second stream) runs beside the
-    // environment kernel; they read the same positions and write disjoint
-    // slots, lambda and step counters are double-buffered
-    // with PME the reciprocal-space chain runs on the second stream beside
-    // the environment pair kernel, followed there by the alchemical kernel;
-    // the environment atoms are integrated once both forces are in
-    for (int i = 0; i < s->interval && e == hipSuccess; ++i) {
-      e = batched_step<T>(s, xb, vb, lb, s->cap_stream);
-      xb ^= 1;
-      lb ^= 1;
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
-    if (e != hipSuccess) return hip_fail(s, e, "graph capture");
-    if (e2 != hipSuccess) return hip_fail(s, e2, "hipStreamEndCapture");
-    hipGraphExec_t ex = nullptr;
-    HIPCHK(s, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-    s->graphs[key] = ex;
-    s->graph_defs[key] = g;
-    it = s->graphs.find(key);
-  }
   HIPCHK(s, hipGraphLaunch(it->second, st));
   s->xb ^= 1;
   s->vb ^= 1;
