@@ -133,6 +133,7 @@ def equilibrate(spec, lam, steps, lambda_dynamics=False):
 # walker-steps/s on 16 x 30k; the device's clocks ramp up under load), the
 # second 20 within 1 %.  The warm-up therefore runs at least this many steps.
 MIN_WARMUP_STEPS = 60
+ALGO_BYTES_PER_ATOM = 56
 
 
 def warm_up(s, spec, n):
@@ -159,23 +160,25 @@ def timed_steps(s, n, mode):
 
 def run_uneven(args):
     """64 walkers of 5k-60k atoms (log-uniform; restrained dense cluster,
-    decoupled ligand, solvent) in one batch, column widths from the
-    autotuner (tuned once per size class and cached), against the same batch
-    at the default width and in plain mode."""
+    decoupled ligand, solvent) in one batch, column widths and prune
+    buffers from the autotuner (tuned once per size class and cached),
+    against the same batch at the defaults and in plain mode."""
     from paper_2307_08006_amd import autotune, labf, synth
     spec, lam = synth.uneven(precision="fp32")
-    widths = autotune.tune(spec, lam, log=log)
+    widths, buffers = autotune.tune(spec, lam, log=log)
     log(f"uneven: {spec.n_walkers} walkers, {spec.n_atoms} atoms; equilibrating")
     spec, lam = equilibrate(spec, lam, args.uneven_equil_steps, lambda_dynamics=True)
     out = {"walkers": spec.n_walkers, "atoms": spec.n_atoms,
            "size_classes": [list(c) for c in autotune.CLASSES],
-           "column_width_per_class": {}}
+           "column_width_per_class": {}, "prune_buffer_per_class": {}}
     n = np.diff(spec.atom_offset)
     for lo, hi in autotune.CLASSES:
         m = (n >= lo) & (n < hi)
         out["column_width_per_class"][f"{lo}-{hi}"] = float(widths[m][0]) if m.any() else None
-    for label, wd in (("tuned", widths), ("default_width", np.ones(spec.n_walkers))):
-        sp = dataclasses.replace(spec, column_width=wd)
+        out["prune_buffer_per_class"][f"{lo}-{hi}"] = float(buffers[m][0]) if m.any() else None
+    for label, wd, pb in (("tuned", widths, buffers),
+                          ("default_width", np.ones(spec.n_walkers), None)):
+        sp = dataclasses.replace(spec, column_width=wd, prune_buffer=pb)
         with labf.System(sp, lam) as s:
             pairs0 = float(s.count_pairs().sum())
             warm_up(s, sp, args.warmup)
@@ -486,7 +489,8 @@ def main(argv=None):
     specb, lamb = synth.batch(spec1, lam1, args.walkers, seed=synth.BASE_SEED + 2)
     log(f"equilibrating the batch at its initial lambdas for {args.batch_equil_steps} steps")
     specb, lamb = equilibrate(specb, lamb, args.batch_equil_steps, lambda_dynamics=True)
-    specb.prune_buffer = args.prune_buffer
+    if args.prune_buffer > 0:
+        specb.prune_buffer = np.full(specb.n_walkers, args.prune_buffer)
     if args.pme_only:
         print(json.dumps({"pme": run_pme(args, specb, lamb)}), flush=True)
         return 0
@@ -578,6 +582,11 @@ def main(argv=None):
             "frac": achieved / VALU_PEAK_TOPS,
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            # positions and velocities read and written (48 B) plus 8 B of
+            # per-atom parameters: what one step must move per atom
+            "traffic_algorithmic": ALGO_BYTES_PER_ATOM * W * args.atoms,
+            "traffic_note": "the measured traffic adds the pruned pair lists (one 4-byte entry per "
+                            "evaluated j atom, streamed once per step) and the gathers' misses",
             "per_unit": f"{SLOTS_PER_PAIR} FP32 VALU lane-ops per in-cutoff environment pair",
             "units_per_launch": env_pairs_per_step,
             "frac_of_packed_fp32_peak": achieved / PACKED_VALU_PEAK_TOPS,

@@ -153,14 +153,15 @@ typedef struct labf_system_desc {
                                   labf_workspace_size bytes (labf_create_system only; ignored by
                                   labf_workspace_size) */
   size_t workspace_bytes;      /* its size in bytes */
-  double prune_buffer;         /* b: the environment kernel evaluates, per cluster of 8 atoms, the
-                                  atoms of its neighbour clusters within r_cut + b of the cluster's
-                                  box, pruned after each rebuild and again whenever an atom of the
-                                  walker has moved more than b/2 since (a larger b prunes less
-                                  often and evaluates more pairs); 0: min(0.5, r_skin/2) in
-                                  length units; else 0 < b <= r_skin.  Unused with pme_order > 0
-                                  (the real-space Ewald kernels prune the cluster lists as they
-                                  evaluate them) */
+  const double *prune_buffer;  /* [W] b per walker, or NULL: the environment kernel evaluates, per
+                                  cluster of 8 atoms, the atoms of its neighbour clusters within
+                                  r_cut + b of the cluster's box, pruned after each rebuild and
+                                  again whenever an atom of the walker has moved more than b/2
+                                  since (a larger b prunes less often and evaluates more pairs);
+                                  0 (or NULL): min(0.5, r_skin/2) in length units; else
+                                  0 < b <= r_skin.  The second knob an autotuner chooses per size
+                                  class.  Unused with pme_order > 0 (the real-space Ewald kernels
+                                  prune the cluster lists as they evaluate them) */
 } labf_system_desc;
 
 /* Extended-lambda and ABF parameters ("Software interface" and "ABF

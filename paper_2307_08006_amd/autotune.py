@@ -1,15 +1,18 @@
-"""Tile-shape autotuner for batches of uneven walkers.
+"""Tile-shape and prune-buffer autotuner for batches of uneven walkers.
 
-The tile of the pair kernel is a cluster of 8 atoms cut from a z-sorted
-x-y column; its shape is set by the column width (in units of
-(8/rho)^(1/3): 1 gives cubic clusters).  Wider columns mean fewer columns
-and less padding but flatter clusters whose boxes admit more j atoms;
-narrower ones the reverse.  For every size class present in a batch the
-tuner times the step of its representative walker (the member of median
-size, replicated to fill the GPU) for each candidate width and keeps the
-fastest.  The cost timed is what the width changes: the environment pair
-kernel per step plus the neighbour rebuild per step (HIP events around
-single launches, labf_profile_steps).
+Two knobs move the environment step.  The tile of the pair kernel is a
+cluster of 8 atoms cut from a z-sorted x-y column; its shape is set by the
+column width (in units of (8/rho)^(1/3): 1 gives cubic clusters).  Wider
+columns mean fewer columns and less padding but flatter clusters whose
+boxes admit more j atoms; narrower ones the reverse.  The prune buffer b
+sets how far beyond r_cut the per-cluster pair lists reach: a larger b
+prunes less often and evaluates more pairs.  For every size class present
+in a batch the tuner times the step of its representative walker (the
+member of median size, replicated to fill the GPU): first each candidate
+width at the default buffer, then each candidate buffer at the best width.
+The cost timed is what the knobs change: the environment pair kernel, the
+pruning and the neighbour rebuild per step (HIP events around single
+launches, labf_profile_steps over one rebuild block, twice).
 
 Results are cached in JSON keyed by GPU architecture, size class and
 precision; the file named by $LABF_AUTOTUNE_CACHE, else autotune_cache.json
@@ -28,6 +31,7 @@ from . import labf, synth
 # size classes by atoms per walker (lower bound inclusive)
 CLASSES = [(0, 10000), (10000, 20000), (20000, 40000), (40000, 1 << 62)]
 CANDIDATES = (0.8, 0.9, 1.0, 1.12, 1.25)
+PRUNE_CANDIDATES = (0.3, 0.5, 0.7, 0.9)  # A, at most the list buffer
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 
@@ -62,52 +66,79 @@ def save_cache(cache: dict, path: str | None = None) -> None:
         json.dump(cache, f, indent=1, sort_keys=True)
 
 
-def time_width(spec, lam, width: float, steps: int = 10, warmup: int = 10) -> dict:
-    """Per-step cost (ms) of a batch at one column width."""
-    sp = dataclasses.replace(spec, column_width=np.full(spec.n_walkers, float(width)))
+def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 2) -> dict:
+    """Per-step cost (ms) of a batch at one column width and prune buffer
+    (0: the library default), the mean of `reps` rebuild blocks."""
+    sp = dataclasses.replace(spec, column_width=np.full(spec.n_walkers, float(width)),
+                             prune_buffer=np.full(spec.n_walkers, float(prune_buffer)))
+    k = int(spec.rebuild_interval)
+    cost = []
     with labf.System(sp, lam) as s:
-        s.step(warmup)
-        prof = s.profile_steps(steps)
-    per_step = prof["env_ms"] + prof["rebuild_ms"] / spec.rebuild_interval
-    return dict(prof, per_step_ms=per_step)
+        s.step(2 * k)
+        for _ in range(reps):
+            prof = s.profile_steps(k)
+            cost.append(prof["env_ms"] + prof.get("prune_ms", 0.0) + prof["rebuild_ms"] / k)
+    return dict(prof, per_step_ms=float(np.mean(cost)))
 
 
 def cached_widths(spec, cache_path: str | None = None) -> np.ndarray:
     """Column widths from the cache only (1 where a class is not cached)."""
+    return cached_knobs(spec, cache_path)[0]
+
+
+def cached_knobs(spec, cache_path: str | None = None):
+    """(column widths, prune buffers) per walker from the cache only (1 and
+    0, the library default, where a class is not cached)."""
     cache = load_cache(cache_path)
     a = arch()
-    return np.array([cache.get(_key(a, size_class(int(x)), spec.precision), {}).get("column_width", 1.0)
-                     for x in np.diff(spec.atom_offset)], dtype=np.float64)
+    ent = [cache.get(_key(a, size_class(int(x)), spec.precision), {}) for x in np.diff(spec.atom_offset)]
+    return (np.array([e.get("column_width", 1.0) for e in ent], dtype=np.float64),
+            np.array([e.get("prune_buffer", 0.0) for e in ent], dtype=np.float64))
 
 
 def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
-         target_atoms: int = 480000, force: bool = False, log=None) -> np.ndarray:
-    """Column width per walker of `spec` (size-class choice, cached)."""
+         prune_candidates=PRUNE_CANDIDATES, target_atoms: int = 480000, force: bool = False,
+         log=None):
+    """(column width, prune buffer) per walker of `spec`: the size-class
+    choices, cached."""
     cache = load_cache(cache_path)
     a = arch()
     n = np.diff(spec.atom_offset)
     widths = np.ones(spec.n_walkers)
+    buffers = np.zeros(spec.n_walkers)
     changed = False
     for cls in CLASSES:
         members = np.nonzero([size_class(int(x)) == cls for x in n])[0]
         if members.size == 0:
             continue
         key = _key(a, cls, spec.precision)
-        if force or key not in cache:
+        if force or key not in cache or "prune_buffer" not in cache[key]:
             rep = int(members[np.argsort(n[members], kind="stable")[members.size // 2]])
             one, lam1 = synth.subset(spec, lam, [rep])
             k = max(1, target_atoms // int(n[rep]))
             batch, lamb = synth.batch(one, lam1, k, seed=spec.seed + 7)
-            timings = {}
+            t_w = {}
             for wdt in candidates:
-                timings[f"{wdt:g}"] = time_width(batch, lamb, wdt)
+                t_w[f"{wdt:g}"] = time_width(batch, lamb, wdt)["per_step_ms"]
                 if log:
-                    log(f"autotune {key}: width {wdt:g} -> {timings[f'{wdt:g}']['per_step_ms']:.4f} ms")
-            best = min(candidates, key=lambda w_: timings[f"{w_:g}"]["per_step_ms"])
-            cache[key] = {"column_width": float(best), "atoms": int(n[rep]), "replicas": k,
-                          "timings_ms": {w_: round(t["per_step_ms"], 5) for w_, t in timings.items()}}
+                    log(f"autotune {key}: width {wdt:g} -> {t_w[f'{wdt:g}']:.4f} ms")
+            best_w = min(candidates, key=lambda w_: t_w[f"{w_:g}"])
+            t_b = {"default": t_w[f"{best_w:g}"]}
+            for b in prune_candidates:
+                if b > spec.r_skin:
+                    continue
+                t_b[f"{b:g}"] = time_width(batch, lamb, best_w, b)["per_step_ms"]
+                if log:
+                    log(f"autotune {key}: width {best_w:g}, prune buffer {b:g} -> {t_b[f'{b:g}']:.4f} ms")
+            best_b = min(t_b, key=t_b.get)
+            cache[key] = {"column_width": float(best_w),
+                          "prune_buffer": 0.0 if best_b == "default" else float(best_b),
+                          "atoms": int(n[rep]), "replicas": k,
+                          "timings_ms": {w_: round(t, 5) for w_, t in t_w.items()},
+                          "prune_timings_ms": {b_: round(t, 5) for b_, t in t_b.items()}}
             changed = True
         widths[members] = cache[key]["column_width"]
+        buffers[members] = cache[key]["prune_buffer"]
     if changed:
         save_cache(cache, cache_path)
-    return widths
+    return widths, buffers

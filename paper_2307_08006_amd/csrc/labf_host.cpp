@@ -287,8 +287,10 @@ labf_status validate_desc(const labf_system_desc *d) {
   if (d->max_bins < 0 || d->max_bins > 4096) return fail(nullptr, LABF_E_ARG, "max_bins must be 0 (1024) or 1..4096");
   if (d->list_capacity != 0 && (d->list_capacity < 16 || d->list_capacity > (1 << 20)))
     return fail(nullptr, LABF_E_ARG, "list_capacity must be 0 (estimated) or 16..2^20");
-  if (!(d->prune_buffer >= 0.0 && d->prune_buffer <= d->r_skin))
-    return fail(nullptr, LABF_E_ARG, "prune_buffer must be 0 (default) or in (0, r_skin]");
+  if (d->prune_buffer)
+    for (int w = 0; w < d->n_walkers; ++w)
+      if (!(d->prune_buffer[w] >= 0.0 && d->prune_buffer[w] <= d->r_skin))
+        return fail(nullptr, LABF_E_ARG, "prune_buffer must be 0 (default) or in (0, r_skin]");
   if (d->column_width)
     for (int w = 0; w < d->n_walkers; ++w)
       if (!(d->column_width[w] >= 0.5 && d->column_width[w] <= 2.0))
@@ -549,6 +551,9 @@ labf_status plan_system(const labf_system_desc *desc, HostLayout &h) {
     m.ncy = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[1] / target)));
     m.cw[0] = m.L[0] / m.ncx;
     m.cw[1] = m.L[1] / m.ncy;
+    // prune buffer: the given one, else half the skin, at most 0.5
+    m.prune_b = desc->prune_buffer && desc->prune_buffer[w] > 0.0 ? desc->prune_buffer[w]
+                                                                   : std::min(0.5, 0.5 * desc->r_skin);
     m.cap_env = (int32_t)((nenv + CL - 1) / CL + (int64_t)m.ncx * m.ncy);
     m.n_acl = (int32_t)na;  // one alchemical atom per cluster
     m.cl_begin = cl;
@@ -1085,13 +1090,6 @@ labf_status create_impl(const labf_system_desc *desc, hipStream_t st, labf_syste
   d.n_clusters = s->C;
   d.list_cap = h.list_cap;
   d.plist_cap = h.plist_cap;
-  {
-    // prune buffer: the given one, else half the skin, at most 0.5; the
-    // re-prune threshold keeps 1e-4 for the rounding of the box distances
-    const double b = desc->prune_buffer > 0.0 ? desc->prune_buffer : std::min(0.5, 0.5 * desc->r_skin);
-    d.prune_r2 = (T)((desc->r_cut + b) * (desc->r_cut + b));
-    d.prune_half = (float)(0.5 * b - 1e-4);
-  }
   d.uniform_lj = h.uniform ? 1 : 0;
   d.r_cut = desc->r_cut;
   d.r_list = desc->r_cut + desc->r_skin;

@@ -57,6 +57,7 @@ struct WalkerMeta {
   double L[3];            // box edges
   double B[3];            // storage offset (power of two >= 2L)
   double cw[2];           // column widths
+  double prune_b;         // prune buffer of the pair lists
 };
 
 // Smooth PME of one walker.  The complex grid holds the environment's charge
@@ -169,8 +170,6 @@ struct Dev {
   uint32_t *pdisp;              // [2][W][PDISP_SLOTS] bits of the largest displacement since
                                 // the last prune (non-negative float), spread over slots
                                 // (fewer atomics per address), double-buffered like lambda
-  T prune_r2;                   // (r_cut + prune buffer)^2
-  float prune_half;             // re-prune once the largest displacement exceeds this
   // --- alchemical blocks (one per alchemical atom)
   double *item_force;           // [I][3] force on the block's atom
   double *item_dudl;            // [I]

@@ -620,8 +620,9 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
   const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
   __shared__ T shtab[4][3][IMG_CODES];
   T *shx = shtab[threadIdx.x >> 6][0], *shy = shtab[threadIdx.x >> 6][1], *shz = shtab[threadIdx.x >> 6][2];
-  int wtab = -1;  // walker of the image-shift table and of D
-  float D = 0.f;
+  int wtab = -1;  // walker of the image-shift table, of D and of the prune radius
+  float D = 0.f, half = 0.f;
+  T pr2 = (T)0;
   for (int64_t e = e_first; e < e_first + PRUNE_CPW && e < r.e0 + r.en; ++e) {
     const int64_t c = d.env_table[e];
     const int w = d.cl_walker[c];
@@ -635,6 +636,9 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) Db = max(Db, (uint32_t)__shfl_xor((int)Db, o, WAVE));
       D = __uint_as_float(Db);
+      // re-prune threshold b/2, less 1e-4 for the rounding of the box distances
+      half = (float)(0.5 * m.prune_b - 1e-4);
+      pr2 = (T)((d.r_cut + m.prune_b) * (d.r_cut + m.prune_b));
       __builtin_amdgcn_wave_barrier();
       shx[lane] = (T)img_x(lane) * (T)m.L[0];
       shy[lane] = (T)img_y(lane) * (T)m.L[1];
@@ -644,7 +648,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
     }
     // the next step's integration measures into the other buffer
     if (loc == 0) d.pdisp[((int64_t)(lb ^ 1) * W + w) * PDISP_SLOTS + lane] = 0u;
-    if (d.plist_n[e] >= 0 && D <= d.prune_half) continue;
+    if (d.plist_n[e] >= 0 && D <= half) continue;
     const int64_t s0 = c * CL;
     if (lane < CL) {
       d.xprune[0][s0 + lane] = X0[s0 + lane];
@@ -699,7 +703,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
         const T gx = fmax(fmax(lox - xj[t], xj[t] - hix), (T)0);
         const T gy = fmax(fmax(loy - yj[t], yj[t] - hiy), (T)0);
         const T gz = fmax(fmax(loz - zj[t], zj[t] - hiz), (T)0);
-        const bool keep = b0 + t * CL + (lane >> 3) < nenv && fma(gz, gz, fma(gy, gy, gx * gx)) < d.prune_r2;
+        const bool keep = b0 + t * CL + (lane >> 3) < nenv && fma(gz, gz, fma(gy, gy, gx * gx)) < pr2;
         const unsigned long long bal = __ballot(keep);
         const int pos = cnt + lanes_below(bal);
         if (keep && (room || pos < cap)) st_off(out, (uint32_t)pos * 4u, val[t]);

@@ -56,7 +56,7 @@ class SystemDesc(C.Structure):
         ("pme_dims", C.c_void_p), ("ewald_beta", C.c_double),
         ("max_bins", C.c_int32), ("list_capacity", C.c_int32),
         ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-        ("prune_buffer", C.c_double),
+        ("prune_buffer", C.c_void_p),
     ]
 
 
@@ -181,6 +181,7 @@ def _desc(spec: SystemSpec, max_bins: int = 0, list_capacity: int = 0):
         charge=_f64(spec.charge), sigma=_f64(spec.sigma), epsilon=_f64(spec.epsilon),
         is_solute=np.ascontiguousarray(spec.is_solute, np.uint8), anchor=_f64(spec.anchor, (-1, 3)),
         k0=_f64(spec.k0), k1=_f64(spec.k1), column_width=_f64(spec.column_width),
+        prune_buffer=_f64(spec.prune_buffer),
         pme_dims=None if spec.pme_dims is None else np.ascontiguousarray(spec.pme_dims, np.int32))
     d = SystemDesc()
     d.n_walkers = spec.n_walkers
@@ -194,7 +195,6 @@ def _desc(spec: SystemSpec, max_bins: int = 0, list_capacity: int = 0):
     d.pme_order = 0 if spec.pme_dims is None else int(spec.pme_order)
     d.ewald_beta = float(spec.ewald_beta) if spec.pme_dims is not None else 0.0
     d.r_skin_alch = float(spec.r_skin_alch)
-    d.prune_buffer = float(spec.prune_buffer)
     d.max_bins = int(max_bins)
     d.list_capacity = int(list_capacity)
     return d, keep

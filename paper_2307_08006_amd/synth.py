@@ -65,7 +65,7 @@ class SystemSpec:
     rebuild_interval: int = 10
     r_skin_alch: float = 0.0             # list buffer of alchemical pairs; 0 -> r_skin
     column_width: Optional[np.ndarray] = None  # float64 [W] cluster column width factor; None -> 1
-    prune_buffer: float = 0.0            # pair-list prune buffer b (A); 0 -> min(0.5, r_skin / 2)
+    prune_buffer: Optional[np.ndarray] = None  # float64 [W] pair-list prune buffer b (A); None/0 -> min(0.5, r_skin / 2)
     pme_dims: Optional[np.ndarray] = None  # int32 [W,3] PME grid (2^a 3^b 5^c, multiples of 8); None -> no PME
     ewald_beta: float = 0.0              # Ewald splitting parameter (1/A) when pme_dims is set
     pme_order: int = 4                   # B-spline order of the PME charge assignment
@@ -387,6 +387,7 @@ def batch(spec: SystemSpec, lam: LambdaSpec, n_walkers: int, seed: int):
         is_solute=rep(spec.is_solute), vel=None, anchor=rep(spec.anchor),
         k0=rep(spec.k0), k1=rep(spec.k1), seed=seed, name=spec.name + f"_x{n_walkers}",
         column_width=None if spec.column_width is None else np.repeat(spec.column_width, n_walkers),
+        prune_buffer=None if spec.prune_buffer is None else np.repeat(spec.prune_buffer, n_walkers),
         pme_dims=None if spec.pme_dims is None else np.repeat(spec.pme_dims, n_walkers, axis=0))
     lam2 = dataclasses.replace(lam, lambda0=rng.uniform(0.0, 1.0, n_walkers), p_lambda0=None,
                                dr_pairs=None if lam.dr_pairs is None
@@ -421,6 +422,7 @@ def subset(spec: SystemSpec, lam: LambdaSpec, walkers) -> tuple:
         epsilon=pick(spec.epsilon), is_solute=pick(spec.is_solute), anchor=pick(spec.anchor),
         k0=pick(spec.k0), k1=pick(spec.k1),
         column_width=None if spec.column_width is None else spec.column_width[walkers],
+        prune_buffer=None if spec.prune_buffer is None else spec.prune_buffer[walkers],
         pme_dims=None if spec.pme_dims is None else spec.pme_dims[walkers])
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lam.lambda0)[walkers],
                                p_lambda0=None if lam.p_lambda0 is None
@@ -447,6 +449,8 @@ def concat(specs, lam: LambdaSpec, lambda0: np.ndarray, seed: int, name: str):
         anchor=cat("anchor") if has_r else None, k0=cat("k0") if has_r else None,
         k1=cat("k1") if has_r else None, seed=seed, name=name,
         column_width=np.concatenate([np.ones(1) if s.column_width is None else s.column_width
+                                     for s in specs]),
+        prune_buffer=np.concatenate([np.zeros(1) if s.prune_buffer is None else s.prune_buffer
                                      for s in specs]),
         pme_dims=None if s0.pme_dims is None else np.concatenate([s.pme_dims for s in specs]))
     lam2 = dataclasses.replace(lam, lambda0=np.asarray(lambda0, np.float64), p_lambda0=None)

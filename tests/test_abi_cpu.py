@@ -155,13 +155,18 @@ def test_workspace_size_is_host_arithmetic():
 @pytest.mark.parametrize("field,value,msg", [
     ("max_bins", -1, "max_bins"), ("max_bins", 5000, "max_bins"),
     ("list_capacity", 3, "list_capacity"), ("list_capacity", (1 << 20) + 1, "list_capacity"),
-    ("prune_buffer", -0.1, "prune_buffer"), ("prune_buffer", 5.0, "prune_buffer"),
-    ("prune_buffer", float("nan"), "prune_buffer"),
+    ("prune_buffer", np.array([-0.1]), "prune_buffer"), ("prune_buffer", np.array([5.0]), "prune_buffer"),
+    ("prune_buffer", np.array([np.nan]), "prune_buffer"),
 ])
 def test_workspace_size_validates_the_descriptor(field, value, msg):
     _ensure_built()
     spec, _ = _spec()
-    d, keep = _raw_desc(spec, **{field: value})
+    if isinstance(value, np.ndarray):
+        value = np.ascontiguousarray(value, np.float64)
+        d, keep = _raw_desc(spec, **{field: value.ctypes.data})
+        keep["_value"] = value
+    else:
+        d, keep = _raw_desc(spec, **{field: value})
     n = C.c_size_t(7)
     assert labf.lib().labf_workspace_size(C.byref(d), C.byref(n)) == -1
     assert n.value == 0

@@ -151,7 +151,7 @@ def _pruned(b):
     """The 3,000-atom system with prune buffer b: 0.02 A re-prunes the pair
     lists at almost every step, 1.5 A (the list buffer) only at rebuilds."""
     spec, lam = _charged3k()
-    spec.prune_buffer = b
+    spec.prune_buffer = np.array([b])
     return spec, lam
 
 
