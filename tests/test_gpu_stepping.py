@@ -155,8 +155,20 @@ def _pruned(b):
     return spec, lam
 
 
+def _pruned_mixed():
+    """Two walkers of the 3,000-atom system in one batch, one re-pruning at
+    almost every step (b = 0.02 A), the other only at rebuilds (b = 1.5 A):
+    the prune decision and radius are per walker."""
+    spec, lam = _charged3k()
+    b2, l2 = synth.batch(spec, lam, 2, seed=synth.BASE_SEED + 12)
+    b2.prune_buffer = np.array([0.02, 1.5])
+    l2.lambda0 = np.array([0.4, 0.6])
+    return b2, l2
+
+
 STEP_CASES = {
     "charged3k_fp32": lambda: _charged3k(),
+    "charged3k_fp32x2_prune_per_walker": _pruned_mixed,
     "charged3k_fp32_mixedlj": lambda: _charged3k(0.15),
     "charged3k_fp32_prune_every_step": lambda: _pruned(0.02),
     "charged3k_fp32_prune_at_rebuilds": lambda: _pruned(1.5),
