@@ -965,6 +965,35 @@ __device__ __forceinline__ double integrate_atom(const Dev<T> &d, int64_t s, int
   return r2;
 }
 
+// One Cartesian component k of integrate_atom (same arithmetic, same noise
+// bits): three lanes integrate an atom side by side.  Returns the squared
+// displacement of this component from the position at the last prune.
+template <typename T>
+__device__ __forceinline__ double integrate_comp(const Dev<T> &d, int64_t s, int k, int xb, int vb,
+                                                 int w, int64_t step, bool pending, double Fk) {
+  const T h = (T)(0.5 * d.dt);
+  const T c1 = (T)d.c1;
+  const T im = d.aim[s], sd = d.nsd[s];
+  const double z = gauss_comp(d.seed, (uint32_t)d.orig[s], (uint32_t)step, (uint32_t)w, 0u, k);
+  // per-lane component: select the array, never index the argument block
+  T *Vk = k == 0 ? d.V[vb][0] : (k == 1 ? d.V[vb][1] : d.V[vb][2]);
+  const T *Xk = k == 0 ? d.X[xb][0] : (k == 1 ? d.X[xb][1] : d.X[xb][2]);
+  T *Xn = k == 0 ? d.X[xb ^ 1][0] : (k == 1 ? d.X[xb ^ 1][1] : d.X[xb ^ 1][2]);
+  const T *Xp = k == 0 ? d.xprune[0] : (k == 1 ? d.xprune[1] : d.xprune[2]);
+  const T fa = (T)Fk;
+  T v = Vk[s];
+  T x = Xk[s];
+  if (pending) v += h * fa * im;
+  v += h * fa * im;
+  x += h * v;
+  v = c1 * v + sd * (T)z;
+  x += h * v;
+  Vk[s] = v;
+  Xn[s] = x;
+  const double u = (double)(x - Xp[s]);  // exact: one storage grid
+  return u * u;
+}
+
 // Largest displacement since the prune over the lanes of one walker, rounded
 // up, into the buffer the next step's prune test reads (slot `slot` of the
 // walker's PDISP_SLOTS: atomics on one address per walker would serialise).
@@ -1305,7 +1334,11 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     }
   }
   double eres = 0.0, dq = 0.0;
-  if ((lane & 7) == 0) {
+  // every lane of a group of 8 holds its atom's force sums; when stepping,
+  // lanes 0-2 of the group integrate the x, y, z components side by side
+  // (the restraint terms below are computed on each of them)
+  const int kc = lane & 7;
+  if (kc < (INTEG ? 3 : 1)) {
     const int64_t s = s0 + (lane >> 3);
     const bool valid = d.orig[s] >= 0;
     double F[3] = {(double)Fx, (double)Fy, (double)Fz};
@@ -1345,17 +1378,25 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
     if (INTEG) {
       if (valid) {
         const int64_t st = d.step[lb * d.n_walkers + w];
-        dq = integrate_atom<T>(d, s, xb, vb, w, st, st != *d.start_step, F);
+        const double Fk = kc == 0 ? F[0] : (kc == 1 ? F[1] : F[2]);
+        dq = integrate_comp<T>(d, s, kc, xb, vb, w, st, st != *d.start_step, Fk);
       } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d.X[xb ^ 1][k][s] = d.X[xb][k][s];
+        T *Xn = kc == 0 ? d.X[xb ^ 1][0] : (kc == 1 ? d.X[xb ^ 1][1] : d.X[xb ^ 1][2]);
+        const T *Xk = kc == 0 ? d.X[xb][0] : (kc == 1 ? d.X[xb][1] : d.X[xb][2]);
+        Xn[s] = Xk[s];
       }
     } else if (!EONLY) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) d.fout[(int64_t)k * d.n_slots + s] = valid ? F[k] : 0.0;
     }
   }
-  if (INTEG) record_disp(d, lb, w, (int)e, dq);
+  if (INTEG) {
+    // the atom's squared displacement, summed in component order on lane 0
+    // of its group
+    const double d1 = __shfl_down(dq, 1, WAVE), d2 = __shfl_down(dq, 2, WAVE);
+    dq = kc == 0 ? (dq + d1) + d2 : 0.0;
+    record_disp(d, lb, w, (int)e, dq);
+  }
   if (ENERGY) {
     const double et = wave_sum(eacc), er = wave_sum(eres);
     if (lane == 0) {
