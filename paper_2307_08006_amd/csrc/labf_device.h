@@ -86,23 +86,30 @@ __device__ inline void gauss4(uint64_t seed, uint32_t atom, uint32_t step, uint3
   }
 }
 
-// The normal z[k] (k < 4) of the same Philox block as gauss4, bit for bit,
-// from the one Box-Muller pair it belongs to: k = 0, 1 take the first pair
-// (cosine, sine), k = 2, 3 the second.  Lets three lanes draw an atom's three
-// components side by side.
-__device__ inline double gauss_comp(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker,
-                                    uint32_t purpose, int k) {
+// One Box-Muller pair of gauss4, bit for bit: p = 0 gives z[0], z[1], p = 1
+// gives z[2], z[3] (cosine, then sine), so that lanes can share an atom's
+// draws.
+__device__ inline void gauss_pair(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker,
+                                  uint32_t purpose, int p, double &zc, double &zs) {
   uint32_t c0 = atom, c1 = step, c2 = walker, c3 = purpose;
   philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
   const double two_pi = 6.283185307179586;
   const double inv = 2.3283064365386963e-10;  // 2^-32
-  const bool second = k >= 2;
-  const double u1 = ((double)(second ? c2 : c0) + 1.0) * inv;
-  const double u2 = (double)(second ? c3 : c1) * inv;
+  const double u1 = ((double)(p ? c2 : c0) + 1.0) * inv;
+  const double u2 = (double)(p ? c3 : c1) * inv;
   const double rad = sqrt(-2.0 * log(u1));
   double sn, cs;
   sincos(two_pi * u2, &sn, &cs);
-  return rad * ((k & 1) ? sn : cs);
+  zc = rad * cs;
+  zs = rad * sn;
+}
+
+// The normal z[k] (k < 4) of gauss4, bit for bit.
+__device__ inline double gauss_comp(uint64_t seed, uint32_t atom, uint32_t step, uint32_t walker,
+                                    uint32_t purpose, int k) {
+  double zc, zs;
+  gauss_pair(seed, atom, step, walker, purpose, k >> 1, zc, zs);
+  return (k & 1) ? zs : zc;
 }
 
 

@@ -860,6 +860,7 @@ void carve(const HostLayout &h, labf_system *s, Dev<T> &d, Carver &cv) {
   cv.take(&d.plist, (size_t)h.E * h.plist_cap);
   cv.take(&d.plist_n, h.E);
   for (int k = 0; k < 3; ++k) cv.take(&d.xprune[k], S);
+  for (int k = 0; k < 3; ++k) cv.take(&d.noise[k], h.plist_cap ? S : 0);
   cv.take(&d.pdisp, (size_t)2 * W * PDISP_SLOTS);
   cv.take(&d.item_force, (size_t)h.I * 3);
   cv.take(&d.item_dudl, (size_t)h.I);

@@ -167,6 +167,8 @@ struct Dev {
   uint32_t *plist;              // [E][plist_cap]
   int32_t *plist_n;             // [E] chunks of 64 in use; -1: stale (rebuilt list)
   T *xprune[3];                 // [3][S] positions at the last prune
+  T *noise[3];                  // [3][S] Langevin normals of the coming step, drawn by the
+                                //   prune kernel for the environment atoms (none with PME)
   uint32_t *pdisp;              // [2][W][PDISP_SLOTS] bits of the largest displacement since
                                 // the last prune (non-negative float), spread over slots
                                 // (fewer atomics per address), double-buffered like lambda

@@ -614,9 +614,35 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
   // prune would load only their XCDs)
   const int lblk = (int)blockIdx.x;
   if (lblk >= nb) return;
-  const int64_t e_first = r.e0 + ((int64_t)lblk * 4 + uni(threadIdx.x >> 6)) * PRUNE_CPW;
+  const int64_t gw = (int64_t)lblk * 4 + uni(threadIdx.x >> 6);
+  const int64_t e_first = r.e0 + gw * PRUNE_CPW;
   const int lane = lane_id();
   const int W = d.n_walkers;
+  {
+    // The Langevin normals of the coming step for the environment atoms,
+    // four items (32 atoms) per wave at full lane width: lane -> item
+    // lane / 16, atom (lane / 2) % 8, Box-Muller pair lane % 2 (z0, z1 or
+    // z2 of gauss4).  Drawn here, the integrating epilogue of the
+    // environment kernel only reads them.
+    const int64_t e = r.e0 + gw * 4 + (lane >> 4);
+    if (e < r.e0 + r.en) {
+      const int64_t c = d.env_table[e];
+      const int w = d.cl_walker[c];
+      const int64_t s = c * CL + ((lane >> 1) & (CL - 1));
+      const int32_t o = d.orig[s];
+      if (c - d.meta[w].cl_begin < d.n_env[w] && o >= 0) {
+        const int p = lane & 1;
+        double zc, zs;
+        gauss_pair(d.seed, (uint32_t)o, (uint32_t)d.step[lb * W + w], (uint32_t)w, 0u, p, zc, zs);
+        if (p == 0) {
+          d.noise[0][s] = (T)zc;
+          d.noise[1][s] = (T)zs;
+        } else {
+          d.noise[2][s] = (T)zc;
+        }
+      }
+    }
+  }
   const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
   __shared__ T shtab[4][3][IMG_CODES];
   T *shx = shtab[threadIdx.x >> 6][0], *shy = shtab[threadIdx.x >> 6][1], *shz = shtab[threadIdx.x >> 6][2];
@@ -965,16 +991,16 @@ __device__ __forceinline__ double integrate_atom(const Dev<T> &d, int64_t s, int
   return r2;
 }
 
-// One Cartesian component k of integrate_atom (same arithmetic, same noise
-// bits): three lanes integrate an atom side by side.  Returns the squared
-// displacement of this component from the position at the last prune.
+// One Cartesian component k of integrate_atom (same arithmetic; z is the
+// normal z[k] of gauss4 rounded to T, as integrate_atom uses it): three lanes
+// integrate an atom side by side.  Returns the squared displacement of this
+// component from the position at the last prune.
 template <typename T>
 __device__ __forceinline__ double integrate_comp(const Dev<T> &d, int64_t s, int k, int xb, int vb,
-                                                 int w, int64_t step, bool pending, double Fk) {
+                                                 bool pending, double Fk, T z) {
   const T h = (T)(0.5 * d.dt);
   const T c1 = (T)d.c1;
   const T im = d.aim[s], sd = d.nsd[s];
-  const double z = gauss_comp(d.seed, (uint32_t)d.orig[s], (uint32_t)step, (uint32_t)w, 0u, k);
   // per-lane component: select the array, never index the argument block
   T *Vk = k == 0 ? d.V[vb][0] : (k == 1 ? d.V[vb][1] : d.V[vb][2]);
   const T *Xk = k == 0 ? d.X[xb][0] : (k == 1 ? d.X[xb][1] : d.X[xb][2]);
@@ -986,7 +1012,7 @@ __device__ __forceinline__ double integrate_comp(const Dev<T> &d, int64_t s, int
   if (pending) v += h * fa * im;
   v += h * fa * im;
   x += h * v;
-  v = c1 * v + sd * (T)z;
+  v = c1 * v + sd * z;
   x += h * v;
   Vk[s] = v;
   Xn[s] = x;
@@ -1379,7 +1405,14 @@ void k_env(Dev<T> d, Range r, int xb, int vb, int lb) {
       if (valid) {
         const int64_t st = d.step[lb * d.n_walkers + w];
         const double Fk = kc == 0 ? F[0] : (kc == 1 ? F[1] : F[2]);
-        dq = integrate_comp<T>(d, s, kc, xb, vb, w, st, st != *d.start_step, Fk);
+        T z;
+        if constexpr (EW) {
+          // no prune kernel with PME: draw here
+          z = (T)gauss_comp(d.seed, (uint32_t)d.orig[s], (uint32_t)st, (uint32_t)w, 0u, kc);
+        } else {
+          z = kc == 0 ? d.noise[0][s] : (kc == 1 ? d.noise[1][s] : d.noise[2][s]);
+        }
+        dq = integrate_comp<T>(d, s, kc, xb, vb, st != *d.start_step, Fk, z);
       } else {
         T *Xn = kc == 0 ? d.X[xb ^ 1][0] : (kc == 1 ? d.X[xb ^ 1][1] : d.X[xb ^ 1][2]);
         const T *Xk = kc == 0 ? d.X[xb][0] : (kc == 1 ? d.X[xb][1] : d.X[xb][2]);
