@@ -472,15 +472,27 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
     const int ry1 = raw((hi[1] + rl - m.B[1]) / m.cw[1] + 1e-9, m.ncy);
     const int nry = ry1 - ry0 + 1;
     const int ncols = (rx1 - rx0 + 1) * nry;
+    const float inv_nry = 1.0f / (float)nry;
     for (int q0 = 0; q0 < ncols; q0 += WAVE) {
       // one lane per column: x-y gap test, cluster count and first cluster
       const int q = q0 + lane;
       int ncl = 0, j0 = 0, sxy = 0;
       if (q < ncols) {
-        const int rx = rx0 + q / nry, ry = ry0 + q % nry;
-        const int cx = ((rx % m.ncx) + m.ncx) % m.ncx, cy = ((ry % m.ncy) + m.ncy) % m.ncy;
-        const int sx = (rx - cx) / m.ncx, sy = (ry - cy) / m.ncy;
-        if (sx >= -1 && sx <= 1 && sy >= -1 && sy <= 1) {
+        // q = qx nry + qy without an integer division: a float estimate of
+        // the quotient, corrected by one step (q < 2^24)
+        int qx = (int)((float)q * inv_nry), qy = q - qx * nry;
+        if (qy < 0) {
+          --qx;
+          qy += nry;
+        } else if (qy >= nry) {
+          ++qx;
+          qy -= nry;
+        }
+        const int rx = rx0 + qx, ry = ry0 + qy;
+        // raw indices lie in [-n, 2n - 1]: one box shift at most per axis
+        const int sx = rx < 0 ? -1 : (rx >= m.ncx ? 1 : 0), sy = ry < 0 ? -1 : (ry >= m.ncy ? 1 : 0);
+        const int cx = rx - sx * m.ncx, cy = ry - sy * m.ncy;
+        {
           const double cxl = m.B[0] + rx * m.cw[0] - tolx, cxh = m.B[0] + (rx + 1) * m.cw[0] + tolx;
           const double cyl = m.B[1] + ry * m.cw[1] - toly, cyh = m.B[1] + (ry + 1) * m.cw[1] + toly;
           const double gx = gap1(lo[0], hi[0], cxl, cxh), gy = gap1(lo[1], hi[1], cyl, cyh);
@@ -559,14 +571,21 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
         const T *bj = d.bbox + J * 6;
         const double b0 = bj[0], b1 = bj[1], b2 = bj[2], b3 = bj[3], b4 = bj[4], b5 = bj[5];
         if (b0 <= b3) {
-          for (int t27 = 0; t27 < 27; ++t27) {
-            const double ox = (t27 / 9 - 1) * m.L[0], oy = ((t27 / 3) % 3 - 1) * m.L[1],
-                         oz = (t27 % 3 - 1) * m.L[2];
+          // squared box gaps per axis and image shift, then all 27 sums
+          double ax2[3], ay2[3], az2[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double ox = (k - 1) * m.L[0], oy = (k - 1) * m.L[1], oz = (k - 1) * m.L[2];
             const double ax = gap1(lo[0], hi[0], b0 + ox, b3 + ox);
             const double ay = gap1(lo[1], hi[1], b1 + oy, b4 + oy);
             const double az = gap1(lo[2], hi[2], b2 + oz, b5 + oz);
-            if (ax * ax + ay * ay + az * az < rla2) mask |= 1u << t27;
+            ax2[k] = ax * ax;
+            ay2[k] = ay * ay;
+            az2[k] = az * az;
           }
+#pragma unroll
+          for (int t27 = 0; t27 < 27; ++t27)
+            if ((ax2[t27 / 9] + ay2[(t27 / 3) % 3]) + az2[t27 % 3] < rla2) mask |= 1u << t27;
         }
       }
       int tot;
@@ -604,7 +623,8 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
 // reference configuration); the cluster list itself stays valid while the
 // displacements since the rebuild stay within the skin (the k_skin test).
 // A stale list (after a rebuild) is always pruned.
-constexpr int PRUNE_CPW = 2;  // clusters per wave of k_prune
+constexpr int PRUNE_CPW = 1;  // clusters per wave of k_prune
+constexpr int PRUNE_NP = 4;   // passes of 8 list entries gathered at once (at most 8)
 template <typename T>
 __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb) {
   const int64_t nw = (r.en + PRUNE_CPW - 1) / PRUNE_CPW;  // waves in all
@@ -646,7 +666,8 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
   const T *X0 = d.X[xb][0], *X1 = d.X[xb][1], *X2 = d.X[xb][2];
   __shared__ T shtab[4][3][IMG_CODES];
   T *shx = shtab[threadIdx.x >> 6][0], *shy = shtab[threadIdx.x >> 6][1], *shz = shtab[threadIdx.x >> 6][2];
-  int wtab = -1;  // walker of the image-shift table, of D and of the prune radius
+  int wtab = -1;    // walker of D and of the prune radius
+  int wshift = -1;  // walker of the image-shift table (filled when a cluster prunes)
   float D = 0.f, half = 0.f;
   T pr2 = (T)0;
   for (int64_t e = e_first; e < e_first + PRUNE_CPW && e < r.e0 + r.en; ++e) {
@@ -665,16 +686,19 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
       // re-prune threshold b/2, less 1e-4 for the rounding of the box distances
       half = (float)(0.5 * m.prune_b - 1e-4);
       pr2 = (T)((d.r_cut + m.prune_b) * (d.r_cut + m.prune_b));
-      __builtin_amdgcn_wave_barrier();
-      shx[lane] = (T)img_x(lane) * (T)m.L[0];
-      shy[lane] = (T)img_y(lane) * (T)m.L[1];
-      shz[lane] = (T)img_z(lane) * (T)m.L[2];
-      __builtin_amdgcn_wave_barrier();
       wtab = w;
     }
     // the next step's integration measures into the other buffer
     if (loc == 0) d.pdisp[((int64_t)(lb ^ 1) * W + w) * PDISP_SLOTS + lane] = 0u;
     if (d.plist_n[e] >= 0 && D <= half) continue;
+    if (w != wshift) {
+      __builtin_amdgcn_wave_barrier();
+      shx[lane] = (T)img_x(lane) * (T)m.L[0];
+      shy[lane] = (T)img_y(lane) * (T)m.L[1];
+      shz[lane] = (T)img_z(lane) * (T)m.L[2];
+      __builtin_amdgcn_wave_barrier();
+      wshift = w;
+    }
     const int64_t s0 = c * CL;
     if (lane < CL) {
       d.xprune[0][s0 + lane] = X0[s0 + lane];
@@ -708,12 +732,12 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
     // B + 3L, farther than L from every atom image: they never pass.
     // Slot offsets are 32-bit byte offsets (fewer than 2^29 slots).
     const uint32_t wsl = (uint32_t)ws0;
-    for (int b0 = 0; b0 < nenv; b0 += 4 * CL) {
-      const uint32_t eb = lst[min(b0 + (lane & 31), nenv - 1)];
-      T xj[4], yj[4], zj[4];
-      uint32_t val[4];
+    for (int b0 = 0; b0 < nenv; b0 += PRUNE_NP * CL) {
+      const uint32_t eb = lst[min(b0 + (lane & (PRUNE_NP * CL - 1)), nenv - 1)];
+      T xj[PRUNE_NP], yj[PRUNE_NP], zj[PRUNE_NP];
+      uint32_t val[PRUNE_NP];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < PRUNE_NP; ++t) {
         const uint32_t ent = (uint32_t)__shfl((int)eb, t * CL + (lane >> 3), WAVE);
         const uint32_t code = ent >> SHIFT_BITS;
         const uint32_t js = (ent & CL_MASK) * CL + (uint32_t)(lane & 7);
@@ -723,9 +747,9 @@ __global__ __launch_bounds__(256) void k_prune(Dev<T> d, Range r, int xb, int lb
         zj[t] = ld_off(X2, bo) + shz[code];
         val[t] = (js - wsl) | (code << SHIFT_BITS);
       }
-      const bool room = cnt + 4 * WAVE <= cap;
+      const bool room = cnt + PRUNE_NP * WAVE <= cap;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < PRUNE_NP; ++t) {
         const T gx = fmax(fmax(lox - xj[t], xj[t] - hix), (T)0);
         const T gy = fmax(fmax(loy - yj[t], yj[t] - hiy), (T)0);
         const T gz = fmax(fmax(loz - zj[t], zj[t] - hiz), (T)0);
