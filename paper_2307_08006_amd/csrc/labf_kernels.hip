@@ -1485,11 +1485,26 @@ struct SoftCore {
   int form, p;
   double alpha, delta;
 };
+// The coupling-dependent constants of the soft-core form at one c (the same
+// for every pair of a walker at a step): form 1 delta (1 - c); form 0
+// alpha (1 - c)^p and alpha p (1 - c)^(p - 1), hoisted out of the pair loop.
+struct ScAt {
+  double c, d1, A, dA;
+};
+__device__ __forceinline__ ScAt sc_at(const SoftCore &sc, double c) {
+  ScAt a;
+  a.c = c;
+  a.d1 = sc.delta * (1.0 - c);
+  a.A = sc.alpha * pow(1.0 - c, (double)sc.p);
+  a.dA = sc.p >= 1 ? sc.alpha * (double)sc.p * pow(1.0 - c, (double)(sc.p - 1)) : 0.0;
+  return a;
+}
 
-__device__ __forceinline__ void softcore_y(const SoftCore &sc, double r2, double sig2, double c,
-                                           double &y, double &dydc, double &fy, double &dys) {
+__device__ __forceinline__ void softcore_y(const SoftCore &sc, const ScAt &at, double r2,
+                                           double sig2, double &y, double &dydc, double &fy,
+                                           double &dys) {
   if (sc.form == 1) {
-    const double s = r2 + sc.delta * (1.0 - c);
+    const double s = r2 + at.d1;
     const double w = sig2 / s;
     y = w * w * w;
     dydc = 3.0 * y * sc.delta / s;
@@ -1498,24 +1513,24 @@ __device__ __forceinline__ void softcore_y(const SoftCore &sc, double r2, double
   } else {
     const double t = r2 / sig2;
     const double u = t * t * t;
-    const double A = sc.alpha * pow(1.0 - c, (double)sc.p);
-    y = 1.0 / (A + u);
-    dydc = sc.p >= 1 ? sc.alpha * (double)sc.p * pow(1.0 - c, (double)(sc.p - 1)) * y * y : 0.0;
+    y = 1.0 / (at.A + u);
+    dydc = at.dA * y * y;
     fy = 3.0 * u * y * y / r2;
     dys = 6.0 * u * y * y;
   }
 }
 
-__device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq, double cv,
-                                            double ce, const SoftCore &scf, double rc,
-                                            double beta) {
+__device__ __forceinline__ PairOut alch_pair(double r2, double sig, double eps, double qq,
+                                            const ScAt &at, double ce, const SoftCore &scf,
+                                            double rc, double beta) {
   PairOut o = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double r = sqrt(r2);
+  const double cv = at.c;
   if (eps != 0.0) {
     const double sig2 = sig * sig;
     double y, dydc, fy, dys, yc, dycc, fyc, dysc;
-    softcore_y(scf, r2, sig2, cv, y, dydc, fy, dys);
-    softcore_y(scf, rc * rc, sig2, cv, yc, dycc, fyc, dysc);
+    softcore_y(scf, at, r2, sig2, y, dydc, fy, dys);
+    softcore_y(scf, at, rc * rc, sig2, yc, dycc, fyc, dysc);
     o.ulj = 4.0 * eps * cv * ((y * y - y) - (yc * yc - yc));
     o.dulj = 4.0 * eps * (((y * y - y) + cv * (2.0 * y - 1.0) * dydc) -
                           ((yc * yc - yc) + cv * (2.0 * yc - 1.0) * dycc));
@@ -1720,7 +1735,7 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
 // block that completes a walker's set runs the walker's lambda/ABF tail.
 // ENERGY: the walker's energy parts (alchemical side); PGRAD: dV/d(eps,
 // sigma, q) of the block's atom; INTEG: the stepping tail.
-template <typename T, bool ENERGY, bool INTEG, bool PGRAD>
+template <typename T, bool ENERGY, bool INTEG, bool PGRAD, bool EW>
 __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
   constexpr int NACC = PGRAD ? 12 : (ENERGY ? 9 : 4);
   __shared__ double red[4][NACC];
@@ -1749,6 +1764,17 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     const int n = d.list_count[c];
     const double rc = d.r_cut, rc2 = rc * rc;
     const SoftCore scf = {lp.sc_form, lp.sc_power, lp.sc_alpha, lp.sc_shift};
+    // soft-core constants of the alchemical pairs (c_v) and of the others (c = 1)
+    double sv_d1, sv_A, sv_dA, s1_d1, s1_A, s1_dA;
+    {
+      const ScAt a = sc_at(scf, cv), b = sc_at(scf, 1.0);
+      sv_d1 = a.d1;
+      sv_A = a.A;
+      sv_dA = a.dA;
+      s1_d1 = b.d1;
+      s1_A = b.A;
+      s1_dA = b.dA;
+    }
     for (int e0 = wv * CL; e0 < n; e0 += 4 * CL) {
       const int ee = e0 + (lane >> 3);
       if (ee >= n) continue;
@@ -1767,8 +1793,13 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
       const double sig = 0.5 * (sgi + d.sig64[js]);
       const double eps = sqrt(epi * d.eps64[js]);
       const double qq = d.coulomb_k * qi * d.q64[js];
-      const PairOut o = alch_pair(r2, sig, eps, qq, alch ? cv : 1.0, alch ? ce : 1.0, scf, rc,
-                                  d.pme_on ? d.ewald_beta : 0.0);
+      ScAt at;
+      at.c = alch ? cv : 1.0;
+      at.d1 = alch ? sv_d1 : s1_d1;
+      at.A = alch ? sv_A : s1_A;
+      at.dA = alch ? sv_dA : s1_dA;
+      const PairOut o = alch_pair(r2, sig, eps, qq, at, alch ? ce : 1.0, scf, rc,
+                                  EW ? d.ewald_beta : 0.0);
       acc[0] -= o.fr * dx;
       acc[1] -= o.fr * dy;
       acc[2] -= o.fr * dz;
@@ -1807,7 +1838,7 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
     double tot[NACC];
 #pragma unroll
     for (int q = 0; q < NACC; ++q) tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
-    if (d.pme_on && c >= 0) {
+    if (EW && c >= 0) {
       // reciprocal space: force from the gather; dV/dlambda of the cross
       // term dce q phi_E for group atoms; energies and dV/dq with the self term
       const int64_t si = c * CL;
@@ -2196,6 +2227,16 @@ __global__ __launch_bounds__(256) void k_env_recip(Dev<T> d, Range r) {
   for (int k = 0; k < 3; ++k) d.fout[k * S + s] += d.pme_frc[k * S + s];
 }
 
+// The alchemical kernel, without or with the real-space Ewald pair (the
+// Ewald form compiled in only where PME is on: it raises the kernel's
+// register count, which the environment kernel beside it pays for).
+template <typename T, bool ENERGY, bool INTEG, bool PGRAD>
+void alch_launch(const Dev<T> &d, const Range &r, int xb, int vb, int lb, hipStream_t s) {
+  if (r.in_ <= 0) return;
+  if (d.pme_on) k_alch<T, ENERGY, INTEG, PGRAD, true><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  else k_alch<T, ENERGY, INTEG, PGRAD, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+}
+
 template <typename T>
 hipError_t Launch<T>::prune(const Dev<T> &d, const Range &r, int xb, int lb, hipStream_t s) {
   if (d.pme_on) return hipSuccess;  // the Ewald kernels prune on the fly
@@ -2219,7 +2260,7 @@ hipError_t Launch<T>::step(const Dev<T> &d, const Range &r, int xb, int vb, int 
   }
   const hipError_t e = prune(d, r, xb, lb, s);
   if (e != hipSuccess) return e;
-  if (r.in_ > 0) k_alch<T, false, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  alch_launch<T, false, true, false>(d, r, xb, vb, lb, s);
   env_launch<T>(d, r, xb, vb, lb, 0, true, s);
   return hipGetLastError();
 }
@@ -2235,7 +2276,7 @@ hipError_t Launch<T>::env_integrate(const Dev<T> &d, const Range &r, int xb, int
 template <typename T>
 hipError_t Launch<T>::step_alch(const Dev<T> &d, const Range &r, int xb, int vb, int lb,
                                 hipStream_t s) {
-  if (r.in_ > 0) k_alch<T, false, true, false><<<(unsigned)r.in_, 256, 0, s>>>(d, r, xb, vb, lb);
+  alch_launch<T, false, true, false>(d, r, xb, vb, lb, s);
   return hipGetLastError();
 }
 
@@ -2258,18 +2299,17 @@ hipError_t Launch<T>::eval(const Dev<T> &d, const Range &r, int xb, int vb, int 
     const hipError_t e = pme(d, r, xb, lb, s);
     if (e != hipSuccess) return e;
   }
-  const unsigned ni = (unsigned)r.in_;
   const hipError_t ep = prune(d, r, xb, lb, s);
   if (ep != hipSuccess) return ep;
   if (mode == EVAL_ENERGY) {
-    if (ni) k_alch<T, true, false, false><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    alch_launch<T, true, false, false>(d, r, xb, vb, lb, s);
     env_launch<T>(d, r, xb, vb, lb, 2, false, s);
   } else if (mode == EVAL_GRAD) {
-    if (ni) k_alch<T, false, false, true><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    alch_launch<T, false, false, true>(d, r, xb, vb, lb, s);
     env_launch<T>(d, r, xb, vb, lb, 0, false, s);
     if (d.pme_on && r.cn > 0) k_env_recip<T><<<nblk(r.cn * CL, 256), 256, 0, s>>>(d, r);
   } else {
-    if (ni) k_alch<T, true, false, true><<<ni, 256, 0, s>>>(d, r, xb, vb, lb);
+    alch_launch<T, true, false, true>(d, r, xb, vb, lb, s);
     env_launch<T>(d, r, xb, vb, lb, 1, false, s);
   }
   return hipGetLastError();
