@@ -951,11 +951,15 @@ hipError_t batched_step(labf_system *s, int xb, int vb, int lb, hipStream_t st) 
   // environment kernel waits for it either way
   hipError_t e = Launch<T>::prune(d, r, xb, lb, st);
   if (e == hipSuccess) e = hipEventRecord(s->fork_ev, st);
+  // without PME the environment kernel is issued first, so that in a graph
+  // it starts right after the prune; the alchemical kernel (at most 96
+  // VGPRs, as the environment kernel) takes the slots of retiring waves
+  if (e == hipSuccess && !d.pme_on) e = Launch<T>::step_env(d, r, xb, vb, lb, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream2, s->fork_ev, 0);
   if (e == hipSuccess && d.pme_on) e = Launch<T>::pme(d, r, xb, lb, s->cap_stream2);
   if (e == hipSuccess && d.pme_on) e = hipEventRecord(s->pme_ev, s->cap_stream2);
   if (e == hipSuccess) e = Launch<T>::step_alch(d, r, xb, vb, lb, s->cap_stream2);
-  if (e == hipSuccess) e = Launch<T>::step_env(d, r, xb, vb, lb, st);
+  if (e == hipSuccess && d.pme_on) e = Launch<T>::step_env(d, r, xb, vb, lb, st);
   if (e == hipSuccess && d.pme_on) e = hipStreamWaitEvent(st, s->pme_ev, 0);
   if (e == hipSuccess && d.pme_on) e = Launch<T>::env_integrate(d, r, xb, vb, lb, st);
   if (e == hipSuccess) e = hipEventRecord(s->join_ev, s->cap_stream2);

@@ -1733,10 +1733,13 @@ __device__ void alch_tail(const Dev<T> &d, int w, int xb, int vb, int lb) {
 // neighbour list, each lane one partner per pass (FP64), and the block
 // reduces force, dV/dlambda and energies in a fixed order (no atomics).  The
 // block that completes a walker's set runs the walker's lambda/ABF tail.
+// Stepping without PME: at most 96 VGPRs, as the environment kernel it runs beside: a
+// wave of it fits where a wave of that kernel retires.
 // ENERGY: the walker's energy parts (alchemical side); PGRAD: dV/d(eps,
 // sigma, q) of the block's atom; INTEG: the stepping tail.
 template <typename T, bool ENERGY, bool INTEG, bool PGRAD, bool EW>
-__global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INTEG && !EW ? 5 : 1)))
+void k_alch(Dev<T> d, Range r, int xb, int vb, int lb) {
   constexpr int NACC = PGRAD ? 12 : (ENERGY ? 9 : 4);
   __shared__ double red[4][NACC];
   __shared__ int is_last;
@@ -1849,7 +1852,9 @@ __global__ __launch_bounds__(256) void k_alch(Dev<T> d, Range r, int xb, int vb,
       if (so) tot[3] += dce * q * pt;
       const double kb = d.coulomb_k * d.ewald_beta * 0.56418958354775628;  // k beta / sqrt(pi)
       if (ENERGY) {
-        tot[so ? 5 : 4] += 0.5 * q * po - kb * q * q;
+        const double es = 0.5 * q * po - kb * q * q;
+        if (so) tot[5] += es;  // constant indices keep tot in registers
+        else tot[4] += es;
         if (so) tot[7] += ce * q * pt;
       }
       if (PGRAD) {
