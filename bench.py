@@ -456,7 +456,7 @@ def main(argv=None):
     ap.add_argument("--pme-only", action="store_true",
                     help="run only the smooth-PME section (for profiling) and print its JSON")
     ap.add_argument("--prune-buffer", type=float, default=0.0,
-                    help="pair-list prune buffer b in A (0: the library default, min(0.5, skin/2))")
+                    help="pair-list prune buffer b in A (0: the library default, min(0.35, skin/2))")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 10 plain device copies of this many MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -158,7 +158,7 @@ typedef struct labf_system_desc {
                                   r_cut + b of the cluster's box, pruned after each rebuild and
                                   again whenever an atom of the walker has moved more than b/2
                                   since (a larger b prunes less often and evaluates more pairs);
-                                  0 (or NULL): min(0.5, r_skin/2) in length units; else
+                                  0 (or NULL): min(0.35, r_skin/2) in length units; else
                                   0 < b <= r_skin.  The second knob an autotuner chooses per size
                                   class.  Unused with pme_order > 0 (the real-space Ewald kernels
                                   prune the cluster lists as they evaluate them) */

@@ -10,9 +10,10 @@ prunes less often and evaluates more pairs.  For every size class present
 in a batch the tuner times the step of its representative walker (the
 member of median size, replicated to fill the GPU): first each candidate
 width at the default buffer, then each candidate buffer at the best width.
-The cost timed is what the knobs change: the environment pair kernel, the
-pruning and the neighbour rebuild per step (HIP events around single
-launches, labf_profile_steps over one rebuild block, twice).
+The cost timed is the wall time per batched step over whole rebuild
+blocks (HIP graphs, after a warm-up), as the batch runs in production:
+timing the kernels one at a time overrates large prune buffers, because the
+environment kernel runs faster alone than beside the alchemical one.
 
 Results are cached in JSON keyed by GPU architecture, size class and
 precision; the file named by $LABF_AUTOTUNE_CACHE, else autotune_cache.json
@@ -23,6 +24,7 @@ from __future__ import annotations
 import dataclasses
 import json
 import os
+import time
 
 import numpy as np
 
@@ -31,7 +33,7 @@ from . import labf, synth
 # size classes by atoms per walker (lower bound inclusive)
 CLASSES = [(0, 10000), (10000, 20000), (20000, 40000), (40000, 1 << 62)]
 CANDIDATES = (0.8, 0.9, 1.0, 1.12, 1.25)
-PRUNE_CANDIDATES = (0.3, 0.5, 0.7, 0.9)  # A, at most the list buffer
+PRUNE_CANDIDATES = (0.25, 0.5, 0.7)  # A (besides the default 0.35), at most the list buffer
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 
@@ -66,19 +68,25 @@ def save_cache(cache: dict, path: str | None = None) -> None:
         json.dump(cache, f, indent=1, sort_keys=True)
 
 
-def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 2) -> dict:
-    """Per-step cost (ms) of a batch at one column width and prune buffer
-    (0: the library default), the mean of `reps` rebuild blocks."""
+def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 4,
+               warm_blocks: int = 6) -> dict:
+    """Per-step wall time (ms) of a batch at one column width and prune
+    buffer (0: the library default): `reps` rebuild blocks of batched steps
+    (HIP graphs, the kernels side by side as in production) after
+    `warm_blocks` blocks of warm-up, which the device clocks need to ramp up.
+    Kernels timed one at a time favour the wrong balance: the environment
+    kernel runs faster alone than beside the alchemical one."""
     sp = dataclasses.replace(spec, column_width=np.full(spec.n_walkers, float(width)),
                              prune_buffer=np.full(spec.n_walkers, float(prune_buffer)))
     k = int(spec.rebuild_interval)
-    cost = []
     with labf.System(sp, lam) as s:
-        s.step(2 * k)
-        for _ in range(reps):
-            prof = s.profile_steps(k)
-            cost.append(prof["env_ms"] + prof.get("prune_ms", 0.0) + prof["rebuild_ms"] / k)
-    return dict(prof, per_step_ms=float(np.mean(cost)))
+        s.step(warm_blocks * k)
+        s.read_walker_state()  # synchronises the library's stream
+        t0 = time.perf_counter()
+        s.step(reps * k)
+        s.read_walker_state()
+        dt = time.perf_counter() - t0
+    return {"per_step_ms": 1e3 * dt / (reps * k)}
 
 
 def cached_widths(spec, cache_path: str | None = None) -> np.ndarray:

@@ -551,9 +551,9 @@ labf_status plan_system(const labf_system_desc *desc, HostLayout &h) {
     m.ncy = (int32_t)std::min(256.0, std::max(1.0, std::floor(m.L[1] / target)));
     m.cw[0] = m.L[0] / m.ncx;
     m.cw[1] = m.L[1] / m.ncy;
-    // prune buffer: the given one, else half the skin, at most 0.5
+    // prune buffer: the given one, else half the skin, at most 0.35
     m.prune_b = desc->prune_buffer && desc->prune_buffer[w] > 0.0 ? desc->prune_buffer[w]
-                                                                   : std::min(0.5, 0.5 * desc->r_skin);
+                                                                   : std::min(0.35, 0.5 * desc->r_skin);
     m.cap_env = (int32_t)((nenv + CL - 1) / CL + (int64_t)m.ncx * m.ncy);
     m.n_acl = (int32_t)na;  // one alchemical atom per cluster
     m.cl_begin = cl;
