@@ -13,7 +13,12 @@ width at the default buffer, then each candidate buffer at the best width.
 The cost timed is the wall time per batched step over whole rebuild
 blocks (HIP graphs, after a warm-up), as the batch runs in production:
 timing the kernels one at a time overrates large prune buffers, because the
-environment kernel runs faster alone than beside the alchemical one.
+environment kernel runs faster alone than beside the alchemical one.  The
+replicas are relaxed first and fill the GPU as the batch does.  A class's
+choice is then kept only if it also speeds up the batch itself (timed
+alternately against the knobs kept so far); otherwise the class keeps the
+library defaults.  Knob effects are a few per cent at most, and a class's
+replicas alone do not always rank them as the mixed batch does.
 
 Results are cached in JSON keyed by GPU architecture, size class and
 precision; the file named by $LABF_AUTOTUNE_CACHE, else autotune_cache.json
@@ -68,16 +73,29 @@ def save_cache(cache: dict, path: str | None = None) -> None:
         json.dump(cache, f, indent=1, sort_keys=True)
 
 
-def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 4,
-               warm_blocks: int = 6) -> dict:
-    """Per-step wall time (ms) of a batch at one column width and prune
-    buffer (0: the library default): `reps` rebuild blocks of batched steps
-    (HIP graphs, the kernels side by side as in production) after
+def relax(spec, lam, steps: int = 300):
+    """The batch after `steps` steps of strong atom friction (50 fs), a 1 fs
+    step and a rebuild every step, lambda fixed, no ABF: the synthetic start
+    relaxed to the bath temperature.  Timed from the lattice start instead,
+    the atoms leaving their sites move faster than in equilibrium and make
+    small prune buffers re-prune more often than they do in production."""
+    eq = dataclasses.replace(spec, gamma=20e-3, dt=1.0, rebuild_interval=1)
+    lm = dataclasses.replace(lam, fixed_lambda=True, abf_on=False)
+    with labf.System(eq, lm) as s:
+        s.step(steps)
+        pos, vel = s.read_atoms()
+    return dataclasses.replace(spec, pos=pos, vel=vel)
+
+
+def time_knobs(spec, lam, widths, buffers, reps: int = 4, warm_blocks: int = 6) -> float:
+    """Per-step wall time (ms) of a batch at per-walker column widths and
+    prune buffers (0: the library default): `reps` rebuild blocks of batched
+    steps (HIP graphs, the kernels side by side as in production) after
     `warm_blocks` blocks of warm-up, which the device clocks need to ramp up.
     Kernels timed one at a time favour the wrong balance: the environment
     kernel runs faster alone than beside the alchemical one."""
-    sp = dataclasses.replace(spec, column_width=np.full(spec.n_walkers, float(width)),
-                             prune_buffer=np.full(spec.n_walkers, float(prune_buffer)))
+    sp = dataclasses.replace(spec, column_width=np.asarray(widths, dtype=np.float64),
+                             prune_buffer=np.asarray(buffers, dtype=np.float64))
     k = int(spec.rebuild_interval)
     with labf.System(sp, lam) as s:
         s.step(warm_blocks * k)
@@ -86,7 +104,15 @@ def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 4
         s.step(reps * k)
         s.read_walker_state()
         dt = time.perf_counter() - t0
-    return {"per_step_ms": 1e3 * dt / (reps * k)}
+    return 1e3 * dt / (reps * k)
+
+
+def time_width(spec, lam, width: float, prune_buffer: float = 0.0, reps: int = 4,
+               warm_blocks: int = 6) -> dict:
+    """time_knobs with one column width and prune buffer for every walker."""
+    W = spec.n_walkers
+    return {"per_step_ms": time_knobs(spec, lam, np.full(W, float(width)),
+                                      np.full(W, float(prune_buffer)), reps, warm_blocks)}
 
 
 def cached_widths(spec, cache_path: str | None = None) -> np.ndarray:
@@ -105,7 +131,7 @@ def cached_knobs(spec, cache_path: str | None = None):
 
 
 def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
-         prune_candidates=PRUNE_CANDIDATES, target_atoms: int = 480000, force: bool = False,
+         prune_candidates=PRUNE_CANDIDATES, target_atoms: int | None = None, force: bool = False,
          log=None):
     """(column width, prune buffer) per walker of `spec`: the size-class
     choices, cached."""
@@ -114,7 +140,7 @@ def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
     n = np.diff(spec.atom_offset)
     widths = np.ones(spec.n_walkers)
     buffers = np.zeros(spec.n_walkers)
-    changed = False
+    tuned = []  # (key, members) of the classes tuned in this call
     for cls in CLASSES:
         members = np.nonzero([size_class(int(x)) == cls for x in n])[0]
         if members.size == 0:
@@ -123,8 +149,11 @@ def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
         if force or key not in cache or "prune_buffer" not in cache[key]:
             rep = int(members[np.argsort(n[members], kind="stable")[members.size // 2]])
             one, lam1 = synth.subset(spec, lam, [rep])
-            k = max(1, target_atoms // int(n[rep]))
+            # replicas fill the GPU as the whole batch does (the per-step fixed
+            # costs weigh as much as in production), unless told otherwise
+            k = max(1, (target_atoms or int(n.sum())) // int(n[rep]))
             batch, lamb = synth.batch(one, lam1, k, seed=spec.seed + 7)
+            batch = relax(batch, lamb)
             t_w = {}
             for wdt in candidates:
                 t_w[f"{wdt:g}"] = time_width(batch, lamb, wdt)["per_step_ms"]
@@ -144,9 +173,47 @@ def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
                           "atoms": int(n[rep]), "replicas": k,
                           "timings_ms": {w_: round(t, 5) for w_, t in t_w.items()},
                           "prune_timings_ms": {b_: round(t, 5) for b_, t in t_b.items()}}
-            changed = True
+            tuned.append((key, members))
         widths[members] = cache[key]["column_width"]
         buffers[members] = cache[key]["prune_buffer"]
-    if changed:
+    if tuned:
+        widths, buffers = check_on_batch(spec, lam, widths, buffers, cache, tuned, log)
         save_cache(cache, cache_path)
     return widths, buffers
+
+
+def check_on_batch(spec, lam, widths, buffers, cache, tuned, log=None, reps: int = 2,
+                   margin: float = 0.003):
+    """Keep a class's replica-tuned knobs only where they speed up the batch
+    itself.  A class's replicas fill the GPU alone; in the batch its walkers
+    share every launch with the other classes, and knob effects of a per
+    cent or two need not carry over.  Starting from the library defaults,
+    each tuned class's knobs are tried on the (relaxed) batch in turn, timed
+    alternately against the knobs kept so far (best of `reps`), and kept if
+    they are faster by more than `margin`."""
+    batch = relax(spec, lam)
+    cur_w, cur_b = np.ones(spec.n_walkers), np.zeros(spec.n_walkers)
+    for key, members in tuned:
+        ent = cache[key]
+        if ent["column_width"] == 1.0 and ent["prune_buffer"] == 0.0:
+            ent.update(batch_check_ms=None, accepted=True)
+            continue
+        cand_w, cand_b = cur_w.copy(), cur_b.copy()
+        cand_w[members] = widths[members]
+        cand_b[members] = buffers[members]
+        t_cur, t_cand = [], []
+        for _ in range(reps):
+            t_cur.append(time_knobs(batch, lam, cur_w, cur_b))
+            t_cand.append(time_knobs(batch, lam, cand_w, cand_b))
+        ok = min(t_cand) < (1.0 - margin) * min(t_cur)
+        ent["replica_choice"] = {"column_width": ent["column_width"], "prune_buffer": ent["prune_buffer"]}
+        ent["batch_check_ms"] = {"kept": round(min(t_cur), 5), "with_class_knobs": round(min(t_cand), 5)}
+        ent["accepted"] = bool(ok)
+        if ok:
+            cur_w, cur_b = cand_w, cand_b
+        else:
+            ent["column_width"], ent["prune_buffer"] = 1.0, 0.0
+        if log:
+            log(f"autotune {key}: on the batch {min(t_cur):.4f} -> {min(t_cand):.4f} ms, "
+                f"{'kept' if ok else 'defaults kept'}")
+    return cur_w, cur_b
