@@ -421,15 +421,19 @@ __device__ __forceinline__ int wave_excl_scan(int v, int &total) {
 // alchemical clusters within r_list_a; an alchemical cluster lists every
 // cluster within r_list_a.  The columns in range are enumerated 64 at a
 // time (one lane per column, x-y gap test, cluster counts scanned across the
-// wave); their clusters are then flattened into passes of 64 lanes, each
-// lane testing the three z images of one cluster, so that a pass loads 64
-// cluster boxes however the columns are filled.  Alchemical partners take
-// one lane each, testing their 27 images in registers.
+// wave, each flattened cluster's column noted in LDS); their clusters are
+// then flattened into passes of 64 lanes, each lane testing one cluster (its
+// z image nearest the box, or all three where the box is short enough for
+// two to be in range), so that a pass loads 64 cluster boxes however the
+// columns are filled.  Alchemical partners take one lane each, testing their
+// 27 images in registers.
+constexpr int LIST_TAB = 1024;  // flattened clusters per column pass with a direct column lookup
 template <typename T>
 __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
   __shared__ int s_pre[4][WAVE + 1];
   __shared__ int s_j0[4][WAVE];
   __shared__ int s_sxy[4][WAVE];
+  __shared__ uint8_t s_cidx[4][LIST_TAB];  // flattened cluster -> column lane
   const int64_t c = r.c0 + (int64_t)blockIdx.x * 4 + uni(threadIdx.x >> 6);
   if (c >= r.c0 + r.cn) return;
   const int w = d.cl_walker[c];
@@ -510,6 +514,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
       s_j0[wv][lane] = j0;
       s_sxy[wv][lane] = sxy;
       if (lane == 0) s_pre[wv][WAVE] = tot;
+      for (int t = pre; t < pre + ncl && t < LIST_TAB; ++t) s_cidx[wv][t] = (uint8_t)lane;
       __builtin_amdgcn_wave_barrier();
       for (int f0 = 0; f0 < tot; f0 += WAVE) {
         const int f = f0 + lane;
@@ -517,12 +522,18 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
         int64_t J = 0;
         int sx = 0, sy = 0;
         if (f < tot) {
-          // the last column slot whose prefix is <= f (that column has clusters)
-          int a = 0, b = WAVE - 1;
-          while (a < b) {
-            const int mid = (a + b + 1) >> 1;
-            if (s_pre[wv][mid] <= f) a = mid;
-            else b = mid - 1;
+          // the column slot of flattened cluster f: looked up, else the last
+          // slot whose prefix is <= f (that column has clusters)
+          int a = 0;
+          if (f < LIST_TAB) {
+            a = s_cidx[wv][f];
+          } else {
+            int b = WAVE - 1;
+            while (a < b) {
+              const int mid = (a + b + 1) >> 1;
+              if (s_pre[wv][mid] <= f) a = mid;
+              else b = mid - 1;
+            }
           }
           J = m.cl_begin + s_j0[wv][a] + (f - s_pre[wv][a]);
           const int code_xy = s_sxy[wv][a];
@@ -534,8 +545,15 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
           const double ax = gap1(lo[0], hi[0], b0 + ox, b3 + ox);
           const double ay = gap1(lo[1], hi[1], b1 + oy, b4 + oy);
           const double axy = ax * ax + ay * ay;
+          // Two z images of the box pair can both lie within r_list only if
+          // the two boxes and 2 r_list span the box length; otherwise only
+          // the image whose centre lies within L/2 can (test that one).
+          const bool all3 = (hi[2] - lo[2]) + (b5 - b2) + 2.0 * rl >= m.L[2] * (1.0 - 1e-6);
+          const double dzc = 0.5 * ((b2 + b5) - (lo[2] + hi[2]));
+          const int sn = dzc > 0.5 * m.L[2] ? -1 : (dzc < -0.5 * m.L[2] ? 1 : 0);
 #pragma unroll
           for (int sz = -1; sz <= 1; ++sz) {
+            if (!all3 && sz != sn) continue;
             const double oz = sz * m.L[2];
             const double az = gap1(lo[2], hi[2], b2 + oz, b5 + oz);
             bool pass = axy + az * az < rl2;
@@ -547,6 +565,7 @@ __global__ __launch_bounds__(256) void k_list(Dev<T> d, Range r) {
         for (int zs = 0; zs < 3; ++zs) {
           const bool pass = (mask >> zs) & 1u;
           const unsigned long long bal = __ballot(pass);
+          if (bal == 0ull) continue;
           if (pass) {
             const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
             const int code = image_code(sx, sy, zs - 1);
