@@ -16,8 +16,8 @@ timing the kernels one at a time overrates large prune buffers, because the
 environment kernel runs faster alone than beside the alchemical one.  The
 replicas are relaxed first and fill the GPU as the batch does.  A class's
 choice is then kept only if it also speeds up the batch itself (timed
-alternately against the knobs kept so far); otherwise the class keeps the
-library defaults.  Knob effects are a few per cent at most, and a class's
+alternately against the knobs kept so far, by more than 1 %); otherwise
+the class keeps the library defaults.  Knob effects are a few per cent at most, and a class's
 replicas alone do not always rank them as the mixed batch does.
 
 Results are cached in JSON keyed by GPU architecture, size class and
@@ -183,14 +183,15 @@ def tune(spec, lam, cache_path: str | None = None, candidates=CANDIDATES,
 
 
 def check_on_batch(spec, lam, widths, buffers, cache, tuned, log=None, reps: int = 2,
-                   margin: float = 0.003):
+                   margin: float = 0.01):
     """Keep a class's replica-tuned knobs only where they speed up the batch
     itself.  A class's replicas fill the GPU alone; in the batch its walkers
     share every launch with the other classes, and knob effects of a per
     cent or two need not carry over.  Starting from the library defaults,
     each tuned class's knobs are tried on the (relaxed) batch in turn, timed
     alternately against the knobs kept so far (best of `reps`), and kept if
-    they are faster by more than `margin`."""
+    they are faster by more than `margin` (about the run-to-run spread of a
+    whole bench run: a smaller gain need not hold in the next run)."""
     batch = relax(spec, lam)
     cur_w, cur_b = np.ones(spec.n_walkers), np.zeros(spec.n_walkers)
     for key, members in tuned:
