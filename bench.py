@@ -556,6 +556,8 @@ def main(argv=None):
                         "over [0.5,1]), batched: 10-step HIP-graph blocks",
             "solvent_sigma_A": 2.04, "lattice": "fcc, charge species on alternating (001) planes",
             "walkers": W, "atoms_per_walker": args.atoms, "cutoff_A": 12.0, "skin_A": 1.0,
+            # the library's default prune buffer is min(0.35 A, skin/2)
+            "prune_buffer_A": float(args.prune_buffer) if args.prune_buffer > 0 else min(0.35, 0.5 * 1.0),
             "rebuild_interval": 10, "abf_bins": 100, "pair_precision": "f32",
             "lambda_precision": "f64", "equilibration_steps_untimed": args.equil_steps,
             "batch_equilibration_steps_untimed": args.batch_equil_steps,
